@@ -1,0 +1,173 @@
+/*
+ * lace.h - C ABI of liblace, the MI355X (gfx950) implementation of the
+ * L-ACE exact-exchange path of Carnimeo, Baroni, Giannozzi,
+ * "Fast hybrid density-functional computations using plane-wave basis sets"
+ * (arXiv:1801.09263).
+ *
+ * Three operations follow the paper's statement of the problem (Sec. 2):
+ *   lace_apply_exchange  W = K psi over the screened orbital pairs
+ *                        (Eq. (2); truncated as in Eqs. (6)-(8)),
+ *   lace_build_ace       M = psi^H W, symmetrize, -M_s = L L^H,
+ *                        xi = W L^{-H} (Eqs. (3)-(5), (9); symmetrizations
+ *                        of the text after Eq. (10)),
+ *   lace_apply_ace       y = -xi (xi^H x) (text after Eq. (5)).
+ *
+ * Conventions.  Hartree atomic units, e^2 = 1.  K = -V_X (the paper's V_X
+ * is made positive, Sec. 2), so M is negative semidefinite and xi is -1
+ * times the paper's xi; xi xi^H is the same.  One spin channel, occupation
+ * 1.  Cubic cell of side L, n^3 FFT grid, Omega = L^3.  Coulomb kernel
+ * truncated at R_c: v(G) = 4 pi (1 - cos |G| R_c) / |G|^2, v(0) = 2 pi R_c^2.
+ *
+ * Plane-wave arrays (psi_g, w_g, xi_g, x_g, y_g) are complex128 (interleaved
+ * re, im doubles), column-major n_pw x n_cols: column j is contiguous and
+ * holds orbital/function j in the order of the Miller list given at plan
+ * creation.  Matrices M and S are n_orb x n_orb, row-major, M[a][b] =
+ * <psi_a|K|psi_b>.
+ *
+ * Ownership.  All data buffers and the workspace belong to the caller; the
+ * library keeps no pointer to them after a call returns.  The plan owns its
+ * own tables (sphere-to-grid map, kernel table, twiddles) in device memory.
+ *
+ * Errors.  Every call returns an int status: LACE_OK (0) or a negative code.
+ * Argument, shape and workspace errors are detected on the host before any
+ * device work is enqueued.  A failed Cholesky factorization (M_s not
+ * negative definite) is a device-side event recorded in the plan's info
+ * word and read with lace_get_info.  HIP runtime errors map to LACE_EHIP.
+ *
+ * Streams.  Work is enqueued on the given stream (0 = null stream) and is
+ * asynchronous, except where a call says it synchronizes.  A plan must be
+ * used by one host thread at a time.
+ */
+#ifndef LACE_H
+#define LACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* lace_stream_t; /* a hipStream_t */
+
+enum {
+  LACE_OK = 0,
+  LACE_EINVAL = -1,      /* bad argument (null pointer, out-of-range value) */
+  LACE_ENOMEM = -2,      /* workspace too small, or a plan allocation failed */
+  LACE_ENOTPD = -3,      /* -M_s not positive definite (via lace_get_info) */
+  LACE_EUNSUPPORTED = -4,/* grid size not supported, or sphere exceeds grid */
+  LACE_EHIP = -5         /* HIP runtime error */
+};
+
+typedef enum {
+  LACE_FP64 = 0,  /* grids, FFTs and pair products in FP64 */
+  LACE_FP32 = 1   /* grids, FFTs and pair products in FP32; screening sums,
+                     exchange-energy sums, M, Cholesky, xi in FP64 */
+} lace_precision;
+
+typedef enum {
+  LACE_SYM_AVG = 0,   /* M_s = (M + M^H) / 2 */
+  LACE_SYM_UPPER = 1, /* upper triangle of M mirrored into the lower */
+  LACE_SYM_LOWER = 2  /* lower triangle of M mirrored into the upper */
+} lace_sym;
+
+typedef struct {
+  double L;              /* cubic cell side (bohr), > 0 */
+  int32_t n;             /* FFT grid points per axis; one of the supported
+                            sizes 8 12 16 24 32 48 64 80 96 120 */
+  double rc;             /* Coulomb truncation radius; <= 0 selects L / 2 */
+  int64_t n_pw;          /* number of plane waves, >= 1 */
+  const int32_t* miller; /* host, n_pw x 3 int32 (m_x, m_y, m_z) per plane
+                            wave; every |m_d| < n / 2 and no duplicates */
+} lace_cell_desc;
+
+typedef struct lace_plan lace_plan; /* opaque */
+
+/* Create a plan for n_cells cells.  Builds on the current device the
+ * sphere-to-grid map, the kernel table v(G) (evaluated in FP64, stored in
+ * the plan precision) and FFT twiddles.  Synchronous.  *out is set only on
+ * success.  Errors: EINVAL (null pointers, n_cells < 1, L <= 0, n_pw < 1,
+ * duplicate Miller triples), EUNSUPPORTED (grid size, sphere outside the
+ * grid), ENOMEM, EHIP. */
+int lace_plan_create(const lace_cell_desc* cells, int n_cells,
+                     lace_precision prec, lace_plan** out);
+
+/* Free the plan's device tables.  Synchronizes the device.  NULL is OK. */
+int lace_plan_destroy(lace_plan* plan);
+
+/* Workspace bytes needed by lace_apply_exchange, lace_build_ace and
+ * lace_apply_ace on this cell for up to n_orb orbitals and n_vec functions
+ * per lace_apply_ace call.  One workspace of this size serves all three. */
+int lace_workspace_size(const lace_plan* plan, int cell, int n_orb, int n_vec,
+                        size_t* bytes);
+
+/* Screening matrix S_ij = integral |psi_i(r)| |psi_j(r)| dr (Eq. (6)),
+ * computed from the orbitals on the grid in the plan precision and summed
+ * in FP64.  psi_g: device, n_pw x n_orb complex128.  s_out: device,
+ * n_orb x n_orb double, row-major.  Also leaves the grid orbitals in the
+ * workspace.  Asynchronous. */
+int lace_screen(lace_plan* plan, int cell, const void* psi_g, int n_orb,
+                double* s_out, void* ws, size_t ws_bytes,
+                lace_stream_t stream);
+
+/* W = K psi restricted to the kept pairs (Eq. (2) truncated by
+ * Eqs. (6)-(8)).
+ *   psi_g   device, n_pw x n_orb complex128, orthonormal orbitals.
+ *   s_thr   screening threshold in [0, 1): an unordered pair (i, j) is kept
+ *           when S_ij >= s_thr; s_thr = 0 keeps every pair (plain ACE).
+ *   pair_i, pair_j  optional host int32 arrays of n_pairs unordered pairs
+ *           (0 <= i <= j < n_orb, no repeats) that override the screening;
+ *           pass NULL/NULL/0 to screen with s_thr.
+ *   w_g     device, n_pw x n_orb complex128 output (K psi on the sphere).
+ *   e_x     device double output (may be NULL): exchange energy
+ *           -(1/2) sum over kept ordered pairs of (ij|ji), summed in FP64
+ *           from the pair densities.
+ *   n_kept  host int64 output (may be NULL): number of unordered pairs run.
+ * With screening (pair_i == NULL and s_thr > 0) the call synchronizes the
+ * stream once to read S back and build the pair schedule on the host;
+ * otherwise it is asynchronous.  Errors: EINVAL, ENOMEM (workspace), EHIP. */
+int lace_apply_exchange(lace_plan* plan, int cell, const void* psi_g,
+                        int n_orb, double s_thr, const int32_t* pair_i,
+                        const int32_t* pair_j, int64_t n_pairs, void* w_g,
+                        double* e_x, int64_t* n_kept, void* ws,
+                        size_t ws_bytes, lace_stream_t stream);
+
+/* ACE projector from psi and W = K psi (Eqs. (3)-(5), (9)).
+ *   m_out   device n_orb x n_orb complex128 (may be NULL): M = psi^H W.
+ *   xi_g    device n_pw x n_orb complex128 output: xi = W L^{-H} with
+ *           -M_s = L L^H, L lower triangular with positive diagonal.
+ *   ex_tr   device double (may be NULL): (1/2) Re tr M.
+ * A non-positive-definite -M_s sets the cell's info word (read with
+ * lace_get_info); xi is then undefined.  Asynchronous. */
+int lace_build_ace(lace_plan* plan, int cell, const void* psi_g,
+                   const void* w_g, int n_orb, lace_sym sym, void* xi_g,
+                   void* m_out, double* ex_tr, void* ws, size_t ws_bytes,
+                   lace_stream_t stream);
+
+/* y = -xi (xi^H x): the compressed exchange applied to n_vec functions.
+ * xi_g device n_pw x n_orb, x_g device n_pw x n_vec, y_g device
+ * n_pw x n_vec (complex128; y_g must not alias x_g).  Asynchronous. */
+int lace_apply_ace(lace_plan* plan, int cell, const void* xi_g, int n_orb,
+                   const void* x_g, int n_vec, void* y_g, void* ws,
+                   size_t ws_bytes, lace_stream_t stream);
+
+/* In-place 3D FFT of `count` n^3 grids stored back to back in the plan
+ * precision (complex64 or complex128, x fastest).  direction -1: forward
+ * (exp(-i G.r)), +1: backward; both unscaled.  Exposed so the transform
+ * itself can be tested.  Asynchronous. */
+int lace_fft3d(lace_plan* plan, int cell, int direction, void* grids,
+               int count, lace_stream_t stream);
+
+/* Info word of the last lace_build_ace on this cell: 0 if the Cholesky
+ * factorization succeeded, else k + 1 for the first non-positive pivot k.
+ * Synchronizes the device.  Returns LACE_OK when the word is 0 and
+ * LACE_ENOTPD when it is not (*info_host is filled in both cases). */
+int lace_get_info(lace_plan* plan, int cell, int32_t* info_host);
+
+/* Static text for a status code. */
+const char* lace_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LACE_H */

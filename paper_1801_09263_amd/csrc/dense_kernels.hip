@@ -1,0 +1,470 @@
+// dense_kernels.hip - FP64 dense linear algebra of the ACE construction.
+//
+//   M   = psi^H W          (Eq. (3); M' of Eq. (9) when W is truncated)
+//   S   = |psi|^T |psi| dV (Eq. (6), screening)
+//   T   = xi^H x,  y = -xi T  (ACE application)
+//   -M_s = L L^H, Z = L^{-H}, xi = W Z  (Eqs. (4)-(5))
+//
+// The contractions run on the FP64 matrix cores with
+// v_mfma_f64_16x16x4_f64: per wave D(16x16) += A(16x4) B(4x16), where
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[l / 16 + 4 e][l % 16] in accumulator element e (rows interleaved; the
+// layout was confirmed with a one-wave probe on gfx950).
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace lace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------
+// Inner-product GEMM with split K:
+//   part[z][a][b] = sum_{k in chunk z} op(A[a][k]) op(B[b][k])
+// MODE 0: complex, op(A) = conj(A), op(B) = B (complex128 inputs)
+// MODE 1: real, op = |.| of float2 inputs (computed in FP64)
+// MODE 2: real, op = |.| of double2 inputs
+// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 output,
+// each wave a 32 x 32 block (2 x 2 MFMA tiles).  K staged through LDS in
+// chunks of 16 with coalesced row loads.
+// ------------------------------------------------------------------
+constexpr int IP_T = 64, IP_KC = 16;
+
+template <int MODE> struct IpLoad;
+template <> struct IpLoad<0> {
+  __device__ static inline void get(const void* p, int64_t off, double& re,
+                                    double& im) {
+    const double2 v = static_cast<const double2*>(p)[off];
+    re = v.x; im = v.y;
+  }
+};
+template <> struct IpLoad<1> {
+  __device__ static inline void get(const void* p, int64_t off, double& re,
+                                    double& im) {
+    const float2 v = static_cast<const float2*>(p)[off];
+    const double x = v.x, y = v.y;
+    re = sqrt(x * x + y * y); im = 0.0;
+  }
+};
+template <> struct IpLoad<2> {
+  __device__ static inline void get(const void* p, int64_t off, double& re,
+                                    double& im) {
+    const double2 v = static_cast<const double2*>(p)[off];
+    re = sqrt(v.x * v.x + v.y * v.y); im = 0.0;
+  }
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_gemm_ip(const void* A, int64_t lda,
+                                                 int na, const void* B,
+                                                 int64_t ldb, int nb,
+                                                 int64_t K, int64_t kchunk,
+                                                 double* part) {
+  constexpr bool CPLX = (MODE == 0);
+  __shared__ double sAr[IP_T][IP_KC + 1];
+  __shared__ double sBr[IP_T][IP_KC + 1];
+  __shared__ double sAi[CPLX ? IP_T : 1][IP_KC + 1];
+  __shared__ double sBi[CPLX ? IP_T : 1][IP_KC + 1];
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int wa = w % 2, wb = w / 2;
+  const int a0 = blockIdx.x * IP_T, b0 = blockIdx.y * IP_T;
+  const int64_t kb = blockIdx.z * kchunk;
+  int64_t ke = kb + kchunk;
+  if (ke > K) ke = K;
+
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      accR[p][q] = d4{0, 0, 0, 0};
+      accI[p][q] = d4{0, 0, 0, 0};
+    }
+
+  for (int64_t k0 = kb; k0 < ke; k0 += IP_KC) {
+#pragma unroll
+    for (int e = 0; e < (IP_T * IP_KC) / 256; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / IP_KC, kk = idx % IP_KC;
+      const int64_t k = k0 + kk;
+      double re = 0.0, im = 0.0;
+      if (a0 + r < na && k < ke) IpLoad<MODE>::get(A, (a0 + r) * lda + k, re, im);
+      sAr[r][kk] = re;
+      if (CPLX) sAi[r][kk] = im;
+      re = 0.0; im = 0.0;
+      if (b0 + r < nb && k < ke) IpLoad<MODE>::get(B, (b0 + r) * ldb + k, re, im);
+      sBr[r][kk] = re;
+      if (CPLX) sBi[r][kk] = im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < IP_KC / 4; ++ks) {
+      const int kk = ks * 4 + lane / 16;
+      double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int ra = wa * 32 + p * 16 + lane % 16;
+        const int rb = wb * 32 + p * 16 + lane % 16;
+        ar[p] = sAr[ra][kk];
+        br[p] = sBr[rb][kk];
+        if (CPLX) {
+          ai[p] = sAi[ra][kk];
+          bi[p] = sBi[rb][kk];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          accR[p][q] = mfma(ar[p], br[q], accR[p][q]);
+          if (CPLX) {
+            // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+            accR[p][q] = mfma(ai[p], bi[q], accR[p][q]);
+            accI[p][q] = mfma(ar[p], bi[q], accI[p][q]);
+            accI[p][q] = mfma(-ai[p], br[q], accI[p][q]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.z * na * nb * (CPLX ? 2 : 1);
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int a = a0 + wa * 32 + p * 16 + lane / 16 + 4 * e;
+        const int b = b0 + wb * 32 + q * 16 + lane % 16;
+        if (a < na && b < nb) {
+          if (CPLX) {
+            out[2 * ((int64_t)a * nb + b)] = accR[p][q][e];
+            out[2 * ((int64_t)a * nb + b) + 1] = accI[p][q][e];
+          } else {
+            out[(int64_t)a * nb + b] = accR[p][q][e];
+          }
+        }
+      }
+}
+
+// out[e] = scale * sum_z part[z][e], fixed order over z
+__global__ void k_splitk_reduce(const double* part, int64_t nel, int nsplit,
+                                double scale, double* out) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nel;
+       e += stride) {
+    double t = 0.0;
+    for (int z = 0; z < nsplit; ++z) t += part[(int64_t)z * nel + e];
+    out[e] = scale * t;
+  }
+}
+
+struct SplitPlan {
+  int nsplit;
+  int64_t kchunk;
+};
+
+static SplitPlan split_plan(int na, int nb, int64_t K) {
+  const int64_t tiles = (int64_t)((na + IP_T - 1) / IP_T) * ((nb + IP_T - 1) / IP_T);
+  int64_t want = (1024 + tiles - 1) / tiles;
+  const int64_t maxs = (K + IP_KC - 1) / IP_KC;
+  if (want > maxs) want = maxs;
+  if (want < 1) want = 1;
+  int64_t chunk = (K + want - 1) / want;
+  chunk = ((chunk + IP_KC - 1) / IP_KC) * IP_KC;
+  if (chunk < IP_KC) chunk = IP_KC;
+  SplitPlan sp;
+  sp.kchunk = chunk;
+  sp.nsplit = (int)((K + chunk - 1) / chunk);
+  if (sp.nsplit < 1) sp.nsplit = 1;
+  return sp;
+}
+
+int64_t gemm_ip_part_bytes(int na, int nb, int64_t K, bool complex_out) {
+  const SplitPlan sp = split_plan(na, nb, K);
+  return (int64_t)sp.nsplit * na * nb * (complex_out ? 16 : 8);
+}
+
+template <int MODE>
+static hipError_t gemm_ip(const void* A, int64_t lda, int na, const void* B,
+                          int64_t ldb, int nb, int64_t K, double scale,
+                          double* out, void* part, int64_t part_bytes,
+                          hipStream_t st) {
+  const SplitPlan sp = split_plan(na, nb, K);
+  const bool cplx = (MODE == 0);
+  if ((int64_t)sp.nsplit * na * nb * (cplx ? 16 : 8) > part_bytes)
+    return hipErrorInvalidValue;
+  dim3 grid((na + IP_T - 1) / IP_T, (nb + IP_T - 1) / IP_T, sp.nsplit);
+  hipLaunchKernelGGL((k_gemm_ip<MODE>), grid, dim3(256), 0, st, A, lda, na, B,
+                     ldb, nb, K, sp.kchunk, static_cast<double*>(part));
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int64_t nel = (int64_t)na * nb * (cplx ? 2 : 1);
+  int64_t blocks = (nel + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const double*>(part), nel, sp.nsplit, scale,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_ip_c128(const void* A, int64_t lda, int na,
+                               const void* B, int64_t ldb, int nb, int64_t K,
+                               double scale, void* out, void* part,
+                               int64_t part_bytes, hipStream_t st) {
+  return gemm_ip<0>(A, lda, na, B, ldb, nb, K, scale,
+                    static_cast<double*>(out), part, part_bytes, st);
+}
+
+hipError_t launch_gemm_ip_abs(bool fp64, const void* A, int64_t lda, int na,
+                              int64_t K, double scale, double* out, void* part,
+                              int64_t part_bytes, hipStream_t st) {
+  return fp64 ? gemm_ip<2>(A, lda, na, A, lda, na, K, scale, out, part,
+                           part_bytes, st)
+              : gemm_ip<1>(A, lda, na, A, lda, na, K, scale, out, part,
+                           part_bytes, st);
+}
+
+// ------------------------------------------------------------------
+// Tall GEMM  Y[b][m] = sum_k X[k][m] Z[k][b]  (complex, no conjugation).
+// Workgroup 256 threads: 64 rows m (one 16-row block per wave) x 64
+// columns b (4 MFMA tiles per wave).  X is read straight from global
+// memory (16 consecutive m per k row per wave), Z is small and cached.
+// ------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_tall(const double2* X,
+                                                   int64_t ldx, int64_t M,
+                                                   int nk, const double2* Z,
+                                                   int nb, double2* Y,
+                                                   int64_t ldy) {
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int64_t m0 = (int64_t)blockIdx.x * 64 + w * 16;
+  const int b0 = blockIdx.y * 64;
+  d4 accR[4], accI[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    accR[q] = d4{0, 0, 0, 0};
+    accI[q] = d4{0, 0, 0, 0};
+  }
+  const int64_t m = m0 + lane % 16;
+  for (int k0 = 0; k0 < nk; k0 += 4) {
+    const int k = k0 + lane / 16;
+    double2 x = make_double2(0.0, 0.0);
+    if (k < nk && m < M) x = X[(int64_t)k * ldx + m];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + q * 16 + lane % 16;
+      double2 z = make_double2(0.0, 0.0);
+      if (k < nk && b < nb) z = Z[(int64_t)k * nb + b];
+      accR[q] = mfma(x.x, z.x, accR[q]);
+      accR[q] = mfma(-x.y, z.y, accR[q]);
+      accI[q] = mfma(x.x, z.y, accI[q]);
+      accI[q] = mfma(x.y, z.x, accI[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int b = b0 + q * 16 + lane % 16;
+    if (b >= nb) continue;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t mm = m0 + lane / 16 + 4 * e;
+      if (mm < M) Y[(int64_t)b * ldy + mm] = make_double2(accR[q][e], accI[q][e]);
+    }
+  }
+}
+
+hipError_t launch_gemm_tall(const void* X, int64_t ldx, int64_t M, int nk,
+                            const void* Z, int nb, void* Y, int64_t ldy,
+                            hipStream_t st) {
+  dim3 grid((unsigned)((M + 63) / 64), (nb + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_tall, grid, dim3(256), 0, st,
+                     static_cast<const double2*>(X), ldx, M, nk,
+                     static_cast<const double2*>(Z), nb,
+                     static_cast<double2*>(Y), ldy);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------
+// A = -sym(M): mode 0 (M + M^H)/2, 1 upper mirrored, 2 lower mirrored;
+// the diagonal is -Re(M_aa) in every mode.
+// ------------------------------------------------------------------
+__global__ void k_neg_sym(const double2* M, int n, int mode, double2* A) {
+  const int64_t total = (int64_t)n * n;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += stride) {
+    const int a = (int)(e / n), b = (int)(e % n);
+    double2 r;
+    if (a == b) {
+      r = make_double2(-M[e].x, 0.0);
+    } else {
+      const double2 u = M[(int64_t)a * n + b];
+      const double2 v = M[(int64_t)b * n + a];
+      if (mode == 0) {
+        r = make_double2(-0.5 * (u.x + v.x), -0.5 * (u.y - v.y));
+      } else if ((mode == 1) == (a < b)) {
+        r = make_double2(-u.x, -u.y);           // take own triangle
+      } else {
+        r = make_double2(-v.x, v.y);            // mirror: -conj(M[b][a])
+      }
+    }
+    A[e] = r;
+  }
+}
+
+hipError_t launch_neg_sym(const void* M, int n, int mode, void* A,
+                          hipStream_t st) {
+  const int64_t total = (int64_t)n * n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_neg_sym, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const double2*>(M), n, mode,
+                     static_cast<double2*>(A));
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------
+// Right-looking Cholesky A = L L^H in one workgroup (n <= a few thousand).
+// A is row-major complex128, overwritten by L (strict upper zeroed).
+// ------------------------------------------------------------------
+constexpr int CH_NT = 1024;
+__global__ __launch_bounds__(CH_NT) void k_cholesky(double2* A, int n,
+                                                    int32_t* info) {
+  __shared__ int fail;
+  __shared__ double lkk;
+  const int tid = threadIdx.x;
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = A[(int64_t)k * n + k].x;
+      if (!(d > 0.0)) {
+        fail = k + 1;
+      } else {
+        lkk = sqrt(d);
+        A[(int64_t)k * n + k] = make_double2(lkk, 0.0);
+      }
+    }
+    __syncthreads();
+    if (fail) break;
+    const double inv = 1.0 / lkk;
+    for (int i = k + 1 + tid; i < n; i += CH_NT) {
+      double2 v = A[(int64_t)i * n + k];
+      A[(int64_t)i * n + k] = make_double2(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int64_t idx = tid; idx < (int64_t)m * m; idx += CH_NT) {
+      const int i = k + 1 + (int)(idx / m), j = k + 1 + (int)(idx % m);
+      if (j > i) continue;
+      const double2 li = A[(int64_t)i * n + k], lj = A[(int64_t)j * n + k];
+      double2 a = A[(int64_t)i * n + j];
+      // a -= li * conj(lj)
+      a.x -= li.x * lj.x + li.y * lj.y;
+      a.y -= li.y * lj.x - li.x * lj.y;
+      A[(int64_t)i * n + j] = a;
+    }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)n * n; e += CH_NT) {
+    const int i = (int)(e / n), j = (int)(e % n);
+    if (j > i) A[e] = make_double2(0.0, 0.0);
+  }
+  if (tid == 0) *info = fail;
+}
+
+hipError_t launch_cholesky(void* A, int n, int32_t* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_NT), 0, st,
+                     static_cast<double2*>(A), n, info);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------
+// Z = (L^{-1})^H.  Workgroup c (one wave) solves L x = e_c by forward
+// substitution with x in LDS, then writes row c of Z: Z[c][i] = conj(x_i).
+// ------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_trinv_adj(const double2* L, int n,
+                                                  double2* Z) {
+  extern __shared__ double2 x[];
+  const int c = blockIdx.x, l = threadIdx.x;
+  for (int i = l; i < n; i += 64) x[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (l == 0) x[c] = make_double2(1.0 / L[(int64_t)c * n + c].x, 0.0);
+  __syncthreads();
+  for (int i = c + 1; i < n; ++i) {
+    double sr = 0.0, si = 0.0;
+    const double2* row = L + (int64_t)i * n;
+    for (int m = c + l; m < i; m += 64) {
+      const double2 a = row[m], b = x[m];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      si += __shfl_xor(si, o, 64);
+    }
+    if (l == 0) {
+      const double d = 1.0 / row[i].x;
+      x[i] = make_double2(-sr * d, -si * d);
+    }
+    __syncthreads();
+  }
+  for (int i = l; i < n; i += 64) {
+    const double2 v = x[i];
+    Z[(int64_t)c * n + i] = (i >= c) ? make_double2(v.x, -v.y)
+                                     : make_double2(0.0, 0.0);
+  }
+}
+
+hipError_t launch_trinv_adj(const void* L, int n, void* Z, hipStream_t st) {
+  hipLaunchKernelGGL(k_trinv_adj, dim3(n), dim3(64), n * sizeof(double2), st,
+                     static_cast<const double2*>(L), n,
+                     static_cast<double2*>(Z));
+  return hipGetLastError();
+}
+
+__global__ void k_trace_re(const double2* M, int n, double factor,
+                           double* out) {
+  __shared__ double red[4];
+  double t = 0.0;
+  for (int a = threadIdx.x; a < n; a += 256) t += M[(int64_t)a * n + a].x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = factor * (red[0] + red[1] + red[2] + red[3]);
+}
+
+hipError_t launch_trace_re(const void* M, int n, double factor, double* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_trace_re, dim3(1), dim3(256), 0, st,
+                     static_cast<const double2*>(M), n, factor, out);
+  return hipGetLastError();
+}
+
+__global__ void k_scale_c128(const double2* x, int64_t n, double s,
+                             double2* y) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
+       e += stride)
+    y[e] = make_double2(s * x[e].x, s * x[e].y);
+}
+
+hipError_t launch_scale_c128(const void* x, int64_t n, double s, void* y,
+                             hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_scale_c128, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const double2*>(x), n, s,
+                     static_cast<double2*>(y));
+  return hipGetLastError();
+}
+
+}  // namespace lace

@@ -1,0 +1,469 @@
+// fft_kernels.hip - 3D FFT passes and the fused pair-exchange pipeline.
+//
+// Grid layout: an n^3 complex grid is stored x fastest, then y, then z
+// (index x + n (y + n z)); batches of grids are back to back.
+//
+// Pair pipeline (Eq. (2) of the paper, one batch of disjoint pairs):
+//   pass A  rho = conj(psi_i) psi_j fused with the forward transform along
+//           x and y (whole xy plane in LDS), or along x then y (pencils);
+//   pass B  forward z transform, multiply by v(G)/N_g, accumulate the
+//           exchange-integral partial sum_G v |rho(G)|^2 in FP64, backward
+//           z transform, all in one kernel;
+//   pass C  backward y and x transforms fused with
+//           W_j -= psi_i V_ij and, for i != j, W_i -= psi_j conj(V_ij)
+//           (V_ji = conj(V_ij) because v is real and even in G).
+// Pairs inside a batch share no orbital, so pass C needs no atomics and the
+// accumulation order is fixed by the host schedule.
+#include "fft_core.hpp"
+#include "internal.hpp"
+
+namespace lace {
+
+// ------------------------------------------------------------- functors
+template <typename T> struct ProGrid {
+  const C<T>* buf;
+  int64_t gs;
+  __device__ C<T> get(int g, int slot) const { return buf[slot * gs + g]; }
+};
+template <typename T> struct ProPair {
+  const C<T>* psi;
+  int64_t gs;
+  PairArgs pa;
+  __device__ C<T> get(int g, int slot) const {
+    const C<T> a = psi[pa.i[slot] * gs + g];
+    const C<T> b = psi[pa.j[slot] * gs + g];
+    return cmul<T>(a, b);
+  }
+};
+template <typename T> struct EpiGrid {
+  C<T>* buf;
+  int64_t gs;
+  T scale;
+  __device__ void put(int g, int slot, C<T> v) const {
+    buf[slot * gs + g] = scl<T>(v, scale);
+  }
+};
+template <typename T> struct EpiAcc {
+  const C<T>* psi;
+  C<T>* w;
+  int64_t gs;
+  PairArgs pa;
+  __device__ void put(int g, int slot, C<T> v) const {
+    const int i = pa.i[slot], j = pa.j[slot];
+    const C<T> pi = psi[i * gs + g];
+    C<T> wj = w[j * gs + g];
+    w[j * gs + g] = sub<T>(wj, mul<T>(pi, v));
+    if (i != j) {
+      const C<T> pj = psi[j * gs + g];
+      C<T> wi = w[i * gs + g];
+      w[i * gs + g] = sub<T>(wi, mulc<T>(pj, v));
+    }
+  }
+};
+
+template <typename T, int N, int NT>
+__device__ inline void load_tw(C<T>* tw, const C<T>* tw_g) {
+  for (int m = threadIdx.x; m < N; m += NT) tw[m] = tw_g[m];
+}
+
+// ------------------------------------------- xy-plane pass (whole plane)
+template <typename T, int N, int NT, int SIGN, class Pro, class Epi>
+__global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
+                                              const C<T>* tw_g) {
+  __shared__ C<T> s[N * N];
+  __shared__ C<T> tw[N];
+  const int z = blockIdx.x, slot = blockIdx.y;
+  load_tw<T, N, NT>(tw, tw_g);
+  const int base = z * N * N;
+  for (int m = threadIdx.x; m < N * N; m += NT) s[m] = pro.get(base + m, slot);
+  __syncthreads();
+  lds_fft<T, N, N, NT, SIGN, false>(s, N, 1, tw);  // along x (rows)
+  lds_fft<T, N, N, NT, SIGN, true>(s, 1, N, tw);   // along y (columns)
+  for (int m = threadIdx.x; m < N * N; m += NT) epi.put(base + m, slot, s[m]);
+}
+
+// ---------------------------------------------- x pencils: TY whole rows
+template <typename T, int N, int TY, int NT, int SIGN, class Pro, class Epi>
+__global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
+                                               const C<T>* tw_g) {
+  __shared__ C<T> s[TY * N];
+  __shared__ C<T> tw[N];
+  const int slot = blockIdx.y;
+  load_tw<T, N, NT>(tw, tw_g);
+  const int base = blockIdx.x * TY * N;
+  for (int m = threadIdx.x; m < TY * N; m += NT) s[m] = pro.get(base + m, slot);
+  __syncthreads();
+  lds_fft<T, N, TY, NT, SIGN, false>(s, N, 1, tw);
+  for (int m = threadIdx.x; m < TY * N; m += NT) epi.put(base + m, slot, s[m]);
+}
+
+// ---------------------- y or z pencils: TX adjacent x columns, whole axis
+template <int N, int AXIS, int TX>
+__device__ inline int col_index(int tile, int m) {
+  const int xt = tile % (N / TX), f = tile / (N / TX);
+  const int xx = m % TX, e = m / TX;
+  const int x = xt * TX + xx;
+  return AXIS == 1 ? x + N * (e + N * f) : x + N * (f + N * e);
+}
+
+template <typename T, int N, int AXIS, int TX, int NT, int SIGN, class Pro,
+          class Epi>
+__global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
+                                             const C<T>* tw_g) {
+  __shared__ C<T> s[TX * N];
+  __shared__ C<T> tw[N];
+  const int tile = blockIdx.x, slot = blockIdx.y;
+  load_tw<T, N, NT>(tw, tw_g);
+  for (int m = threadIdx.x; m < TX * N; m += NT)
+    s[m] = pro.get(col_index<N, AXIS, TX>(tile, m), slot);
+  __syncthreads();
+  lds_fft<T, N, TX, NT, SIGN, true>(s, 1, TX, tw);
+  for (int m = threadIdx.x; m < TX * N; m += NT)
+    epi.put(col_index<N, AXIS, TX>(tile, m), slot, s[m]);
+}
+
+template <int NT>
+__device__ inline double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NT / 64; ++k) t += red[k];
+  }
+  return t;  // valid in thread 0
+}
+
+// ---- pass B: z forward, x v(G)/N_g with energy partial, z backward ----
+template <typename T, int N, int TX, int NT>
+__global__ __launch_bounds__(NT) void k_zconv(C<T>* tmp, int64_t gs,
+                                              const T* vtab, PairArgs pa,
+                                              double* epart, int ntiles,
+                                              const C<T>* tw_g) {
+  __shared__ C<T> s[TX * N];
+  __shared__ C<T> tw[N];
+  __shared__ double red[NT / 64];
+  const int tile = blockIdx.x, slot = blockIdx.y;
+  load_tw<T, N, NT>(tw, tw_g);
+  C<T>* g = tmp + slot * gs;
+  for (int m = threadIdx.x; m < TX * N; m += NT)
+    s[m] = g[col_index<N, 2, TX>(tile, m)];
+  __syncthreads();
+  lds_fft<T, N, TX, NT, -1, true>(s, 1, TX, tw);
+  double e = 0.0;
+  for (int m = threadIdx.x; m < TX * N; m += NT) {
+    const T v = vtab[col_index<N, 2, TX>(tile, m)];
+    const C<T> r = s[m];
+    e += double(v) * (double(r.x) * double(r.x) + double(r.y) * double(r.y));
+    s[m] = scl<T>(r, v);
+  }
+  __syncthreads();
+  lds_fft<T, N, TX, NT, +1, true>(s, 1, TX, tw);
+  for (int m = threadIdx.x; m < TX * N; m += NT)
+    g[col_index<N, 2, TX>(tile, m)] = s[m];
+  const double tot = block_sum<NT>(e, red);
+  if (threadIdx.x == 0) {
+    const double wgt = (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
+    epart[slot * ntiles + tile] += wgt * tot;
+  }
+}
+
+// ------------------------------------------------------------- helpers
+__global__ void k_zero(uint4* p, int64_t n16) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < n16;
+       k += stride)
+    p[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+__global__ void k_zero_tail(unsigned char* p, int64_t n) {
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) p[k] = 0;
+}
+
+template <typename T>
+__global__ void k_scatter(const double2* coeffs, int64_t n_pw,
+                          const int32_t* gidx, C<T>* psi, int64_t gs,
+                          int n_orb) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t total = n_pw * n_orb;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t j = k / n_pw, m = k % n_pw;
+    const double2 c = coeffs[k];
+    psi[j * gs + gidx[m]] = mk<T>(T(c.x), T(c.y));
+  }
+}
+
+template <typename T>
+__global__ void k_gather(const C<T>* w, int64_t gs, const int32_t* gidx,
+                         int64_t n_pw, int n_orb, double scale,
+                         double2* out) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t total = n_pw * n_orb;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t j = k / n_pw, m = k % n_pw;
+    const C<T> v = w[j * gs + gidx[m]];
+    out[k] = make_double2(scale * double(v.x), scale * double(v.y));
+  }
+}
+
+__global__ void k_reduce_sum(const double* part, int64_t count, double factor,
+                             double* out) {
+  __shared__ double red[256 / 64];
+  double t = 0.0;
+  for (int64_t k = threadIdx.x; k < count; k += 256) t += part[k];
+  const double tot = block_sum<256>(t, red);
+  if (threadIdx.x == 0) *out = factor * tot;
+}
+
+// ----------------------------------------------------- tile parameters
+template <typename T, int N> struct Cfg {
+  // plane pass: whole N x N plane in LDS
+  static constexpr bool plane = (int64_t)N * N * sizeof(C<T>) <= 150 * 1024;
+  static constexpr int NT_PLANE = 512;
+  // y/z pencils: TX columns (>= 128 bytes of x per row when N allows)
+  static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int TX = (N % TX0 == 0) ? TX0 : ((N % 8 == 0) ? 8 : 4);
+  static constexpr int NT_COLS = 256;
+  // x pencils: TY rows
+  static constexpr int TY = (N % 8 == 0) ? 8 : 4;
+  static constexpr int NT_X = 256;
+};
+
+template <typename T, int N> struct Engine {
+  using Cf = Cfg<T, N>;
+  static constexpr int64_t NG = (int64_t)N * N * N;
+
+  template <int SIGN, class Pro, class Epi>
+  static hipError_t plane(Pro p, Epi e, int count, const C<T>* tw,
+                          hipStream_t st) {
+    if constexpr (Cf::plane) {
+      hipLaunchKernelGGL((k_plane<T, N, Cf::NT_PLANE, SIGN, Pro, Epi>),
+                         dim3(N, count), dim3(Cf::NT_PLANE), 0, st, p, e, tw);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  template <int SIGN, class Pro, class Epi>
+  static hipError_t xlines(Pro p, Epi e, int count, const C<T>* tw,
+                           hipStream_t st) {
+    hipLaunchKernelGGL((k_xlines<T, N, Cf::TY, Cf::NT_X, SIGN, Pro, Epi>),
+                       dim3(N * N / Cf::TY, count), dim3(Cf::NT_X), 0, st, p,
+                       e, tw);
+    return hipGetLastError();
+  }
+  template <int AXIS, int SIGN, class Pro, class Epi>
+  static hipError_t cols(Pro p, Epi e, int count, const C<T>* tw,
+                         hipStream_t st) {
+    hipLaunchKernelGGL((k_cols<T, N, AXIS, Cf::TX, Cf::NT_COLS, SIGN, Pro, Epi>),
+                       dim3(N * (N / Cf::TX), count), dim3(Cf::NT_COLS), 0, st,
+                       p, e, tw);
+    return hipGetLastError();
+  }
+
+  // in-place transform of `count` grids, optional scale on the last pass
+  template <int SIGN>
+  static hipError_t fft3d(C<T>* g, int count, T scale, const C<T>* tw,
+                          hipStream_t st) {
+    ProGrid<T> p{g, NG};
+    EpiGrid<T> e1{g, NG, T(1)};
+    EpiGrid<T> es{g, NG, scale};
+    hipError_t err;
+    if constexpr (Cf::plane) {
+      err = plane<SIGN>(p, e1, count, tw, st);
+    } else {
+      err = xlines<SIGN>(p, e1, count, tw, st);
+      if (err == hipSuccess) err = cols<1, SIGN>(p, e1, count, tw, st);
+    }
+    if (err == hipSuccess) err = cols<2, SIGN>(p, es, count, tw, st);
+    return err;
+  }
+
+  static hipError_t pair_batch(const CellDev& c, const PairArgs& pa,
+                               const C<T>* psi, C<T>* w, C<T>* tmp,
+                               double* epart, hipStream_t st) {
+    const C<T>* tw = static_cast<const C<T>*>(c.tw);
+    const int cnt = pa.n;
+    ProPair<T> pp{psi, NG, pa};
+    ProGrid<T> pt{tmp, NG};
+    EpiGrid<T> et{tmp, NG, T(1)};
+    EpiAcc<T> ea{psi, w, NG, pa};
+    hipError_t err;
+    // pass A
+    if constexpr (Cf::plane) {
+      err = plane<-1>(pp, et, cnt, tw, st);
+    } else {
+      err = xlines<-1>(pp, et, cnt, tw, st);
+      if (err == hipSuccess) err = cols<1, -1>(pt, et, cnt, tw, st);
+    }
+    if (err != hipSuccess) return err;
+    // pass B
+    const int ntiles = N * (N / Cf::TX);
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::NT_COLS>), dim3(ntiles, cnt),
+                       dim3(Cf::NT_COLS), 0, st, tmp, NG,
+                       static_cast<const T*>(c.vtab), pa, epart, ntiles, tw);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    // pass C
+    if constexpr (Cf::plane) {
+      err = plane<+1>(pt, ea, cnt, tw, st);
+    } else {
+      err = cols<1, +1>(pt, et, cnt, tw, st);
+      if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
+    }
+    return err;
+  }
+
+  static int64_t tiles() { return (int64_t)N * (N / Cf::TX); }
+};
+
+// ------------------------------------------------------ runtime dispatch
+#define LACE_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(80) X(96) X(120)
+
+bool grid_supported(int n) {
+  switch (n) {
+#define X(NN) case NN: return true;
+    LACE_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+bool plane_fits(int n, bool fp64) {
+  switch (n) {
+#define X(NN) \
+  case NN: return fp64 ? Cfg<double, NN>::plane : Cfg<float, NN>::plane;
+    LACE_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+int64_t energy_tiles(int n, bool fp64) {
+  switch (n) {
+#define X(NN) \
+  case NN: return fp64 ? Engine<double, NN>::tiles() : Engine<float, NN>::tiles();
+    LACE_SIZES(X)
+#undef X
+    default: return 0;
+  }
+}
+
+template <typename T>
+static hipError_t fft3d_t(const CellDev& c, int sign, void* grids, int count,
+                          T scale, hipStream_t st) {
+  C<T>* g = static_cast<C<T>*>(grids);
+  const C<T>* tw = static_cast<const C<T>*>(c.tw);
+  switch (c.n) {
+#define X(NN)                                                            \
+  case NN:                                                               \
+    return sign < 0 ? Engine<T, NN>::template fft3d<-1>(g, count, scale, tw, st) \
+                    : Engine<T, NN>::template fft3d<+1>(g, count, scale, tw, st);
+    LACE_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fft3d(const CellDev& c, bool fp64, int sign, void* grids,
+                        int count, hipStream_t st) {
+  return fp64 ? fft3d_t<double>(c, sign, grids, count, 1.0, st)
+              : fft3d_t<float>(c, sign, grids, count, 1.0f, st);
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
+  if (bytes <= 0) return hipSuccess;
+  const int64_t n16 = bytes / 16;
+  if (n16 > 0) {
+    int64_t blocks = (n16 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<uint4*>(p), n16);
+  }
+  const int64_t rem = bytes - n16 * 16;
+  if (rem > 0)
+    hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(64), 0, st,
+                       static_cast<unsigned char*>(p) + n16 * 16, rem);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t orb_to_grid_t(const CellDev& c, const void* coeffs,
+                                int n_orb, void* psi, hipStream_t st) {
+  const int64_t bytes = (int64_t)n_orb * c.ng * sizeof(C<T>);
+  hipError_t err = launch_zero(psi, bytes, st);
+  if (err != hipSuccess) return err;
+  const int64_t total = c.n_pw * n_orb;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const double2*>(coeffs), c.n_pw, c.gidx,
+                     static_cast<C<T>*>(psi), c.ng, n_orb);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return fft3d_t<T>(c, +1, psi, n_orb, T(1.0 / std::sqrt(c.omega)), st);
+}
+
+hipError_t launch_orbitals_to_grid(const CellDev& c, bool fp64,
+                                   const void* coeffs, int n_orb, void* psi,
+                                   hipStream_t st) {
+  return fp64 ? orb_to_grid_t<double>(c, coeffs, n_orb, psi, st)
+              : orb_to_grid_t<float>(c, coeffs, n_orb, psi, st);
+}
+
+template <typename T>
+static hipError_t grid_to_pw_t(const CellDev& c, void* w, int n_orb,
+                               void* w_pw, hipStream_t st) {
+  hipError_t err = fft3d_t<T>(c, -1, w, n_orb, T(1), st);
+  if (err != hipSuccess) return err;
+  const int64_t total = c.n_pw * n_orb;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const C<T>*>(w), c.ng, c.gidx, c.n_pw, n_orb,
+                     std::sqrt(c.omega) / double(c.ng),
+                     static_cast<double2*>(w_pw));
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
+                             void* w_pw, hipStream_t st) {
+  return fp64 ? grid_to_pw_t<double>(c, w, n_orb, w_pw, st)
+              : grid_to_pw_t<float>(c, w, n_orb, w_pw, st);
+}
+
+template <typename T>
+static hipError_t pair_batch_t(const CellDev& c, const PairArgs& pa,
+                               const void* psi, void* w, void* tmp,
+                               double* epart, hipStream_t st) {
+  switch (c.n) {
+#define X(NN)                                                          \
+  case NN:                                                             \
+    return Engine<T, NN>::pair_batch(c, pa, static_cast<const C<T>*>(psi), \
+                                     static_cast<C<T>*>(w),            \
+                                     static_cast<C<T>*>(tmp), epart, st);
+    LACE_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
+                             const void* psi, void* w, void* tmp,
+                             double* epart, hipStream_t st) {
+  if (pa.n <= 0) return hipSuccess;
+  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st)
+              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st);
+}
+
+hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,
+                             double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, part, count,
+                     factor, out);
+  return hipGetLastError();
+}
+
+}  // namespace lace

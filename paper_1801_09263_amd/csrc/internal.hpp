@@ -1,0 +1,86 @@
+// internal.hpp - launchers shared between the C-ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lace {
+
+constexpr int PMAX = 64;  // pairs per batch (kernel-argument table)
+
+struct PairArgs {
+  int n;
+  int i[PMAX];
+  int j[PMAX];
+};
+
+// Geometry and device tables of one cell, shared by all launchers.
+struct CellDev {
+  int n;              // grid points per axis
+  int64_t ng;         // n^3
+  int64_t n_pw;
+  double L, rc, omega;
+  const int32_t* gidx;  // n_pw linear grid indices (x + n (y + n z))
+  const void* vtab;     // ng kernel values v(G) / ng in the plan precision
+  const void* tw;       // n twiddles exp(-2 pi i m / n), plan precision
+};
+
+bool grid_supported(int n);
+// Whether the fused xy-plane pass fits LDS for this size and precision.
+bool plane_fits(int n, bool fp64);
+
+// All launchers enqueue on `st` and return hipSuccess or the launch error.
+// Grids are `count` n^3 arrays back to back, x fastest.
+hipError_t launch_fft3d(const CellDev& c, bool fp64, int sign, void* grids,
+                        int count, hipStream_t st);
+// psi grids <- Omega^{-1/2} B[scatter(C)], C device complex128 n_pw x n_orb.
+hipError_t launch_orbitals_to_grid(const CellDev& c, bool fp64,
+                                   const void* coeffs, int n_orb, void* psi,
+                                   hipStream_t st);
+// What <- Omega^{1/2}/ng * F[W] gathered on the sphere; W grids destroyed.
+hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
+                             void* w_pw, hipStream_t st);
+// One batch of pairs (no orbital used twice): forward, kernel multiply,
+// backward, accumulate into W; adds per-tile energy partials.
+hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
+                             const void* psi, void* w, void* tmp,
+                             double* epart, hipStream_t st);
+// Number of energy partial slots per pair slot (tiles of the z pass).
+int64_t energy_tiles(int n, bool fp64);
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
+// out = factor * sum(part[0..count)), fixed summation order.
+hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,
+                             double* out, hipStream_t st);
+
+// ---- dense linear algebra (FP64, MFMA) ----
+// out[a][b] (+ split-K partials in `part`) = scale * sum_k conj(A[a][k]) B[b][k]
+// A: na rows of K complex128 (row stride lda), B: nb rows (ldb).
+hipError_t launch_gemm_ip_c128(const void* A, int64_t lda, int na,
+                               const void* B, int64_t ldb, int nb, int64_t K,
+                               double scale, void* out, void* part,
+                               int64_t part_bytes, hipStream_t st);
+// S[a][b] = scale * sum_k |A[a][k]| |A[b][k]| over K grid values (float2 or
+// double2 per fp64), real output.
+hipError_t launch_gemm_ip_abs(bool fp64, const void* A, int64_t lda, int na,
+                              int64_t K, double scale, double* out, void* part,
+                              int64_t part_bytes, hipStream_t st);
+int64_t gemm_ip_part_bytes(int na, int nb, int64_t K, bool complex_out);
+// Y[b][m] = sum_k X[k][m] Z[k][b]: X nk rows of M complex128 (ldx), Z nk x nb
+// row-major complex128, Y nb rows (ldy).
+hipError_t launch_gemm_tall(const void* X, int64_t ldx, int64_t M, int nk,
+                            const void* Z, int nb, void* Y, int64_t ldy,
+                            hipStream_t st);
+// A <- -sym(M) (mode 0 avg, 1 upper, 2 lower), n x n complex128 row-major.
+hipError_t launch_neg_sym(const void* M, int n, int mode, void* A,
+                          hipStream_t st);
+// In-place Cholesky A = L L^H (lower), info <- 0 or failing pivot + 1.
+hipError_t launch_cholesky(void* A, int n, int32_t* info, hipStream_t st);
+// Z <- (L^{-1})^H, upper triangular, n x n row-major.
+hipError_t launch_trinv_adj(const void* L, int n, void* Z, hipStream_t st);
+// out <- factor * Re tr(M)
+hipError_t launch_trace_re(const void* M, int n, double factor, double* out,
+                           hipStream_t st);
+// y <- -x elementwise on n complex128 (scale copy)
+hipError_t launch_scale_c128(const void* x, int64_t n, double s, void* y,
+                             hipStream_t st);
+
+}  // namespace lace

@@ -1,0 +1,465 @@
+// lace_api.hip - host side of the C ABI declared in include/lace.h:
+// argument validation, plan tables, workspace layout, the pair schedule,
+// and the order of launches for the three operations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "lace.h"
+
+using namespace lace;
+
+namespace {
+
+struct CellPlan {
+  CellDev dev;
+  int32_t* d_gidx = nullptr;
+  void* d_vtab = nullptr;
+  void* d_tw = nullptr;
+  int32_t* d_info = nullptr;
+};
+
+int default_pairs_per_batch(int n) {
+  const char* e = std::getenv("LACE_PAIRS_PER_BATCH");
+  if (e) {
+    int v = std::atoi(e);
+    if (v >= 1 && v <= PMAX) return v;
+  }
+  // enough xy planes in flight to cover the chip several times
+  int p = (4096 + n - 1) / n;
+  if (p > 32) p = 32;
+  if (p < 8) p = 8;
+  return p;
+}
+
+}  // namespace
+
+struct lace_plan {
+  lace_precision prec;
+  int device = 0;
+  std::vector<CellPlan> cells;
+};
+
+// ---------------------------------------------------------------- helpers
+static int hip_status(hipError_t e) { return e == hipSuccess ? LACE_OK : LACE_EHIP; }
+
+static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t psi, w, tmp, epart, s, part, mw, a, z, t, total;
+  int pairs_per_batch;
+};
+
+static size_t grid_bytes(const lace_plan* p) {
+  return p->prec == LACE_FP64 ? 16 : 8;
+}
+
+static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
+  const CellDev& c = p->cells[cell].dev;
+  const bool fp64 = p->prec == LACE_FP64;
+  Layout L{};
+  L.pairs_per_batch = default_pairs_per_batch(c.n);
+  const size_t gb = (size_t)c.ng * grid_bytes(p);
+  size_t off = 0;
+  L.psi = off; off += align_up(gb * n_orb);
+  L.w = off; off += align_up(gb * n_orb);
+  L.tmp = off; off += align_up(gb * L.pairs_per_batch);
+  L.epart = off;
+  off += align_up(sizeof(double) * L.pairs_per_batch * energy_tiles(c.n, fp64));
+  L.s = off; off += align_up(sizeof(double) * n_orb * n_orb);
+  int64_t part = gemm_ip_part_bytes(n_orb, n_orb, c.n_pw, true);
+  part = std::max(part, gemm_ip_part_bytes(n_orb, n_orb, c.ng, false));
+  part = std::max(part, gemm_ip_part_bytes(n_orb, std::max(n_vec, 1), c.n_pw, true));
+  L.part = off; off += align_up((size_t)part);
+  L.mw = off; off += align_up(16 * (size_t)n_orb * n_orb);
+  L.a = off; off += align_up(16 * (size_t)n_orb * n_orb);
+  L.z = off; off += align_up(16 * (size_t)n_orb * std::max(n_orb, n_vec));
+  L.t = off; off += align_up(16 * (size_t)n_orb * std::max(n_vec, 1));
+  L.total = off;
+  return L;
+}
+
+static char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
+
+static bool device_ok(const lace_plan* p) {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess) return false;
+  return d == p->device;
+}
+
+static void free_cell(CellPlan& c) {
+  if (c.d_gidx) (void)hipFree(c.d_gidx);
+  if (c.d_vtab) (void)hipFree(c.d_vtab);
+  if (c.d_tw) (void)hipFree(c.d_tw);
+  if (c.d_info) (void)hipFree(c.d_info);
+  c.d_gidx = nullptr; c.d_vtab = nullptr; c.d_tw = nullptr; c.d_info = nullptr;
+}
+
+// Signed frequency of FFT index k on an n-point axis.
+static int signed_freq(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
+
+// Pairs of one call, grouped into batches in which no orbital appears
+// twice (so the accumulation into W has no write conflicts).  First fit
+// over a window of open batches, pairs taken in the given order.
+static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
+                           int n_orb, int per_batch,
+                           std::vector<PairArgs>& out) {
+  out.clear();
+  const int words = (n_orb + 63) / 64;
+  struct Open {
+    size_t idx;
+    std::vector<uint64_t> used;
+  };
+  std::vector<Open> open;
+  const size_t window = 64;
+  for (const auto& pr : pairs) {
+    const int i = pr.first, j = pr.second;
+    bool placed = false;
+    for (size_t o = 0; o < open.size(); ++o) {
+      Open& ob = open[o];
+      const bool ui = (ob.used[i / 64] >> (i % 64)) & 1ull;
+      const bool uj = (ob.used[j / 64] >> (j % 64)) & 1ull;
+      if (ui || uj) continue;
+      PairArgs& b = out[ob.idx];
+      b.i[b.n] = i; b.j[b.n] = j; ++b.n;
+      ob.used[i / 64] |= 1ull << (i % 64);
+      ob.used[j / 64] |= 1ull << (j % 64);
+      if (b.n == per_batch) open.erase(open.begin() + o);
+      placed = true;
+      break;
+    }
+    if (placed) continue;
+    PairArgs b;
+    std::memset(&b, 0, sizeof(b));
+    b.n = 1; b.i[0] = i; b.j[0] = j;
+    out.push_back(b);
+    if (per_batch > 1) {
+      Open ob;
+      ob.idx = out.size() - 1;
+      ob.used.assign(words, 0ull);
+      ob.used[i / 64] |= 1ull << (i % 64);
+      ob.used[j / 64] |= 1ull << (j % 64);
+      open.push_back(ob);
+      if (open.size() > window) open.erase(open.begin());
+    }
+  }
+}
+
+// ------------------------------------------------------------------ API
+extern "C" {
+
+const char* lace_status_string(int s) {
+  switch (s) {
+    case LACE_OK: return "ok";
+    case LACE_EINVAL: return "invalid argument";
+    case LACE_ENOMEM: return "workspace too small or allocation failed";
+    case LACE_ENOTPD: return "-M_s is not positive definite";
+    case LACE_EUNSUPPORTED: return "unsupported grid size or sphere outside the grid";
+    case LACE_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int lace_plan_create(const lace_cell_desc* cells, int n_cells,
+                     lace_precision prec, lace_plan** out) {
+  if (!cells || !out || n_cells < 1) return LACE_EINVAL;
+  if (prec != LACE_FP64 && prec != LACE_FP32) return LACE_EINVAL;
+  // validate everything before touching the device
+  for (int ci = 0; ci < n_cells; ++ci) {
+    const lace_cell_desc& d = cells[ci];
+    if (!(d.L > 0.0) || d.n_pw < 1 || !d.miller || !std::isfinite(d.L))
+      return LACE_EINVAL;
+    if (!grid_supported(d.n)) return LACE_EUNSUPPORTED;
+    const int n = d.n;
+    std::vector<uint8_t> seen((size_t)n * n * n, 0);
+    for (int64_t m = 0; m < d.n_pw; ++m) {
+      for (int a = 0; a < 3; ++a) {
+        const int v = d.miller[3 * m + a];
+        if (2 * std::abs(v) >= n) return LACE_EUNSUPPORTED;
+      }
+      const int x = (d.miller[3 * m] % n + n) % n;
+      const int y = (d.miller[3 * m + 1] % n + n) % n;
+      const int z = (d.miller[3 * m + 2] % n + n) % n;
+      const size_t g = (size_t)x + (size_t)n * (y + (size_t)n * z);
+      if (seen[g]) return LACE_EINVAL;
+      seen[g] = 1;
+    }
+  }
+  lace_plan* p = new (std::nothrow) lace_plan;
+  if (!p) return LACE_ENOMEM;
+  p->prec = prec;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return LACE_EHIP; }
+  p->cells.resize(n_cells);
+  const bool fp64 = prec == LACE_FP64;
+  for (int ci = 0; ci < n_cells; ++ci) {
+    const lace_cell_desc& d = cells[ci];
+    CellPlan& cp = p->cells[ci];
+    const int n = d.n;
+    const int64_t ng = (int64_t)n * n * n;
+    const double rc = d.rc > 0.0 ? d.rc : 0.5 * d.L;
+    cp.dev.n = n; cp.dev.ng = ng; cp.dev.n_pw = d.n_pw;
+    cp.dev.L = d.L; cp.dev.rc = rc; cp.dev.omega = d.L * d.L * d.L;
+    // sphere -> grid map
+    std::vector<int32_t> gidx(d.n_pw);
+    for (int64_t m = 0; m < d.n_pw; ++m) {
+      const int x = (d.miller[3 * m] % n + n) % n;
+      const int y = (d.miller[3 * m + 1] % n + n) % n;
+      const int z = (d.miller[3 * m + 2] % n + n) % n;
+      gidx[m] = x + n * (y + n * z);
+    }
+    // kernel table v(G)/N_g: 8 pi sin^2(|G| rc / 2) / |G|^2, v(0) = 2 pi rc^2
+    std::vector<double> v(ng);
+    const double g1 = 2.0 * M_PI / d.L;
+    for (int z = 0; z < n; ++z)
+      for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) {
+          const double gx = g1 * signed_freq(x, n), gy = g1 * signed_freq(y, n),
+                       gz = g1 * signed_freq(z, n);
+          const double gg2 = gx * gx + gy * gy + gz * gz;
+          double val;
+          if (gg2 == 0.0) {
+            val = 2.0 * M_PI * rc * rc;
+          } else {
+            const double s = std::sin(0.5 * std::sqrt(gg2) * rc);
+            val = 8.0 * M_PI * s * s / gg2;
+          }
+          v[x + (int64_t)n * (y + (int64_t)n * z)] = val / double(ng);
+        }
+    // twiddles exp(-2 pi i m / n)
+    std::vector<double> tw(2 * n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = 2.0 * M_PI * double(m) / double(n);
+      tw[2 * m] = std::cos(ang);
+      tw[2 * m + 1] = -std::sin(ang);
+    }
+    hipError_t e = hipSuccess;
+    e = hipMalloc(&cp.d_gidx, sizeof(int32_t) * d.n_pw);
+    if (e == hipSuccess) e = hipMalloc(&cp.d_vtab, (fp64 ? 8 : 4) * (size_t)ng);
+    if (e == hipSuccess) e = hipMalloc(&cp.d_tw, (fp64 ? 16 : 8) * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&cp.d_info, sizeof(int32_t));
+    if (e == hipSuccess)
+      e = hipMemcpy(cp.d_gidx, gidx.data(), sizeof(int32_t) * d.n_pw,
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      if (fp64) {
+        e = hipMemcpy(cp.d_vtab, v.data(), 8 * (size_t)ng, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMemcpy(cp.d_tw, tw.data(), 16 * (size_t)n, hipMemcpyHostToDevice);
+      } else {
+        std::vector<float> vf(ng), twf(2 * n);
+        for (int64_t k = 0; k < ng; ++k) vf[k] = static_cast<float>(v[k]);
+        for (int k = 0; k < 2 * n; ++k) twf[k] = static_cast<float>(tw[k]);
+        e = hipMemcpy(cp.d_vtab, vf.data(), 4 * (size_t)ng, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMemcpy(cp.d_tw, twf.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
+      }
+    }
+    if (e == hipSuccess) {
+      int32_t zero = 0;
+      e = hipMemcpy(cp.d_info, &zero, sizeof(zero), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+      for (auto& c2 : p->cells) free_cell(c2);
+      delete p;
+      return e == hipErrorOutOfMemory ? LACE_ENOMEM : LACE_EHIP;
+    }
+    cp.dev.gidx = cp.d_gidx;
+    cp.dev.vtab = cp.d_vtab;
+    cp.dev.tw = cp.d_tw;
+  }
+  *out = p;
+  return LACE_OK;
+}
+
+int lace_plan_destroy(lace_plan* p) {
+  if (!p) return LACE_OK;
+  (void)hipDeviceSynchronize();
+  for (auto& c : p->cells) free_cell(c);
+  delete p;
+  return LACE_OK;
+}
+
+int lace_workspace_size(const lace_plan* p, int cell, int n_orb, int n_vec,
+                        size_t* bytes) {
+  if (!p || !bytes || cell < 0 || cell >= (int)p->cells.size() || n_orb < 1 ||
+      n_vec < 0)
+    return LACE_EINVAL;
+  *bytes = layout_for(p, cell, n_orb, n_vec).total;
+  return LACE_OK;
+}
+
+static int check_common(const lace_plan* p, int cell, int n_orb) {
+  if (!p || cell < 0 || cell >= (int)p->cells.size() || n_orb < 1)
+    return LACE_EINVAL;
+  if (!device_ok(p)) return LACE_EINVAL;
+  return LACE_OK;
+}
+
+int lace_screen(lace_plan* p, int cell, const void* psi_g, int n_orb,
+                double* s_out, void* ws, size_t ws_bytes, lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_g || !s_out || !ws) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  const CellDev& c = p->cells[cell].dev;
+  const bool fp64 = p->prec == LACE_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, at(ws, L.psi), st);
+  if (e == hipSuccess)
+    e = launch_gemm_ip_abs(fp64, at(ws, L.psi), c.ng, n_orb, c.ng,
+                           c.omega / double(c.ng), s_out, at(ws, L.part),
+                           (int64_t)(L.mw - L.part), st);
+  return hip_status(e);
+}
+
+int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
+                        double s_thr, const int32_t* pair_i,
+                        const int32_t* pair_j, int64_t n_pairs, void* w_g,
+                        double* e_x, int64_t* n_kept, void* ws, size_t ws_bytes,
+                        lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_g || !w_g || !ws) return LACE_EINVAL;
+  if (!(s_thr >= 0.0 && s_thr < 1.0)) return LACE_EINVAL;
+  if ((pair_i == nullptr) != (pair_j == nullptr)) return LACE_EINVAL;
+  if (pair_i && n_pairs < 0) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  std::vector<std::pair<int, int>> pairs;
+  if (pair_i) {
+    std::vector<uint8_t> seen((size_t)n_orb * n_orb, 0);
+    pairs.reserve(n_pairs);
+    for (int64_t k = 0; k < n_pairs; ++k) {
+      const int i = pair_i[k], j = pair_j[k];
+      if (i < 0 || j < 0 || i > j || j >= n_orb) return LACE_EINVAL;
+      if (seen[(size_t)i * n_orb + j]) return LACE_EINVAL;
+      seen[(size_t)i * n_orb + j] = 1;
+      pairs.emplace_back(i, j);
+    }
+  }
+  const CellDev& c = p->cells[cell].dev;
+  const bool fp64 = p->prec == LACE_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void* psi = at(ws, L.psi);
+  void* w = at(ws, L.w);
+  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, psi, st);
+  if (e != hipSuccess) return LACE_EHIP;
+  if (!pair_i) {
+    if (s_thr > 0.0) {
+      double* s = reinterpret_cast<double*>(at(ws, L.s));
+      e = launch_gemm_ip_abs(fp64, psi, c.ng, n_orb, c.ng,
+                             c.omega / double(c.ng), s, at(ws, L.part),
+                             (int64_t)(L.mw - L.part), st);
+      if (e != hipSuccess) return LACE_EHIP;
+      std::vector<double> hs((size_t)n_orb * n_orb);
+      e = hipMemcpyAsync(hs.data(), s, sizeof(double) * hs.size(),
+                         hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return LACE_EHIP;
+      for (int j = 0; j < n_orb; ++j)
+        for (int i = 0; i <= j; ++i)
+          if (hs[(size_t)i * n_orb + j] >= s_thr) pairs.emplace_back(i, j);
+    } else {
+      pairs.reserve((size_t)n_orb * (n_orb + 1) / 2);
+      for (int j = 0; j < n_orb; ++j)
+        for (int i = 0; i <= j; ++i) pairs.emplace_back(i, j);
+    }
+  }
+  std::vector<PairArgs> sched;
+  build_schedule(pairs, n_orb, L.pairs_per_batch, sched);
+  const int64_t ntiles = energy_tiles(c.n, fp64);
+  double* epart = reinterpret_cast<double*>(at(ws, L.epart));
+  e = launch_zero(w, (int64_t)c.ng * n_orb * grid_bytes(p), st);
+  if (e == hipSuccess)
+    e = launch_zero(epart, (int64_t)sizeof(double) * L.pairs_per_batch * ntiles, st);
+  for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b)
+    e = launch_pair_batch(c, fp64, sched[b], psi, w, at(ws, L.tmp), epart, st);
+  if (e == hipSuccess && e_x)
+    e = launch_reduce_sum(epart, (int64_t)L.pairs_per_batch * ntiles,
+                          -0.5 * c.omega / double(c.ng), e_x, st);
+  if (e == hipSuccess) e = launch_grid_to_pw(c, fp64, w, n_orb, w_g, st);
+  if (e != hipSuccess) return LACE_EHIP;
+  if (n_kept) *n_kept = (int64_t)pairs.size();
+  return LACE_OK;
+}
+
+int lace_build_ace(lace_plan* p, int cell, const void* psi_g, const void* w_g,
+                   int n_orb, lace_sym sym, void* xi_g, void* m_out,
+                   double* ex_tr, void* ws, size_t ws_bytes,
+                   lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_g || !w_g || !xi_g || !ws) return LACE_EINVAL;
+  if (sym != LACE_SYM_AVG && sym != LACE_SYM_UPPER && sym != LACE_SYM_LOWER)
+    return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  const CellPlan& cp = p->cells[cell];
+  const CellDev& c = cp.dev;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void* m = m_out ? m_out : at(ws, L.mw);
+  hipError_t e = launch_gemm_ip_c128(psi_g, c.n_pw, n_orb, w_g, c.n_pw, n_orb,
+                                     c.n_pw, 1.0, m, at(ws, L.part),
+                                     (int64_t)(L.mw - L.part), st);
+  if (e == hipSuccess && ex_tr) e = launch_trace_re(m, n_orb, 0.5, ex_tr, st);
+  if (e == hipSuccess) e = launch_neg_sym(m, n_orb, (int)sym, at(ws, L.a), st);
+  if (e == hipSuccess) e = launch_cholesky(at(ws, L.a), n_orb, cp.d_info, st);
+  if (e == hipSuccess) e = launch_trinv_adj(at(ws, L.a), n_orb, at(ws, L.z), st);
+  if (e == hipSuccess)
+    e = launch_gemm_tall(w_g, c.n_pw, c.n_pw, n_orb, at(ws, L.z), n_orb, xi_g,
+                         c.n_pw, st);
+  return hip_status(e);
+}
+
+int lace_apply_ace(lace_plan* p, int cell, const void* xi_g, int n_orb,
+                   const void* x_g, int n_vec, void* y_g, void* ws,
+                   size_t ws_bytes, lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!xi_g || !x_g || !y_g || !ws || n_vec < 1) return LACE_EINVAL;
+  if (x_g == y_g) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, n_vec);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  const CellDev& c = p->cells[cell].dev;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // T = -(xi^H x), then y = xi T
+  hipError_t e = launch_gemm_ip_c128(xi_g, c.n_pw, n_orb, x_g, c.n_pw, n_vec,
+                                     c.n_pw, -1.0, at(ws, L.t), at(ws, L.part),
+                                     (int64_t)(L.mw - L.part), st);
+  if (e == hipSuccess)
+    e = launch_gemm_tall(xi_g, c.n_pw, c.n_pw, n_orb, at(ws, L.t), n_vec, y_g,
+                         c.n_pw, st);
+  return hip_status(e);
+}
+
+int lace_fft3d(lace_plan* p, int cell, int direction, void* grids, int count,
+               lace_stream_t stream) {
+  if (!p || cell < 0 || cell >= (int)p->cells.size() || !grids || count < 1)
+    return LACE_EINVAL;
+  if (direction != -1 && direction != 1) return LACE_EINVAL;
+  if (!device_ok(p)) return LACE_EINVAL;
+  return hip_status(launch_fft3d(p->cells[cell].dev, p->prec == LACE_FP64,
+                                 direction, grids, count,
+                                 static_cast<hipStream_t>(stream)));
+}
+
+int lace_get_info(lace_plan* p, int cell, int32_t* info_host) {
+  if (!p || !info_host || cell < 0 || cell >= (int)p->cells.size())
+    return LACE_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return LACE_EHIP;
+  int32_t v = 0;
+  if (hipMemcpy(&v, p->cells[cell].d_info, sizeof(v), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return LACE_EHIP;
+  *info_host = v;
+  return v == 0 ? LACE_OK : LACE_ENOTPD;
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of liblace (include/lace.h).
+
+Argument marshalling only: every step of the exchange path runs in the HIP
+library.  Device buffers are torch tensors on the GPU (PyTorch provides the
+memory and the stream); pair lists are host arrays.  When the library has not
+been built, every entry point raises ``LaceUnavailable``: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblace.so")
+
+LACE_OK = 0
+LACE_EINVAL = -1
+LACE_ENOMEM = -2
+LACE_ENOTPD = -3
+LACE_EUNSUPPORTED = -4
+LACE_EHIP = -5
+
+LACE_FP64 = 0
+LACE_FP32 = 1
+LACE_SYM_AVG = 0
+LACE_SYM_UPPER = 1
+LACE_SYM_LOWER = 2
+SYM_MODES = {"avg": LACE_SYM_AVG, "upper": LACE_SYM_UPPER,
+             "lower": LACE_SYM_LOWER}
+
+# Every entry point declared in include/lace.h.
+SYMBOLS = (
+    "lace_plan_create", "lace_plan_destroy", "lace_workspace_size",
+    "lace_screen", "lace_apply_exchange", "lace_build_ace", "lace_apply_ace",
+    "lace_fft3d", "lace_get_info", "lace_status_string",
+)
+
+
+class LaceUnavailable(RuntimeError):
+    pass
+
+
+class LaceError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {lace_status_string(code)} ({code})")
+
+
+class CellDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("n", ctypes.c_int32),
+                ("rc", ctypes.c_double), ("n_pw", ctypes.c_int64),
+                ("miller", ctypes.POINTER(ctypes.c_int32))]
+
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblace.so and declare the signatures (no GPU work)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise LaceUnavailable(
+            f"{path} is not built; run python -m paper_1801_09263_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                             ctypes.c_double, ctypes.c_size_t)
+    p_i32 = ctypes.POINTER(ctypes.c_int32)
+    lib.lace_plan_create.argtypes = [ctypes.POINTER(CellDesc), i32, i32,
+                                     ctypes.POINTER(vp)]
+    lib.lace_plan_destroy.argtypes = [vp]
+    lib.lace_workspace_size.argtypes = [vp, i32, i32, i32,
+                                        ctypes.POINTER(sz)]
+    lib.lace_screen.argtypes = [vp, i32, vp, i32, vp, vp, sz, vp]
+    lib.lace_apply_exchange.argtypes = [vp, i32, vp, i32, dbl, p_i32, p_i32,
+                                        i64, vp, vp,
+                                        ctypes.POINTER(ctypes.c_int64), vp, sz,
+                                        vp]
+    lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
+                                   sz, vp]
+    lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
+    lib.lace_fft3d.argtypes = [vp, i32, i32, vp, i32, vp]
+    lib.lace_get_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.lace_status_string.argtypes = [i32]
+    lib.lace_status_string.restype = ctypes.c_char_p
+    for name in SYMBOLS:
+        if name != "lace_status_string":
+            getattr(lib, name).restype = i32
+    _LIB = lib
+    return lib
+
+
+def lace_status_string(code: int) -> str:
+    return load().lace_status_string(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != LACE_OK:
+        raise LaceError(code, what)
+
+
+def _ptr(t, dtype=None, what="buffer"):
+    """Raw device pointer of a contiguous torch CUDA tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Owner of a ``lace_plan*``; destroyed on ``close()`` or collection."""
+
+    def __init__(self, handle, cells, precision):
+        self.handle = handle
+        self.cells = cells
+        self.precision = precision
+
+    def close(self):
+        if self.handle:
+            load().lace_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lace_plan_create(cells, precision=LACE_FP64) -> Plan:
+    """``cells``: list of dicts with L, n, miller (n_pw x 3 int array) and
+    optional rc."""
+    lib = load()
+    keep = []
+    arr = (CellDesc * len(cells))()
+    for k, c in enumerate(cells):
+        m = np.ascontiguousarray(c["miller"], dtype=np.int32)
+        keep.append(m)
+        arr[k].L = float(c["L"])
+        arr[k].n = int(c["n"])
+        arr[k].rc = float(c.get("rc", 0.0) or 0.0)
+        arr[k].n_pw = int(m.shape[0])
+        arr[k].miller = m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    h = ctypes.c_void_p()
+    _check(lib.lace_plan_create(arr, len(cells), int(precision),
+                                ctypes.byref(h)), "lace_plan_create")
+    return Plan(h, cells, precision)
+
+
+def lace_workspace_size(plan: Plan, cell: int, n_orb: int, n_vec: int = 0):
+    out = ctypes.c_size_t()
+    _check(load().lace_workspace_size(plan.handle, cell, n_orb, n_vec,
+                                      ctypes.byref(out)),
+           "lace_workspace_size")
+    return out.value
+
+
+def lace_screen(plan, cell, psi_g, n_orb, s_out, ws, stream=None):
+    import torch
+    _check(load().lace_screen(plan.handle, cell,
+                              _ptr(psi_g, torch.complex128, "psi_g"), n_orb,
+                              _ptr(s_out, torch.float64, "s_out"),
+                              _ptr(ws, None, "ws"), ws.numel() * ws.element_size(),
+                              _stream(stream)), "lace_screen")
+
+
+def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,
+                        stream=None) -> int:
+    """``pairs``: None (screen with s_thr) or an (n, 2) int array of
+    unordered pairs i <= j.  Returns the number of pairs run."""
+    import torch
+    if pairs is None:
+        pi = pj = None
+        npairs = 0
+    else:
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        pi_arr = np.ascontiguousarray(pr[:, 0])
+        pj_arr = np.ascontiguousarray(pr[:, 1])
+        pi = pi_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        pj = pj_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        npairs = pr.shape[0]
+    kept = ctypes.c_int64(0)
+    _check(load().lace_apply_exchange(
+        plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), n_orb,
+        float(s_thr), pi, pj, npairs, _ptr(w_g, torch.complex128, "w_g"),
+        _ptr(e_x, torch.float64, "e_x"), ctypes.byref(kept),
+        _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)),
+        "lace_apply_exchange")
+    return kept.value
+
+
+def lace_build_ace(plan, cell, psi_g, w_g, n_orb, sym, xi_g, m_out, ex_tr, ws,
+                   stream=None):
+    import torch
+    mode = SYM_MODES[sym] if isinstance(sym, str) else int(sym)
+    _check(load().lace_build_ace(
+        plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"),
+        _ptr(w_g, torch.complex128, "w_g"), n_orb, mode,
+        _ptr(xi_g, torch.complex128, "xi_g"),
+        _ptr(m_out, torch.complex128, "m_out"),
+        _ptr(ex_tr, torch.float64, "ex_tr"), _ptr(ws, None, "ws"),
+        ws.numel() * ws.element_size(), _stream(stream)), "lace_build_ace")
+
+
+def lace_apply_ace(plan, cell, xi_g, n_orb, x_g, n_vec, y_g, ws, stream=None):
+    import torch
+    _check(load().lace_apply_ace(
+        plan.handle, cell, _ptr(xi_g, torch.complex128, "xi_g"), n_orb,
+        _ptr(x_g, torch.complex128, "x_g"), n_vec,
+        _ptr(y_g, torch.complex128, "y_g"), _ptr(ws, None, "ws"),
+        ws.numel() * ws.element_size(), _stream(stream)), "lace_apply_ace")
+
+
+def lace_fft3d(plan, cell, direction, grids, count, stream=None):
+    _check(load().lace_fft3d(plan.handle, cell, int(direction),
+                             _ptr(grids, None, "grids"), int(count),
+                             _stream(stream)), "lace_fft3d")
+
+
+def lace_get_info(plan, cell) -> int:
+    info = ctypes.c_int32(0)
+    code = load().lace_get_info(plan.handle, cell, ctypes.byref(info))
+    if code not in (LACE_OK, LACE_ENOTPD):
+        _check(code, "lace_get_info")
+    return info.value

@@ -1,0 +1,87 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+entry point declared in include/lace.h, and rejects bad arguments on the
+host before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1801_09263_amd import lace
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "lace.h")).read()
+    return sorted(set(re.findall(r"\b(lace_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lace.LIB_PATH):
+        pytest.skip("liblace.so not built")
+    return lace.load()
+
+
+def test_header_and_binding_agree():
+    assert header_symbols() == sorted(lace.SYMBOLS)
+
+
+def test_library_exports_every_header_symbol(lib):
+    for name in header_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in (lace.LACE_OK, lace.LACE_EINVAL, lace.LACE_ENOMEM,
+                 lace.LACE_ENOTPD, lace.LACE_EUNSUPPORTED, lace.LACE_EHIP):
+        s = lace.lace_status_string(code)
+        assert s and s != "unknown status"
+    assert lace.lace_status_string(-99) == "unknown status"
+
+
+def _cell(L=10.0, n=24, miller=None, rc=0.0):
+    m = np.zeros((1, 3), np.int32) if miller is None else miller
+    return dict(L=L, n=n, miller=m, rc=rc)
+
+
+@pytest.mark.parametrize("cell,code", [
+    (_cell(L=-1.0), lace.LACE_EINVAL),
+    (_cell(n=25), lace.LACE_EUNSUPPORTED),          # 25 = 5^2: not built
+    (_cell(n=14), lace.LACE_EUNSUPPORTED),          # 7 is not a radix
+    (_cell(miller=np.array([[12, 0, 0]], np.int32)), lace.LACE_EUNSUPPORTED),
+    (_cell(miller=np.array([[1, 2, 3], [1, 2, 3]], np.int32)), lace.LACE_EINVAL),
+])
+def test_plan_create_rejects_before_device_work(lib, cell, code):
+    with pytest.raises(lace.LaceError) as ei:
+        lace.lace_plan_create([cell], lace.LACE_FP32)
+    assert ei.value.code == code
+
+
+def test_null_arguments_rejected(lib):
+    out = ctypes.c_void_p()
+    assert lib.lace_plan_create(None, 1, 0, ctypes.byref(out)) == lace.LACE_EINVAL
+    assert lib.lace_plan_create(None, 0, 0, None) == lace.LACE_EINVAL
+    nb = ctypes.c_size_t()
+    assert lib.lace_workspace_size(None, 0, 8, 0, ctypes.byref(nb)) == lace.LACE_EINVAL
+    assert lib.lace_apply_exchange(None, 0, None, 8, 0.0, None, None, 0, None,
+                                   None, None, None, 0, None) == lace.LACE_EINVAL
+    assert lib.lace_build_ace(None, 0, None, None, 8, 0, None, None, None,
+                              None, 0, None) == lace.LACE_EINVAL
+    assert lib.lace_apply_ace(None, 0, None, 8, None, 1, None, None, 0,
+                              None) == lace.LACE_EINVAL
+    assert lib.lace_fft3d(None, 0, -1, None, 1, None) == lace.LACE_EINVAL
+    assert lib.lace_screen(None, 0, None, 8, None, None, 0, None) == lace.LACE_EINVAL
+    info = ctypes.c_int32()
+    assert lib.lace_get_info(None, 0, ctypes.byref(info)) == lace.LACE_EINVAL
+    assert lib.lace_plan_destroy(None) == lace.LACE_OK
+
+
+def test_library_built_for_gfx950():
+    """The shared object carries a gfx950 code object."""
+    if not os.path.exists(lace.LIB_PATH):
+        pytest.skip("liblace.so not built")
+    data = open(lace.LIB_PATH, "rb").read()
+    assert b"gfx950" in data

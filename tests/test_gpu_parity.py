@@ -1,0 +1,289 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Tolerances are relative Frobenius norms against the FP64 oracle.  FP64 path:
+rounding-order differences only.  FP32 path: pair densities, FFTs and W in
+FP32 (unit roundoff 6e-8, grown by ~log2(N_g) FFT stages and the sum over
+orbitals) with FP64 energies, M, Cholesky and xi; the exchange energy must
+meet 1e-5 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+from paper_1801_09263_amd import lace  # noqa: E402
+from paper_1801_09263_amd.session import CellSession  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = lace.LACE_FP64, lace.LACE_FP32
+TOL = {
+    FP64: dict(fft=1e-13, w=1e-11, m=1e-11, ex=1e-12, xi=1e-10, ace=1e-11,
+               s=1e-12),
+    FP32: dict(fft=2e-6, w=1e-5, m=1e-5, ex=1e-5, xi=1e-4, ace=1e-5, s=1e-6),
+}
+NAMES = {FP64: "fp64", FP32: "fp32"}
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ FFT
+def brute_dft3(a, sign):
+    n = a.shape[-1]
+    k = np.arange(n)
+    f = np.exp(sign * 2j * np.pi * np.outer(k, k) / n)
+    return np.einsum("az,by,cx,...zyx->...abc", f, f, f, a, optimize=True)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 80, 96, 120])
+def test_fft3d_against_definition(n, prec):
+    say(f"fft3d n={n} prec={NAMES[prec]}")
+    cell = dict(L=7.0, n=n, miller=np.zeros((1, 3), np.int32))
+    plan = lace.lace_plan_create([cell], prec)
+    count = 3
+    rng = np.random.default_rng(n)
+    x = (rng.standard_normal((count, n, n, n))
+         + 1j * rng.standard_normal((count, n, n, n)))
+    cdt = torch.complex128 if prec == FP64 else torch.complex64
+    for direction in (-1, +1):
+        t = torch.tensor(x, dtype=cdt, device="cuda")
+        lace.lace_fft3d(plan, 0, direction, t, count)
+        got = t.cpu().numpy().astype(np.complex128)
+        if n <= 12:
+            ref = brute_dft3(x, direction)
+        elif direction < 0:
+            ref = np.fft.fftn(x, axes=(1, 2, 3))
+        else:
+            ref = np.fft.ifftn(x, axes=(1, 2, 3)) * n ** 3
+        assert rel(got, ref) <= TOL[prec]["fft"], (n, direction)
+    plan.close()
+
+
+# ------------------------------------------------------- dense kernels
+@pytest.mark.parametrize("n_orb,n_pw", [(8, 2777), (37, 1001), (70, 5003)])
+def test_exchange_matrix_gemm(n_orb, n_pw):
+    """M = psi^H W for arbitrary inputs (MFMA split-K GEMM), ragged sizes."""
+    say(f"gemm psi^H W n_orb={n_orb} n_pw={n_pw}")
+    rng = np.random.default_rng(n_orb)
+    miller = synth.miller_sphere(40.0, 30.0)[:n_pw]
+    cell = dict(L=40.0, n=120, miller=miller)
+    s = CellSession(cell, n_orb, FP64, n_vec=n_orb)
+    a = rng.standard_normal((n_orb, n_pw)) + 1j * rng.standard_normal((n_orb, n_pw))
+    b = rng.standard_normal((n_orb, n_pw)) + 1j * rng.standard_normal((n_orb, n_pw))
+    s.psi.copy_(torch.tensor(a))
+    s.w.copy_(torch.tensor(b))
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    ref = np.conj(a) @ b.T
+    err = rel(s.m.cpu().numpy(), ref)
+    say("  rel err", err)
+    assert err <= 1e-13
+    assert s.ex_tr.item() == pytest.approx(0.5 * np.trace(ref).real, rel=1e-12)
+    s.close()
+
+
+@pytest.mark.parametrize("n_orb,n_vec,n_pw", [(8, 3, 2777), (37, 70, 1001)])
+def test_ace_application_gemms(n_orb, n_vec, n_pw):
+    """y = -xi (xi^H x) for arbitrary xi, x (split-K GEMM + tall GEMM)."""
+    say(f"apply_ace n_orb={n_orb} n_vec={n_vec} n_pw={n_pw}")
+    rng = np.random.default_rng(n_vec)
+    miller = synth.miller_sphere(40.0, 30.0)[:n_pw]
+    cell = dict(L=40.0, n=120, miller=miller)
+    s = CellSession(cell, n_orb, FP64, n_vec=n_vec)
+    xi = rng.standard_normal((n_orb, n_pw)) + 1j * rng.standard_normal((n_orb, n_pw))
+    x = rng.standard_normal((n_vec, n_pw)) + 1j * rng.standard_normal((n_vec, n_pw))
+    s.xi.copy_(torch.tensor(xi))
+    y = s.apply_ace(torch.tensor(x, device="cuda")).cpu().numpy()
+    err = rel(y, O.apply_ace(xi, x))
+    say("  rel err", err)
+    assert err <= 1e-13
+    s.close()
+
+
+def test_cholesky_and_projector_on_known_matrix():
+    """psi orthonormal, W = -psi A with A Hermitian positive definite:
+    M = -A, L = chol(A), xi = W L^{-H}."""
+    say("cholesky + projector on a known matrix")
+    rng = np.random.default_rng(11)
+    n_orb, n_pw = 40, 3001
+    miller = synth.miller_sphere(40.0, 30.0)[:n_pw]
+    cell = dict(L=40.0, n=120, miller=miller)
+    q, _ = np.linalg.qr(rng.standard_normal((n_pw, n_orb))
+                        + 1j * rng.standard_normal((n_pw, n_orb)))
+    psi = q.T.copy()
+    z = rng.standard_normal((n_orb, n_orb)) + 1j * rng.standard_normal((n_orb, n_orb))
+    a = z @ z.conj().T + n_orb * np.eye(n_orb)
+    w = -(a.T @ psi)                   # column j of W = -sum_k psi_k A_kj
+    s = CellSession(cell, n_orb, FP64)
+    s.psi.copy_(torch.tensor(psi))
+    s.w.copy_(torch.tensor(w))
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    m = s.m.cpu().numpy()
+    say("  M err", rel(m, -a))
+    assert rel(m, -a) <= 1e-13
+    assert s.info() == 0
+    res_l = O.cholesky_neg(O.symmetrize(m))
+    xi_ref = O.projector(w, res_l)
+    say("  xi err", rel(s.xi.cpu().numpy(), xi_ref))
+    assert rel(s.xi.cpu().numpy(), xi_ref) <= 1e-12
+    s.close()
+
+
+# --------------------------------------------------- 24^3 plain ACE (c0)
+@pytest.fixture(scope="module")
+def c0():
+    inp = synth.make_config_inputs(0)
+    res = O.run_path(inp["coeffs"], inp["miller"], inp["L"], inp["n"])
+    return inp, res
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+def test_plain_ace_24(c0, prec):
+    inp, res = c0
+    say(f"plain ACE 24^3 N=8 prec={NAMES[prec]}")
+    tol = TOL[prec]
+    n_orb = inp["coeffs"].shape[0]
+    s = CellSession(inp, n_orb, prec, n_vec=4)
+    s.set_orbitals(inp["coeffs"])
+    s.apply_exchange(0.0)
+    torch.cuda.synchronize()
+    say("  W rel err", rel(s.w.cpu().numpy(), res["W_pw"]),
+        "E_x", s.e_x.item(), res["ex_pairs"])
+    assert s.n_kept == n_orb * (n_orb + 1) // 2
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(res["ex_pairs"])
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    say("  M rel err", rel(s.m.cpu().numpy(), res["M"]))
+    assert rel(s.m.cpu().numpy(), res["M"]) <= tol["m"]
+    assert abs(s.ex_tr.item() - res["ex_trace"]) <= tol["ex"] * abs(res["ex_trace"])
+    assert s.info() == 0
+    assert rel(s.xi.cpu().numpy(), res["xi"]) <= tol["xi"]
+    # ACE on its build set and on random functions
+    y = s.apply_ace(s.psi).cpu().numpy()
+    assert rel(y, res["W_pw"]) <= tol["ace"]
+    rng = np.random.default_rng(5)
+    x = (rng.standard_normal((3, s.n_pw)) + 1j * rng.standard_normal((3, s.n_pw)))
+    yx = s.apply_ace(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert rel(yx, O.apply_ace(res["xi"], x)) <= tol["ace"]
+    s.close()
+
+
+# ----------------------------------- ragged multi-tile case, several sizes
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("L,n,ecut,n_orb", [(9.0, 16, 6.0, 5),
+                                            (12.0, 48, 20.0, 19),
+                                            (16.0, 80, 30.0, 7)])
+def test_plain_ace_sizes(L, n, ecut, n_orb, prec):
+    say(f"plain ACE n={n} N={n_orb} prec={NAMES[prec]}")
+    tol = TOL[prec]
+    miller = synth.miller_sphere(L, ecut)
+    assert np.abs(miller).max() < n / 2
+    coeffs = synth.random_orbitals(miller, L, n_orb, synth.rng_for(77, n))
+    res = O.run_path(coeffs, miller, L, n)
+    cell = dict(L=L, n=n, miller=miller)
+    s = CellSession(cell, n_orb, prec)
+    s.set_orbitals(coeffs)
+    s.apply_exchange(0.0)
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    assert s.info() == 0
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+    assert rel(s.m.cpu().numpy(), res["M"]) <= tol["m"]
+    assert rel(s.xi.cpu().numpy(), res["xi"]) <= tol["xi"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(res["ex_pairs"])
+    s.close()
+
+
+# ------------------------------------------- screened (L-ACE) small case
+@pytest.fixture(scope="module")
+def localized():
+    L, n, ecut = 16.0, 32, 15.0
+    miller = synth.miller_sphere(L, ecut)
+    coeffs = synth.gaussian_orbitals(miller, L, 16, 8, synth.rng_for(90))
+    psi = O.orbitals_on_grid(coeffs, miller, L, n)
+    S = O.overlap_of_moduli(psi, L)
+    return dict(L=L, n=n, miller=miller, coeffs=coeffs, S=S)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("s_thr", [2e-3, 5e-3])
+def test_screened_lace_small(localized, prec, s_thr):
+    loc = localized
+    say(f"L-ACE 32^3 N=16 s_thr={s_thr} prec={NAMES[prec]}")
+    tol = TOL[prec]
+    cell = dict(L=loc["L"], n=loc["n"], miller=loc["miller"])
+    s = CellSession(cell, 16, prec, n_vec=16)
+    s.set_orbitals(loc["coeffs"])
+    S = s.screen().cpu().numpy()
+    assert rel(S, loc["S"]) <= tol["s"]
+    pairs = O.kept_pairs(loc["S"], s_thr)
+    # screening decision: identical unless an S_ij sits within rounding of
+    # the threshold
+    margin = np.abs(loc["S"] - s_thr).min() / s_thr
+    s.apply_exchange(s_thr)
+    if margin > 1e-6:
+        assert s.n_kept == len(pairs)
+    # parity of W', M', xi with the oracle's own pair list
+    s.apply_exchange(s_thr, pairs=np.array(pairs))
+    assert s.n_kept == len(pairs)
+    for sym in ("avg", "upper", "lower"):
+        res = O.run_path(loc["coeffs"], loc["miller"], loc["L"], loc["n"],
+                         pairs=pairs, sym=sym)
+        s.build_ace(sym)
+        torch.cuda.synchronize()
+        assert s.info() == 0
+        assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+        assert rel(s.m.cpu().numpy(), res["M"]) <= tol["m"]
+        assert rel(s.xi.cpu().numpy(), res["xi"]) <= tol["xi"]
+        assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(
+            res["ex_pairs"])
+    s.close()
+
+
+def test_cholesky_failure_sets_info(c0):
+    """A non-positive-definite -M_s (here: W replaced by +W, so M is
+    positive) is reported through the info word, not by a fault."""
+    inp, res = c0
+    say("cholesky failure path")
+    s = CellSession(inp, 8, FP64)
+    s.set_orbitals(inp["coeffs"])
+    s.w.copy_(torch.tensor(-res["W_pw"], device="cuda"))
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    assert s.info() == 1
+    s.close()
+
+
+def test_explicit_pairs_rejected_when_invalid(c0):
+    inp, _ = c0
+    s = CellSession(inp, 8, FP64)
+    for bad in ([[1, 0]], [[0, 8]], [[0, 1], [0, 1]], [[-1, 2]]):
+        with pytest.raises(lace.LaceError) as ei:
+            s.apply_exchange(0.0, pairs=np.array(bad))
+        assert ei.value.code == lace.LACE_EINVAL
+    with pytest.raises(lace.LaceError):
+        s.apply_exchange(1.5)
+    s.close()
+
+
+def test_deterministic_repeat(c0):
+    """Same inputs, same schedule: bitwise identical W and E_x."""
+    inp, _ = c0
+    s = CellSession(inp, 8, FP32)
+    s.set_orbitals(inp["coeffs"])
+    s.apply_exchange(0.0)
+    w1, e1 = s.w.clone(), s.e_x.clone()
+    s.apply_exchange(0.0)
+    assert torch.equal(w1, s.w) and torch.equal(e1, s.e_x)
+    s.close()
