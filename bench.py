@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Throughput of the L-ACE exchange path on one MI355X.
+
+One step is the whole hot path on the localized 120^3 workload (L = 23.5
+bohr, 256 Loewdin-orthonormalized Gaussian orbitals on 128 random centres,
+S_thr = 1e-3, FP32 pair densities and FFTs, FP64 screening sums, M,
+Cholesky and xi): orbitals to the grid, screening, the kept pair FFTs with
+the kernel multiply and accumulation into W, W back to plane waves, M,
+symmetrization, Cholesky, xi, E_x, and ACE applied to the 256 orbitals.
+
+Prints one JSON line: value = kept pair-FFTs per second over the whole step,
+plus the roofline of the dominant pair-pipeline kernel (HIP-event timing
+inside the library, algorithmic bytes), the plain unscreened FP64 path on
+the 120^3 random-orbital workload for comparison, and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("fft_core.hpp", "fft_kernels.hip", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1801_09263_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# grids moved per pair by each pass of the fused pipeline (algorithmic):
+#   A reads psi_i, psi_j, writes the pair buffer; B reads and writes it;
+#   C reads it and psi_i, psi_j and read-modify-writes W_i, W_j.
+# A diagonal pair reads psi_i once and touches W_i only.
+GRIDS_OFF = (3, 2, 7)
+GRIDS_DIAG = (2, 2, 4)
+PASS_NAMES = ("pair-product+xy-forward", "z-forward*v*z-backward",
+              "xy-backward+accumulate")
+
+
+def pass_roofline(prof, grid_bytes):
+    rows = []
+    for k in range(3):
+        ms = prof["ms"][k]
+        nbytes = (GRIDS_OFF[k] * prof["pairs_off"][k]
+                  + GRIDS_DIAG[k] * prof["pairs_diag"][k]) * grid_bytes
+        launches = max(prof["launches"][k], 1)
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        rows.append(dict(name=PASS_NAMES[k], ms_total=ms,
+                         launches=prof["launches"][k],
+                         avg_launch_us=1e3 * ms / launches,
+                         bytes_per_launch=nbytes / launches,
+                         achieved_GBs=gbs))
+    return rows
+
+
+def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del x, y
+    return 2 * nbytes * reps / dt / 1e9
+
+
+def run_step(sess, s_thr, y):
+    sess.apply_exchange(s_thr)
+    sess.build_ace("avg")
+    sess.apply_ace(sess.psi, y)
+    return sess.n_kept
+
+
+def time_steps(torch, sess, s_thr, steps, warmup, profile=False):
+    from paper_1801_09263_amd import lace
+    y = torch.empty_like(sess.psi)
+    for _ in range(warmup):
+        run_step(sess, s_thr, y)
+    torch.cuda.synchronize()
+    if profile:
+        lace.lace_profile_enable(sess.plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_kept = 0
+    for _ in range(steps):
+        n_kept = run_step(sess, s_thr, y)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = None
+    if profile:
+        prof = lace.lace_profile_read(sess.plan)
+        lace.lace_profile_enable(sess.plan, False)
+    return n_kept, (t1 - t0) / steps, prof
+
+
+def time_exchange(torch, sess, s_thr):
+    sess.apply_exchange(s_thr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sess.apply_exchange(s_thr)
+    torch.cuda.synchronize()
+    return sess.n_kept, time.perf_counter() - t0
+
+
+def cpu_baseline(inp, n_sample_orb=12):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    the exchange among `n_sample_orb` orbitals spread over the cell (their
+    grid orbitals, screening among them, every kept ordered pair)."""
+    import numpy as np
+    import oracle
+    idx = np.linspace(0, inp["coeffs"].shape[0] - 1, n_sample_orb).astype(int)
+    coeffs = inp["coeffs"][idx]
+    t0 = time.perf_counter()
+    psi = oracle.orbitals_on_grid(coeffs, inp["miller"], inp["L"], inp["n"])
+    v = oracle.coulomb_kernel(inp["L"], inp["n"])
+    s = oracle.overlap_of_moduli(psi, inp["L"])
+    pairs = oracle.kept_pairs(s, inp["s_thr"])
+    oracle.apply_exchange(psi, v, pairs)
+    dt = time.perf_counter() - t0
+    return dict(value=len(pairs) / dt, unit="pair-FFTs/s", cores=1,
+                kind="oracle",
+                sample=(f"{n_sample_orb} of the 256 orbitals of the lace-120 "
+                        f"workload: grid orbitals, screening among them and "
+                        f"the {len(pairs)} kept pairs (each as two ordered "
+                        f"Poisson solves), numpy FFT, one thread; "
+                        f"{dt:.1f} s"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain 120^3 comparison rows")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle baseline")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is described, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1801_09263_amd import lace
+    from paper_1801_09263_amd.session import CellSession
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    lace.load()
+
+    log("generating the localized 120^3 workload")
+    inp = synth.make_config_inputs(2, seed=args.seed)
+    n_orb = inp["coeffs"].shape[0]
+    ng = inp["n"] ** 3
+    sess = CellSession(inp, n_orb, lace.LACE_FP32, n_vec=n_orb)
+    sess.set_orbitals(inp["coeffs"])
+    log(f"timing {args.steps} steps after {args.warmup} warmup")
+    n_kept, t_step, prof = time_steps(torch, sess, inp["s_thr"], args.steps,
+                                      args.warmup, profile=True)
+    n_total = n_orb * (n_orb + 1) // 2
+    e_x = sess.e_x.item()
+    ex_tr = sess.ex_tr.item()
+    info = sess.info()
+    _, t_exch = time_exchange(torch, sess, inp["s_thr"])
+    value = n_kept / t_step
+    log(f"step {t_step * 1e3:.1f} ms, kept {n_kept}/{n_total}, "
+        f"exchange {t_exch * 1e3:.1f} ms")
+
+    # roofline of the dominant kernel of the pair pipeline
+    rows = pass_roofline(prof, ng * 8)
+    dom = max(range(3), key=lambda k: rows[k]["ms_total"])
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tr.get("passes", {}).get(str(dom))
+    pipe_ms = sum(prof["ms"])
+    pipe_bytes = sum((GRIDS_OFF[k] * prof["pairs_off"][k]
+                      + GRIDS_DIAG[k] * prof["pairs_diag"][k]) * ng * 8
+                     for k in range(3))
+    roofline = dict(
+        bound="hbm", kernel=rows[dom]["name"],
+        achieved=round(rows[dom]["achieved_GBs"], 1), peak=HBM_PEAK_GBS,
+        unit="GB/s", frac=round(rows[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
+        traffic=traffic,
+        avg_launch_us=round(rows[dom]["avg_launch_us"], 2),
+        bytes_per_launch=rows[dom]["bytes_per_launch"],
+        passes=[{k: (round(v, 3) if isinstance(v, float) else v)
+                 for k, v in r.items()} for r in rows],
+        pipeline_GBs=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9, 1),
+        pipeline_frac=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    )
+    sess.close()
+    del sess
+    torch.cuda.empty_cache()
+
+    compare = None
+    if not args.no_compare:
+        compare = {}
+        log("plain unscreened 120^3 random orbitals (FP64 and FP32 pairs)")
+        inp1 = synth.make_config_inputs(1, seed=args.seed)
+        for name, prec in (("plain_fp64", lace.LACE_FP64),
+                           ("plain_fp32", lace.LACE_FP32)):
+            s1 = CellSession(inp1, n_orb, prec, n_vec=n_orb)
+            s1.set_orbitals(inp1["coeffs"])
+            n1, t1 = time_exchange(torch, s1, 0.0)
+            _, ts1, _ = time_steps(torch, s1, 0.0, 1, 0)
+            compare[name] = dict(pairs=n1, exchange_ms=round(t1 * 1e3, 1),
+                                 step_ms=round(ts1 * 1e3, 1),
+                                 pair_ffts_per_s=round(n1 / ts1, 1),
+                                 exchange_pair_ffts_per_s=round(n1 / t1, 1))
+            log(name, compare[name])
+            s1.close()
+            del s1
+            torch.cuda.empty_cache()
+        compare["lace_fp32_vs_plain_fp64_step_speedup"] = round(
+            compare["plain_fp64"]["step_ms"] / (t_step * 1e3), 3)
+    copy_gbs = copy_bandwidth(torch)
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle sample")
+        cpu = cpu_baseline(inp)
+
+    out = {
+        "metric": "pair-FFTs/s + HBM roofline %, L-ACE vs plain FP64; "
+                  "p50/p99 job latency",
+        "value": round(value, 1),
+        "unit": "pair-FFTs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "lace-120: L=23.5 bohr cubic cell, 120^3 grid, "
+                        "Ecut=40 Ha (156795 plane waves), 256 Gaussian "
+                        "orbitals on 128 centres, Loewdin, S_thr=1e-3; FP32 "
+                        "pairs/FFTs, FP64 screening, M, Cholesky, xi",
+            "kept_pairs": n_kept, "total_pairs": n_total,
+            "kept_fraction": round(n_kept / n_total, 4),
+            "exchange_ms": round(t_exch * 1e3, 1),
+            "exchange_pair_ffts_per_s": round(n_kept / t_exch, 1),
+            "e_x": e_x, "e_x_trace": ex_tr, "cholesky_info": info,
+            "parallelism": "1 GPU",
+        },
+        "roofline": roofline,
+        "copy_GBs_measured": round(copy_gbs, 1),
+        "compare": compare,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,32 @@ int lace_fft3d(lace_plan* plan, int cell, int direction, void* grids,
  * LACE_ENOTPD when it is not (*info_host is filled in both cases). */
 int lace_get_info(lace_plan* plan, int cell, int32_t* info_host);
 
+/* Host only, no device work: the batch schedule lace_apply_exchange uses.
+ * The n_pairs unordered pairs (host arrays, 0 <= i <= j < n_orb) are
+ * grouped into batches of at most per_batch (1..64) pairs in which no
+ * orbital appears twice; batch_of[k] (host, n_pairs int32) receives the
+ * batch of pair k and *n_batches the number of batches.  Pairs are ordered
+ * by their round in a round-robin tournament over the orbitals, whose rounds
+ * are sets of disjoint pairs. */
+int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
+                        int64_t n_pairs, int n_orb, int per_batch,
+                        int32_t* batch_of, int64_t* n_batches);
+
+/* Kernel timing of the pair pipeline of lace_apply_exchange, for
+ * roofline measurement.  While enabled, every batch of the pipeline is
+ * bracketed by HIP events on the call's stream, one interval per pass:
+ *   0  pass A: pair product + forward transform along x and y,
+ *   1  pass B: forward z transform, kernel multiply, backward z transform,
+ *   2  pass C: backward transform along y and x + accumulation into W.
+ * lace_profile_enable(plan, 1) clears the totals and starts recording,
+ * (plan, 0) stops.  lace_profile_read synchronizes the device and returns
+ * per pass: total milliseconds ms[3], launches (batches) launches[3],
+ * diagonal and off-diagonal pairs processed pairs_diag[3], pairs_off[3].
+ * Arrays are host memory of 3 elements; any may be NULL. */
+int lace_profile_enable(lace_plan* plan, int enable);
+int lace_profile_read(lace_plan* plan, double* ms, int64_t* launches,
+                      int64_t* pairs_diag, int64_t* pairs_off);
+
 /* Static text for a status code. */
 const char* lace_status_string(int status);
 

@@ -20,13 +20,19 @@
 namespace lace {
 
 // ------------------------------------------------------------- functors
+// Prologues produce the value of grid point g of slot `slot`; epilogues
+// consume it.  Epilogues that read memory split into pre() (issue loads)
+// and put() (combine and store), so a thread can have a whole chunk of
+// loads in flight before it stores anything.
+struct NoPre {};
+
 template <typename T> struct ProGrid {
-  const C<T>* buf;
+  const C<T>* __restrict__ buf;
   int64_t gs;
   __device__ C<T> get(int g, int slot) const { return buf[slot * gs + g]; }
 };
 template <typename T> struct ProPair {
-  const C<T>* psi;
+  const C<T>* __restrict__ psi;
   int64_t gs;
   PairArgs pa;
   __device__ C<T> get(int g, int slot) const {
@@ -36,34 +42,98 @@ template <typename T> struct ProPair {
   }
 };
 template <typename T> struct EpiGrid {
-  C<T>* buf;
+  using Pre = NoPre;
+  C<T>* __restrict__ buf;
   int64_t gs;
   T scale;
-  __device__ void put(int g, int slot, C<T> v) const {
+  __device__ void pre(int, int, Pre&) const {}
+  __device__ void put(int g, int slot, C<T> v, const Pre&) const {
     buf[slot * gs + g] = scl<T>(v, scale);
   }
 };
+template <typename T> struct AccPre {
+  C<T> pi, pj, wi, wj;
+};
+// W_j -= psi_i V and, for i != j, W_i -= psi_j conj(V)
 template <typename T> struct EpiAcc {
-  const C<T>* psi;
-  C<T>* w;
+  using Pre = AccPre<T>;
+  const C<T>* __restrict__ psi;
+  C<T>* __restrict__ w;
   int64_t gs;
   PairArgs pa;
-  __device__ void put(int g, int slot, C<T> v) const {
+  __device__ void pre(int g, int slot, Pre& r) const {
     const int i = pa.i[slot], j = pa.j[slot];
-    const C<T> pi = psi[i * gs + g];
-    C<T> wj = w[j * gs + g];
-    w[j * gs + g] = sub<T>(wj, mul<T>(pi, v));
+    r.pi = psi[i * gs + g];
+    r.wj = w[j * gs + g];
     if (i != j) {
-      const C<T> pj = psi[j * gs + g];
-      C<T> wi = w[i * gs + g];
-      w[i * gs + g] = sub<T>(wi, mulc<T>(pj, v));
+      r.pj = psi[j * gs + g];
+      r.wi = w[i * gs + g];
     }
+  }
+  __device__ void put(int g, int slot, C<T> v, const Pre& r) const {
+    const int i = pa.i[slot], j = pa.j[slot];
+    w[j * gs + g] = sub<T>(r.wj, mul<T>(r.pi, v));
+    if (i != j) w[i * gs + g] = sub<T>(r.wi, mulc<T>(r.pj, v));
   }
 };
 
 template <typename T, int N, int NT>
 __device__ inline void load_tw(C<T>* tw, const C<T>* tw_g) {
   for (int m = threadIdx.x; m < N; m += NT) tw[m] = tw_g[m];
+}
+
+// Fill s[m], m < NE, from pro.get(idx(m)): all loads of a thread first,
+// then the LDS stores.
+template <typename T, int NE, int NT, class Pro, class Idx>
+__device__ inline void stage_in(C<T>* s, const Pro& pro, int slot, Idx idx) {
+  constexpr int PER = (NE + NT - 1) / NT;
+  C<T> v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int m = threadIdx.x + q * NT;
+    if (NE % NT == 0 || m < NE) v[q] = pro.get(idx(m), slot);
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int m = threadIdx.x + q * NT;
+    if (NE % NT == 0 || m < NE) s[m] = v[q];
+  }
+}
+
+// Drain s[m] through the epilogue in chunks of CH elements per thread:
+// the chunk's loads are issued before any of its stores.
+template <typename T, int NE, int NT, class Epi, class Idx>
+__device__ inline void stage_out(const C<T>* s, const Epi& epi, int slot,
+                                 Idx idx) {
+  constexpr int PER = (NE + NT - 1) / NT;
+  constexpr int CH0 = sizeof(T) == 4 ? 8 : 4;   // register budget
+  constexpr int CH = PER < CH0 ? PER : CH0;
+#pragma unroll
+  for (int q0 = 0; q0 < PER; q0 += CH) {
+    typename Epi::Pre pre[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int m = threadIdx.x + (q0 + c) * NT;
+      if (q0 + c < PER && (NE % NT == 0 || m < NE)) epi.pre(idx(m), slot, pre[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int m = threadIdx.x + (q0 + c) * NT;
+      if (q0 + c < PER && (NE % NT == 0 || m < NE))
+        epi.put(idx(m), slot, s[m], pre[c]);
+    }
+  }
+}
+
+// Workgroups are dealt to the 8 XCDs round robin by id.  Remap the flat
+// id so that each XCD receives a contiguous range of logical tiles, which
+// then share its L2 (tiles that split a cache line, or read the same
+// kernel-table tile).
+__device__ inline int xcd_logical(int bid, int total) {
+  constexpr int NX = 8;
+  const int per = total / NX;
+  if (bid >= per * NX) return bid;  // ragged tail keeps identity
+  return (bid % NX) * per + bid / NX;
 }
 
 // ------------------------------------------- xy-plane pass (whole plane)
@@ -75,11 +145,12 @@ __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
   const int z = blockIdx.x, slot = blockIdx.y;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = z * N * N;
-  for (int m = threadIdx.x; m < N * N; m += NT) s[m] = pro.get(base + m, slot);
+  auto idx = [base](int m) { return base + m; };
+  stage_in<T, N * N, NT>(s, pro, slot, idx);
   __syncthreads();
   lds_fft<T, N, N, NT, SIGN, false>(s, N, 1, tw);  // along x (rows)
   lds_fft<T, N, N, NT, SIGN, true>(s, 1, N, tw);   // along y (columns)
-  for (int m = threadIdx.x; m < N * N; m += NT) epi.put(base + m, slot, s[m]);
+  stage_out<T, N * N, NT>(s, epi, slot, idx);
 }
 
 // ---------------------------------------------- x pencils: TY whole rows
@@ -91,10 +162,11 @@ __global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
   const int slot = blockIdx.y;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = blockIdx.x * TY * N;
-  for (int m = threadIdx.x; m < TY * N; m += NT) s[m] = pro.get(base + m, slot);
+  auto idx = [base](int m) { return base + m; };
+  stage_in<T, TY * N, NT>(s, pro, slot, idx);
   __syncthreads();
   lds_fft<T, N, TY, NT, SIGN, false>(s, N, 1, tw);
-  for (int m = threadIdx.x; m < TY * N; m += NT) epi.put(base + m, slot, s[m]);
+  stage_out<T, TY * N, NT>(s, epi, slot, idx);
 }
 
 // ---------------------- y or z pencils: TX adjacent x columns, whole axis
@@ -106,20 +178,23 @@ __device__ inline int col_index(int tile, int m) {
   return AXIS == 1 ? x + N * (e + N * f) : x + N * (f + N * e);
 }
 
+// Grid: one flat dimension of ntiles * nslots workgroups, remapped so that
+// an XCD takes consecutive tiles and all slots of a tile together.
 template <typename T, int N, int AXIS, int TX, int NT, int SIGN, class Pro,
           class Epi>
 __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
-                                             const C<T>* tw_g) {
+                                             const C<T>* tw_g, int nslots) {
   __shared__ C<T> s[TX * N];
   __shared__ C<T> tw[N];
-  const int tile = blockIdx.x, slot = blockIdx.y;
+  constexpr int NTILES = N * (N / TX);
+  const int lg = xcd_logical(blockIdx.x, NTILES * nslots);
+  const int tile = lg / nslots, slot = lg % nslots;
   load_tw<T, N, NT>(tw, tw_g);
-  for (int m = threadIdx.x; m < TX * N; m += NT)
-    s[m] = pro.get(col_index<N, AXIS, TX>(tile, m), slot);
+  auto idx = [tile](int m) { return col_index<N, AXIS, TX>(tile, m); };
+  stage_in<T, TX * N, NT>(s, pro, slot, idx);
   __syncthreads();
   lds_fft<T, N, TX, NT, SIGN, true>(s, 1, TX, tw);
-  for (int m = threadIdx.x; m < TX * N; m += NT)
-    epi.put(col_index<N, AXIS, TX>(tile, m), slot, s[m]);
+  stage_out<T, TX * N, NT>(s, epi, slot, idx);
 }
 
 template <int NT>
@@ -138,18 +213,21 @@ __device__ inline double block_sum(double v, double* red) {
 
 // ---- pass B: z forward, x v(G)/N_g with energy partial, z backward ----
 template <typename T, int N, int TX, int NT>
-__global__ __launch_bounds__(NT) void k_zconv(C<T>* tmp, int64_t gs,
-                                              const T* vtab, PairArgs pa,
-                                              double* epart, int ntiles,
-                                              const C<T>* tw_g) {
+__global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
+                                              int64_t gs,
+                                              const T* __restrict__ vtab,
+                                              PairArgs pa, double* epart,
+                                              int ntiles, const C<T>* tw_g) {
   __shared__ C<T> s[TX * N];
   __shared__ C<T> tw[N];
   __shared__ double red[NT / 64];
-  const int tile = blockIdx.x, slot = blockIdx.y;
+  const int lg = xcd_logical(blockIdx.x, ntiles * pa.n);
+  const int tile = lg / pa.n, slot = lg % pa.n;
   load_tw<T, N, NT>(tw, tw_g);
   C<T>* g = tmp + slot * gs;
-  for (int m = threadIdx.x; m < TX * N; m += NT)
-    s[m] = g[col_index<N, 2, TX>(tile, m)];
+  ProGrid<T> pro{g, 0};
+  auto idx = [tile](int m) { return col_index<N, 2, TX>(tile, m); };
+  stage_in<T, TX * N, NT>(s, pro, 0, idx);
   __syncthreads();
   lds_fft<T, N, TX, NT, -1, true>(s, 1, TX, tw);
   double e = 0.0;
@@ -161,8 +239,8 @@ __global__ __launch_bounds__(NT) void k_zconv(C<T>* tmp, int64_t gs,
   }
   __syncthreads();
   lds_fft<T, N, TX, NT, +1, true>(s, 1, TX, tw);
-  for (int m = threadIdx.x; m < TX * N; m += NT)
-    g[col_index<N, 2, TX>(tile, m)] = s[m];
+  EpiGrid<T> epi{g, 0, T(1)};
+  stage_out<T, TX * N, NT>(s, epi, 0, idx);
   const double tot = block_sum<NT>(e, red);
   if (threadIdx.x == 0) {
     const double wgt = (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
@@ -222,7 +300,7 @@ __global__ void k_reduce_sum(const double* part, int64_t count, double factor,
 template <typename T, int N> struct Cfg {
   // plane pass: whole N x N plane in LDS
   static constexpr bool plane = (int64_t)N * N * sizeof(C<T>) <= 150 * 1024;
-  static constexpr int NT_PLANE = 512;
+  static constexpr int NT_PLANE = 1024;
   // y/z pencils: TX columns (>= 128 bytes of x per row when N allows)
   static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
   static constexpr int TX = (N % TX0 == 0) ? TX0 : ((N % 8 == 0) ? 8 : 4);
@@ -259,8 +337,8 @@ template <typename T, int N> struct Engine {
   static hipError_t cols(Pro p, Epi e, int count, const C<T>* tw,
                          hipStream_t st) {
     hipLaunchKernelGGL((k_cols<T, N, AXIS, Cf::TX, Cf::NT_COLS, SIGN, Pro, Epi>),
-                       dim3(N * (N / Cf::TX), count), dim3(Cf::NT_COLS), 0, st,
-                       p, e, tw);
+                       dim3(N * (N / Cf::TX) * count), dim3(Cf::NT_COLS), 0,
+                       st, p, e, tw, count);
     return hipGetLastError();
   }
 
@@ -284,7 +362,8 @@ template <typename T, int N> struct Engine {
 
   static hipError_t pair_batch(const CellDev& c, const PairArgs& pa,
                                const C<T>* psi, C<T>* w, C<T>* tmp,
-                               double* epart, hipStream_t st) {
+                               double* epart, hipStream_t st,
+                               hipEvent_t* ev = nullptr) {
     const C<T>* tw = static_cast<const C<T>*>(c.tw);
     const int cnt = pa.n;
     ProPair<T> pp{psi, NG, pa};
@@ -292,6 +371,7 @@ template <typename T, int N> struct Engine {
     EpiGrid<T> et{tmp, NG, T(1)};
     EpiAcc<T> ea{psi, w, NG, pa};
     hipError_t err;
+    if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     // pass A
     if constexpr (Cf::plane) {
       err = plane<-1>(pp, et, cnt, tw, st);
@@ -300,13 +380,15 @@ template <typename T, int N> struct Engine {
       if (err == hipSuccess) err = cols<1, -1>(pt, et, cnt, tw, st);
     }
     if (err != hipSuccess) return err;
+    if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     // pass B
     const int ntiles = N * (N / Cf::TX);
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::NT_COLS>), dim3(ntiles, cnt),
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::NT_COLS>), dim3(ntiles * cnt),
                        dim3(Cf::NT_COLS), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pa, epart, ntiles, tw);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
+    if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
     // pass C
     if constexpr (Cf::plane) {
       err = plane<+1>(pt, ea, cnt, tw, st);
@@ -314,6 +396,7 @@ template <typename T, int N> struct Engine {
       err = cols<1, +1>(pt, et, cnt, tw, st);
       if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
     }
+    if (err == hipSuccess && ev) err = hipEventRecord(ev[3], st);
     return err;
   }
 
@@ -438,13 +521,14 @@ hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
 template <typename T>
 static hipError_t pair_batch_t(const CellDev& c, const PairArgs& pa,
                                const void* psi, void* w, void* tmp,
-                               double* epart, hipStream_t st) {
+                               double* epart, hipStream_t st,
+                               hipEvent_t* ev) {
   switch (c.n) {
 #define X(NN)                                                          \
   case NN:                                                             \
     return Engine<T, NN>::pair_batch(c, pa, static_cast<const C<T>*>(psi), \
                                      static_cast<C<T>*>(w),            \
-                                     static_cast<C<T>*>(tmp), epart, st);
+                                     static_cast<C<T>*>(tmp), epart, st, ev);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -455,8 +539,17 @@ hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
                              const void* psi, void* w, void* tmp,
                              double* epart, hipStream_t st) {
   if (pa.n <= 0) return hipSuccess;
-  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st)
-              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st);
+  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st, nullptr)
+              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st, nullptr);
+}
+
+hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
+                                   const PairArgs& pa, const void* psi,
+                                   void* w, void* tmp, double* epart,
+                                   hipStream_t st, hipEvent_t* ev) {
+  if (pa.n <= 0) return hipSuccess;
+  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st, ev)
+              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st, ev);
 }
 
 hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,

@@ -44,6 +44,12 @@ hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
 hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
                              const void* psi, void* w, void* tmp,
                              double* epart, hipStream_t st);
+// Same, with ev[0..3] recorded before pass A, between the passes and
+// after pass C.
+hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
+                                   const PairArgs& pa, const void* psi,
+                                   void* w, void* tmp, double* epart,
+                                   hipStream_t st, hipEvent_t* ev);
 // Number of energy partial slots per pair slot (tiles of the z pass).
 int64_t energy_tiles(int n, bool fp64);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);

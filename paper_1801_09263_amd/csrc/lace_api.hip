@@ -40,10 +40,25 @@ int default_pairs_per_batch(int n) {
 
 }  // namespace
 
+struct Profile {
+  bool on = false;
+  std::vector<hipEvent_t> pool;     // created events, reused across calls
+  size_t used = 0;                  // events handed out since the last read
+  struct Rec {
+    size_t ev;                      // index of the first of 4 events
+    int64_t diag, off;
+  };
+  std::vector<Rec> recs;
+  double ms[3] = {0, 0, 0};
+  int64_t launches[3] = {0, 0, 0};
+  int64_t diag[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+};
+
 struct lace_plan {
   lace_precision prec;
   int device = 0;
   std::vector<CellPlan> cells;
+  Profile prof;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -101,25 +116,78 @@ static void free_cell(CellPlan& c) {
   c.d_gidx = nullptr; c.d_vtab = nullptr; c.d_tw = nullptr; c.d_info = nullptr;
 }
 
+// Next free profiling event (created on first use).
+static hipEvent_t prof_event(Profile& pr) {
+  if (pr.used == pr.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pr.pool.push_back(e);
+  }
+  return pr.pool[pr.used++];
+}
+
+// Fold the recorded intervals into the totals (events must be complete).
+static hipError_t prof_collect(Profile& pr) {
+  for (const auto& r : pr.recs) {
+    for (int k = 0; k < 3; ++k) {
+      float t = 0.f;
+      hipError_t e = hipEventElapsedTime(&t, pr.pool[r.ev + k], pr.pool[r.ev + k + 1]);
+      if (e != hipSuccess) return e;
+      pr.ms[k] += t;
+      pr.launches[k] += 1;
+      pr.diag[k] += r.diag;
+      pr.off[k] += r.off;
+    }
+  }
+  pr.recs.clear();
+  pr.used = 0;
+  return hipSuccess;
+}
+
 // Signed frequency of FFT index k on an n-point axis.
 static int signed_freq(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
 
-// Pairs of one call, grouped into batches in which no orbital appears
-// twice (so the accumulation into W has no write conflicts).  First fit
-// over a window of open batches, pairs taken in the given order.
+// Round of an unordered pair in the circle-method round robin over n'
+// vertices (n' = n_orb rounded up to even): vertex n'-1 stays fixed and
+// round r pairs it with r and pairs (r + k, r - k) mod (n'-1); so pair
+// (i, j) with i < j < n'-1 sits in round (i + j) / 2 mod (n'-1), and every
+// round is a set of disjoint pairs.  Diagonal pairs form one extra round.
+static int pair_round(int i, int j, int nv) {
+  if (i == j) return nv - 1;
+  if (j == nv - 1) return i;
+  const int64_t m = nv - 1;                  // odd
+  return (int)(((int64_t)(i + j) * (nv / 2)) % m);  // (nv/2) = 1/2 mod m
+}
+
+// Group pairs into batches of at most per_batch pairs in which no orbital
+// appears twice, so the accumulation into W has no write conflicts.  Pairs
+// are taken round by round (stable within a round) and placed first-fit
+// into a small window of open batches; a round is itself conflict-free, so
+// batches fill to per_batch except at round boundaries.
 static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
                            int n_orb, int per_batch,
-                           std::vector<PairArgs>& out) {
+                           std::vector<PairArgs>& out,
+                           std::vector<int32_t>* batch_of = nullptr) {
   out.clear();
+  const int nv = n_orb + (n_orb & 1);
+  std::vector<int> order(pairs.size());
+  std::vector<int> round(pairs.size());
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    order[k] = (int)k;
+    round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return round[a] < round[b]; });
+  if (batch_of) batch_of->assign(pairs.size(), -1);
   const int words = (n_orb + 63) / 64;
   struct Open {
     size_t idx;
     std::vector<uint64_t> used;
   };
   std::vector<Open> open;
-  const size_t window = 64;
-  for (const auto& pr : pairs) {
-    const int i = pr.first, j = pr.second;
+  const size_t window = 8;
+  for (int k : order) {
+    const int i = pairs[k].first, j = pairs[k].second;
     bool placed = false;
     for (size_t o = 0; o < open.size(); ++o) {
       Open& ob = open[o];
@@ -128,6 +196,7 @@ static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
       if (ui || uj) continue;
       PairArgs& b = out[ob.idx];
       b.i[b.n] = i; b.j[b.n] = j; ++b.n;
+      if (batch_of) (*batch_of)[k] = (int32_t)ob.idx;
       ob.used[i / 64] |= 1ull << (i % 64);
       ob.used[j / 64] |= 1ull << (j % 64);
       if (b.n == per_batch) open.erase(open.begin() + o);
@@ -139,6 +208,7 @@ static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
     std::memset(&b, 0, sizeof(b));
     b.n = 1; b.i[0] = i; b.j[0] = j;
     out.push_back(b);
+    if (batch_of) (*batch_of)[k] = (int32_t)(out.size() - 1);
     if (per_batch > 1) {
       Open ob;
       ob.idx = out.size() - 1;
@@ -281,6 +351,7 @@ int lace_plan_destroy(lace_plan* p) {
   if (!p) return LACE_OK;
   (void)hipDeviceSynchronize();
   for (auto& c : p->cells) free_cell(c);
+  for (auto ev : p->prof.pool) (void)hipEventDestroy(ev);
   delete p;
   return LACE_OK;
 }
@@ -379,8 +450,27 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   e = launch_zero(w, (int64_t)c.ng * n_orb * grid_bytes(p), st);
   if (e == hipSuccess)
     e = launch_zero(epart, (int64_t)sizeof(double) * L.pairs_per_batch * ntiles, st);
-  for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b)
-    e = launch_pair_batch(c, fp64, sched[b], psi, w, at(ws, L.tmp), epart, st);
+  Profile& pr = p->prof;
+  if (pr.on && pr.used + 4 * sched.size() > 65536) {
+    // bound the number of outstanding events: fold what is recorded
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = prof_collect(pr);
+  }
+  for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b) {
+    if (pr.on) {
+      const size_t first = pr.used;
+      hipEvent_t ev[4];
+      for (int k = 0; k < 4; ++k) ev[k] = prof_event(pr);
+      if (!ev[0] || !ev[1] || !ev[2] || !ev[3]) return LACE_EHIP;
+      int64_t nd = 0;
+      for (int q = 0; q < sched[b].n; ++q) nd += sched[b].i[q] == sched[b].j[q];
+      pr.recs.push_back({first, nd, sched[b].n - nd});
+      e = launch_pair_batch_timed(c, fp64, sched[b], psi, w, at(ws, L.tmp),
+                                  epart, st, ev);
+    } else {
+      e = launch_pair_batch(c, fp64, sched[b], psi, w, at(ws, L.tmp), epart, st);
+    }
+  }
   if (e == hipSuccess && e_x)
     e = launch_reduce_sum(epart, (int64_t)L.pairs_per_batch * ntiles,
                           -0.5 * c.omega / double(c.ng), e_x, st);
@@ -448,6 +538,57 @@ int lace_fft3d(lace_plan* p, int cell, int direction, void* grids, int count,
   return hip_status(launch_fft3d(p->cells[cell].dev, p->prec == LACE_FP64,
                                  direction, grids, count,
                                  static_cast<hipStream_t>(stream)));
+}
+
+int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
+                        int64_t n_pairs, int n_orb, int per_batch,
+                        int32_t* batch_of, int64_t* n_batches) {
+  if (!pair_i || !pair_j || !batch_of || !n_batches || n_pairs < 0 ||
+      n_orb < 1 || per_batch < 1 || per_batch > PMAX)
+    return LACE_EINVAL;
+  std::vector<std::pair<int, int>> pairs;
+  pairs.reserve(n_pairs);
+  for (int64_t k = 0; k < n_pairs; ++k) {
+    const int i = pair_i[k], j = pair_j[k];
+    if (i < 0 || j < i || j >= n_orb) return LACE_EINVAL;
+    pairs.emplace_back(i, j);
+  }
+  std::vector<PairArgs> sched;
+  std::vector<int32_t> bo;
+  build_schedule(pairs, n_orb, per_batch, sched, &bo);
+  for (int64_t k = 0; k < n_pairs; ++k) batch_of[k] = bo[k];
+  *n_batches = (int64_t)sched.size();
+  return LACE_OK;
+}
+
+int lace_profile_enable(lace_plan* p, int enable) {
+  if (!p) return LACE_EINVAL;
+  Profile& pr = p->prof;
+  if (enable) {
+    if (!pr.recs.empty() && hipDeviceSynchronize() != hipSuccess) return LACE_EHIP;
+    pr.recs.clear();
+    pr.used = 0;
+    for (int k = 0; k < 3; ++k) {
+      pr.ms[k] = 0; pr.launches[k] = 0; pr.diag[k] = 0; pr.off[k] = 0;
+    }
+  }
+  pr.on = enable != 0;
+  return LACE_OK;
+}
+
+int lace_profile_read(lace_plan* p, double* ms, int64_t* launches,
+                      int64_t* pairs_diag, int64_t* pairs_off) {
+  if (!p) return LACE_EINVAL;
+  Profile& pr = p->prof;
+  if (hipDeviceSynchronize() != hipSuccess) return LACE_EHIP;
+  if (prof_collect(pr) != hipSuccess) return LACE_EHIP;
+  for (int k = 0; k < 3; ++k) {
+    if (ms) ms[k] = pr.ms[k];
+    if (launches) launches[k] = pr.launches[k];
+    if (pairs_diag) pairs_diag[k] = pr.diag[k];
+    if (pairs_off) pairs_off[k] = pr.off[k];
+  }
+  return LACE_OK;
 }
 
 int lace_get_info(lace_plan* p, int cell, int32_t* info_host) {

@@ -36,6 +36,7 @@ SYMBOLS = (
     "lace_plan_create", "lace_plan_destroy", "lace_workspace_size",
     "lace_screen", "lace_apply_exchange", "lace_build_ace", "lace_apply_ace",
     "lace_fft3d", "lace_get_info", "lace_status_string",
+    "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
 )
 
 
@@ -85,6 +86,12 @@ def load(path: str = LIB_PATH):
     lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
     lib.lace_fft3d.argtypes = [vp, i32, i32, vp, i32, vp]
     lib.lace_get_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.lace_profile_enable.argtypes = [vp, i32]
+    p_i64 = ctypes.POINTER(ctypes.c_int64)
+    lib.lace_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                      p_i64, p_i64, p_i64]
+    lib.lace_schedule_pairs.argtypes = [p_i32, p_i32, i64, i32, i32, p_i32,
+                                        p_i64]
     lib.lace_status_string.argtypes = [i32]
     lib.lace_status_string.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -239,3 +246,36 @@ def lace_get_info(plan, cell) -> int:
     if code not in (LACE_OK, LACE_ENOTPD):
         _check(code, "lace_get_info")
     return info.value
+
+
+def lace_profile_enable(plan, enable=True):
+    _check(load().lace_profile_enable(plan.handle, 1 if enable else 0),
+           "lace_profile_enable")
+
+
+def lace_profile_read(plan):
+    """Per-pass totals of the pair pipeline since profiling was enabled:
+    dict of lists (index 0 pass A, 1 pass B, 2 pass C)."""
+    ms = (ctypes.c_double * 3)()
+    la = (ctypes.c_int64 * 3)()
+    pdg = (ctypes.c_int64 * 3)()
+    pof = (ctypes.c_int64 * 3)()
+    _check(load().lace_profile_read(plan.handle, ms, la, pdg, pof),
+           "lace_profile_read")
+    return dict(ms=list(ms), launches=list(la), pairs_diag=list(pdg),
+                pairs_off=list(pof))
+
+
+def lace_schedule_pairs(pairs, n_orb, per_batch):
+    """Batch index of every pair (host only).  Returns (batch_of, n)."""
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    pi = np.ascontiguousarray(pr[:, 0])
+    pj = np.ascontiguousarray(pr[:, 1])
+    out = np.empty(pr.shape[0], dtype=np.int32)
+    nb = ctypes.c_int64(0)
+    P = ctypes.POINTER(ctypes.c_int32)
+    _check(load().lace_schedule_pairs(pi.ctypes.data_as(P), pj.ctypes.data_as(P),
+                                      pr.shape[0], int(n_orb), int(per_batch),
+                                      out.ctypes.data_as(P), ctypes.byref(nb)),
+           "lace_schedule_pairs")
+    return out, nb.value

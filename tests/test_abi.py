@@ -85,3 +85,48 @@ def test_library_built_for_gfx950():
         pytest.skip("liblace.so not built")
     data = open(lace.LIB_PATH, "rb").read()
     assert b"gfx950" in data
+
+
+def _check_schedule(pairs, n_orb, per_batch):
+    batch_of, nb = lace.lace_schedule_pairs(pairs, n_orb, per_batch)
+    assert batch_of.min() >= 0 and batch_of.max() == nb - 1
+    for b in range(nb):
+        members = [pairs[k] for k in np.nonzero(batch_of == b)[0]]
+        assert 1 <= len(members) <= per_batch
+        used = [o for (i, j) in members for o in ({i, j})]
+        assert len(used) == len(set(used)), "orbital used twice in a batch"
+    return nb
+
+
+@pytest.mark.parametrize("n_orb,per_batch", [(8, 4), (256, 32), (255, 16),
+                                             (32, 16), (128, 32)])
+def test_schedule_complete_pair_set_is_tight(lib, n_orb, per_batch):
+    pairs = [(i, j) for j in range(n_orb) for i in range(j + 1)]
+    nb = _check_schedule(pairs, n_orb, per_batch)
+    # each round robin round holds floor(n'/2) disjoint pairs
+    nv = n_orb + (n_orb & 1)
+    rounds = nv - 1
+    per_round = -(-(nv // 2) // per_batch)
+    bound = rounds * per_round + -(-n_orb // per_batch)
+    assert nb <= bound
+    if n_orb == 256:
+        assert nb == len(pairs) // per_batch   # perfect packing
+
+
+@pytest.mark.parametrize("keep", [0.7, 0.3])
+def test_schedule_screened_pair_set(lib, keep):
+    rng = np.random.default_rng(int(keep * 10))
+    n_orb, per_batch = 256, 32
+    pairs = [(i, j) for j in range(n_orb) for i in range(j + 1)
+             if i == j or rng.random() < keep]
+    nb = _check_schedule(pairs, n_orb, per_batch)
+    assert nb <= 1.25 * len(pairs) / per_batch + n_orb
+
+
+def test_schedule_rejects_bad_pairs(lib):
+    with pytest.raises(lace.LaceError):
+        lace.lace_schedule_pairs([(2, 1)], 4, 4)
+    with pytest.raises(lace.LaceError):
+        lace.lace_schedule_pairs([(0, 4)], 4, 4)
+    with pytest.raises(lace.LaceError):
+        lace.lace_schedule_pairs([(0, 1)], 4, 65)
