@@ -145,6 +145,31 @@ def cpu_baseline(inp, n_sample_orb=12):
                         f"{dt:.1f} s"))
 
 
+def pmc_sample(torch, seed):
+    """Fixed small workload for counter collection: a plain 1 GiB device
+    copy (the calibration of FETCH_SIZE / WRITE_SIZE), then one exchange
+    application over 128 off-diagonal pairs of the localized 120^3
+    workload (4 full batches of the pair pipeline)."""
+    import numpy as np
+    import synth
+    from paper_1801_09263_amd import lace
+    from paper_1801_09263_amd.session import CellSession
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    inp = synth.make_config_inputs(2, seed=seed)
+    n_orb = inp["coeffs"].shape[0]
+    sess = CellSession(inp, n_orb, lace.LACE_FP32)
+    sess.set_orbitals(inp["coeffs"])
+    # 128 disjoint-friendly pairs: two round-robin rounds of 64 each
+    pairs = [(i, i + 128) for i in range(128)]
+    sess.apply_exchange(0.0, pairs=np.array(pairs))
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_sample": "ok", "pairs": len(pairs)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +180,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="small fixed run for hardware-counter passes: a "
+                         "1 GiB copy (calibration) and 4 pair batches of "
+                         "the localized workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -169,6 +198,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     lace.load()
+
+    if args.pmc_sample:
+        pmc_sample(torch, args.seed)
+        return
 
     log("generating the localized 120^3 workload")
     inp = synth.make_config_inputs(2, seed=args.seed)

@@ -84,8 +84,9 @@ __device__ inline void load_tw(C<T>* tw, const C<T>* tw_g) {
 
 // Fill s[m], m < NE, from pro.get(idx(m)): all loads of a thread first,
 // then the LDS stores.
-template <typename T, int NE, int NT, class Pro, class Idx>
-__device__ inline void stage_in(C<T>* s, const Pro& pro, int slot, Idx idx) {
+template <typename T, int NE, int NT, class Pro, class Idx, class Lds>
+__device__ inline void stage_in(C<T>* s, const Pro& pro, int slot, Idx idx,
+                                Lds lds) {
   constexpr int PER = (NE + NT - 1) / NT;
   C<T> v[PER];
 #pragma unroll
@@ -96,15 +97,15 @@ __device__ inline void stage_in(C<T>* s, const Pro& pro, int slot, Idx idx) {
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int m = threadIdx.x + q * NT;
-    if (NE % NT == 0 || m < NE) s[m] = v[q];
+    if (NE % NT == 0 || m < NE) s[lds(m)] = v[q];
   }
 }
 
 // Drain s[m] through the epilogue in chunks of CH elements per thread:
 // the chunk's loads are issued before any of its stores.
-template <typename T, int NE, int NT, class Epi, class Idx>
+template <typename T, int NE, int NT, class Epi, class Idx, class Lds>
 __device__ inline void stage_out(const C<T>* s, const Epi& epi, int slot,
-                                 Idx idx) {
+                                 Idx idx, Lds lds) {
   constexpr int PER = (NE + NT - 1) / NT;
   constexpr int CH0 = sizeof(T) == 4 ? 8 : 4;   // register budget
   constexpr int CH = PER < CH0 ? PER : CH0;
@@ -120,7 +121,7 @@ __device__ inline void stage_out(const C<T>* s, const Epi& epi, int slot,
     for (int c = 0; c < CH; ++c) {
       const int m = threadIdx.x + (q0 + c) * NT;
       if (q0 + c < PER && (NE % NT == 0 || m < NE))
-        epi.put(idx(m), slot, s[m], pre[c]);
+        epi.put(idx(m), slot, s[lds(m)], pre[c]);
     }
   }
 }
@@ -136,46 +137,63 @@ __device__ inline int xcd_logical(int bid, int total) {
   return (bid % NX) * per + bid / NX;
 }
 
+// LDS layout.  Every kernel keeps each transform line contiguous in LDS
+// with the line stride padded to N + 1 (odd), and lets consecutive lanes
+// walk consecutive lines.  A lane stride of N + 1 complex words touches
+// distinct banks for 8- and 16-byte elements, for the strided writes of
+// the first radix stage as well as for the reads.
+template <int N> struct Pad { static constexpr int LS = N + 1; };
+
 // ------------------------------------------- xy-plane pass (whole plane)
 template <typename T, int N, int NT, int SIGN, class Pro, class Epi>
 __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
                                               const C<T>* tw_g) {
-  __shared__ C<T> s[N * N];
+  constexpr int LS = Pad<N>::LS;
+  __shared__ C<T> s[N * LS];
   __shared__ C<T> tw[N];
   const int z = blockIdx.x, slot = blockIdx.y;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = z * N * N;
   auto idx = [base](int m) { return base + m; };
-  stage_in<T, N * N, NT>(s, pro, slot, idx);
+  auto lds = [](int m) { return (m / N) * LS + m % N; };  // row y, col x
+  stage_in<T, N * N, NT>(s, pro, slot, idx, lds);
   __syncthreads();
-  lds_fft<T, N, N, NT, SIGN, false>(s, N, 1, tw);  // along x (rows)
-  lds_fft<T, N, N, NT, SIGN, true>(s, 1, N, tw);   // along y (columns)
-  stage_out<T, N * N, NT>(s, epi, slot, idx);
+  lds_fft<T, N, N, NT, SIGN, true>(s, LS, 1, tw);  // along x: lines = rows
+  lds_fft<T, N, N, NT, SIGN, true>(s, 1, LS, tw);  // along y: lines = columns
+  stage_out<T, N * N, NT>(s, epi, slot, idx, lds);
 }
 
 // ---------------------------------------------- x pencils: TY whole rows
 template <typename T, int N, int TY, int NT, int SIGN, class Pro, class Epi>
 __global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
                                                const C<T>* tw_g) {
-  __shared__ C<T> s[TY * N];
+  constexpr int LS = Pad<N>::LS;
+  __shared__ C<T> s[TY * LS];
   __shared__ C<T> tw[N];
   const int slot = blockIdx.y;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = blockIdx.x * TY * N;
   auto idx = [base](int m) { return base + m; };
-  stage_in<T, TY * N, NT>(s, pro, slot, idx);
+  auto lds = [](int m) { return (m / N) * LS + m % N; };
+  stage_in<T, TY * N, NT>(s, pro, slot, idx, lds);
   __syncthreads();
-  lds_fft<T, N, TY, NT, SIGN, false>(s, N, 1, tw);
-  stage_out<T, TY * N, NT>(s, epi, slot, idx);
+  lds_fft<T, N, TY, NT, SIGN, true>(s, LS, 1, tw);
+  stage_out<T, TY * N, NT>(s, epi, slot, idx, lds);
 }
 
 // ---------------------- y or z pencils: TX adjacent x columns, whole axis
+// Element m of a tile: column xx = m % TX (fast in global memory), position
+// e = m / TX along the transform axis.  LDS holds column xx as line xx.
 template <int N, int AXIS, int TX>
 __device__ inline int col_index(int tile, int m) {
   const int xt = tile % (N / TX), f = tile / (N / TX);
   const int xx = m % TX, e = m / TX;
   const int x = xt * TX + xx;
   return AXIS == 1 ? x + N * (e + N * f) : x + N * (f + N * e);
+}
+template <int N, int TX>
+__device__ inline int col_lds(int m) {
+  return (m % TX) * Pad<N>::LS + m / TX;
 }
 
 // Grid: one flat dimension of ntiles * nslots workgroups, remapped so that
@@ -184,17 +202,19 @@ template <typename T, int N, int AXIS, int TX, int NT, int SIGN, class Pro,
           class Epi>
 __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
                                              const C<T>* tw_g, int nslots) {
-  __shared__ C<T> s[TX * N];
+  constexpr int LS = Pad<N>::LS;
+  __shared__ C<T> s[TX * LS];
   __shared__ C<T> tw[N];
   constexpr int NTILES = N * (N / TX);
   const int lg = xcd_logical(blockIdx.x, NTILES * nslots);
   const int tile = lg / nslots, slot = lg % nslots;
   load_tw<T, N, NT>(tw, tw_g);
   auto idx = [tile](int m) { return col_index<N, AXIS, TX>(tile, m); };
-  stage_in<T, TX * N, NT>(s, pro, slot, idx);
+  auto lds = [](int m) { return col_lds<N, TX>(m); };
+  stage_in<T, TX * N, NT>(s, pro, slot, idx, lds);
   __syncthreads();
-  lds_fft<T, N, TX, NT, SIGN, true>(s, 1, TX, tw);
-  stage_out<T, TX * N, NT>(s, epi, slot, idx);
+  lds_fft<T, N, TX, NT, SIGN, true>(s, LS, 1, tw);
+  stage_out<T, TX * N, NT>(s, epi, slot, idx, lds);
 }
 
 template <int NT>
@@ -218,7 +238,8 @@ __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
                                               const T* __restrict__ vtab,
                                               PairArgs pa, double* epart,
                                               int ntiles, const C<T>* tw_g) {
-  __shared__ C<T> s[TX * N];
+  constexpr int LS = Pad<N>::LS;
+  __shared__ C<T> s[TX * LS];
   __shared__ C<T> tw[N];
   __shared__ double red[NT / 64];
   const int lg = xcd_logical(blockIdx.x, ntiles * pa.n);
@@ -227,20 +248,22 @@ __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
   C<T>* g = tmp + slot * gs;
   ProGrid<T> pro{g, 0};
   auto idx = [tile](int m) { return col_index<N, 2, TX>(tile, m); };
-  stage_in<T, TX * N, NT>(s, pro, 0, idx);
+  auto lds = [](int m) { return col_lds<N, TX>(m); };
+  stage_in<T, TX * N, NT>(s, pro, 0, idx, lds);
   __syncthreads();
-  lds_fft<T, N, TX, NT, -1, true>(s, 1, TX, tw);
+  lds_fft<T, N, TX, NT, -1, true>(s, LS, 1, tw);
   double e = 0.0;
   for (int m = threadIdx.x; m < TX * N; m += NT) {
     const T v = vtab[col_index<N, 2, TX>(tile, m)];
-    const C<T> r = s[m];
+    const int q = col_lds<N, TX>(m);
+    const C<T> r = s[q];
     e += double(v) * (double(r.x) * double(r.x) + double(r.y) * double(r.y));
-    s[m] = scl<T>(r, v);
+    s[q] = scl<T>(r, v);
   }
   __syncthreads();
-  lds_fft<T, N, TX, NT, +1, true>(s, 1, TX, tw);
+  lds_fft<T, N, TX, NT, +1, true>(s, LS, 1, tw);
   EpiGrid<T> epi{g, 0, T(1)};
-  stage_out<T, TX * N, NT>(s, epi, 0, idx);
+  stage_out<T, TX * N, NT>(s, epi, 0, idx, lds);
   const double tot = block_sum<NT>(e, red);
   if (threadIdx.x == 0) {
     const double wgt = (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
@@ -300,7 +323,7 @@ __global__ void k_reduce_sum(const double* part, int64_t count, double factor,
 template <typename T, int N> struct Cfg {
   // plane pass: whole N x N plane in LDS
   static constexpr bool plane = (int64_t)N * N * sizeof(C<T>) <= 150 * 1024;
-  static constexpr int NT_PLANE = 1024;
+  static constexpr int NT_PLANE = sizeof(T) == 4 ? 1024 : 512;
   // y/z pencils: TX columns (>= 128 bytes of x per row when N allows)
   static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
   static constexpr int TX = (N % TX0 == 0) ? TX0 : ((N % 8 == 0) ? 8 : 4);
