@@ -229,8 +229,11 @@ def main():
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_source_hash") == kernel_source_hash():
-            traffic = tr.get("passes", {}).get(str(dom))
+        ps = tr.get("passes", {}).get(str(dom))
+        if tr.get("kernel_source_hash") == kernel_source_hash() and ps:
+            # counter-measured bytes / algorithmic bytes of this kernel in the
+            # counter sample, applied to this run's mean launch
+            traffic = round(ps["ratio"] * rows[dom]["bytes_per_launch"], 0)
     pipe_ms = sum(prof["ms"])
     pipe_bytes = sum((GRIDS_OFF[k] * prof["pairs_off"][k]
                       + GRIDS_DIAG[k] * prof["pairs_diag"][k]) * ng * 8
