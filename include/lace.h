@@ -151,6 +151,64 @@ int lace_apply_ace(lace_plan* plan, int cell, const void* xi_g, int n_orb,
                    const void* x_g, int n_vec, void* y_g, void* ws,
                    size_t ws_bytes, lace_stream_t stream);
 
+/* One job of lace_apply_exchange_batched: the exchange (and optionally the
+ * ACE build) of one set of orbitals on one cell of the plan.  Fields are as
+ * in lace_apply_exchange / lace_build_ace; each job brings its own
+ * workspace (sized by lace_workspace_size for its cell and n_orb) because
+ * jobs run concurrently.  n_kept is an output, written by the call. */
+typedef struct {
+  int32_t cell;
+  const void* psi_g;     /* device n_pw x n_orb complex128 */
+  int32_t n_orb;
+  double s_thr;          /* [0, 1) */
+  void* w_g;             /* device n_pw x n_orb complex128, output */
+  double* e_x;           /* device, may be NULL */
+  int64_t n_kept;        /* output: pairs run */
+  int32_t sym;           /* lace_sym, used when xi_g != NULL */
+  void* xi_g;            /* device n_pw x n_orb, or NULL: no ACE build */
+  void* m_out;           /* device n_orb x n_orb complex128, may be NULL */
+  double* ex_tr;         /* device, may be NULL */
+  void* ws;              /* device workspace of this job */
+  size_t ws_bytes;
+} lace_job;
+
+#define LACE_BATCH_GRAPH 1  /* capture the device work in one HIP graph */
+
+/* Several independent exchange applications (and ACE builds) at once, on
+ * cells of any supported sizes: the multi-cell batching of the same method.
+ * Jobs are spread over the plan's internal streams (forked from and joined
+ * back to `stream`), so small cells overlap on the device.  Grid orbitals
+ * and screening run first; if any job screens (s_thr > 0) the call
+ * synchronizes once to build all pair schedules on the host.  With
+ * LACE_BATCH_GRAPH, the pair pipelines, W back-transforms and ACE builds of
+ * all jobs are captured in one HIP graph that is cached on the plan and
+ * replayed while the jobs, their pair lists and buffers stay the same.
+ * Results are identical to running each job alone (same kernels, same
+ * schedule, same summation order).  Errors: EINVAL (a bad job), ENOMEM (a
+ * job workspace too small), EHIP. */
+int lace_apply_exchange_batched(lace_plan* plan, lace_job* jobs, int n_jobs,
+                                int flags, lace_stream_t stream);
+
+/* Per-cell tuning of the pair pipeline: pairs per batch (1..64) and the xy
+ * schedule (use_plane = 1: fused xy-plane passes, where the plane fits LDS;
+ * 0: separate x and y pencil passes).  Host only. */
+int lace_set_tuning(lace_plan* plan, int cell, int pairs_per_batch,
+                    int use_plane);
+int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
+                    int* use_plane);
+
+/* Autotuner: times the pair pipeline of this cell on the given orbitals for
+ * every candidate (pairs per batch 8, 16, 32, 64; plane and pencil
+ * schedules where both exist), over the same fixed set of pairs, and keeps
+ * the fastest with lace_set_tuning.  Writes up to *n_cand candidates
+ * (cand_ppb, cand_plane, cand_us_per_pair; host arrays, may be NULL) and
+ * sets *n_cand to the number timed.  Synchronizes the stream.  The
+ * workspace is the one of lace_workspace_size (W is overwritten). */
+int lace_autotune(lace_plan* plan, int cell, const void* psi_g, int n_orb,
+                  void* ws, size_t ws_bytes, lace_stream_t stream,
+                  int* cand_ppb, int* cand_plane, double* cand_us_per_pair,
+                  int* n_cand);
+
 /* In-place 3D FFT of `count` n^3 grids stored back to back in the plan
  * precision (complex64 or complex128, x fastest).  direction -1: forward
  * (exp(-i G.r)), +1: backward; both unscaled.  Exposed so the transform

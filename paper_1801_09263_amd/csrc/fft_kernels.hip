@@ -368,12 +368,12 @@ template <typename T, int N> struct Engine {
   // in-place transform of `count` grids, optional scale on the last pass
   template <int SIGN>
   static hipError_t fft3d(C<T>* g, int count, T scale, const C<T>* tw,
-                          hipStream_t st) {
+                          bool use_plane, hipStream_t st) {
     ProGrid<T> p{g, NG};
     EpiGrid<T> e1{g, NG, T(1)};
     EpiGrid<T> es{g, NG, scale};
     hipError_t err;
-    if constexpr (Cf::plane) {
+    if (Cf::plane && use_plane) {
       err = plane<SIGN>(p, e1, count, tw, st);
     } else {
       err = xlines<SIGN>(p, e1, count, tw, st);
@@ -394,9 +394,10 @@ template <typename T, int N> struct Engine {
     EpiGrid<T> et{tmp, NG, T(1)};
     EpiAcc<T> ea{psi, w, NG, pa};
     hipError_t err;
+    const bool use_plane = Cf::plane && c.use_plane;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     // pass A
-    if constexpr (Cf::plane) {
+    if (use_plane) {
       err = plane<-1>(pp, et, cnt, tw, st);
     } else {
       err = xlines<-1>(pp, et, cnt, tw, st);
@@ -413,7 +414,7 @@ template <typename T, int N> struct Engine {
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
     // pass C
-    if constexpr (Cf::plane) {
+    if (use_plane) {
       err = plane<+1>(pt, ea, cnt, tw, st);
     } else {
       err = cols<1, +1>(pt, et, cnt, tw, st);
@@ -466,8 +467,10 @@ static hipError_t fft3d_t(const CellDev& c, int sign, void* grids, int count,
   switch (c.n) {
 #define X(NN)                                                            \
   case NN:                                                               \
-    return sign < 0 ? Engine<T, NN>::template fft3d<-1>(g, count, scale, tw, st) \
-                    : Engine<T, NN>::template fft3d<+1>(g, count, scale, tw, st);
+    return sign < 0 ? Engine<T, NN>::template fft3d<-1>(g, count, scale, tw, \
+                                                         c.use_plane != 0, st) \
+                    : Engine<T, NN>::template fft3d<+1>(g, count, scale, tw, \
+                                                         c.use_plane != 0, st);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;

@@ -22,6 +22,8 @@ struct CellDev {
   const int32_t* gidx;  // n_pw linear grid indices (x + n (y + n z))
   const void* vtab;     // ng kernel values v(G) / ng in the plan precision
   const void* tw;       // n twiddles exp(-2 pi i m / n), plan precision
+  int ppb;              // pairs per batch (1..PMAX)
+  int use_plane;        // 1: fused xy-plane passes where the plane fits LDS
 };
 
 bool grid_supported(int n);

@@ -54,11 +54,23 @@ struct Profile {
   int64_t diag[3] = {0, 0, 0}, off[3] = {0, 0, 0};
 };
 
+// Cached HIP graph of the device work of one batched call.
+struct GraphCache {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct lace_plan {
   lace_precision prec;
   int device = 0;
   std::vector<CellPlan> cells;
   Profile prof;
+  // internal streams (default priority) for concurrent jobs, created lazily
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;   // fork/join events, no timing
+  hipStream_t origin = nullptr;     // capture stream of the batched call
+  GraphCache graph;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -79,14 +91,16 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   const CellDev& c = p->cells[cell].dev;
   const bool fp64 = p->prec == LACE_FP64;
   Layout L{};
-  L.pairs_per_batch = default_pairs_per_batch(c.n);
+  L.pairs_per_batch = c.ppb;
   const size_t gb = (size_t)c.ng * grid_bytes(p);
   size_t off = 0;
+  // pair buffer and energy partials sized for the largest batch, so that
+  // one workspace serves every tuning of the cell
   L.psi = off; off += align_up(gb * n_orb);
   L.w = off; off += align_up(gb * n_orb);
-  L.tmp = off; off += align_up(gb * L.pairs_per_batch);
+  L.tmp = off; off += align_up(gb * PMAX);
   L.epart = off;
-  off += align_up(sizeof(double) * L.pairs_per_batch * energy_tiles(c.n, fp64));
+  off += align_up(sizeof(double) * PMAX * energy_tiles(c.n, fp64));
   L.s = off; off += align_up(sizeof(double) * n_orb * n_orb);
   int64_t part = gemm_ip_part_bytes(n_orb, n_orb, c.n_pw, true);
   part = std::max(part, gemm_ip_part_bytes(n_orb, n_orb, c.ng, false));
@@ -275,6 +289,8 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
     const double rc = d.rc > 0.0 ? d.rc : 0.5 * d.L;
     cp.dev.n = n; cp.dev.ng = ng; cp.dev.n_pw = d.n_pw;
     cp.dev.L = d.L; cp.dev.rc = rc; cp.dev.omega = d.L * d.L * d.L;
+    cp.dev.ppb = default_pairs_per_batch(n);
+    cp.dev.use_plane = plane_fits(n, fp64) ? 1 : 0;
     // sphere -> grid map
     std::vector<int32_t> gidx(d.n_pw);
     for (int64_t m = 0; m < d.n_pw; ++m) {
@@ -352,6 +368,11 @@ int lace_plan_destroy(lace_plan* p) {
   (void)hipDeviceSynchronize();
   for (auto& c : p->cells) free_cell(c);
   for (auto ev : p->prof.pool) (void)hipEventDestroy(ev);
+  if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
+  if (p->graph.graph) (void)hipGraphDestroy(p->graph.graph);
+  for (auto ev : p->events) (void)hipEventDestroy(ev);
+  for (auto st : p->streams) (void)hipStreamDestroy(st);
+  if (p->origin) (void)hipStreamDestroy(p->origin);
   delete p;
   return LACE_OK;
 }
@@ -390,6 +411,113 @@ int lace_screen(lace_plan* p, int cell, const void* psi_g, int n_orb,
   return hip_status(e);
 }
 
+// Host copy of an explicit pair list after validation; false on a bad list.
+static bool copy_pairs(const int32_t* pair_i, const int32_t* pair_j,
+                       int64_t n_pairs, int n_orb,
+                       std::vector<std::pair<int, int>>& pairs) {
+  std::vector<uint8_t> seen((size_t)n_orb * n_orb, 0);
+  pairs.clear();
+  pairs.reserve(n_pairs);
+  for (int64_t k = 0; k < n_pairs; ++k) {
+    const int i = pair_i[k], j = pair_j[k];
+    if (i < 0 || j < 0 || i > j || j >= n_orb) return false;
+    if (seen[(size_t)i * n_orb + j]) return false;
+    seen[(size_t)i * n_orb + j] = 1;
+    pairs.emplace_back(i, j);
+  }
+  return true;
+}
+
+static void all_pairs(int n_orb, std::vector<std::pair<int, int>>& pairs) {
+  pairs.clear();
+  pairs.reserve((size_t)n_orb * (n_orb + 1) / 2);
+  for (int j = 0; j < n_orb; ++j)
+    for (int i = 0; i <= j; ++i) pairs.emplace_back(i, j);
+}
+
+// Kept pairs from a host copy of S: S_ij >= s_thr (upper triangle, Eq. (6)).
+static void kept_from_s(const std::vector<double>& hs, int n_orb, double s_thr,
+                        std::vector<std::pair<int, int>>& pairs) {
+  pairs.clear();
+  for (int j = 0; j < n_orb; ++j)
+    for (int i = 0; i <= j; ++i)
+      if (hs[(size_t)i * n_orb + j] >= s_thr) pairs.emplace_back(i, j);
+}
+
+// S into the workspace from the grid orbitals already in it.
+static hipError_t enqueue_screen(const lace_plan* p, const CellDev& c, int n_orb,
+                                 const Layout& L, void* ws, double* s_out,
+                                 hipStream_t st) {
+  const bool fp64 = p->prec == LACE_FP64;
+  return launch_gemm_ip_abs(fp64, at(ws, L.psi), c.ng, n_orb, c.ng,
+                            c.omega / double(c.ng), s_out, at(ws, L.part),
+                            (int64_t)(L.mw - L.part), st);
+}
+
+// Pair pipeline over a schedule, energy reduction, W back to plane waves.
+// Requires the grid orbitals in the workspace.
+static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
+                                   const std::vector<PairArgs>& sched,
+                                   const Layout& L, void* ws, void* w_g,
+                                   double* e_x, hipStream_t st, bool profile) {
+  const bool fp64 = p->prec == LACE_FP64;
+  void* psi = at(ws, L.psi);
+  void* w = at(ws, L.w);
+  const int64_t ntiles = energy_tiles(c.n, fp64);
+  double* epart = reinterpret_cast<double*>(at(ws, L.epart));
+  hipError_t e = launch_zero(w, (int64_t)c.ng * n_orb * grid_bytes(p), st);
+  if (e == hipSuccess)
+    e = launch_zero(epart, (int64_t)sizeof(double) * PMAX * ntiles, st);
+  Profile& pr = p->prof;
+  const bool timed = profile && pr.on;
+  if (e == hipSuccess && timed && pr.used + 4 * sched.size() > 65536) {
+    // bound the number of outstanding events: fold what is recorded
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = prof_collect(pr);
+  }
+  for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b) {
+    if (timed) {
+      const size_t first = pr.used;
+      hipEvent_t ev[4];
+      for (int k = 0; k < 4; ++k) ev[k] = prof_event(pr);
+      if (!ev[0] || !ev[1] || !ev[2] || !ev[3]) return hipErrorOutOfMemory;
+      int64_t nd = 0;
+      for (int q = 0; q < sched[b].n; ++q) nd += sched[b].i[q] == sched[b].j[q];
+      pr.recs.push_back({first, nd, sched[b].n - nd});
+      e = launch_pair_batch_timed(c, fp64, sched[b], psi, w, at(ws, L.tmp),
+                                  epart, st, ev);
+    } else {
+      e = launch_pair_batch(c, fp64, sched[b], psi, w, at(ws, L.tmp), epart, st);
+    }
+  }
+  if (e == hipSuccess && e_x)
+    e = launch_reduce_sum(epart, (int64_t)PMAX * ntiles,
+                          -0.5 * c.omega / double(c.ng), e_x, st);
+  if (e == hipSuccess) e = launch_grid_to_pw(c, fp64, w, n_orb, w_g, st);
+  return e;
+}
+
+// M, E_x trace, -M_s, Cholesky, Z = L^{-H}, xi = W Z.
+static hipError_t enqueue_build_ace(const CellPlan& cp, int n_orb, int sym,
+                                    const Layout& L, void* ws,
+                                    const void* psi_g, const void* w_g,
+                                    void* xi_g, void* m_out, double* ex_tr,
+                                    hipStream_t st) {
+  const CellDev& c = cp.dev;
+  void* m = m_out ? m_out : at(ws, L.mw);
+  hipError_t e = launch_gemm_ip_c128(psi_g, c.n_pw, n_orb, w_g, c.n_pw, n_orb,
+                                     c.n_pw, 1.0, m, at(ws, L.part),
+                                     (int64_t)(L.mw - L.part), st);
+  if (e == hipSuccess && ex_tr) e = launch_trace_re(m, n_orb, 0.5, ex_tr, st);
+  if (e == hipSuccess) e = launch_neg_sym(m, n_orb, sym, at(ws, L.a), st);
+  if (e == hipSuccess) e = launch_cholesky(at(ws, L.a), n_orb, cp.d_info, st);
+  if (e == hipSuccess) e = launch_trinv_adj(at(ws, L.a), n_orb, at(ws, L.z), st);
+  if (e == hipSuccess)
+    e = launch_gemm_tall(w_g, c.n_pw, c.n_pw, n_orb, at(ws, L.z), n_orb, xi_g,
+                         c.n_pw, st);
+  return e;
+}
+
 int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
                         double s_thr, const int32_t* pair_i,
                         const int32_t* pair_j, int64_t n_pairs, void* w_g,
@@ -404,77 +532,31 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
   std::vector<std::pair<int, int>> pairs;
-  if (pair_i) {
-    std::vector<uint8_t> seen((size_t)n_orb * n_orb, 0);
-    pairs.reserve(n_pairs);
-    for (int64_t k = 0; k < n_pairs; ++k) {
-      const int i = pair_i[k], j = pair_j[k];
-      if (i < 0 || j < 0 || i > j || j >= n_orb) return LACE_EINVAL;
-      if (seen[(size_t)i * n_orb + j]) return LACE_EINVAL;
-      seen[(size_t)i * n_orb + j] = 1;
-      pairs.emplace_back(i, j);
-    }
-  }
+  if (pair_i && !copy_pairs(pair_i, pair_j, n_pairs, n_orb, pairs))
+    return LACE_EINVAL;
   const CellDev& c = p->cells[cell].dev;
   const bool fp64 = p->prec == LACE_FP64;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  void* psi = at(ws, L.psi);
-  void* w = at(ws, L.w);
-  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, psi, st);
+  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, at(ws, L.psi), st);
   if (e != hipSuccess) return LACE_EHIP;
   if (!pair_i) {
     if (s_thr > 0.0) {
       double* s = reinterpret_cast<double*>(at(ws, L.s));
-      e = launch_gemm_ip_abs(fp64, psi, c.ng, n_orb, c.ng,
-                             c.omega / double(c.ng), s, at(ws, L.part),
-                             (int64_t)(L.mw - L.part), st);
+      e = enqueue_screen(p, c, n_orb, L, ws, s, st);
       if (e != hipSuccess) return LACE_EHIP;
       std::vector<double> hs((size_t)n_orb * n_orb);
       e = hipMemcpyAsync(hs.data(), s, sizeof(double) * hs.size(),
                          hipMemcpyDeviceToHost, st);
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       if (e != hipSuccess) return LACE_EHIP;
-      for (int j = 0; j < n_orb; ++j)
-        for (int i = 0; i <= j; ++i)
-          if (hs[(size_t)i * n_orb + j] >= s_thr) pairs.emplace_back(i, j);
+      kept_from_s(hs, n_orb, s_thr, pairs);
     } else {
-      pairs.reserve((size_t)n_orb * (n_orb + 1) / 2);
-      for (int j = 0; j < n_orb; ++j)
-        for (int i = 0; i <= j; ++i) pairs.emplace_back(i, j);
+      all_pairs(n_orb, pairs);
     }
   }
   std::vector<PairArgs> sched;
-  build_schedule(pairs, n_orb, L.pairs_per_batch, sched);
-  const int64_t ntiles = energy_tiles(c.n, fp64);
-  double* epart = reinterpret_cast<double*>(at(ws, L.epart));
-  e = launch_zero(w, (int64_t)c.ng * n_orb * grid_bytes(p), st);
-  if (e == hipSuccess)
-    e = launch_zero(epart, (int64_t)sizeof(double) * L.pairs_per_batch * ntiles, st);
-  Profile& pr = p->prof;
-  if (pr.on && pr.used + 4 * sched.size() > 65536) {
-    // bound the number of outstanding events: fold what is recorded
-    e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = prof_collect(pr);
-  }
-  for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b) {
-    if (pr.on) {
-      const size_t first = pr.used;
-      hipEvent_t ev[4];
-      for (int k = 0; k < 4; ++k) ev[k] = prof_event(pr);
-      if (!ev[0] || !ev[1] || !ev[2] || !ev[3]) return LACE_EHIP;
-      int64_t nd = 0;
-      for (int q = 0; q < sched[b].n; ++q) nd += sched[b].i[q] == sched[b].j[q];
-      pr.recs.push_back({first, nd, sched[b].n - nd});
-      e = launch_pair_batch_timed(c, fp64, sched[b], psi, w, at(ws, L.tmp),
-                                  epart, st, ev);
-    } else {
-      e = launch_pair_batch(c, fp64, sched[b], psi, w, at(ws, L.tmp), epart, st);
-    }
-  }
-  if (e == hipSuccess && e_x)
-    e = launch_reduce_sum(epart, (int64_t)L.pairs_per_batch * ntiles,
-                          -0.5 * c.omega / double(c.ng), e_x, st);
-  if (e == hipSuccess) e = launch_grid_to_pw(c, fp64, w, n_orb, w_g, st);
+  build_schedule(pairs, n_orb, c.ppb, sched);
+  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true);
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();
   return LACE_OK;
@@ -491,21 +573,9 @@ int lace_build_ace(lace_plan* p, int cell, const void* psi_g, const void* w_g,
     return LACE_EINVAL;
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
-  const CellPlan& cp = p->cells[cell];
-  const CellDev& c = cp.dev;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  void* m = m_out ? m_out : at(ws, L.mw);
-  hipError_t e = launch_gemm_ip_c128(psi_g, c.n_pw, n_orb, w_g, c.n_pw, n_orb,
-                                     c.n_pw, 1.0, m, at(ws, L.part),
-                                     (int64_t)(L.mw - L.part), st);
-  if (e == hipSuccess && ex_tr) e = launch_trace_re(m, n_orb, 0.5, ex_tr, st);
-  if (e == hipSuccess) e = launch_neg_sym(m, n_orb, (int)sym, at(ws, L.a), st);
-  if (e == hipSuccess) e = launch_cholesky(at(ws, L.a), n_orb, cp.d_info, st);
-  if (e == hipSuccess) e = launch_trinv_adj(at(ws, L.a), n_orb, at(ws, L.z), st);
-  if (e == hipSuccess)
-    e = launch_gemm_tall(w_g, c.n_pw, c.n_pw, n_orb, at(ws, L.z), n_orb, xi_g,
-                         c.n_pw, st);
-  return hip_status(e);
+  return hip_status(enqueue_build_ace(p->cells[cell], n_orb, (int)sym, L, ws,
+                                      psi_g, w_g, xi_g, m_out, ex_tr,
+                                      static_cast<hipStream_t>(stream)));
 }
 
 int lace_apply_ace(lace_plan* p, int cell, const void* xi_g, int n_orb,
@@ -559,6 +629,288 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
   for (int64_t k = 0; k < n_pairs; ++k) batch_of[k] = bo[k];
   *n_batches = (int64_t)sched.size();
   return LACE_OK;
+}
+
+int lace_set_tuning(lace_plan* p, int cell, int ppb, int use_plane) {
+  if (!p || cell < 0 || cell >= (int)p->cells.size()) return LACE_EINVAL;
+  if (ppb < 1 || ppb > PMAX || (use_plane != 0 && use_plane != 1))
+    return LACE_EINVAL;
+  CellDev& c = p->cells[cell].dev;
+  if (use_plane && !plane_fits(c.n, p->prec == LACE_FP64)) return LACE_EUNSUPPORTED;
+  c.ppb = ppb;
+  c.use_plane = use_plane;
+  return LACE_OK;
+}
+
+int lace_get_tuning(const lace_plan* p, int cell, int* ppb, int* use_plane) {
+  if (!p || cell < 0 || cell >= (int)p->cells.size()) return LACE_EINVAL;
+  if (ppb) *ppb = p->cells[cell].dev.ppb;
+  if (use_plane) *use_plane = p->cells[cell].dev.use_plane;
+  return LACE_OK;
+}
+
+int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
+                  void* ws, size_t ws_bytes, lace_stream_t stream,
+                  int* cand_ppb, int* cand_plane, double* cand_us, int* n_cand) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_g || !ws) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  CellDev& c = p->cells[cell].dev;
+  const bool fp64 = p->prec == LACE_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, at(ws, L.psi), st);
+  if (e != hipSuccess) return LACE_EHIP;
+  // fixed pair set: the first 4 * PMAX pairs in round-robin order
+  std::vector<std::pair<int, int>> pairs;
+  all_pairs(n_orb, pairs);
+  {
+    std::vector<PairArgs> full;
+    build_schedule(pairs, n_orb, PMAX, full);
+    pairs.clear();
+    for (const auto& b : full) {
+      for (int q = 0; q < b.n && pairs.size() < (size_t)(4 * PMAX); ++q)
+        pairs.emplace_back(b.i[q], b.j[q]);
+      if (pairs.size() >= (size_t)(4 * PMAX)) break;
+    }
+  }
+  struct Cand { int ppb, plane; double us; };
+  std::vector<Cand> cands;
+  const int ppbs[4] = {8, 16, 32, 64};
+  for (int plane = 1; plane >= 0; --plane) {
+    if (plane && !plane_fits(c.n, fp64)) continue;
+    for (int k = 0; k < 4; ++k) cands.push_back({ppbs[k], plane, 0.0});
+  }
+  const int save_ppb = c.ppb, save_plane = c.use_plane;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+    return LACE_EHIP;
+  for (auto& cd : cands) {
+    c.ppb = cd.ppb;
+    c.use_plane = cd.plane;
+    std::vector<PairArgs> sched;
+    build_schedule(pairs, n_orb, cd.ppb, sched);
+    double best = 1e30;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+      const bool fp = fp64;
+      double* epart = reinterpret_cast<double*>(at(ws, L.epart));
+      e = hipEventRecord(t0, st);
+      for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b)
+        e = launch_pair_batch(c, fp, sched[b], at(ws, L.psi), at(ws, L.w),
+                              at(ws, L.tmp), epart, st);
+      if (e == hipSuccess) e = hipEventRecord(t1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+      if (rep > 0 && ms < best) best = ms;   // first repetition warms up
+    }
+    cd.us = 1e3 * best / double(pairs.size());
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e != hipSuccess) {
+    c.ppb = save_ppb;
+    c.use_plane = save_plane;
+    return LACE_EHIP;
+  }
+  size_t bi = 0;
+  for (size_t k = 1; k < cands.size(); ++k)
+    if (cands[k].us < cands[bi].us) bi = k;
+  c.ppb = cands[bi].ppb;
+  c.use_plane = cands[bi].plane;
+  if (n_cand) {
+    const int cap = *n_cand;
+    for (int k = 0; k < (int)cands.size() && k < cap; ++k) {
+      if (cand_ppb) cand_ppb[k] = cands[k].ppb;
+      if (cand_plane) cand_plane[k] = cands[k].plane;
+      if (cand_us) cand_us[k] = cands[k].us;
+    }
+    *n_cand = (int)cands.size();
+  }
+  return LACE_OK;
+}
+
+// ------------------------------------------------------------ batching
+static hipError_t ensure_streams(lace_plan* p, int k) {
+  while ((int)p->streams.size() < k) {
+    hipStream_t s;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    p->streams.push_back(s);
+  }
+  while ((int)p->events.size() < k + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    p->events.push_back(ev);
+  }
+  if (!p->origin) {
+    hipError_t e = hipStreamCreateWithFlags(&p->origin, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// `to` waits for everything enqueued so far on `from` (event k).
+static hipError_t link(lace_plan* p, hipStream_t from, hipStream_t to, int k) {
+  hipError_t e = hipEventRecord(p->events[k], from);
+  if (e == hipSuccess) e = hipStreamWaitEvent(to, p->events[k], 0);
+  return e;
+}
+
+static void hash_mix(std::vector<uint64_t>& key, uint64_t v) { key.push_back(v); }
+
+int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
+                                int flags, lace_stream_t stream) {
+  if (!p || !jobs || n_jobs < 1) return LACE_EINVAL;
+  if (!device_ok(p)) return LACE_EINVAL;
+  if (flags & ~LACE_BATCH_GRAPH) return LACE_EINVAL;
+  std::vector<Layout> lay(n_jobs);
+  for (int k = 0; k < n_jobs; ++k) {
+    const lace_job& j = jobs[k];
+    int rc = check_common(p, j.cell, j.n_orb);
+    if (rc) return rc;
+    if (!j.psi_g || !j.w_g || !j.ws) return LACE_EINVAL;
+    if (!(j.s_thr >= 0.0 && j.s_thr < 1.0)) return LACE_EINVAL;
+    if (j.xi_g && j.sym != LACE_SYM_AVG && j.sym != LACE_SYM_UPPER &&
+        j.sym != LACE_SYM_LOWER)
+      return LACE_EINVAL;
+    lay[k] = layout_for(p, j.cell, j.n_orb, 0);
+    if (j.ws_bytes < lay[k].total) return LACE_ENOMEM;
+    for (int q = 0; q < k; ++q)
+      if (jobs[q].ws == j.ws || jobs[q].w_g == j.w_g) return LACE_EINVAL;
+  }
+  const bool fp64 = p->prec == LACE_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int ns = n_jobs < 8 ? n_jobs : 8;
+  hipError_t e = ensure_streams(p, ns);
+  if (e != hipSuccess) return LACE_EHIP;
+  // jobs to streams, largest first onto the least loaded stream
+  std::vector<int> order(n_jobs), on(n_jobs);
+  for (int k = 0; k < n_jobs; ++k) order[k] = k;
+  auto cost = [&](int k) {
+    const CellDev& c = p->cells[jobs[k].cell].dev;
+    return double(c.ng) * jobs[k].n_orb * jobs[k].n_orb;
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<double> load(ns, 0.0);
+  for (int k : order) {
+    int best = 0;
+    for (int q = 1; q < ns; ++q) if (load[q] < load[best]) best = q;
+    on[k] = best;
+    load[best] += cost(k);
+  }
+  // phase 1: grid orbitals and screening, eagerly
+  for (int q = 0; q < ns && e == hipSuccess; ++q) e = link(p, st, p->streams[q], q);
+  bool any_screen = false;
+  for (int k = 0; k < n_jobs && e == hipSuccess; ++k) {
+    const lace_job& j = jobs[k];
+    const CellDev& c = p->cells[j.cell].dev;
+    hipStream_t js = p->streams[on[k]];
+    e = launch_orbitals_to_grid(c, fp64, j.psi_g, j.n_orb, at(j.ws, lay[k].psi), js);
+    if (e == hipSuccess && j.s_thr > 0.0) {
+      any_screen = true;
+      e = enqueue_screen(p, c, j.n_orb, lay[k], j.ws,
+                         reinterpret_cast<double*>(at(j.ws, lay[k].s)), js);
+    }
+  }
+  if (e != hipSuccess) return LACE_EHIP;
+  std::vector<std::vector<PairArgs>> scheds(n_jobs);
+  {
+    std::vector<std::vector<double>> hs(n_jobs);
+    for (int k = 0; k < n_jobs && e == hipSuccess; ++k) {
+      if (jobs[k].s_thr > 0.0) {
+        hs[k].resize((size_t)jobs[k].n_orb * jobs[k].n_orb);
+        e = hipMemcpyAsync(hs[k].data(), at(jobs[k].ws, lay[k].s),
+                           sizeof(double) * hs[k].size(), hipMemcpyDeviceToHost,
+                           p->streams[on[k]]);
+      }
+    }
+    if (any_screen)
+      for (int q = 0; q < ns && e == hipSuccess; ++q)
+        e = hipStreamSynchronize(p->streams[q]);
+    if (e != hipSuccess) return LACE_EHIP;
+    for (int k = 0; k < n_jobs; ++k) {
+      std::vector<std::pair<int, int>> pairs;
+      if (jobs[k].s_thr > 0.0) kept_from_s(hs[k], jobs[k].n_orb, jobs[k].s_thr, pairs);
+      else all_pairs(jobs[k].n_orb, pairs);
+      jobs[k].n_kept = (int64_t)pairs.size();
+      build_schedule(pairs, jobs[k].n_orb, p->cells[jobs[k].cell].dev.ppb,
+                     scheds[k]);
+    }
+  }
+  // phase 2: pair pipelines, back-transforms, ACE builds
+  auto enqueue_phase2 = [&]() -> hipError_t {
+    hipError_t r = hipSuccess;
+    for (int k = 0; k < n_jobs && r == hipSuccess; ++k) {
+      const lace_job& j = jobs[k];
+      const CellPlan& cp = p->cells[j.cell];
+      hipStream_t js = p->streams[on[k]];
+      r = enqueue_exchange(p, cp.dev, j.n_orb, scheds[k], lay[k], j.ws, j.w_g,
+                           j.e_x, js, false);
+      if (r == hipSuccess && j.xi_g)
+        r = enqueue_build_ace(cp, j.n_orb, j.sym, lay[k], j.ws, j.psi_g, j.w_g,
+                              j.xi_g, j.m_out, j.ex_tr, js);
+    }
+    return r;
+  };
+  if (!(flags & LACE_BATCH_GRAPH)) {
+    e = enqueue_phase2();
+    for (int q = 0; q < ns && e == hipSuccess; ++q)
+      e = link(p, p->streams[q], st, q);
+    return hip_status(e);
+  }
+  // graph: key on everything the captured work depends on
+  std::vector<uint64_t> key;
+  hash_mix(key, (uint64_t)n_jobs);
+  for (int k = 0; k < n_jobs; ++k) {
+    const lace_job& j = jobs[k];
+    const CellDev& c = p->cells[j.cell].dev;
+    for (uint64_t v : {(uint64_t)j.cell, (uint64_t)(uintptr_t)j.psi_g,
+                       (uint64_t)j.n_orb, (uint64_t)(uintptr_t)j.w_g,
+                       (uint64_t)(uintptr_t)j.e_x, (uint64_t)j.sym,
+                       (uint64_t)(uintptr_t)j.xi_g, (uint64_t)(uintptr_t)j.m_out,
+                       (uint64_t)(uintptr_t)j.ex_tr, (uint64_t)(uintptr_t)j.ws,
+                       (uint64_t)on[k], (uint64_t)c.ppb, (uint64_t)c.use_plane,
+                       (uint64_t)scheds[k].size()})
+      hash_mix(key, v);
+    uint64_t h = 1469598103934665603ull;
+    for (const auto& b : scheds[k])
+      for (int q = 0; q < b.n; ++q) {
+        h = (h ^ (uint64_t)(b.i[q] * 65536 + b.j[q] + 1)) * 1099511628211ull;
+      }
+    hash_mix(key, h);
+  }
+  // the origin stream waits for phase 1 on every internal stream
+  for (int q = 0; q < ns && e == hipSuccess; ++q) e = link(p, p->streams[q], p->origin, q);
+  if (e != hipSuccess) return LACE_EHIP;
+  if (!p->graph.exec || p->graph.key != key) {
+    if (p->graph.exec) { (void)hipGraphExecDestroy(p->graph.exec); p->graph.exec = nullptr; }
+    if (p->graph.graph) { (void)hipGraphDestroy(p->graph.graph); p->graph.graph = nullptr; }
+    e = hipStreamBeginCapture(p->origin, hipStreamCaptureModeThreadLocal);
+    for (int q = 0; q < ns && e == hipSuccess; ++q)
+      e = link(p, p->origin, p->streams[q], ns);
+    hipError_t r = (e == hipSuccess) ? enqueue_phase2() : e;
+    for (int q = 0; q < ns && r == hipSuccess; ++q)
+      r = link(p, p->streams[q], p->origin, q);
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(p->origin, &g);
+    if (r != hipSuccess || ec != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return LACE_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return LACE_EHIP; }
+    p->graph.graph = g;
+    p->graph.exec = ex;
+    p->graph.key = key;
+  }
+  e = hipGraphLaunch(p->graph.exec, p->origin);
+  if (e == hipSuccess) e = link(p, p->origin, st, ns + 1);
+  return hip_status(e);
 }
 
 int lace_profile_enable(lace_plan* p, int enable) {

@@ -37,7 +37,10 @@ SYMBOLS = (
     "lace_screen", "lace_apply_exchange", "lace_build_ace", "lace_apply_ace",
     "lace_fft3d", "lace_get_info", "lace_status_string",
     "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
+    "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
+    "lace_autotune",
 )
+LACE_BATCH_GRAPH = 1
 
 
 class LaceUnavailable(RuntimeError):
@@ -54,6 +57,16 @@ class CellDesc(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("n", ctypes.c_int32),
                 ("rc", ctypes.c_double), ("n_pw", ctypes.c_int64),
                 ("miller", ctypes.POINTER(ctypes.c_int32))]
+
+
+class LaceJob(ctypes.Structure):
+    _fields_ = [("cell", ctypes.c_int32), ("psi_g", ctypes.c_void_p),
+                ("n_orb", ctypes.c_int32), ("s_thr", ctypes.c_double),
+                ("w_g", ctypes.c_void_p), ("e_x", ctypes.c_void_p),
+                ("n_kept", ctypes.c_int64), ("sym", ctypes.c_int32),
+                ("xi_g", ctypes.c_void_p), ("m_out", ctypes.c_void_p),
+                ("ex_tr", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("ws_bytes", ctypes.c_size_t)]
 
 
 _LIB = None
@@ -92,6 +105,16 @@ def load(path: str = LIB_PATH):
                                       p_i64, p_i64, p_i64]
     lib.lace_schedule_pairs.argtypes = [p_i32, p_i32, i64, i32, i32, p_i32,
                                         p_i64]
+    lib.lace_apply_exchange_batched.argtypes = [vp, ctypes.POINTER(LaceJob),
+                                                i32, i32, vp]
+    lib.lace_set_tuning.argtypes = [vp, i32, i32, i32]
+    lib.lace_get_tuning.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int),
+                                    ctypes.POINTER(ctypes.c_int)]
+    lib.lace_autotune.argtypes = [vp, i32, vp, i32, vp, sz, vp,
+                                  ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_int)]
     lib.lace_status_string.argtypes = [i32]
     lib.lace_status_string.restype = ctypes.c_char_p
     for name in SYMBOLS:
@@ -279,3 +302,73 @@ def lace_schedule_pairs(pairs, n_orb, per_batch):
                                       out.ctypes.data_as(P), ctypes.byref(nb)),
            "lace_schedule_pairs")
     return out, nb.value
+
+
+def _vp(t):
+    return None if t is None else t.data_ptr()
+
+
+def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
+    """``jobs``: list of dicts with cell, psi_g, n_orb, s_thr, w_g and
+    optional e_x, sym, xi_g, m_out, ex_tr, plus ws (torch tensors).
+    Returns the kept pair count of each job."""
+    import torch
+    arr = (LaceJob * len(jobs))()
+    for k, j in enumerate(jobs):
+        for name in ("psi_g", "w_g", "xi_g", "m_out"):
+            t = j.get(name)
+            if t is not None:
+                _ptr(t, torch.complex128, name)
+        for name in ("e_x", "ex_tr"):
+            t = j.get(name)
+            if t is not None:
+                _ptr(t, torch.float64, name)
+        _ptr(j["ws"], None, "ws")
+        arr[k].cell = int(j.get("cell", 0))
+        arr[k].psi_g = _vp(j["psi_g"])
+        arr[k].n_orb = int(j["n_orb"])
+        arr[k].s_thr = float(j.get("s_thr", 0.0))
+        arr[k].w_g = _vp(j["w_g"])
+        arr[k].e_x = _vp(j.get("e_x"))
+        arr[k].sym = SYM_MODES.get(j.get("sym", "avg"), 0) \
+            if isinstance(j.get("sym", "avg"), str) else int(j["sym"])
+        arr[k].xi_g = _vp(j.get("xi_g"))
+        arr[k].m_out = _vp(j.get("m_out"))
+        arr[k].ex_tr = _vp(j.get("ex_tr"))
+        arr[k].ws = _vp(j["ws"])
+        arr[k].ws_bytes = j["ws"].numel() * j["ws"].element_size()
+    _check(load().lace_apply_exchange_batched(
+        plan.handle, arr, len(jobs), LACE_BATCH_GRAPH if graph else 0,
+        _stream(stream)), "lace_apply_exchange_batched")
+    return [arr[k].n_kept for k in range(len(jobs))]
+
+
+def lace_set_tuning(plan, cell, pairs_per_batch, use_plane):
+    _check(load().lace_set_tuning(plan.handle, cell, int(pairs_per_batch),
+                                  int(use_plane)), "lace_set_tuning")
+
+
+def lace_get_tuning(plan, cell):
+    ppb = ctypes.c_int()
+    pl = ctypes.c_int()
+    _check(load().lace_get_tuning(plan.handle, cell, ctypes.byref(ppb),
+                                  ctypes.byref(pl)), "lace_get_tuning")
+    return ppb.value, pl.value
+
+
+def lace_autotune(plan, cell, psi_g, n_orb, ws, stream=None):
+    """Time every pipeline candidate on this cell, keep the fastest.
+    Returns a list of (pairs_per_batch, use_plane, us_per_pair)."""
+    import torch
+    cap = 16
+    ppb = (ctypes.c_int * cap)()
+    pl = (ctypes.c_int * cap)()
+    us = (ctypes.c_double * cap)()
+    n = ctypes.c_int(cap)
+    _check(load().lace_autotune(plan.handle, cell,
+                                _ptr(psi_g, torch.complex128, "psi_g"), n_orb,
+                                _ptr(ws, None, "ws"),
+                                ws.numel() * ws.element_size(),
+                                _stream(stream), ppb, pl, us,
+                                ctypes.byref(n)), "lace_autotune")
+    return [(ppb[k], pl[k], us[k]) for k in range(min(n.value, cap))]
