@@ -145,6 +145,88 @@ def cpu_baseline(inp, n_sample_orb=12):
                         f"{dt:.1f} s"))
 
 
+def batched_rows(torch, seed, steps):
+    """The 16-cell batched workload: 4 cells of each of 48^3/32, 64^3/64,
+    80^3/96, 96^3/128 localized orbitals, S_thr = 1e-3, all in one call;
+    autotuned per class; eager streams and the replayed HIP graph."""
+    import synth
+    from paper_1801_09263_amd import lace
+    from paper_1801_09263_amd.batch import MultiCell
+    cells = synth.make_batch_cells(seed)
+    mc = MultiCell(cells, [c["coeffs"].shape[0] for c in cells],
+                   lace.LACE_FP32)
+    for k, c in enumerate(cells):
+        mc.set_orbitals(k, c["coeffs"])
+    tuned = {}
+    for k, c in enumerate(cells):
+        key = (c["n"], c["coeffs"].shape[0])
+        if key not in tuned:
+            cands = mc.autotune(k)
+            tuned[key] = lace.lace_get_tuning(mc.plan, k) + (
+                min(t for _, _, t in cands),)
+        lace.lace_set_tuning(mc.plan, k, tuned[key][0], tuned[key][1])
+    st = torch.cuda.Stream()
+    out = {}
+    for mode in ("eager", "graph"):
+        with torch.cuda.stream(st):
+            mc.run(graph=(mode == "graph"), stream=st)
+            st.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                mc.run(graph=(mode == "graph"), stream=st)
+            st.synchronize()
+            out[mode] = (time.perf_counter() - t0) / steps
+    kept = sum(mc.n_kept)
+    total = sum(n * (n + 1) // 2 for n in mc.n_orbs)
+    res = dict(
+        cells=len(cells), kept_pairs=kept, total_pairs=total,
+        ms_eager=round(out["eager"] * 1e3, 1),
+        ms_graph=round(out["graph"] * 1e3, 1),
+        pair_ffts_per_s_eager=round(kept / out["eager"], 1),
+        pair_ffts_per_s_graph=round(kept / out["graph"], 1),
+        tuning={f"{n}^3/{no}": dict(pairs_per_batch=t[0], use_plane=t[1],
+                                   us_per_pair=round(t[2], 2))
+                for (n, no), t in tuned.items()},
+        kept_fraction_by_class={})
+    for k, c in enumerate(cells[:4]):
+        n = mc.n_orbs[k]
+        res["kept_fraction_by_class"][f"{c['n']}^3/{n}"] = round(
+            mc.n_kept[k] / (n * (n + 1) / 2), 3)
+    mc.close()
+    return res
+
+
+def serving_rows(torch, seed, n_jobs):
+    """Poisson stream at 40 jobs/s: 95% of jobs from the four batched cell
+    classes, 5% localized 120^3 cells, 4 outer iterations each."""
+    import synth
+    from paper_1801_09263_amd import lace
+    from paper_1801_09263_amd.serving import Job, JobClass, Server, summarize
+    raw = synth.serving_classes(seed)
+    classes = []
+    for c in raw:
+        pool = [torch.tensor(v, device="cuda") for v in c["variants"]]
+        cell = {k: c[k] for k in ("L", "n", "miller", "s_thr", "rc")}
+        classes.append(JobClass(c["name"], cell, c["n_orb"], pool))
+    spec = synth.serving_stream(n_jobs, 4, [len(c.pool) for c in classes],
+                                rate=synth.SERVE_RATE, seed=seed)
+    srv = Server(classes, lace.LACE_FP32, n_slots=4)
+    # one warm-up job per class (allocator, code objects)
+    srv.run([Job(-1 - k, 0.0, k, [0]) for k in range(len(classes))])
+    jobs = srv.run([Job(j, t, c, v) for j, t, c, v in spec])
+    srv.close()
+    res = summarize(jobs, synth.SERVE_RATE)
+    res = {k: (round(v, 4) if isinstance(v, float) else v)
+           for k, v in res.items()}
+    res["slots"] = 4
+    res["large_jobs"] = sum(1 for j in jobs if j.cls == 4)
+    res["note"] = ("finite stream of J jobs; one GPU is oversubscribed at "
+                   "40 jobs/s, so latency grows with J")
+    del classes
+    torch.cuda.empty_cache()
+    return res
+
+
 def pmc_sample(torch, seed):
     """Fixed small workload for counter collection: a plain 1 GiB device
     copy (the calibration of FETCH_SIZE / WRITE_SIZE), then one exchange
@@ -180,6 +262,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU oracle baseline")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 16-cell batched row")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving stream row")
+    ap.add_argument("--serve-jobs", type=int, default=48,
+                    help="jobs in the serving stream")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="small fixed run for hardware-counter passes: a "
                          "1 GiB copy (calibration) and 4 pair batches of "
@@ -276,6 +364,16 @@ def main():
         compare["lace_fp32_vs_plain_fp64_step_speedup"] = round(
             compare["plain_fp64"]["step_ms"] / (t_step * 1e3), 3)
     copy_gbs = copy_bandwidth(torch)
+    batched = None
+    if not args.no_batched:
+        log("16-cell batched workload")
+        batched = batched_rows(torch, args.seed, max(1, args.steps))
+        log("batched", batched)
+    serving = None
+    if not args.no_serve:
+        log(f"serving stream of {args.serve_jobs} jobs")
+        serving = serving_rows(torch, args.seed, args.serve_jobs)
+        log("serving", serving)
 
     cpu = None
     if not args.no_cpu:
@@ -311,6 +409,8 @@ def main():
         "roofline": roofline,
         "copy_GBs_measured": round(copy_gbs, 1),
         "compare": compare,
+        "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -18,4 +18,8 @@ from .generators import (  # noqa: F401
     gaussian_params,
     orbitals_from_params,
     poisson_arrivals,
+    serving_classes,
+    serving_stream,
+    SERVE_RATE,
+    SERVE_STEPS,
 )

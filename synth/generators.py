@@ -187,3 +187,60 @@ def make_batch_cells(seed: int = 0, classes=None, cells_per_class: int = 4):
 def poisson_arrivals(rate: float, n_jobs: int, rng: np.random.Generator):
     """Arrival times (s) of a Poisson stream: cumulative exponential gaps."""
     return np.cumsum(rng.exponential(1.0 / rate, size=n_jobs))
+
+
+# Serving stream: the four batched cell classes plus the localized 120^3 cell.
+SERVE_RATE = 40.0
+SERVE_STEPS = 4
+SERVE_LARGE_FRACTION = 0.05
+
+
+def serving_classes(seed: int = 0, n_variants: int = 4,
+                    n_variants_large: int = 2, include_large: bool = True,
+                    specs=None):
+    """Size classes of the serving stream.  Each class holds a few orbital
+    sets that follow one another as synthetic outer iterations: Gaussian
+    centres move by 0.02 z bohr and widths scale by (1 + 0.01 z) from one
+    set to the next, then Loewdin.  Returns dicts with the cell fields and
+    `variants` (list of (n_orb, n_pw) arrays)."""
+    if specs is None:
+        specs = [(L, n, n_orb) for (L, n, n_orb) in BATCH_CLASSES]
+        if include_large:
+            specs.append((23.5, 120, 256))
+    out = []
+    for k, (L, n, n_orb) in enumerate(specs):
+        miller = miller_sphere(L, BATCH_ECUT)
+        pos, widths = gaussian_params(L, n_orb, n_orb // 2,
+                                      rng_for(4, k, 0, 0, seed))
+        nv = n_variants_large if n == 120 else n_variants
+        variants = []
+        for v in range(nv):
+            if v > 0:
+                pos, widths = perturb_gaussian_params(
+                    pos, widths, rng_for(4, k, 0, v, seed))
+            variants.append(orbitals_from_params(miller, L, pos, widths))
+        out.append(dict(name=f"serve-{int(L)}-{n}-{n_orb}", L=L, n=n,
+                        ecut=BATCH_ECUT, miller=miller, s_thr=BATCH_S_THR,
+                        rc=L / 2.0, n_orb=n_orb, variants=variants))
+    return out
+
+
+def serving_stream(n_jobs: int, n_small_classes: int, n_variants,
+                   rate: float = SERVE_RATE, n_steps: int = SERVE_STEPS,
+                   large_fraction: float = SERVE_LARGE_FRACTION,
+                   seed: int = 0):
+    """Job list of a Poisson stream: (job id, arrival s, class, variant of
+    each outer step).  A fraction `large_fraction` of the jobs use class
+    `n_small_classes` (the large cell), the rest a uniform small class.
+    `n_variants[c]` is the number of orbital sets of class c."""
+    rng = rng_for(4, 99, 0, 0, seed)
+    arrivals = poisson_arrivals(rate, n_jobs, rng)
+    jobs = []
+    for j in range(n_jobs):
+        large = large_fraction > 0 and rng.random() < large_fraction
+        cls = n_small_classes if large else int(rng.integers(n_small_classes))
+        nv = n_variants[cls]
+        start = int(rng.integers(nv))
+        jobs.append((j, float(arrivals[j]), cls,
+                     [(start + s) % nv for s in range(n_steps)]))
+    return jobs
