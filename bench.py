@@ -42,22 +42,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# grids moved per pair by each pass of the fused pipeline (algorithmic):
-#   A reads psi_i, psi_j, writes the pair buffer; B reads and writes it;
-#   C reads it and psi_i, psi_j and read-modify-writes W_i, W_j.
-# A diagonal pair reads psi_i once and touches W_i only.
-GRIDS_OFF = (3, 2, 7)
-GRIDS_DIAG = (2, 2, 4)
+# Algorithmic bytes of each pass come from the library (lace_profile_read):
+# per transform slot with o distinct orbitals, pass A moves o G + U (read the
+# orbitals, write the pair buffer), pass B 2 U, pass C U + 3 o G (read the
+# buffer and the orbitals, read and write their W); U = one complex grid,
+# G = one orbital grid (U, or U / 2 for real orbitals).
 PASS_NAMES = ("pair-product+xy-forward", "z-forward*v*z-backward",
               "xy-backward+accumulate")
 
 
-def pass_roofline(prof, grid_bytes):
+def pass_roofline(prof):
     rows = []
     for k in range(3):
         ms = prof["ms"][k]
-        nbytes = (GRIDS_OFF[k] * prof["pairs_off"][k]
-                  + GRIDS_DIAG[k] * prof["pairs_diag"][k]) * grid_bytes
+        nbytes = prof["alg_bytes"][k]
         launches = max(prof["launches"][k], 1)
         gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         rows.append(dict(name=PASS_NAMES[k], ms_total=ms,
@@ -154,7 +152,7 @@ def batched_rows(torch, seed, steps):
     from paper_1801_09263_amd.batch import MultiCell
     cells = synth.make_batch_cells(seed)
     mc = MultiCell(cells, [c["coeffs"].shape[0] for c in cells],
-                   lace.LACE_FP32)
+                   lace.LACE_FP32_GAMMA)
     for k, c in enumerate(cells):
         mc.set_orbitals(k, c["coeffs"])
     tuned = {}
@@ -210,7 +208,7 @@ def serving_rows(torch, seed, n_jobs):
         classes.append(JobClass(c["name"], cell, c["n_orb"], pool))
     spec = synth.serving_stream(n_jobs, 4, [len(c.pool) for c in classes],
                                 rate=synth.SERVE_RATE, seed=seed)
-    srv = Server(classes, lace.LACE_FP32, n_slots=4)
+    srv = Server(classes, lace.LACE_FP32_GAMMA, n_slots=4)
     # one warm-up job per class (allocator, code objects)
     srv.run([Job(-1 - k, 0.0, k, [0]) for k in range(len(classes))])
     jobs = srv.run([Job(j, t, c, v) for j, t, c, v in spec])
@@ -243,7 +241,7 @@ def pmc_sample(torch, seed):
     del x, y
     inp = synth.make_config_inputs(2, seed=seed)
     n_orb = inp["coeffs"].shape[0]
-    sess = CellSession(inp, n_orb, lace.LACE_FP32)
+    sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA)
     sess.set_orbitals(inp["coeffs"])
     # 128 disjoint-friendly pairs: two round-robin rounds of 64 each
     pairs = [(i, i + 128) for i in range(128)]
@@ -294,9 +292,13 @@ def main():
     log("generating the localized 120^3 workload")
     inp = synth.make_config_inputs(2, seed=args.seed)
     n_orb = inp["coeffs"].shape[0]
-    ng = inp["n"] ** 3
-    sess = CellSession(inp, n_orb, lace.LACE_FP32, n_vec=n_orb)
+    sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA, n_vec=n_orb)
     sess.set_orbitals(inp["coeffs"])
+    real_dev = sess.check_real()
+    log(f"orbitals real to {real_dev:.1e}; autotuning the pair pipeline")
+    cands = lace.lace_autotune(sess.plan, 0, sess.psi, n_orb, sess.ws)
+    tuning = lace.lace_get_tuning(sess.plan, 0)
+    log("tuning", tuning, cands)
     log(f"timing {args.steps} steps after {args.warmup} warmup")
     n_kept, t_step, prof = time_steps(torch, sess, inp["s_thr"], args.steps,
                                       args.warmup, profile=True)
@@ -310,7 +312,7 @@ def main():
         f"exchange {t_exch * 1e3:.1f} ms")
 
     # roofline of the dominant kernel of the pair pipeline
-    rows = pass_roofline(prof, ng * 8)
+    rows = pass_roofline(prof)
     dom = max(range(3), key=lambda k: rows[k]["ms_total"])
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
@@ -323,9 +325,7 @@ def main():
             # counter sample, applied to this run's mean launch
             traffic = round(ps["ratio"] * rows[dom]["bytes_per_launch"], 0)
     pipe_ms = sum(prof["ms"])
-    pipe_bytes = sum((GRIDS_OFF[k] * prof["pairs_off"][k]
-                      + GRIDS_DIAG[k] * prof["pairs_diag"][k]) * ng * 8
-                     for k in range(3))
+    pipe_bytes = sum(prof["alg_bytes"])
     roofline = dict(
         bound="hbm", kernel=rows[dom]["name"],
         achieved=round(rows[dom]["achieved_GBs"], 1), peak=HBM_PEAK_GBS,
@@ -345,6 +345,17 @@ def main():
     compare = None
     if not args.no_compare:
         compare = {}
+        log("same localized workload on the complex FP32 path")
+        s2 = CellSession(inp, n_orb, lace.LACE_FP32, n_vec=n_orb)
+        s2.set_orbitals(inp["coeffs"])
+        n2, t2 = time_exchange(torch, s2, inp["s_thr"])
+        _, ts2, _ = time_steps(torch, s2, inp["s_thr"], 1, 0)
+        compare["lace_fp32_complex"] = dict(
+            pairs=n2, exchange_ms=round(t2 * 1e3, 1),
+            step_ms=round(ts2 * 1e3, 1), pair_ffts_per_s=round(n2 / ts2, 1))
+        s2.close()
+        del s2
+        torch.cuda.empty_cache()
         log("plain unscreened 120^3 random orbitals (FP64 and FP32 pairs)")
         inp1 = synth.make_config_inputs(1, seed=args.seed)
         for name, prec in (("plain_fp64", lace.LACE_FP64),
@@ -398,12 +409,16 @@ def main():
             "workload": "lace-120: L=23.5 bohr cubic cell, 120^3 grid, "
                         "Ecut=40 Ha (156795 plane waves), 256 Gaussian "
                         "orbitals on 128 centres, Loewdin, S_thr=1e-3; FP32 "
-                        "pairs/FFTs, FP64 screening, M, Cholesky, xi",
+                        "pairs/FFTs (real-orbital packing), FP64 screening "
+                        "sums, energies, M, Cholesky, xi",
             "kept_pairs": n_kept, "total_pairs": n_total,
             "kept_fraction": round(n_kept / n_total, 4),
             "exchange_ms": round(t_exch * 1e3, 1),
             "exchange_pair_ffts_per_s": round(n_kept / t_exch, 1),
             "e_x": e_x, "e_x_trace": ex_tr, "cholesky_info": info,
+            "orbitals": "real (Gamma point), checked to %.1e; two pair "
+                        "densities per complex FFT" % real_dev,
+            "tuning": {"pairs_per_batch": tuning[0], "use_plane": tuning[1]},
             "parallelism": "1 GPU",
         },
         "roofline": roofline,

@@ -61,8 +61,15 @@ enum {
 
 typedef enum {
   LACE_FP64 = 0,  /* grids, FFTs and pair products in FP64 */
-  LACE_FP32 = 1   /* grids, FFTs and pair products in FP32; screening sums,
+  LACE_FP32 = 1,  /* grids, FFTs and pair products in FP32; screening sums,
                      exchange-energy sums, M, Cholesky, xi in FP64 */
+  /* Real orbitals (Gamma point: C_{-G} = conj(C_G) for every orbital; the
+   * caller guarantees it, lace_check_real measures it).  Orbitals and W are
+   * stored as real grids and two pair densities of the same kind share one
+   * complex transform (rho_ij + i rho_kl: the potentials come back as real
+   * and imaginary parts), halving the transforms and the grid traffic. */
+  LACE_FP64_GAMMA = 2,
+  LACE_FP32_GAMMA = 3
 } lace_precision;
 
 typedef enum {
@@ -87,8 +94,9 @@ typedef struct lace_plan lace_plan; /* opaque */
  * sphere-to-grid map, the kernel table v(G) (evaluated in FP64, stored in
  * the plan precision) and FFT twiddles.  Synchronous.  *out is set only on
  * success.  Errors: EINVAL (null pointers, n_cells < 1, L <= 0, n_pw < 1,
- * duplicate Miller triples), EUNSUPPORTED (grid size, sphere outside the
- * grid), ENOMEM, EHIP. */
+ * duplicate Miller triples; for the Gamma precisions, a triple m whose -m
+ * is not in the list), EUNSUPPORTED (grid size, sphere outside the grid),
+ * ENOMEM, EHIP. */
 int lace_plan_create(const lace_cell_desc* cells, int n_cells,
                      lace_precision prec, lace_plan** out);
 
@@ -241,12 +249,25 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
  *   2  pass C: backward transform along y and x + accumulation into W.
  * lace_profile_enable(plan, 1) clears the totals and starts recording,
  * (plan, 0) stops.  lace_profile_read synchronizes the device and returns
- * per pass: total milliseconds ms[3], launches (batches) launches[3],
- * diagonal and off-diagonal pairs processed pairs_diag[3], pairs_off[3].
- * Arrays are host memory of 3 elements; any may be NULL. */
+ * per pass: total milliseconds ms[3], launches (batches) launches[3], pairs
+ * processed pairs[3], and algorithmic HBM bytes alg_bytes[3].  With U the
+ * bytes of one complex grid, G those of one orbital grid (U, or U/2 for
+ * real orbitals) and o the distinct orbitals of a transform slot, a slot
+ * moves o G + U in pass A (read the orbitals, write the pair buffer), 2 U
+ * in pass B, and U + 3 o G in pass C (read the buffer and the orbitals,
+ * read and write their W).  Arrays are host memory of 3 elements; any may
+ * be NULL. */
 int lace_profile_enable(lace_plan* plan, int enable);
 int lace_profile_read(lace_plan* plan, double* ms, int64_t* launches,
-                      int64_t* pairs_diag, int64_t* pairs_off);
+                      int64_t* pairs, double* alg_bytes);
+
+/* Reality of the orbitals for the Gamma precisions: returns in *rel_dev
+ * sqrt(sum |C_m - conj(C_{-m})|^2 / sum |C_m|^2) over all orbitals (0 for
+ * real orbitals up to rounding).  Synchronizes the stream.  EINVAL if the
+ * plan is not a Gamma plan. */
+int lace_check_real(lace_plan* plan, int cell, const void* psi_g, int n_orb,
+                    void* ws, size_t ws_bytes, lace_stream_t stream,
+                    double* rel_dev);
 
 /* Static text for a status code. */
 const char* lace_status_string(int status);

@@ -29,6 +29,7 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
 // MODE 0: complex, op(A) = conj(A), op(B) = B (complex128 inputs)
 // MODE 1: real, op = |.| of float2 inputs (computed in FP64)
 // MODE 2: real, op = |.| of double2 inputs
+// MODE 3, 4: real, op = |.| of float / double inputs (real grids)
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 output,
 // each wave a 32 x 32 block (2 x 2 MFMA tiles).  K staged through LDS in
 // chunks of 16 with coalesced row loads.
@@ -56,6 +57,19 @@ template <> struct IpLoad<2> {
                                     double& im) {
     const double2 v = static_cast<const double2*>(p)[off];
     re = sqrt(v.x * v.x + v.y * v.y); im = 0.0;
+  }
+};
+
+template <> struct IpLoad<3> {
+  __device__ static inline void get(const void* p, int64_t off, double& re,
+                                    double& im) {
+    re = fabs(double(static_cast<const float*>(p)[off])); im = 0.0;
+  }
+};
+template <> struct IpLoad<4> {
+  __device__ static inline void get(const void* p, int64_t off, double& re,
+                                    double& im) {
+    re = fabs(static_cast<const double*>(p)[off]); im = 0.0;
   }
 };
 
@@ -227,6 +241,16 @@ hipError_t launch_gemm_ip_abs(bool fp64, const void* A, int64_t lda, int na,
   return fp64 ? gemm_ip<2>(A, lda, na, A, lda, na, K, scale, out, part,
                            part_bytes, st)
               : gemm_ip<1>(A, lda, na, A, lda, na, K, scale, out, part,
+                           part_bytes, st);
+}
+
+hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
+                                   int na, int64_t K, double scale,
+                                   double* out, void* part, int64_t part_bytes,
+                                   hipStream_t st) {
+  return fp64 ? gemm_ip<4>(A, lda, na, A, lda, na, K, scale, out, part,
+                           part_bytes, st)
+              : gemm_ip<3>(A, lda, na, A, lda, na, K, scale, out, part,
                            part_bytes, st);
 }
 

@@ -77,6 +77,58 @@ template <typename T> struct EpiAcc {
   }
 };
 
+// Real orbitals, packed slot: value rho_ij + i rho_kl.
+template <typename T> struct ProQuad {
+  const T* __restrict__ psi;
+  int64_t gs;
+  QuadArgs qa;
+  __device__ C<T> get(int g, int slot) const {
+    const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    const T a = psi[i * gs + g] * psi[j * gs + g];
+    T b = T(0);
+    if (k >= 0) b = psi[k * gs + g] * psi[l * gs + g];
+    return mk<T>(a, b);
+  }
+};
+template <typename T> struct QuadPre {
+  T pi, pj, pk, pl, wi, wj, wk, wl;
+};
+// V = V_ij + i V_kl (both real):  W_j -= psi_i V_ij, W_i -= psi_j V_ij,
+// W_l -= psi_k V_kl, W_k -= psi_l V_kl (one update for a diagonal pair).
+template <typename T> struct EpiAccQuad {
+  using Pre = QuadPre<T>;
+  const T* __restrict__ psi;
+  T* __restrict__ w;
+  int64_t gs;
+  QuadArgs qa;
+  __device__ void pre(int g, int slot, Pre& r) const {
+    const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    r.pi = psi[i * gs + g];
+    r.wj = w[j * gs + g];
+    if (i != j) {
+      r.pj = psi[j * gs + g];
+      r.wi = w[i * gs + g];
+    }
+    if (k >= 0) {
+      r.pk = psi[k * gs + g];
+      r.wl = w[l * gs + g];
+      if (k != l) {
+        r.pl = psi[l * gs + g];
+        r.wk = w[k * gs + g];
+      }
+    }
+  }
+  __device__ void put(int g, int slot, C<T> v, const Pre& r) const {
+    const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    w[j * gs + g] = r.wj - r.pi * v.x;
+    if (i != j) w[i * gs + g] = r.wi - r.pj * v.x;
+    if (k >= 0) {
+      w[l * gs + g] = r.wl - r.pk * v.y;
+      if (k != l) w[k * gs + g] = r.wk - r.pl * v.y;
+    }
+  }
+};
+
 template <typename T, int N, int NT>
 __device__ inline void load_tw(C<T>* tw, const C<T>* tw_g) {
   for (int m = threadIdx.x; m < N; m += NT) tw[m] = tw_g[m];
@@ -424,6 +476,48 @@ template <typename T, int N> struct Engine {
     return err;
   }
 
+  // Packed slots of real orbitals: same passes, real grids in and out.
+  static hipError_t quad_batch(const CellDev& c, const QuadArgs& qa,
+                               const T* psi, T* w, C<T>* tmp, double* epart,
+                               hipStream_t st, hipEvent_t* ev) {
+    const C<T>* tw = static_cast<const C<T>*>(c.tw);
+    const int cnt = qa.n;
+    ProQuad<T> pp{psi, NG, qa};
+    ProGrid<T> pt{tmp, NG};
+    EpiGrid<T> et{tmp, NG, T(1)};
+    EpiAccQuad<T> ea{psi, w, NG, qa};
+    // energy weights: both pairs of a slot are of the same kind
+    PairArgs pw;
+    pw.n = cnt;
+    for (int q = 0; q < cnt; ++q) { pw.i[q] = qa.i[q]; pw.j[q] = qa.j[q]; }
+    const bool use_plane = Cf::plane && c.use_plane;
+    hipError_t err;
+    if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
+    if (use_plane) {
+      err = plane<-1>(pp, et, cnt, tw, st);
+    } else {
+      err = xlines<-1>(pp, et, cnt, tw, st);
+      if (err == hipSuccess) err = cols<1, -1>(pt, et, cnt, tw, st);
+    }
+    if (err != hipSuccess) return err;
+    if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
+    const int ntiles = N * (N / Cf::TX);
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::NT_COLS>), dim3(ntiles * cnt),
+                       dim3(Cf::NT_COLS), 0, st, tmp, NG,
+                       static_cast<const T*>(c.vtab), pw, epart, ntiles, tw);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
+    if (use_plane) {
+      err = plane<+1>(pt, ea, cnt, tw, st);
+    } else {
+      err = cols<1, +1>(pt, et, cnt, tw, st);
+      if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
+    }
+    if (err == hipSuccess && ev) err = hipEventRecord(ev[3], st);
+    return err;
+  }
+
   static int64_t tiles() { return (int64_t)N * (N / Cf::TX); }
 };
 
@@ -582,6 +676,205 @@ hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,
                              double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, part, count,
                      factor, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------ real (Gamma-point) orbitals
+// grid p <- C_{2p} + i C_{2p+1} on the sphere (zero elsewhere)
+template <typename T>
+__global__ void k_scatter_pairs(const double2* coeffs, int64_t n_pw,
+                                const int32_t* gidx, C<T>* z, int64_t gs,
+                                int n_orb) {
+  const int npair = (n_orb + 1) / 2;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t total = n_pw * npair;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t p = k / n_pw, m = k % n_pw;
+    const double2 a = coeffs[(2 * p) * n_pw + m];
+    double2 b = make_double2(0.0, 0.0);
+    if (2 * p + 1 < n_orb) b = coeffs[(2 * p + 1) * n_pw + m];
+    z[p * gs + gidx[m]] = mk<T>(T(a.x - b.y), T(a.y + b.x));
+  }
+}
+
+// psi_{2p} <- Re z_p, psi_{2p+1} <- Im z_p
+template <typename T>
+__global__ void k_split_real(const C<T>* z, int64_t gs, T* psi, int n_orb) {
+  const int npair = (n_orb + 1) / 2;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t total = gs * npair;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t p = k / gs, g = k % gs;
+    const C<T> v = z[k];
+    psi[(2 * p) * gs + g] = v.x;
+    if (2 * p + 1 < n_orb) psi[(2 * p + 1) * gs + g] = v.y;
+  }
+}
+
+// z_p <- W_{2p} + i W_{2p+1}
+template <typename T>
+__global__ void k_pack_real(const T* w, int64_t gs, int n_orb, C<T>* z) {
+  const int npair = (n_orb + 1) / 2;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t total = gs * npair;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t p = k / gs, g = k % gs;
+    const T a = w[(2 * p) * gs + g];
+    const T b = (2 * p + 1 < n_orb) ? w[(2 * p + 1) * gs + g] : T(0);
+    z[k] = mk<T>(a, b);
+  }
+}
+
+// Unpack two real transforms: with Z = F[W_a + i W_b],
+// F[W_a](G) = (Z(G) + conj Z(-G)) / 2, F[W_b](G) = (Z(G) - conj Z(-G)) / 2i.
+template <typename T>
+__global__ void k_gather_pairs(const C<T>* z, int64_t gs, const int32_t* gidx,
+                               const int32_t* negidx, int64_t n_pw, int n_orb,
+                               double scale, double2* out) {
+  const int npair = (n_orb + 1) / 2;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t total = n_pw * npair;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t p = k / n_pw, m = k % n_pw;
+    const C<T> a = z[p * gs + gidx[m]];
+    const C<T> b = z[p * gs + gidx[negidx[m]]];
+    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+    out[(2 * p) * n_pw + m] =
+        make_double2(0.5 * scale * (ax + bx), 0.5 * scale * (ay - by));
+    if (2 * p + 1 < n_orb)
+      out[(2 * p + 1) * n_pw + m] =
+          make_double2(0.5 * scale * (ay + by), -0.5 * scale * (ax - bx));
+  }
+}
+
+static unsigned grid_for(int64_t total) {
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)blocks;
+}
+
+template <typename T>
+static hipError_t orb_to_grid_real_t(const CellDev& c, const void* coeffs,
+                                     int n_orb, void* psi, void* scratch,
+                                     hipStream_t st) {
+  const int npair = (n_orb + 1) / 2;
+  hipError_t err = launch_zero(scratch, (int64_t)npair * c.ng * sizeof(C<T>), st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_scatter_pairs<T>), dim3(grid_for(c.n_pw * npair)),
+                     dim3(256), 0, st, static_cast<const double2*>(coeffs),
+                     c.n_pw, c.gidx, static_cast<C<T>*>(scratch), c.ng, n_orb);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  err = fft3d_t<T>(c, +1, scratch, npair, T(1.0 / std::sqrt(c.omega)), st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_split_real<T>), dim3(grid_for(c.ng * npair)), dim3(256),
+                     0, st, static_cast<const C<T>*>(scratch), c.ng,
+                     static_cast<T*>(psi), n_orb);
+  return hipGetLastError();
+}
+
+hipError_t launch_orbitals_to_grid_real(const CellDev& c, bool fp64,
+                                        const void* coeffs, int n_orb,
+                                        void* psi, void* scratch,
+                                        hipStream_t st) {
+  return fp64 ? orb_to_grid_real_t<double>(c, coeffs, n_orb, psi, scratch, st)
+              : orb_to_grid_real_t<float>(c, coeffs, n_orb, psi, scratch, st);
+}
+
+template <typename T>
+static hipError_t grid_to_pw_real_t(const CellDev& c, const void* w, int n_orb,
+                                    void* scratch, void* w_pw, hipStream_t st) {
+  const int npair = (n_orb + 1) / 2;
+  hipLaunchKernelGGL((k_pack_real<T>), dim3(grid_for(c.ng * npair)), dim3(256),
+                     0, st, static_cast<const T*>(w), c.ng, n_orb,
+                     static_cast<C<T>*>(scratch));
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  err = fft3d_t<T>(c, -1, scratch, npair, T(1), st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_gather_pairs<T>), dim3(grid_for(c.n_pw * npair)),
+                     dim3(256), 0, st, static_cast<const C<T>*>(scratch), c.ng,
+                     c.gidx, c.negidx, c.n_pw, n_orb,
+                     std::sqrt(c.omega) / double(c.ng),
+                     static_cast<double2*>(w_pw));
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64,
+                                  const void* w_real, int n_orb, void* scratch,
+                                  void* w_pw, hipStream_t st) {
+  return fp64 ? grid_to_pw_real_t<double>(c, w_real, n_orb, scratch, w_pw, st)
+              : grid_to_pw_real_t<float>(c, w_real, n_orb, scratch, w_pw, st);
+}
+
+template <typename T>
+static hipError_t quad_batch_t(const CellDev& c, const QuadArgs& qa,
+                               const void* psi, void* w, void* tmp,
+                               double* epart, hipStream_t st, hipEvent_t* ev) {
+  switch (c.n) {
+#define X(NN)                                                              \
+  case NN:                                                                 \
+    return Engine<T, NN>::quad_batch(c, qa, static_cast<const T*>(psi),    \
+                                     static_cast<T*>(w),                   \
+                                     static_cast<C<T>*>(tmp), epart, st, ev);
+    LACE_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
+                             const void* psi, void* w, void* tmp,
+                             double* epart, hipStream_t st, hipEvent_t* ev) {
+  if (qa.n <= 0) return hipSuccess;
+  return fp64 ? quad_batch_t<double>(c, qa, psi, w, tmp, epart, st, ev)
+              : quad_batch_t<float>(c, qa, psi, w, tmp, epart, st, ev);
+}
+
+// per block: sum |C_m - conj C_{-m}|^2 and sum |C_m|^2 over its share
+__global__ void k_real_check(const double2* coeffs, int64_t n_pw, int n_orb,
+                             const int32_t* negidx, double* part) {
+  __shared__ double red[2][4];
+  double d = 0.0, t = 0.0;
+  const int64_t total = n_pw * n_orb;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
+       k += stride) {
+    const int64_t j = k / n_pw, m = k % n_pw;
+    const double2 a = coeffs[k];
+    const double2 b = coeffs[j * n_pw + negidx[m]];
+    const double dx = a.x - b.x, dy = a.y + b.y;
+    d += dx * dx + dy * dy;
+    t += a.x * a.x + a.y * a.y;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    d += __shfl_xor(d, o, 64);
+    t += __shfl_xor(t, o, 64);
+  }
+  if (threadIdx.x % 64 == 0) {
+    red[0][threadIdx.x / 64] = d;
+    red[1][threadIdx.x / 64] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    part[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+hipError_t launch_real_check(const CellDev& c, const void* coeffs, int n_orb,
+                             double* part, int* nblocks, hipStream_t st) {
+  unsigned nb = grid_for(c.n_pw * n_orb);
+  if (nb > 1024) nb = 1024;
+  *nblocks = (int)nb;
+  hipLaunchKernelGGL(k_real_check, dim3(nb), dim3(256), 0, st,
+                     static_cast<const double2*>(coeffs), c.n_pw, n_orb,
+                     c.negidx, part);
   return hipGetLastError();
 }
 

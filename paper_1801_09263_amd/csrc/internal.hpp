@@ -13,6 +13,15 @@ struct PairArgs {
   int j[PMAX];
 };
 
+// Real (Gamma-point) orbitals: two pair densities of the same kind (both
+// diagonal or both off-diagonal) share one complex transform, rho_ij +
+// i rho_kl.  k = l = -1 when the slot holds a single pair.
+constexpr int QMAX = PMAX / 2 + 1;
+struct QuadArgs {
+  int n;
+  int i[QMAX], j[QMAX], k[QMAX], l[QMAX];
+};
+
 // Geometry and device tables of one cell, shared by all launchers.
 struct CellDev {
   int n;              // grid points per axis
@@ -22,6 +31,7 @@ struct CellDev {
   const int32_t* gidx;  // n_pw linear grid indices (x + n (y + n z))
   const void* vtab;     // ng kernel values v(G) / ng in the plan precision
   const void* tw;       // n twiddles exp(-2 pi i m / n), plan precision
+  const int32_t* negidx;  // n_pw: position of -m in the Miller list (Gamma)
   int ppb;              // pairs per batch (1..PMAX)
   int use_plane;        // 1: fused xy-plane passes where the plane fits LDS
 };
@@ -52,6 +62,32 @@ hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
                                    const PairArgs& pa, const void* psi,
                                    void* w, void* tmp, double* epart,
                                    hipStream_t st, hipEvent_t* ev);
+// ---- real (Gamma-point) orbitals: real grids, packed complex transforms
+// psi_real (n_orb real grids) <- real parts of Omega^{-1/2} B[C]; two
+// orbitals per complex transform in `scratch` (ceil(n_orb/2) complex grids).
+hipError_t launch_orbitals_to_grid_real(const CellDev& c, bool fp64,
+                                        const void* coeffs, int n_orb,
+                                        void* psi_real, void* scratch,
+                                        hipStream_t st);
+// What <- Omega^{1/2}/ng F[W] on the sphere for real W grids, two per
+// complex transform in `scratch`; W is left intact.
+hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64,
+                                  const void* w_real, int n_orb, void* scratch,
+                                  void* w_pw, hipStream_t st);
+// One batch of packed pair slots of real orbitals (no orbital twice).
+hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
+                             const void* psi_real, void* w_real, void* tmp,
+                             double* epart, hipStream_t st, hipEvent_t* ev);
+// Sum over orbitals of sum_m |C_m - conj(C_{-m})|^2 and sum_m |C_m|^2 into
+// part[2 * nblocks] (host reduces); returns the number of blocks used.
+hipError_t launch_real_check(const CellDev& c, const void* coeffs, int n_orb,
+                             double* part, int* nblocks, hipStream_t st);
+// S from real grids (float or double per fp64).
+hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
+                                   int na, int64_t K, double scale,
+                                   double* out, void* part, int64_t part_bytes,
+                                   hipStream_t st);
+
 // Number of energy partial slots per pair slot (tiles of the z pass).
 int64_t energy_tiles(int n, bool fp64);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);

@@ -20,6 +20,7 @@ namespace {
 struct CellPlan {
   CellDev dev;
   int32_t* d_gidx = nullptr;
+  int32_t* d_negidx = nullptr;
   void* d_vtab = nullptr;
   void* d_tw = nullptr;
   int32_t* d_info = nullptr;
@@ -46,12 +47,14 @@ struct Profile {
   size_t used = 0;                  // events handed out since the last read
   struct Rec {
     size_t ev;                      // index of the first of 4 events
-    int64_t diag, off;
+    int64_t pairs;
+    double bytes[3];                // algorithmic bytes per pass
   };
   std::vector<Rec> recs;
   double ms[3] = {0, 0, 0};
   int64_t launches[3] = {0, 0, 0};
-  int64_t diag[3] = {0, 0, 0}, off[3] = {0, 0, 0};
+  int64_t pairs[3] = {0, 0, 0};
+  double bytes[3] = {0, 0, 0};
 };
 
 // Cached HIP graph of the device work of one batched call.
@@ -63,6 +66,8 @@ struct GraphCache {
 
 struct lace_plan {
   lace_precision prec;
+  bool fp64 = false;   // grid precision
+  bool gamma = false;  // real orbitals, packed transforms
   int device = 0;
   std::vector<CellPlan> cells;
   Profile prof;
@@ -83,21 +88,27 @@ struct Layout {
   int pairs_per_batch;
 };
 
-static size_t grid_bytes(const lace_plan* p) {
-  return p->prec == LACE_FP64 ? 16 : 8;
+// bytes of one complex grid point in the plan precision
+static size_t grid_bytes(const lace_plan* p) { return p->fp64 ? 16 : 8; }
+// bytes of one orbital grid point (real for Gamma plans)
+static size_t orb_bytes(const lace_plan* p) {
+  return p->gamma ? grid_bytes(p) / 2 : grid_bytes(p);
 }
 
 static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   const CellDev& c = p->cells[cell].dev;
-  const bool fp64 = p->prec == LACE_FP64;
+  const bool fp64 = p->fp64;
   Layout L{};
   L.pairs_per_batch = c.ppb;
   const size_t gb = (size_t)c.ng * grid_bytes(p);
   size_t off = 0;
   // pair buffer and energy partials sized for the largest batch, so that
   // one workspace serves every tuning of the cell
-  L.psi = off; off += align_up(gb * n_orb);
-  L.w = off; off += align_up(gb * n_orb);
+  // orbital and W grids; for real orbitals these hold n_orb real grids and
+  // double as the scratch of ceil(n_orb / 2) packed complex transforms
+  const size_t ob = p->gamma ? gb * ((n_orb + 1) / 2) : gb * n_orb;
+  L.psi = off; off += align_up(ob);
+  L.w = off; off += align_up(ob);
   L.tmp = off; off += align_up(gb * PMAX);
   L.epart = off;
   off += align_up(sizeof(double) * PMAX * energy_tiles(c.n, fp64));
@@ -116,6 +127,13 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
 
 static char* at(void* ws, size_t off) { return static_cast<char*>(ws) + off; }
 
+static hipError_t enqueue_orbitals(const lace_plan* p, const CellDev& c,
+                                   const void* psi_g, int n_orb,
+                                   const Layout& L, void* ws, hipStream_t st);
+static hipError_t enqueue_screen(const lace_plan* p, const CellDev& c, int n_orb,
+                                 const Layout& L, void* ws, double* s_out,
+                                 hipStream_t st);
+
 static bool device_ok(const lace_plan* p) {
   int d = -1;
   if (hipGetDevice(&d) != hipSuccess) return false;
@@ -124,6 +142,8 @@ static bool device_ok(const lace_plan* p) {
 
 static void free_cell(CellPlan& c) {
   if (c.d_gidx) (void)hipFree(c.d_gidx);
+  if (c.d_negidx) (void)hipFree(c.d_negidx);
+  c.d_negidx = nullptr;
   if (c.d_vtab) (void)hipFree(c.d_vtab);
   if (c.d_tw) (void)hipFree(c.d_tw);
   if (c.d_info) (void)hipFree(c.d_info);
@@ -149,8 +169,8 @@ static hipError_t prof_collect(Profile& pr) {
       if (e != hipSuccess) return e;
       pr.ms[k] += t;
       pr.launches[k] += 1;
-      pr.diag[k] += r.diag;
-      pr.off[k] += r.off;
+      pr.pairs[k] += r.pairs;
+      pr.bytes[k] += r.bytes[k];
     }
   }
   pr.recs.clear();
@@ -253,7 +273,10 @@ const char* lace_status_string(int s) {
 int lace_plan_create(const lace_cell_desc* cells, int n_cells,
                      lace_precision prec, lace_plan** out) {
   if (!cells || !out || n_cells < 1) return LACE_EINVAL;
-  if (prec != LACE_FP64 && prec != LACE_FP32) return LACE_EINVAL;
+  if (prec != LACE_FP64 && prec != LACE_FP32 && prec != LACE_FP64_GAMMA &&
+      prec != LACE_FP32_GAMMA)
+    return LACE_EINVAL;
+  const bool gamma = prec == LACE_FP64_GAMMA || prec == LACE_FP32_GAMMA;
   // validate everything before touching the device
   for (int ci = 0; ci < n_cells; ++ci) {
     const lace_cell_desc& d = cells[ci];
@@ -274,13 +297,23 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
       if (seen[g]) return LACE_EINVAL;
       seen[g] = 1;
     }
+    if (gamma) {
+      for (int64_t m = 0; m < d.n_pw; ++m) {
+        const int x = ((-d.miller[3 * m]) % n + n) % n;
+        const int y = ((-d.miller[3 * m + 1]) % n + n) % n;
+        const int z = ((-d.miller[3 * m + 2]) % n + n) % n;
+        if (!seen[(size_t)x + (size_t)n * (y + (size_t)n * z)]) return LACE_EINVAL;
+      }
+    }
   }
   lace_plan* p = new (std::nothrow) lace_plan;
   if (!p) return LACE_ENOMEM;
   p->prec = prec;
+  p->fp64 = prec == LACE_FP64 || prec == LACE_FP64_GAMMA;
+  p->gamma = gamma;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return LACE_EHIP; }
   p->cells.resize(n_cells);
-  const bool fp64 = prec == LACE_FP64;
+  const bool fp64 = p->fp64;
   for (int ci = 0; ci < n_cells; ++ci) {
     const lace_cell_desc& d = cells[ci];
     CellPlan& cp = p->cells[ci];
@@ -298,6 +331,18 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
       const int y = (d.miller[3 * m + 1] % n + n) % n;
       const int z = (d.miller[3 * m + 2] % n + n) % n;
       gidx[m] = x + n * (y + n * z);
+    }
+    std::vector<int32_t> negidx;
+    if (gamma) {
+      std::vector<int32_t> at_grid((size_t)ng, -1);
+      for (int64_t m = 0; m < d.n_pw; ++m) at_grid[gidx[m]] = (int32_t)m;
+      negidx.resize(d.n_pw);
+      for (int64_t m = 0; m < d.n_pw; ++m) {
+        const int x = ((-d.miller[3 * m]) % n + n) % n;
+        const int y = ((-d.miller[3 * m + 1]) % n + n) % n;
+        const int z = ((-d.miller[3 * m + 2]) % n + n) % n;
+        negidx[m] = at_grid[x + (int64_t)n * (y + (int64_t)n * z)];
+      }
     }
     // kernel table v(G)/N_g: 8 pi sin^2(|G| rc / 2) / |G|^2, v(0) = 2 pi rc^2
     std::vector<double> v(ng);
@@ -329,6 +374,12 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
     if (e == hipSuccess) e = hipMalloc(&cp.d_vtab, (fp64 ? 8 : 4) * (size_t)ng);
     if (e == hipSuccess) e = hipMalloc(&cp.d_tw, (fp64 ? 16 : 8) * (size_t)n);
     if (e == hipSuccess) e = hipMalloc(&cp.d_info, sizeof(int32_t));
+    if (e == hipSuccess && gamma) {
+      e = hipMalloc(&cp.d_negidx, sizeof(int32_t) * d.n_pw);
+      if (e == hipSuccess)
+        e = hipMemcpy(cp.d_negidx, negidx.data(), sizeof(int32_t) * d.n_pw,
+                      hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess)
       e = hipMemcpy(cp.d_gidx, gidx.data(), sizeof(int32_t) * d.n_pw,
                     hipMemcpyHostToDevice);
@@ -356,6 +407,7 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
       return e == hipErrorOutOfMemory ? LACE_ENOMEM : LACE_EHIP;
     }
     cp.dev.gidx = cp.d_gidx;
+    cp.dev.negidx = cp.d_negidx;
     cp.dev.vtab = cp.d_vtab;
     cp.dev.tw = cp.d_tw;
   }
@@ -401,13 +453,10 @@ int lace_screen(lace_plan* p, int cell, const void* psi_g, int n_orb,
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
   const CellDev& c = p->cells[cell].dev;
-  const bool fp64 = p->prec == LACE_FP64;
+  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, at(ws, L.psi), st);
-  if (e == hipSuccess)
-    e = launch_gemm_ip_abs(fp64, at(ws, L.psi), c.ng, n_orb, c.ng,
-                           c.omega / double(c.ng), s_out, at(ws, L.part),
-                           (int64_t)(L.mw - L.part), st);
+  hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
+  if (e == hipSuccess) e = enqueue_screen(p, c, n_orb, L, ws, s_out, st);
   return hip_status(e);
 }
 
@@ -444,14 +493,77 @@ static void kept_from_s(const std::vector<double>& hs, int n_orb, double s_thr,
       if (hs[(size_t)i * n_orb + j] >= s_thr) pairs.emplace_back(i, j);
 }
 
+// Grid orbitals into the workspace (real grids for Gamma plans, packed two
+// per complex transform in the W region).
+static hipError_t enqueue_orbitals(const lace_plan* p, const CellDev& c,
+                                   const void* psi_g, int n_orb,
+                                   const Layout& L, void* ws, hipStream_t st) {
+  if (p->gamma)
+    return launch_orbitals_to_grid_real(c, p->fp64, psi_g, n_orb,
+                                        at(ws, L.psi), at(ws, L.w), st);
+  return launch_orbitals_to_grid(c, p->fp64, psi_g, n_orb, at(ws, L.psi), st);
+}
+
 // S into the workspace from the grid orbitals already in it.
 static hipError_t enqueue_screen(const lace_plan* p, const CellDev& c, int n_orb,
                                  const Layout& L, void* ws, double* s_out,
                                  hipStream_t st) {
-  const bool fp64 = p->prec == LACE_FP64;
-  return launch_gemm_ip_abs(fp64, at(ws, L.psi), c.ng, n_orb, c.ng,
-                            c.omega / double(c.ng), s_out, at(ws, L.part),
-                            (int64_t)(L.mw - L.part), st);
+  const double dv = c.omega / double(c.ng);
+  const int64_t pb = (int64_t)(L.mw - L.part);
+  if (p->gamma)
+    return launch_gemm_ip_abs_real(p->fp64, at(ws, L.psi), c.ng, n_orb, c.ng,
+                                   dv, s_out, at(ws, L.part), pb, st);
+  return launch_gemm_ip_abs(p->fp64, at(ws, L.psi), c.ng, n_orb, c.ng, dv,
+                            s_out, at(ws, L.part), pb, st);
+}
+
+// Packed slots of one batch for real orbitals: pairs of the same kind two
+// by two (the energy weight of a slot is then that of either pair).
+static QuadArgs to_quads(const PairArgs& b) {
+  QuadArgs q;
+  std::memset(&q, 0, sizeof(q));
+  int d[PMAX], o[PMAX], nd = 0, no = 0;
+  for (int k = 0; k < b.n; ++k) {
+    if (b.i[k] == b.j[k]) d[nd++] = k;
+    else o[no++] = k;
+  }
+  auto add = [&](int a, int c) {
+    q.i[q.n] = b.i[a];
+    q.j[q.n] = b.j[a];
+    q.k[q.n] = c >= 0 ? b.i[c] : -1;
+    q.l[q.n] = c >= 0 ? b.j[c] : -1;
+    ++q.n;
+  };
+  for (int k = 0; k < no; k += 2) add(o[k], k + 1 < no ? o[k + 1] : -1);
+  for (int k = 0; k < nd; k += 2) add(d[k], k + 1 < nd ? d[k + 1] : -1);
+  return q;
+}
+
+// Algorithmic bytes of one batch per pass (see lace_profile_read).
+static void batch_bytes(const lace_plan* p, const CellDev& c, const PairArgs& b,
+                        double out[3]) {
+  const double U = double(c.ng) * grid_bytes(p);
+  const double G = double(c.ng) * orb_bytes(p);
+  double orbs = 0.0;
+  for (int k = 0; k < b.n; ++k) orbs += (b.i[k] == b.j[k]) ? 1.0 : 2.0;
+  const double slots = p->gamma ? to_quads(b).n : b.n;
+  out[0] = orbs * G + slots * U;
+  out[1] = 2.0 * slots * U;
+  out[2] = slots * U + 3.0 * orbs * G;
+}
+
+// One batch of the pair pipeline (pairs, or packed slots for Gamma plans).
+static hipError_t enqueue_batch(const lace_plan* p, const CellDev& c,
+                                const PairArgs& b, const Layout& L, void* ws,
+                                double* epart, hipStream_t st, hipEvent_t* ev) {
+  if (p->gamma)
+    return launch_quad_batch(c, p->fp64, to_quads(b), at(ws, L.psi),
+                             at(ws, L.w), at(ws, L.tmp), epart, st, ev);
+  if (ev)
+    return launch_pair_batch_timed(c, p->fp64, b, at(ws, L.psi), at(ws, L.w),
+                                   at(ws, L.tmp), epart, st, ev);
+  return launch_pair_batch(c, p->fp64, b, at(ws, L.psi), at(ws, L.w),
+                           at(ws, L.tmp), epart, st);
 }
 
 // Pair pipeline over a schedule, energy reduction, W back to plane waves.
@@ -460,12 +572,11 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
                                    const std::vector<PairArgs>& sched,
                                    const Layout& L, void* ws, void* w_g,
                                    double* e_x, hipStream_t st, bool profile) {
-  const bool fp64 = p->prec == LACE_FP64;
-  void* psi = at(ws, L.psi);
+  const bool fp64 = p->fp64;
   void* w = at(ws, L.w);
   const int64_t ntiles = energy_tiles(c.n, fp64);
   double* epart = reinterpret_cast<double*>(at(ws, L.epart));
-  hipError_t e = launch_zero(w, (int64_t)c.ng * n_orb * grid_bytes(p), st);
+  hipError_t e = launch_zero(w, (int64_t)c.ng * n_orb * orb_bytes(p), st);
   if (e == hipSuccess)
     e = launch_zero(epart, (int64_t)sizeof(double) * PMAX * ntiles, st);
   Profile& pr = p->prof;
@@ -481,19 +592,25 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
       hipEvent_t ev[4];
       for (int k = 0; k < 4; ++k) ev[k] = prof_event(pr);
       if (!ev[0] || !ev[1] || !ev[2] || !ev[3]) return hipErrorOutOfMemory;
-      int64_t nd = 0;
-      for (int q = 0; q < sched[b].n; ++q) nd += sched[b].i[q] == sched[b].j[q];
-      pr.recs.push_back({first, nd, sched[b].n - nd});
-      e = launch_pair_batch_timed(c, fp64, sched[b], psi, w, at(ws, L.tmp),
-                                  epart, st, ev);
+      Profile::Rec r;
+      r.ev = first;
+      r.pairs = sched[b].n;
+      batch_bytes(p, c, sched[b], r.bytes);
+      pr.recs.push_back(r);
+      e = enqueue_batch(p, c, sched[b], L, ws, epart, st, ev);
     } else {
-      e = launch_pair_batch(c, fp64, sched[b], psi, w, at(ws, L.tmp), epart, st);
+      e = enqueue_batch(p, c, sched[b], L, ws, epart, st, nullptr);
     }
   }
   if (e == hipSuccess && e_x)
     e = launch_reduce_sum(epart, (int64_t)PMAX * ntiles,
                           -0.5 * c.omega / double(c.ng), e_x, st);
-  if (e == hipSuccess) e = launch_grid_to_pw(c, fp64, w, n_orb, w_g, st);
+  if (e == hipSuccess) {
+    if (p->gamma)  // the orbital grids are no longer needed: scratch
+      e = launch_grid_to_pw_real(c, fp64, w, n_orb, at(ws, L.psi), w_g, st);
+    else
+      e = launch_grid_to_pw(c, fp64, w, n_orb, w_g, st);
+  }
   return e;
 }
 
@@ -535,9 +652,9 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   if (pair_i && !copy_pairs(pair_i, pair_j, n_pairs, n_orb, pairs))
     return LACE_EINVAL;
   const CellDev& c = p->cells[cell].dev;
-  const bool fp64 = p->prec == LACE_FP64;
+  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, at(ws, L.psi), st);
+  hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e != hipSuccess) return LACE_EHIP;
   if (!pair_i) {
     if (s_thr > 0.0) {
@@ -605,7 +722,7 @@ int lace_fft3d(lace_plan* p, int cell, int direction, void* grids, int count,
     return LACE_EINVAL;
   if (direction != -1 && direction != 1) return LACE_EINVAL;
   if (!device_ok(p)) return LACE_EINVAL;
-  return hip_status(launch_fft3d(p->cells[cell].dev, p->prec == LACE_FP64,
+  return hip_status(launch_fft3d(p->cells[cell].dev, p->fp64,
                                  direction, grids, count,
                                  static_cast<hipStream_t>(stream)));
 }
@@ -636,7 +753,7 @@ int lace_set_tuning(lace_plan* p, int cell, int ppb, int use_plane) {
   if (ppb < 1 || ppb > PMAX || (use_plane != 0 && use_plane != 1))
     return LACE_EINVAL;
   CellDev& c = p->cells[cell].dev;
-  if (use_plane && !plane_fits(c.n, p->prec == LACE_FP64)) return LACE_EUNSUPPORTED;
+  if (use_plane && !plane_fits(c.n, p->fp64)) return LACE_EUNSUPPORTED;
   c.ppb = ppb;
   c.use_plane = use_plane;
   return LACE_OK;
@@ -658,9 +775,9 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
   CellDev& c = p->cells[cell].dev;
-  const bool fp64 = p->prec == LACE_FP64;
+  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_orbitals_to_grid(c, fp64, psi_g, n_orb, at(ws, L.psi), st);
+  hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e != hipSuccess) return LACE_EHIP;
   // fixed pair set: the first 4 * PMAX pairs in round-robin order
   std::vector<std::pair<int, int>> pairs;
@@ -696,9 +813,9 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
       const bool fp = fp64;
       double* epart = reinterpret_cast<double*>(at(ws, L.epart));
       e = hipEventRecord(t0, st);
+      (void)fp;
       for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b)
-        e = launch_pair_batch(c, fp, sched[b], at(ws, L.psi), at(ws, L.w),
-                              at(ws, L.tmp), epart, st);
+        e = enqueue_batch(p, c, sched[b], L, ws, epart, st, nullptr);
       if (e == hipSuccess) e = hipEventRecord(t1, st);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
@@ -781,7 +898,7 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     for (int q = 0; q < k; ++q)
       if (jobs[q].ws == j.ws || jobs[q].w_g == j.w_g) return LACE_EINVAL;
   }
-  const bool fp64 = p->prec == LACE_FP64;
+  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int ns = n_jobs < 8 ? n_jobs : 8;
   hipError_t e = ensure_streams(p, ns);
@@ -809,7 +926,7 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     const lace_job& j = jobs[k];
     const CellDev& c = p->cells[j.cell].dev;
     hipStream_t js = p->streams[on[k]];
-    e = launch_orbitals_to_grid(c, fp64, j.psi_g, j.n_orb, at(j.ws, lay[k].psi), js);
+    e = enqueue_orbitals(p, c, j.psi_g, j.n_orb, lay[k], j.ws, js);
     if (e == hipSuccess && j.s_thr > 0.0) {
       any_screen = true;
       e = enqueue_screen(p, c, j.n_orb, lay[k], j.ws,
@@ -921,7 +1038,7 @@ int lace_profile_enable(lace_plan* p, int enable) {
     pr.recs.clear();
     pr.used = 0;
     for (int k = 0; k < 3; ++k) {
-      pr.ms[k] = 0; pr.launches[k] = 0; pr.diag[k] = 0; pr.off[k] = 0;
+      pr.ms[k] = 0; pr.launches[k] = 0; pr.pairs[k] = 0; pr.bytes[k] = 0;
     }
   }
   pr.on = enable != 0;
@@ -929,7 +1046,7 @@ int lace_profile_enable(lace_plan* p, int enable) {
 }
 
 int lace_profile_read(lace_plan* p, double* ms, int64_t* launches,
-                      int64_t* pairs_diag, int64_t* pairs_off) {
+                      int64_t* pairs, double* alg_bytes) {
   if (!p) return LACE_EINVAL;
   Profile& pr = p->prof;
   if (hipDeviceSynchronize() != hipSuccess) return LACE_EHIP;
@@ -937,9 +1054,33 @@ int lace_profile_read(lace_plan* p, double* ms, int64_t* launches,
   for (int k = 0; k < 3; ++k) {
     if (ms) ms[k] = pr.ms[k];
     if (launches) launches[k] = pr.launches[k];
-    if (pairs_diag) pairs_diag[k] = pr.diag[k];
-    if (pairs_off) pairs_off[k] = pr.off[k];
+    if (pairs) pairs[k] = pr.pairs[k];
+    if (alg_bytes) alg_bytes[k] = pr.bytes[k];
   }
+  return LACE_OK;
+}
+
+int lace_check_real(lace_plan* p, int cell, const void* psi_g, int n_orb,
+                    void* ws, size_t ws_bytes, lace_stream_t stream,
+                    double* rel_dev) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!p->gamma || !psi_g || !ws || !rel_dev) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* part = reinterpret_cast<double*>(at(ws, L.part));
+  int nb = 0;
+  hipError_t e = launch_real_check(p->cells[cell].dev, psi_g, n_orb, part, &nb, st);
+  std::vector<double> h(2 * (size_t)nb);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(),
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return LACE_EHIP;
+  double d = 0.0, t = 0.0;
+  for (int k = 0; k < nb; ++k) { d += h[2 * k]; t += h[2 * k + 1]; }
+  *rel_dev = t > 0.0 ? std::sqrt(d / t) : 0.0;
   return LACE_OK;
 }
 

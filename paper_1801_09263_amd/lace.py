@@ -25,6 +25,8 @@ LACE_EHIP = -5
 
 LACE_FP64 = 0
 LACE_FP32 = 1
+LACE_FP64_GAMMA = 2
+LACE_FP32_GAMMA = 3
 LACE_SYM_AVG = 0
 LACE_SYM_UPPER = 1
 LACE_SYM_LOWER = 2
@@ -38,7 +40,7 @@ SYMBOLS = (
     "lace_fft3d", "lace_get_info", "lace_status_string",
     "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
-    "lace_autotune",
+    "lace_autotune", "lace_check_real",
 )
 LACE_BATCH_GRAPH = 1
 
@@ -102,7 +104,10 @@ def load(path: str = LIB_PATH):
     lib.lace_profile_enable.argtypes = [vp, i32]
     p_i64 = ctypes.POINTER(ctypes.c_int64)
     lib.lace_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
-                                      p_i64, p_i64, p_i64]
+                                      p_i64, p_i64,
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.lace_check_real.argtypes = [vp, i32, vp, i32, vp, sz, vp,
+                                    ctypes.POINTER(ctypes.c_double)]
     lib.lace_schedule_pairs.argtypes = [p_i32, p_i32, i64, i32, i32, p_i32,
                                         p_i64]
     lib.lace_apply_exchange_batched.argtypes = [vp, ctypes.POINTER(LaceJob),
@@ -278,15 +283,29 @@ def lace_profile_enable(plan, enable=True):
 
 def lace_profile_read(plan):
     """Per-pass totals of the pair pipeline since profiling was enabled:
-    dict of lists (index 0 pass A, 1 pass B, 2 pass C)."""
+    dict of lists (index 0 pass A, 1 pass B, 2 pass C): milliseconds,
+    launches, pairs and algorithmic HBM bytes."""
     ms = (ctypes.c_double * 3)()
     la = (ctypes.c_int64 * 3)()
-    pdg = (ctypes.c_int64 * 3)()
-    pof = (ctypes.c_int64 * 3)()
-    _check(load().lace_profile_read(plan.handle, ms, la, pdg, pof),
+    pr = (ctypes.c_int64 * 3)()
+    by = (ctypes.c_double * 3)()
+    _check(load().lace_profile_read(plan.handle, ms, la, pr, by),
            "lace_profile_read")
-    return dict(ms=list(ms), launches=list(la), pairs_diag=list(pdg),
-                pairs_off=list(pof))
+    return dict(ms=list(ms), launches=list(la), pairs=list(pr),
+                alg_bytes=list(by))
+
+
+def lace_check_real(plan, cell, psi_g, n_orb, ws, stream=None) -> float:
+    """Relative deviation of the orbitals from C_{-G} = conj(C_G)."""
+    import torch
+    out = ctypes.c_double(0.0)
+    _check(load().lace_check_real(plan.handle, cell,
+                                  _ptr(psi_g, torch.complex128, "psi_g"),
+                                  n_orb, _ptr(ws, None, "ws"),
+                                  ws.numel() * ws.element_size(),
+                                  _stream(stream), ctypes.byref(out)),
+           "lace_check_real")
+    return out.value
 
 
 def lace_schedule_pairs(pairs, n_orb, per_batch):

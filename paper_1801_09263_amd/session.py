@@ -57,6 +57,10 @@ class CellSession:
                             self.xi, self.m, self.ex_tr, self.ws, stream)
         return self.xi
 
+    def check_real(self, stream=None) -> float:
+        return lace.lace_check_real(self.plan, 0, self.psi, self.n_orb,
+                                    self.ws, stream)
+
     def info(self) -> int:
         return lace.lace_get_info(self.plan, 0)
 

@@ -127,12 +127,14 @@ def orbitals_from_params(miller: np.ndarray, L: float, pos: np.ndarray,
         row /= np.sqrt(np.vdot(row, row).real)
         c[o] = row
     # Two Loewdin passes: the second removes the ~kappa(S) * eps residue
-    # left by the first when two widths on one centre nearly coincide.
+    # left by the first when two widths on one centre nearly coincide.  The
+    # orbitals are real functions, so S is real: its real part is used,
+    # which keeps C_{-G} = conj(C_G) exact through the transformation.
     for _ in range(2):
-        s = c.conj() @ c.T            # s[a, b] = <c_a | c_b>
-        s = 0.5 * (s + s.conj().T)
+        s = (c.conj() @ c.T).real     # s[a, b] = <c_a | c_b>
+        s = 0.5 * (s + s.T)
         w, u = np.linalg.eigh(s)
-        s_inv_half = (u * (1.0 / np.sqrt(w))) @ u.conj().T
+        s_inv_half = (u * (1.0 / np.sqrt(w))) @ u.T
         # new orbital b = sum_a c_a (S^{-1/2})_{ab}
         c = s_inv_half.T @ c
     return np.ascontiguousarray(c)

@@ -82,6 +82,38 @@ def test_sampled_pairs_full_size_localized(lace120, prec, tol):
     sampled_pair_parity(lace120, prec, tol)
 
 
+def test_sampled_pairs_full_size_gamma(lace120):
+    say("localized 120^3 sampled pairs, real-orbital packing fp32")
+    sampled_pair_parity(lace120, lace.LACE_FP32_GAMMA, 1e-5)
+
+
+def test_gamma_full_step_matches_complex_path(lace120):
+    """Whole screened step at 120^3: packed real-orbital path against the
+    complex FP32 path (same pair set)."""
+    inp = lace120
+    n_orb = inp["coeffs"].shape[0]
+    out = {}
+    for prec in (FP32, lace.LACE_FP32_GAMMA):
+        s = CellSession(inp, n_orb, prec, n_vec=n_orb)
+        s.set_orbitals(inp["coeffs"])
+        s.apply_exchange(inp["s_thr"])
+        s.build_ace("avg")
+        torch.cuda.synchronize()
+        out[prec] = dict(w=s.w.cpu().numpy(), m=s.m.cpu().numpy(),
+                         xi=s.xi.cpu().numpy(), ex=s.e_x.item(),
+                         kept=s.n_kept, info=s.info())
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    a, b = out[FP32], out[lace.LACE_FP32_GAMMA]
+    say(f"  kept {a['kept']}/{b['kept']}, E_x {a['ex']} / {b['ex']}")
+    assert a["kept"] == b["kept"] and b["info"] == 0
+    assert abs(a["ex"] - b["ex"]) <= 1e-6 * abs(a["ex"])
+    assert rel(b["w"], a["w"]) <= 2e-6
+    assert rel(b["m"], a["m"]) <= 2e-6
+    assert rel(b["xi"], a["xi"]) <= 1e-4
+
+
 def test_sampled_pairs_full_size_plain(plain120):
     say("plain 120^3 sampled pairs fp32")
     sampled_pair_parity(plain120, FP32, 1e-5)

@@ -287,3 +287,61 @@ def test_deterministic_repeat(c0):
     s.apply_exchange(0.0)
     assert torch.equal(w1, s.w) and torch.equal(e1, s.e_x)
     s.close()
+
+
+# ----------------------------------------- real (Gamma-point) orbitals
+FP64G, FP32G = lace.LACE_FP64_GAMMA, lace.LACE_FP32_GAMMA
+TOL[FP64G] = TOL[FP64]
+TOL[FP32G] = TOL[FP32]
+
+
+@pytest.mark.parametrize("prec", [FP64G, FP32G], ids=["fp64g", "fp32g"])
+@pytest.mark.parametrize("s_thr,n_orb", [(0.0, 16), (5e-3, 16), (2e-3, 15)])
+def test_gamma_packed_real_orbitals(prec, s_thr, n_orb):
+    """Real orbitals with two pair densities per complex transform (and an
+    odd orbital count: one orbital transformed alone) against the oracle,
+    which treats them as general complex orbitals."""
+    say(f"gamma packing n_orb={n_orb} s_thr={s_thr} prec={prec}")
+    tol = TOL[prec]
+    L, n, ecut = 16.0, 32, 15.0
+    miller = synth.miller_sphere(L, ecut)
+    coeffs = synth.gaussian_orbitals(miller, L, n_orb, 8, synth.rng_for(90))
+    psi = O.orbitals_on_grid(coeffs, miller, L, n)
+    S = O.overlap_of_moduli(psi, L)
+    pairs = O.kept_pairs(S, s_thr)
+    cell = dict(L=L, n=n, miller=miller)
+    s = CellSession(cell, n_orb, prec, n_vec=n_orb)
+    s.set_orbitals(coeffs)
+    assert s.check_real() <= 1e-14
+    assert rel(s.screen().cpu().numpy(), S) <= tol["s"]
+    s.apply_exchange(s_thr, pairs=np.array(pairs))
+    assert s.n_kept == len(pairs)
+    for sym in ("avg", "upper", "lower"):
+        res = O.run_path(coeffs, miller, L, n, pairs=pairs, sym=sym)
+        s.build_ace(sym)
+        torch.cuda.synchronize()
+        assert s.info() == 0
+        assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+        assert rel(s.m.cpu().numpy(), res["M"]) <= tol["m"]
+        assert rel(s.xi.cpu().numpy(), res["xi"]) <= tol["xi"]
+        assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(
+            res["ex_pairs"])
+    s.close()
+
+
+def test_gamma_check_flags_complex_orbitals(c0):
+    inp, _ = c0
+    s = CellSession(inp, 8, FP32G)
+    s.set_orbitals(inp["coeffs"])
+    dev = s.check_real()
+    say("  deviation of random complex orbitals", dev)
+    assert dev > 0.5
+    s.close()
+
+
+def test_gamma_plan_needs_symmetric_sphere():
+    m = synth.miller_sphere(10.0, 15.0)
+    half = m[(m[:, 2] > 0) | ((m[:, 2] == 0) & (m[:, 1] > 0))]
+    with pytest.raises(lace.LaceError) as ei:
+        lace.lace_plan_create([dict(L=10.0, n=24, miller=half)], FP32G)
+    assert ei.value.code == lace.LACE_EINVAL
