@@ -208,9 +208,11 @@ def serving_rows(torch, seed, n_jobs):
         classes.append(JobClass(c["name"], cell, c["n_orb"], pool))
     spec = synth.serving_stream(n_jobs, 4, [len(c.pool) for c in classes],
                                 rate=synth.SERVE_RATE, seed=seed)
+    # warm-up on one slot first, so every kernel is loaded by one thread
+    warm = Server(classes, lace.LACE_FP32_GAMMA, n_slots=1)
+    warm.run([Job(-1 - k, 0.0, k, [0]) for k in range(len(classes))])
+    warm.close()
     srv = Server(classes, lace.LACE_FP32_GAMMA, n_slots=4)
-    # one warm-up job per class (allocator, code objects)
-    srv.run([Job(-1 - k, 0.0, k, [0]) for k in range(len(classes))])
     jobs = srv.run([Job(j, t, c, v) for j, t, c, v in spec])
     srv.close()
     res = summarize(jobs, synth.SERVE_RATE)

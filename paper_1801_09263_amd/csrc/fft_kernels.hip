@@ -20,111 +20,179 @@
 namespace lace {
 
 // ------------------------------------------------------------- functors
-// Prologues produce the value of grid point g of slot `slot`; epilogues
-// consume it.  Epilogues that read memory split into pre() (issue loads)
-// and put() (combine and store), so a thread can have a whole chunk of
-// loads in flight before it stores anything.
+// Prologues produce the values of grid points g .. g+V-1 of slot `slot`;
+// epilogues consume them.  V consecutive points are moved with one 16-byte
+// access per array.  Epilogues that read memory split into prev() (issue
+// the loads) and putv() (combine and store), so a thread can have a whole
+// chunk of loads in flight before it stores anything.  Loads never sit
+// behind a branch: unused ones read a valid address and are discarded.
+
+template <typename E, int V> struct Vec { E e[V]; };
+
+template <typename E, int V>
+__device__ inline Vec<E, V> ldv(const E* p) {
+  Vec<E, V> r;
+  if constexpr (sizeof(E) * V == 16) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    __builtin_memcpy(&r, &t, 16);
+  } else if constexpr (sizeof(E) * V == 8) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    __builtin_memcpy(&r, &t, 8);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) r.e[v] = p[v];
+  }
+  return r;
+}
+template <typename E, int V>
+__device__ inline void stv(E* p, const Vec<E, V>& r) {
+  if constexpr (sizeof(E) * V == 16) {
+    float4 t;
+    __builtin_memcpy(&t, &r, 16);
+    *reinterpret_cast<float4*>(p) = t;
+  } else if constexpr (sizeof(E) * V == 8) {
+    float2 t;
+    __builtin_memcpy(&t, &r, 8);
+    *reinterpret_cast<float2*>(p) = t;
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) p[v] = r.e[v];
+  }
+}
+
 struct NoPre {};
 
 template <typename T> struct ProGrid {
+  static constexpr int V = 16 / sizeof(C<T>);
   const C<T>* __restrict__ buf;
   int64_t gs;
-  __device__ C<T> get(int g, int slot) const { return buf[slot * gs + g]; }
+  __device__ void getv(int g, int slot, C<T>* out) const {
+    const Vec<C<T>, V> x = ldv<C<T>, V>(buf + slot * gs + g);
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = x.e[v];
+  }
 };
+// rho = conj(psi_i) psi_j
 template <typename T> struct ProPair {
+  static constexpr int V = 16 / sizeof(C<T>);
   const C<T>* __restrict__ psi;
   int64_t gs;
   PairArgs pa;
-  __device__ C<T> get(int g, int slot) const {
-    const C<T> a = psi[pa.i[slot] * gs + g];
-    const C<T> b = psi[pa.j[slot] * gs + g];
-    return cmul<T>(a, b);
+  __device__ void getv(int g, int slot, C<T>* out) const {
+    const Vec<C<T>, V> a = ldv<C<T>, V>(psi + pa.i[slot] * gs + g);
+    const Vec<C<T>, V> b = ldv<C<T>, V>(psi + pa.j[slot] * gs + g);
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = cmul<T>(a.e[v], b.e[v]);
   }
 };
 template <typename T> struct EpiGrid {
+  static constexpr int V = 16 / sizeof(C<T>);
+  static constexpr int CH = 4;   // vectors per chunk of in-flight loads
   using Pre = NoPre;
   C<T>* __restrict__ buf;
   int64_t gs;
   T scale;
-  __device__ void pre(int, int, Pre&) const {}
-  __device__ void put(int g, int slot, C<T> v, const Pre&) const {
-    buf[slot * gs + g] = scl<T>(v, scale);
+  __device__ void prev(int, int, Pre&) const {}
+  __device__ void putv(int g, int slot, const C<T>* x, const Pre&) const {
+    Vec<C<T>, V> y;
+#pragma unroll
+    for (int v = 0; v < V; ++v) y.e[v] = scl<T>(x[v], scale);
+    stv<C<T>, V>(buf + slot * gs + g, y);
   }
 };
 template <typename T> struct AccPre {
-  C<T> pi, pj, wi, wj;
+  Vec<C<T>, 16 / sizeof(C<T>)> pi, pj, wi, wj;
 };
 // W_j -= psi_i V and, for i != j, W_i -= psi_j conj(V)
 template <typename T> struct EpiAcc {
+  static constexpr int V = 16 / sizeof(C<T>);
+  static constexpr int CH = 4;
   using Pre = AccPre<T>;
   const C<T>* __restrict__ psi;
   C<T>* __restrict__ w;
   int64_t gs;
   PairArgs pa;
-  __device__ void pre(int g, int slot, Pre& r) const {
+  __device__ void prev(int g, int slot, Pre& r) const {
+    // a diagonal pair reads its orbital twice (from cache); stores decide
     const int i = pa.i[slot], j = pa.j[slot];
-    r.pi = psi[i * gs + g];
-    r.wj = w[j * gs + g];
-    if (i != j) {
-      r.pj = psi[j * gs + g];
-      r.wi = w[i * gs + g];
-    }
+    r.pi = ldv<C<T>, V>(psi + i * gs + g);
+    r.wj = ldv<C<T>, V>(w + j * gs + g);
+    r.pj = ldv<C<T>, V>(psi + j * gs + g);
+    r.wi = ldv<C<T>, V>(w + i * gs + g);
   }
-  __device__ void put(int g, int slot, C<T> v, const Pre& r) const {
+  __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
     const int i = pa.i[slot], j = pa.j[slot];
-    w[j * gs + g] = sub<T>(r.wj, mul<T>(r.pi, v));
-    if (i != j) w[i * gs + g] = sub<T>(r.wi, mulc<T>(r.pj, v));
+    Vec<C<T>, V> yj, yi;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      yj.e[v] = sub<T>(r.wj.e[v], mul<T>(r.pi.e[v], x[v]));
+      yi.e[v] = sub<T>(r.wi.e[v], mulc<T>(r.pj.e[v], x[v]));
+    }
+    stv<C<T>, V>(w + j * gs + g, yj);
+    if (i != j) stv<C<T>, V>(w + i * gs + g, yi);
   }
 };
 
 // Real orbitals, packed slot: value rho_ij + i rho_kl.
 template <typename T> struct ProQuad {
+  static constexpr int V = 16 / sizeof(T);
   const T* __restrict__ psi;
   int64_t gs;
   QuadArgs qa;
-  __device__ C<T> get(int g, int slot) const {
+  __device__ void getv(int g, int slot, C<T>* out) const {
+    // a slot without a second pair reads orbital i twice and discards it
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
-    const T a = psi[i * gs + g] * psi[j * gs + g];
-    T b = T(0);
-    if (k >= 0) b = psi[k * gs + g] * psi[l * gs + g];
-    return mk<T>(a, b);
+    const bool two = k >= 0;
+    const int kk = two ? k : i, ll = two ? l : i;
+    const Vec<T, V> a = ldv<T, V>(psi + i * gs + g);
+    const Vec<T, V> b = ldv<T, V>(psi + j * gs + g);
+    const Vec<T, V> c = ldv<T, V>(psi + kk * gs + g);
+    const Vec<T, V> d = ldv<T, V>(psi + ll * gs + g);
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      out[v] = mk<T>(a.e[v] * b.e[v], two ? c.e[v] * d.e[v] : T(0));
   }
 };
 template <typename T> struct QuadPre {
-  T pi, pj, pk, pl, wi, wj, wk, wl;
+  Vec<T, 16 / sizeof(T)> pi, pj, pk, pl, wi, wj, wk, wl;
 };
 // V = V_ij + i V_kl (both real):  W_j -= psi_i V_ij, W_i -= psi_j V_ij,
 // W_l -= psi_k V_kl, W_k -= psi_l V_kl (one update for a diagonal pair).
 template <typename T> struct EpiAccQuad {
+  static constexpr int V = 16 / sizeof(T);
+  static constexpr int CH = 2;
   using Pre = QuadPre<T>;
   const T* __restrict__ psi;
   T* __restrict__ w;
   int64_t gs;
   QuadArgs qa;
-  __device__ void pre(int g, int slot, Pre& r) const {
+  __device__ void prev(int g, int slot, Pre& r) const {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
-    r.pi = psi[i * gs + g];
-    r.wj = w[j * gs + g];
-    if (i != j) {
-      r.pj = psi[j * gs + g];
-      r.wi = w[i * gs + g];
-    }
-    if (k >= 0) {
-      r.pk = psi[k * gs + g];
-      r.wl = w[l * gs + g];
-      if (k != l) {
-        r.pl = psi[l * gs + g];
-        r.wk = w[k * gs + g];
-      }
-    }
+    const int kk = k >= 0 ? k : i, ll = k >= 0 ? l : i;
+    r.pi = ldv<T, V>(psi + i * gs + g);
+    r.wj = ldv<T, V>(w + j * gs + g);
+    r.pj = ldv<T, V>(psi + j * gs + g);
+    r.wi = ldv<T, V>(w + i * gs + g);
+    r.pk = ldv<T, V>(psi + kk * gs + g);
+    r.wl = ldv<T, V>(w + ll * gs + g);
+    r.pl = ldv<T, V>(psi + ll * gs + g);
+    r.wk = ldv<T, V>(w + kk * gs + g);
   }
-  __device__ void put(int g, int slot, C<T> v, const Pre& r) const {
+  __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
-    w[j * gs + g] = r.wj - r.pi * v.x;
-    if (i != j) w[i * gs + g] = r.wi - r.pj * v.x;
+    Vec<T, V> yj, yi, yl, yk;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      yj.e[v] = r.wj.e[v] - r.pi.e[v] * x[v].x;
+      yi.e[v] = r.wi.e[v] - r.pj.e[v] * x[v].x;
+      yl.e[v] = r.wl.e[v] - r.pk.e[v] * x[v].y;
+      yk.e[v] = r.wk.e[v] - r.pl.e[v] * x[v].y;
+    }
+    stv<T, V>(w + j * gs + g, yj);
+    if (i != j) stv<T, V>(w + i * gs + g, yi);
     if (k >= 0) {
-      w[l * gs + g] = r.wl - r.pk * v.y;
-      if (k != l) w[k * gs + g] = r.wk - r.pl * v.y;
+      stv<T, V>(w + l * gs + g, yl);
+      if (k != l) stv<T, V>(w + k * gs + g, yk);
     }
   }
 };
@@ -134,46 +202,59 @@ __device__ inline void load_tw(C<T>* tw, const C<T>* tw_g) {
   for (int m = threadIdx.x; m < N; m += NT) tw[m] = tw_g[m];
 }
 
-// Fill s[m], m < NE, from pro.get(idx(m)): all loads of a thread first,
-// then the LDS stores.
+// Fill s[lds(m)], m < NE, from the prologue: thread t takes the vectors
+// t, t + NT, ... of V consecutive points (idx(m) .. idx(m) + V - 1 are
+// consecutive in memory), all loads first, then the LDS stores.
 template <typename T, int NE, int NT, class Pro, class Idx, class Lds>
 __device__ inline void stage_in(C<T>* s, const Pro& pro, int slot, Idx idx,
                                 Lds lds) {
-  constexpr int PER = (NE + NT - 1) / NT;
-  C<T> v[PER];
+  constexpr int V = Pro::V;
+  static_assert(NE % V == 0, "tile not a multiple of the vector width");
+  constexpr int NV = NE / V;
+  constexpr int PER = (NV + NT - 1) / NT;
+  C<T> x[PER][V];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int m = threadIdx.x + q * NT;
-    if (NE % NT == 0 || m < NE) v[q] = pro.get(idx(m), slot);
+    const int mv = threadIdx.x + q * NT;
+    if (q < NV / NT || mv < NV) pro.getv(idx(mv * V), slot, x[q]);
   }
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int m = threadIdx.x + q * NT;
-    if (NE % NT == 0 || m < NE) s[lds(m)] = v[q];
+    const int mv = threadIdx.x + q * NT;
+    if (q < NV / NT || mv < NV) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) s[lds(mv * V + v)] = x[q][v];
+    }
   }
 }
 
-// Drain s[m] through the epilogue in chunks of CH elements per thread:
-// the chunk's loads are issued before any of its stores.
+// Drain s through the epilogue in chunks of CH vectors per thread: the
+// chunk's loads are issued before any of its stores.
 template <typename T, int NE, int NT, class Epi, class Idx, class Lds>
 __device__ inline void stage_out(const C<T>* s, const Epi& epi, int slot,
                                  Idx idx, Lds lds) {
-  constexpr int PER = (NE + NT - 1) / NT;
-  constexpr int CH0 = sizeof(T) == 4 ? 8 : 4;   // register budget
-  constexpr int CH = PER < CH0 ? PER : CH0;
+  constexpr int V = Epi::V;
+  static_assert(NE % V == 0, "tile not a multiple of the vector width");
+  constexpr int NV = NE / V;
+  constexpr int PER = (NV + NT - 1) / NT;
+  constexpr int CH = PER < Epi::CH ? PER : Epi::CH;   // register budget
 #pragma unroll
   for (int q0 = 0; q0 < PER; q0 += CH) {
     typename Epi::Pre pre[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = threadIdx.x + (q0 + c) * NT;
-      if (q0 + c < PER && (NE % NT == 0 || m < NE)) epi.pre(idx(m), slot, pre[c]);
+      const int q = q0 + c, mv = threadIdx.x + q * NT;
+      if (q < PER && (q < NV / NT || mv < NV)) epi.prev(idx(mv * V), slot, pre[c]);
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int m = threadIdx.x + (q0 + c) * NT;
-      if (q0 + c < PER && (NE % NT == 0 || m < NE))
-        epi.put(idx(m), slot, s[lds(m)], pre[c]);
+      const int q = q0 + c, mv = threadIdx.x + q * NT;
+      if (q < PER && (q < NV / NT || mv < NV)) {
+        C<T> x[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = s[lds(mv * V + v)];
+        epi.putv(idx(mv * V), slot, x, pre[c]);
+      }
     }
   }
 }
@@ -284,42 +365,78 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---- pass B: z forward, x v(G)/N_g with energy partial, z backward ----
-template <typename T, int N, int TX, int NT>
+// Workgroup (tile, group): TX columns of SL consecutive pair slots, one LDS
+// line per column and slot; the kernel-table tile is shared by the SL
+// slots.  Slots past the end of the batch load slot 0 (discarded) and are
+// neither stored nor summed.
+template <typename T, int N, int TX, int SL, int NT>
 __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
                                               int64_t gs,
                                               const T* __restrict__ vtab,
                                               PairArgs pa, double* epart,
                                               int ntiles, const C<T>* tw_g) {
   constexpr int LS = Pad<N>::LS;
-  __shared__ C<T> s[TX * LS];
+  constexpr int NE1 = TX * N;          // points of one slot's tile
+  constexpr int NE = SL * NE1;
+  constexpr int V = ProGrid<T>::V;
+  constexpr int NV = NE / V;
+  constexpr int PER = (NV + NT - 1) / NT;
+  __shared__ C<T> s[SL * TX * LS];
   __shared__ C<T> tw[N];
   __shared__ double red[NT / 64];
-  const int lg = xcd_logical(blockIdx.x, ntiles * pa.n);
-  const int tile = lg / pa.n, slot = lg % pa.n;
+  const int ngroups = (pa.n + SL - 1) / SL;
+  const int lg = xcd_logical(blockIdx.x, ntiles * ngroups);
+  const int tile = lg / ngroups, slot0 = (lg % ngroups) * SL;
+  const int nsl = min(SL, pa.n - slot0);
   load_tw<T, N, NT>(tw, tw_g);
-  C<T>* g = tmp + slot * gs;
+  C<T>* g = tmp + slot0 * gs;
+  // element m of the group: slot m / NE1, tile point m % NE1
+  auto gidx = [tile, nsl, gs](int m) {
+    const int sl = m / NE1;
+    return (sl < nsl ? sl : 0) * (int)gs + col_index<N, 2, TX>(tile, m % NE1);
+  };
+  auto lds = [](int m) {
+    const int sl = m / NE1, r = m % NE1;
+    return (sl * TX + r % TX) * LS + r / TX;
+  };
   ProGrid<T> pro{g, 0};
-  auto idx = [tile](int m) { return col_index<N, 2, TX>(tile, m); };
-  auto lds = [](int m) { return col_lds<N, TX>(m); };
-  stage_in<T, TX * N, NT>(s, pro, 0, idx, lds);
+  stage_in<T, NE, NT>(s, pro, 0, gidx, lds);
   __syncthreads();
-  lds_fft<T, N, TX, NT, -1, true>(s, LS, 1, tw);
-  double e = 0.0;
-  for (int m = threadIdx.x; m < TX * N; m += NT) {
+  lds_fft<T, N, SL * TX, NT, -1, true>(s, LS, 1, tw);
+  double e[SL];
+#pragma unroll
+  for (int sl = 0; sl < SL; ++sl) e[sl] = 0.0;
+  for (int m = threadIdx.x; m < NE1; m += NT) {
     const T v = vtab[col_index<N, 2, TX>(tile, m)];
-    const int q = col_lds<N, TX>(m);
-    const C<T> r = s[q];
-    e += double(v) * (double(r.x) * double(r.x) + double(r.y) * double(r.y));
-    s[q] = scl<T>(r, v);
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int q = lds(sl * NE1 + m);
+      const C<T> r = s[q];
+      e[sl] += double(v) * (double(r.x) * double(r.x) + double(r.y) * double(r.y));
+      s[q] = scl<T>(r, v);
+    }
   }
   __syncthreads();
-  lds_fft<T, N, TX, NT, +1, true>(s, LS, 1, tw);
-  EpiGrid<T> epi{g, 0, T(1)};
-  stage_out<T, TX * N, NT>(s, epi, 0, idx, lds);
-  const double tot = block_sum<NT>(e, red);
-  if (threadIdx.x == 0) {
-    const double wgt = (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
-    epart[slot * ntiles + tile] += wgt * tot;
+  lds_fft<T, N, SL * TX, NT, +1, true>(s, LS, 1, tw);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int mv = threadIdx.x + q * NT;
+    if ((q < NV / NT || mv < NV) && (mv * V) / NE1 < nsl) {
+      Vec<C<T>, V> y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) y.e[v] = s[lds(mv * V + v)];
+      stv<C<T>, V>(g + gidx(mv * V), y);
+    }
+  }
+#pragma unroll
+  for (int sl = 0; sl < SL; ++sl) {
+    const double tot = block_sum<NT>(e[sl], red);
+    if (threadIdx.x == 0 && sl < nsl) {
+      const int slot = slot0 + sl;
+      const double wgt = (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
+      epart[slot * ntiles + tile] += wgt * tot;
+    }
+    __syncthreads();   // red is reused by the next slot
   }
 }
 
@@ -380,6 +497,8 @@ template <typename T, int N> struct Cfg {
   static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
   static constexpr int TX = (N % TX0 == 0) ? TX0 : ((N % 8 == 0) ? 8 : 4);
   static constexpr int NT_COLS = 256;
+  // z pass: pair slots per workgroup
+  static constexpr int SL = sizeof(T) == 4 ? 4 : 2;
   // x pencils: TY rows
   static constexpr int TY = (N % 8 == 0) ? 8 : 4;
   static constexpr int NT_X = 256;
@@ -459,7 +578,8 @@ template <typename T, int N> struct Engine {
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     // pass B
     const int ntiles = N * (N / Cf::TX);
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::NT_COLS>), dim3(ntiles * cnt),
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::SL, Cf::NT_COLS>),
+                       dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
                        dim3(Cf::NT_COLS), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pa, epart, ntiles, tw);
     err = hipGetLastError();
@@ -502,7 +622,8 @@ template <typename T, int N> struct Engine {
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     const int ntiles = N * (N / Cf::TX);
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::NT_COLS>), dim3(ntiles * cnt),
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::SL, Cf::NT_COLS>),
+                       dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
                        dim3(Cf::NT_COLS), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pw, epart, ntiles, tw);
     err = hipGetLastError();
