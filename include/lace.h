@@ -198,16 +198,18 @@ int lace_apply_exchange_batched(lace_plan* plan, lace_job* jobs, int n_jobs,
                                 int flags, lace_stream_t stream);
 
 /* Per-cell tuning of the pair pipeline: pairs per batch (1..64) and the xy
- * schedule (use_plane = 1: fused xy-plane passes, where the plane fits LDS;
- * 0: separate x and y pencil passes).  Host only. */
+ * schedule: use_plane = 1, fused xy-plane passes (where the plane fits
+ * LDS); 2, the xy plane in two halves of N/2 rows after a radix-2 split
+ * along y (half the LDS, two workgroups per CU); 0, separate x and y pencil
+ * passes.  Host only. */
 int lace_set_tuning(lace_plan* plan, int cell, int pairs_per_batch,
                     int use_plane);
 int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
                     int* use_plane);
 
 /* Autotuner: times the pair pipeline of this cell on the given orbitals for
- * every candidate (pairs per batch 8, 16, 32, 64; plane and pencil
- * schedules where both exist), over the same fixed set of pairs, and keeps
+ * every candidate (pairs per batch 8, 16, 32, 64; half-plane, plane and
+ * pencil schedules where they exist), over the same fixed set of pairs, and keeps
  * the fastest with lace_set_tuning.  Writes up to *n_cand candidates
  * (cand_ppb, cand_plane, cand_us_per_pair; host arrays, may be NULL) and
  * sets *n_cand to the number timed.  Synchronizes the stream.  The

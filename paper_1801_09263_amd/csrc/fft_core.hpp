@@ -134,12 +134,16 @@ template <int N> struct Plan;
     static constexpr int nst = NS;                               \
     static constexpr int r[NS] = {__VA_ARGS__};                  \
   };
+LACE_PLAN(4, 1, 4)
+LACE_PLAN(6, 2, 3, 2)
 LACE_PLAN(8, 1, 8)
 LACE_PLAN(12, 2, 4, 3)
 LACE_PLAN(16, 2, 4, 4)
 LACE_PLAN(24, 2, 8, 3)
 LACE_PLAN(32, 2, 8, 4)
+LACE_PLAN(40, 2, 8, 5)
 LACE_PLAN(48, 3, 4, 4, 3)
+LACE_PLAN(60, 3, 4, 5, 3)
 LACE_PLAN(64, 2, 8, 8)
 LACE_PLAN(80, 3, 4, 4, 5)
 LACE_PLAN(96, 3, 8, 4, 3)
@@ -153,9 +157,10 @@ template <int N> struct StageP<N, 0> { static constexpr int value = 1; };
 
 // One Stockham stage.  LINES_FAST: consecutive threads walk consecutive
 // lines (use when lines are adjacent in LDS, i.e. ls == 1), else
-// consecutive butterflies of one line.  tw[m] = exp(-2 pi i m / N).
+// consecutive butterflies of one line.  tw[m TWS] = exp(-2 pi i m / N): the
+// table may belong to a TWS times longer transform.
 template <typename T, int N, int R, int P, int NL, int NT, int SIGN,
-          bool LINES_FAST>
+          bool LINES_FAST, int TWS>
 __device__ inline void lds_stage(C<T>* s, int ls, int es, const C<T>* tw) {
   constexpr int NR = N / R;
   constexpr int B = NL * NR;
@@ -184,7 +189,7 @@ __device__ inline void lds_stage(C<T>* s, int ls, int es, const C<T>* tw) {
       if (P > 1) {
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          C<T> w = tw[t * k * (N / (P * R))];
+          C<T> w = tw[t * k * (N / (P * R)) * TWS];
           if (SIGN > 0) w.y = -w.y;
           v[b][t] = mul<T>(v[b][t], w);
         }
@@ -203,24 +208,28 @@ template <int N, int S> struct NextS {
   static constexpr int value = (S + 1 < Plan<N>::nst) ? S + 1 : -1;
 };
 
-template <typename T, int N, int S, int NL, int NT, int SIGN, bool LF>
+template <typename T, int N, int S, int NL, int NT, int SIGN, bool LF,
+          int TWS>
 struct StagesFrom {
   __device__ static inline void run(C<T>* s, int ls, int es, const C<T>* tw) {
-    lds_stage<T, N, Plan<N>::r[S], StageP<N, S>::value, NL, NT, SIGN, LF>(
-        s, ls, es, tw);
-    StagesFrom<T, N, NextS<N, S>::value, NL, NT, SIGN, LF>::run(s, ls, es, tw);
+    lds_stage<T, N, Plan<N>::r[S], StageP<N, S>::value, NL, NT, SIGN, LF,
+              TWS>(s, ls, es, tw);
+    StagesFrom<T, N, NextS<N, S>::value, NL, NT, SIGN, LF, TWS>::run(s, ls,
+                                                                    es, tw);
   }
 };
-template <typename T, int N, int NL, int NT, int SIGN, bool LF>
-struct StagesFrom<T, N, -1, NL, NT, SIGN, LF> {
+template <typename T, int N, int NL, int NT, int SIGN, bool LF, int TWS>
+struct StagesFrom<T, N, -1, NL, NT, SIGN, LF, TWS> {
   __device__ static inline void run(C<T>*, int, int, const C<T>*) {}
 };
 
 // NL length-N transforms in LDS.  Caller must __syncthreads() after filling
-// s; the call ends with a barrier.
-template <typename T, int N, int NL, int NT, int SIGN, bool LINES_FAST>
+// s; the call ends with a barrier.  The twiddle table holds the roots of a
+// length N * TWS transform.
+template <typename T, int N, int NL, int NT, int SIGN, bool LINES_FAST,
+          int TWS = 1>
 __device__ inline void lds_fft(C<T>* s, int ls, int es, const C<T>* tw) {
-  StagesFrom<T, N, 0, NL, NT, SIGN, LINES_FAST>::run(s, ls, es, tw);
+  StagesFrom<T, N, 0, NL, NT, SIGN, LINES_FAST, TWS>::run(s, ls, es, tw);
 }
 
 }  // namespace lace

@@ -296,6 +296,70 @@ __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
   stage_out<T, N * N, NT>(s, epi, slot, idx, lds);
 }
 
+// ------------------------------ xy plane in two halves (half the LDS)
+// Decimation in frequency along y, H = N/2: rows y and y + H of the input
+// plane f give a = f_y + f_{y+H} and b = (f_y - f_{y+H}) w^y (w the N-th
+// root of unity of the transform's sign).  The length-N (x) by length-H (y)
+// transforms of a and b are the even and the odd rows of the plane's
+// transform.  One workgroup forms and transforms one of the two halves in
+// an LDS buffer of H rows, so two workgroups share a CU and one's memory
+// phases overlap the other's FFT.  Both halves of a plane read the same
+// input; the remap puts them on one XCD, back to back, so the second read
+// is served by that XCD's L2.  The epilogue is pointwise: the interleaved
+// row order of the result costs nothing.
+template <typename T, int N, int NT, int MINW, int SIGN, class Pro, class Epi>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
+void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
+  constexpr int H = N / 2;
+  constexpr int LS = Pad<N>::LS;
+  constexpr int V = Pro::V;
+  constexpr int NVH = H * N / V;
+  constexpr int PER = (NVH + NT - 1) / NT;
+  static_assert((H * N) % V == 0 && N % V == 0, "vector width");
+  __shared__ C<T> s[H * LS];
+  __shared__ C<T> tw[N];
+  const int lg = xcd_logical(blockIdx.x, 2 * N * nslots);
+  const int half = lg & 1, zs = lg >> 1;
+  const int z = zs % N, slot = zs / N;
+  load_tw<T, N, NT>(tw, tw_g);
+  const int base = z * N * N;
+  C<T> f1[PER][V], f2[PER][V];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int mv = threadIdx.x + q * NT;
+    if (q < NVH / NT || mv < NVH) {
+      const int m0 = mv * V;
+      pro.getv(base + m0, slot, f1[q]);
+      pro.getv(base + H * N + m0, slot, f2[q]);
+    }
+  }
+  __syncthreads();   // twiddles in LDS
+  auto lds = [](int m) { return (m / N) * LS + m % N; };
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int mv = threadIdx.x + q * NT;
+    if (q < NVH / NT || mv < NVH) {
+      const int m0 = mv * V;
+      C<T> w = tw[m0 / N];
+      if (SIGN > 0) w.y = -w.y;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        C<T> r;
+        if (half == 0) r = add<T>(f1[q][v], f2[q][v]);
+        else r = mul<T>(sub<T>(f1[q][v], f2[q][v]), w);
+        s[lds(m0 + v)] = r;
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N, H, NT, SIGN, true>(s, LS, 1, tw);          // x: H rows
+  lds_fft<T, H, N, NT, SIGN, true, 2>(s, 1, LS, tw);       // y: N columns
+  auto out = [base, half](int m) {
+    return base + (2 * (m / N) + half) * N + m % N;
+  };
+  stage_out<T, H * N, NT>(s, epi, slot, out, lds);
+}
+
 // ---------------------------------------------- x pencils: TY whole rows
 template <typename T, int N, int TY, int NT, int SIGN, class Pro, class Epi>
 __global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
@@ -519,6 +583,19 @@ template <typename T, int N> struct Engine {
       return hipErrorInvalidValue;
     }
   }
+  static constexpr int NT_HALF = 512;
+  // waves per SIMD to budget registers for: two workgroups of 8 waves when
+  // two half planes fit the 160 KiB of LDS of a CU
+  static constexpr int W_HALF =
+      (N / 2 * (N + 1) + N) * (int)sizeof(C<T>) * 2 <= 160 * 1024 ? 4 : 2;
+  template <int SIGN, class Pro, class Epi>
+  static hipError_t half(Pro p, Epi e, int count, const C<T>* tw,
+                         hipStream_t st) {
+    hipLaunchKernelGGL((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi>),
+                       dim3(2 * N * count), dim3(NT_HALF), 0, st, p, e, tw,
+                       count);
+    return hipGetLastError();
+  }
   template <int SIGN, class Pro, class Epi>
   static hipError_t xlines(Pro p, Epi e, int count, const C<T>* tw,
                            hipStream_t st) {
@@ -539,12 +616,14 @@ template <typename T, int N> struct Engine {
   // in-place transform of `count` grids, optional scale on the last pass
   template <int SIGN>
   static hipError_t fft3d(C<T>* g, int count, T scale, const C<T>* tw,
-                          bool use_plane, hipStream_t st) {
+                          int mode, hipStream_t st) {
     ProGrid<T> p{g, NG};
     EpiGrid<T> e1{g, NG, T(1)};
     EpiGrid<T> es{g, NG, scale};
     hipError_t err;
-    if (Cf::plane && use_plane) {
+    if (mode == 2) {
+      err = half<SIGN>(p, e1, count, tw, st);
+    } else if (Cf::plane && mode == 1) {
       err = plane<SIGN>(p, e1, count, tw, st);
     } else {
       err = xlines<SIGN>(p, e1, count, tw, st);
@@ -565,10 +644,12 @@ template <typename T, int N> struct Engine {
     EpiGrid<T> et{tmp, NG, T(1)};
     EpiAcc<T> ea{psi, w, NG, pa};
     hipError_t err;
-    const bool use_plane = Cf::plane && c.use_plane;
+    const int mode = (c.use_plane == 1 && !Cf::plane) ? 0 : c.use_plane;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     // pass A
-    if (use_plane) {
+    if (mode == 2) {
+      err = half<-1>(pp, et, cnt, tw, st);
+    } else if (mode == 1) {
       err = plane<-1>(pp, et, cnt, tw, st);
     } else {
       err = xlines<-1>(pp, et, cnt, tw, st);
@@ -586,7 +667,9 @@ template <typename T, int N> struct Engine {
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
     // pass C
-    if (use_plane) {
+    if (mode == 2) {
+      err = half<+1>(pt, ea, cnt, tw, st);
+    } else if (mode == 1) {
       err = plane<+1>(pt, ea, cnt, tw, st);
     } else {
       err = cols<1, +1>(pt, et, cnt, tw, st);
@@ -610,10 +693,12 @@ template <typename T, int N> struct Engine {
     PairArgs pw;
     pw.n = cnt;
     for (int q = 0; q < cnt; ++q) { pw.i[q] = qa.i[q]; pw.j[q] = qa.j[q]; }
-    const bool use_plane = Cf::plane && c.use_plane;
+    const int mode = (c.use_plane == 1 && !Cf::plane) ? 0 : c.use_plane;
     hipError_t err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
-    if (use_plane) {
+    if (mode == 2) {
+      err = half<-1>(pp, et, cnt, tw, st);
+    } else if (mode == 1) {
       err = plane<-1>(pp, et, cnt, tw, st);
     } else {
       err = xlines<-1>(pp, et, cnt, tw, st);
@@ -629,7 +714,9 @@ template <typename T, int N> struct Engine {
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
-    if (use_plane) {
+    if (mode == 2) {
+      err = half<+1>(pt, ea, cnt, tw, st);
+    } else if (mode == 1) {
       err = plane<+1>(pt, ea, cnt, tw, st);
     } else {
       err = cols<1, +1>(pt, et, cnt, tw, st);
@@ -683,9 +770,9 @@ static hipError_t fft3d_t(const CellDev& c, int sign, void* grids, int count,
 #define X(NN)                                                            \
   case NN:                                                               \
     return sign < 0 ? Engine<T, NN>::template fft3d<-1>(g, count, scale, tw, \
-                                                         c.use_plane != 0, st) \
+                                                         c.use_plane, st)   \
                     : Engine<T, NN>::template fft3d<+1>(g, count, scale, tw, \
-                                                         c.use_plane != 0, st);
+                                                         c.use_plane, st);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;

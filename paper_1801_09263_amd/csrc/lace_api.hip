@@ -323,7 +323,7 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
     cp.dev.n = n; cp.dev.ng = ng; cp.dev.n_pw = d.n_pw;
     cp.dev.L = d.L; cp.dev.rc = rc; cp.dev.omega = d.L * d.L * d.L;
     cp.dev.ppb = default_pairs_per_batch(n);
-    cp.dev.use_plane = plane_fits(n, fp64) ? 1 : 0;
+    cp.dev.use_plane = plane_fits(n, fp64) ? 1 : 2;
     // sphere -> grid map
     std::vector<int32_t> gidx(d.n_pw);
     for (int64_t m = 0; m < d.n_pw; ++m) {
@@ -750,10 +750,10 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
 
 int lace_set_tuning(lace_plan* p, int cell, int ppb, int use_plane) {
   if (!p || cell < 0 || cell >= (int)p->cells.size()) return LACE_EINVAL;
-  if (ppb < 1 || ppb > PMAX || (use_plane != 0 && use_plane != 1))
+  if (ppb < 1 || ppb > PMAX || use_plane < 0 || use_plane > 2)
     return LACE_EINVAL;
   CellDev& c = p->cells[cell].dev;
-  if (use_plane && !plane_fits(c.n, p->fp64)) return LACE_EUNSUPPORTED;
+  if (use_plane == 1 && !plane_fits(c.n, p->fp64)) return LACE_EUNSUPPORTED;
   c.ppb = ppb;
   c.use_plane = use_plane;
   return LACE_OK;
@@ -795,8 +795,8 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   struct Cand { int ppb, plane; double us; };
   std::vector<Cand> cands;
   const int ppbs[4] = {8, 16, 32, 64};
-  for (int plane = 1; plane >= 0; --plane) {
-    if (plane && !plane_fits(c.n, fp64)) continue;
+  for (int plane = 2; plane >= 0; --plane) {
+    if (plane == 1 && !plane_fits(c.n, fp64)) continue;
     for (int k = 0; k < 4; ++k) cands.push_back({ppbs[k], plane, 0.0});
   }
   const int save_ppb = c.ppb, save_plane = c.use_plane;

@@ -1,8 +1,8 @@
 """Autotuning results cached on disk.
 
 The autotuner itself is ``lace_autotune`` in the library: it times every
-pipeline candidate of a cell (pairs per batch, plane or pencil schedule) on
-real orbitals and keeps the fastest.  This module stores the winners in a
+pipeline candidate of a cell (pairs per batch; pencil, whole-plane or
+half-plane xy schedule) on real orbitals and keeps the fastest.  This module stores the winners in a
 JSON file keyed by precision, grid size and orbital count, and applies them
 to new plans, so later runs skip the timing.
 """

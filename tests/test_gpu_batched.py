@@ -134,7 +134,7 @@ def test_autotune_picks_a_candidate_and_stays_correct():
     mc.set_orbitals(0, coeffs)
     cands = mc.autotune(0)
     say("  candidates", cands)
-    assert len(cands) == 8
+    assert len(cands) == 12     # 4 batch sizes x 3 xy schedules
     assert all(t > 0 for _, _, t in cands)
     ppb, plane = lace.lace_get_tuning(mc.plan, 0)
     best = min(cands, key=lambda c: c[2])
@@ -156,7 +156,7 @@ def test_autotune_picks_a_candidate_and_stays_correct():
 def test_tuning_rejects_bad_values():
     cell = dict(L=10.0, n=24, miller=synth.miller_sphere(10.0, 15.0))
     plan = lace.lace_plan_create([cell], FP32)
-    for ppb, pl in ((0, 1), (65, 1), (8, 2)):
+    for ppb, pl in ((0, 1), (65, 1), (8, 3), (8, -1)):
         with pytest.raises(lace.LaceError):
             lace.lace_set_tuning(plan, 0, ppb, pl)
     plan.close()

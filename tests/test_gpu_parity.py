@@ -43,12 +43,28 @@ def brute_dft3(a, sign):
     return np.einsum("az,by,cx,...zyx->...abc", f, f, f, a, optimize=True)
 
 
+def set_schedule(plan, mode):
+    """Select an xy schedule (0 pencils, 1 whole plane, 2 half planes) on
+    cell 0; False where the whole plane does not fit LDS."""
+    ppb, _ = lace.lace_get_tuning(plan, 0)
+    try:
+        lace.lace_set_tuning(plan, 0, ppb, mode)
+    except lace.LaceError:
+        assert mode == 1
+        return False
+    return True
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["pencil", "plane", "half"])
 @pytest.mark.parametrize("prec", [FP64, FP32], ids=["fp64", "fp32"])
 @pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 80, 96, 120])
-def test_fft3d_against_definition(n, prec):
-    say(f"fft3d n={n} prec={NAMES[prec]}")
+def test_fft3d_against_definition(n, prec, mode):
+    say(f"fft3d n={n} prec={NAMES[prec]} mode={mode}")
     cell = dict(L=7.0, n=n, miller=np.zeros((1, 3), np.int32))
     plan = lace.lace_plan_create([cell], prec)
+    if not set_schedule(plan, mode):
+        plan.close()
+        pytest.skip("xy plane does not fit LDS")
     count = 3
     rng = np.random.default_rng(n)
     x = (rng.standard_normal((count, n, n, n))
@@ -345,3 +361,29 @@ def test_gamma_plan_needs_symmetric_sphere():
     with pytest.raises(lace.LaceError) as ei:
         lace.lace_plan_create([dict(L=10.0, n=24, miller=half)], FP32G)
     assert ei.value.code == lace.LACE_EINVAL
+
+
+# ------------------------------- the three xy schedules of the pair passes
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["pencil", "plane", "half"])
+@pytest.mark.parametrize("prec", [FP64, FP32, FP64G, FP32G],
+                         ids=["fp64", "fp32", "fp64g", "fp32g"])
+@pytest.mark.parametrize("L,n,ecut,n_orb", [(10.0, 24, 15.0, 7),
+                                            (12.0, 48, 20.0, 11)])
+def test_pair_passes_every_schedule(L, n, ecut, n_orb, prec, mode):
+    """Pencil, whole-plane and half-plane xy passes, on complex and on
+    packed real orbitals (odd count), give the oracle's W and E_x."""
+    say(f"schedule mode={mode} n={n} N={n_orb} prec={prec}")
+    tol = TOL[prec]
+    miller = synth.miller_sphere(L, ecut)
+    coeffs = synth.gaussian_orbitals(miller, L, n_orb, (n_orb + 1) // 2,
+                                     synth.rng_for(78, n))
+    res = O.run_path(coeffs, miller, L, n)
+    s = CellSession(dict(L=L, n=n, miller=miller), n_orb, prec)
+    assert set_schedule(s.plan, mode)
+    s.set_orbitals(coeffs)
+    s.apply_exchange(0.0)
+    torch.cuda.synchronize()
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(
+        res["ex_pairs"])
+    s.close()
