@@ -243,6 +243,22 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int64_t* n_batches);
 
+/* Host only, no device work: the schedule lace_apply_exchange uses on plans
+ * of real orbitals (LACE_*_GAMMA), where two pair densities share one
+ * complex transform, a slot.  Same arguments as lace_schedule_pairs, plus
+ * slot_of[k] (host, n_pairs int32), the slot of pair k within its batch.
+ * A slot holds one or two pairs of the same kind (both diagonal or both
+ * off-diagonal); two off-diagonal pairs of a slot share an orbital where the
+ * pair set allows it, so the slot reads and updates three orbital grids
+ * instead of four (the pair products are those inside the integrals of
+ * Eqs. (2) and (8)).  No orbital
+ * appears in two slots of one batch; a batch holds at most per_batch pairs
+ * and (per_batch + 1) / 2 slots. */
+int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
+                        int64_t n_pairs, int n_orb, int per_batch,
+                        int32_t* batch_of, int32_t* slot_of,
+                        int64_t* n_batches);
+
 /* Kernel timing of the pair pipeline of lace_apply_exchange, for
  * roofline measurement.  While enabled, every batch of the pipeline is
  * bracketed by HIP events on the call's stream, one interval per pass:

@@ -158,6 +158,7 @@ template <typename T> struct QuadPre {
 };
 // V = V_ij + i V_kl (both real):  W_j -= psi_i V_ij, W_i -= psi_j V_ij,
 // W_l -= psi_k V_kl, W_k -= psi_l V_kl (one update for a diagonal pair).
+// A star slot (k = i) folds both updates of the shared orbital into one.
 template <typename T> struct EpiAccQuad {
   static constexpr int V = 16 / sizeof(T);
   static constexpr int CH = 2;
@@ -180,6 +181,7 @@ template <typename T> struct EpiAccQuad {
   }
   __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    const bool star = k == i;
     Vec<T, V> yj, yi, yl, yk;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -187,12 +189,13 @@ template <typename T> struct EpiAccQuad {
       yi.e[v] = r.wi.e[v] - r.pj.e[v] * x[v].x;
       yl.e[v] = r.wl.e[v] - r.pk.e[v] * x[v].y;
       yk.e[v] = r.wk.e[v] - r.pl.e[v] * x[v].y;
+      if (star) yi.e[v] -= r.pl.e[v] * x[v].y;
     }
     stv<T, V>(w + j * gs + g, yj);
     if (i != j) stv<T, V>(w + i * gs + g, yi);
     if (k >= 0) {
       stv<T, V>(w + l * gs + g, yl);
-      if (k != l) stv<T, V>(w + k * gs + g, yk);
+      if (k != l && !star) stv<T, V>(w + k * gs + g, yk);
     }
   }
 };

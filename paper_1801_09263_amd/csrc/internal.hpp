@@ -15,7 +15,9 @@ struct PairArgs {
 
 // Real (Gamma-point) orbitals: two pair densities of the same kind (both
 // diagonal or both off-diagonal) share one complex transform, rho_ij +
-// i rho_kl.  k = l = -1 when the slot holds a single pair.
+// i rho_kl.  k = l = -1 when the slot holds a single pair; k = i (a star
+// slot) when the two pairs share orbital i, which is then read once and
+// its W updated once.
 constexpr int QMAX = PMAX / 2 + 1;
 struct QuadArgs {
   int n;

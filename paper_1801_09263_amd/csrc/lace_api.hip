@@ -193,6 +193,13 @@ static int pair_round(int i, int j, int nv) {
   return (int)(((int64_t)(i + j) * (nv / 2)) % m);  // (nv/2) = 1/2 mod m
 }
 
+// One batch of the pair pipeline: its pairs and, for plans of real
+// orbitals, the packed slots (the pairs then listed slot by slot).
+struct Batch {
+  PairArgs p;
+  QuadArgs q;
+};
+
 // Group pairs into batches of at most per_batch pairs in which no orbital
 // appears twice, so the accumulation into W has no write conflicts.  Pairs
 // are taken round by round (stable within a round) and placed first-fit
@@ -200,9 +207,9 @@ static int pair_round(int i, int j, int nv) {
 // batches fill to per_batch except at round boundaries.
 static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
                            int n_orb, int per_batch,
-                           std::vector<PairArgs>& out,
+                           std::vector<Batch>& outb,
                            std::vector<int32_t>* batch_of = nullptr) {
-  out.clear();
+  std::vector<PairArgs> out;
   const int nv = n_orb + (n_orb & 1);
   std::vector<int> order(pairs.size());
   std::vector<int> round(pairs.size());
@@ -253,6 +260,219 @@ static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
       if (open.size() > window) open.erase(open.begin());
     }
   }
+  outb.resize(out.size());
+  for (size_t b = 0; b < out.size(); ++b) {
+    outb[b].p = out[b];
+    outb[b].q.n = 0;
+  }
+}
+
+// Plans of real orbitals pack two pair densities into one complex
+// transform (a slot); slots of one batch use disjoint orbitals.  A slot
+// whose two pairs share an orbital (a star slot) reads and updates three
+// orbital grids instead of four.  Stars come from trails: a walk along
+// pairs not yet used, cut into runs of two consecutive pairs, which share
+// the orbital between them.  Off-diagonal pairs are first walked two
+// round-robin rounds at a time (each round a set of disjoint pairs, so the
+// stars of one group overlap little and pack densely into batches); what
+// is left (one pair per trail of odd length) is walked once more as a
+// whole, and the rest is packed two by two, then the diagonal pairs; a
+// last odd pair of either kind gets a slot of its own.
+struct Slot {
+  int i, j, k, l;   // k = l = -1: a single pair; k = i: a star slot
+  int pk[2];        // the slot's pairs (indices into the pair list, or -1)
+};
+
+static int slot_orbitals(const Slot& s, int o[4]) {
+  int n = 0;
+  for (int v : {s.i, s.j, s.k, s.l}) {
+    if (v < 0) continue;
+    bool seen = false;
+    for (int t = 0; t < n; ++t) seen = seen || o[t] == v;
+    if (!seen) o[n++] = v;
+  }
+  return n;
+}
+
+static Slot make_slot(const std::vector<std::pair<int, int>>& pairs, int a,
+                      int b) {
+  Slot s;
+  s.pk[0] = a;
+  s.pk[1] = b;
+  int i = pairs[a].first, j = pairs[a].second;
+  if (b < 0) {
+    s.i = i; s.j = j; s.k = s.l = -1;
+    return s;
+  }
+  int k = pairs[b].first, l = pairs[b].second;
+  if (i != j) {   // a shared orbital goes first in both pairs
+    if (j == k || j == l) std::swap(i, j);
+    if (k != i && l == i) std::swap(k, l);
+  }
+  s.i = i; s.j = j; s.k = k; s.l = l;
+  return s;
+}
+
+// Trail decomposition of the off-diagonal pairs `edges`: consecutive pairs
+// of each walk become star slots, the last pair of an odd walk goes to
+// `left`.  Walks start at orbitals with an odd number of unused pairs.
+static void trail_slots(const std::vector<std::pair<int, int>>& pairs,
+                        const std::vector<int>& edges, int n_orb,
+                        std::vector<char>& done, std::vector<Slot>& slots,
+                        std::vector<int>& left) {
+  std::vector<int> off(n_orb + 1, 0), rem(n_orb, 0);
+  for (int e : edges) {
+    ++off[pairs[e].first + 1];
+    ++off[pairs[e].second + 1];
+  }
+  for (int v = 0; v < n_orb; ++v) off[v + 1] += off[v];
+  std::vector<int> adj(off[n_orb]), cur(off.begin(), off.end() - 1);
+  for (int e : edges)
+    for (int v : {pairs[e].first, pairs[e].second}) adj[cur[v]++] = e;
+  for (int v = 0; v < n_orb; ++v) {
+    cur[v] = off[v];
+    rem[v] = off[v + 1] - off[v];
+  }
+  auto walk = [&](int v) {
+    int pend = -1;
+    for (;;) {
+      while (cur[v] < off[v + 1] && done[adj[cur[v]]]) ++cur[v];
+      if (cur[v] == off[v + 1]) break;
+      const int e = adj[cur[v]++];
+      done[e] = 1;
+      --rem[pairs[e].first];
+      --rem[pairs[e].second];
+      if (pend < 0) {
+        pend = e;
+      } else {
+        slots.push_back(make_slot(pairs, pend, e));
+        pend = -1;
+      }
+      v = pairs[e].first == v ? pairs[e].second : pairs[e].first;
+    }
+    if (pend >= 0) left.push_back(pend);
+  };
+  for (int e : edges)
+    for (int v : {pairs[e].first, pairs[e].second})
+      if (rem[v] & 1) walk(v);
+  for (int e : edges)
+    if (!done[e]) walk(pairs[e].first);
+}
+
+static void make_slots(const std::vector<std::pair<int, int>>& pairs,
+                       int n_orb, bool pack, std::vector<Slot>& slots) {
+  slots.clear();
+  if (!pack) {
+    for (size_t k = 0; k < pairs.size(); ++k)
+      slots.push_back(make_slot(pairs, (int)k, -1));
+    return;
+  }
+  const int nv = n_orb + (n_orb & 1);
+  std::vector<int> off, diag, left, rest;
+  std::vector<int> round(pairs.size(), 0);
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    if (pairs[k].first == pairs[k].second) {
+      diag.push_back((int)k);
+    } else {
+      off.push_back((int)k);
+      round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
+    }
+  }
+  std::stable_sort(off.begin(), off.end(),
+                   [&](int a, int b) { return round[a] < round[b]; });
+  std::vector<int> group;
+  std::vector<char> done(pairs.size(), 0);
+  for (size_t a = 0; a < off.size();) {
+    const int g = round[off[a]] / 2;
+    group.clear();
+    while (a < off.size() && round[off[a]] / 2 == g) group.push_back(off[a++]);
+    trail_slots(pairs, group, n_orb, done, slots, left);
+  }
+  for (int e : left) done[e] = 0;
+  trail_slots(pairs, left, n_orb, done, slots, rest);
+  for (size_t t = 0; t < rest.size(); t += 2)
+    slots.push_back(make_slot(pairs, rest[t],
+                              t + 1 < rest.size() ? rest[t + 1] : -1));
+  for (size_t t = 0; t < diag.size(); t += 2)
+    slots.push_back(make_slot(pairs, diag[t],
+                              t + 1 < diag.size() ? diag[t + 1] : -1));
+}
+
+// Slots into batches of at most per_batch pairs and (per_batch + 1) / 2
+// slots, first-fit over a window of open batches, no orbital twice in a
+// batch.
+static void build_slot_schedule(const std::vector<std::pair<int, int>>& pairs,
+                                int n_orb, int per_batch,
+                                std::vector<Batch>& out,
+                                std::vector<int32_t>* batch_of = nullptr,
+                                std::vector<int32_t>* slot_of = nullptr) {
+  out.clear();
+  std::vector<Slot> slots;
+  make_slots(pairs, n_orb, per_batch >= 2, slots);
+  if (batch_of) batch_of->assign(pairs.size(), -1);
+  if (slot_of) slot_of->assign(pairs.size(), -1);
+  const int cap_slots = (per_batch + 1) / 2;
+  const int words = (n_orb + 63) / 64;
+  struct Open {
+    size_t idx;
+    std::vector<uint64_t> used;
+  };
+  std::vector<Open> open;
+  const size_t window = 8;
+  auto put = [&](size_t idx, const Slot& sl) {
+    Batch& b = out[idx];
+    const int q = b.q.n++;
+    b.q.i[q] = sl.i; b.q.j[q] = sl.j; b.q.k[q] = sl.k; b.q.l[q] = sl.l;
+    for (int t = 0; t < 2; ++t) {
+      const int k = sl.pk[t];
+      if (k < 0) continue;
+      b.p.i[b.p.n] = pairs[k].first;
+      b.p.j[b.p.n] = pairs[k].second;
+      ++b.p.n;
+      if (batch_of) (*batch_of)[k] = (int32_t)idx;
+      if (slot_of) (*slot_of)[k] = q;
+    }
+  };
+  for (const Slot& sl : slots) {
+    int o[4];
+    const int no = slot_orbitals(sl, o);
+    const int np = sl.pk[1] >= 0 ? 2 : 1;
+    bool placed = false;
+    for (size_t w = 0; w < open.size() && !placed; ++w) {
+      Open& ob = open[w];
+      const Batch& b = out[ob.idx];
+      if (b.p.n + np > per_batch) continue;
+      bool clash = false;
+      for (int t = 0; t < no; ++t)
+        clash = clash || ((ob.used[o[t] / 64] >> (o[t] % 64)) & 1ull);
+      if (clash) continue;
+      put(ob.idx, sl);
+      for (int t = 0; t < no; ++t) ob.used[o[t] / 64] |= 1ull << (o[t] % 64);
+      if (out[ob.idx].p.n == per_batch || out[ob.idx].q.n == cap_slots)
+        open.erase(open.begin() + w);
+      placed = true;
+    }
+    if (placed) continue;
+    Batch nb;
+    std::memset(&nb, 0, sizeof(nb));
+    out.push_back(nb);
+    put(out.size() - 1, sl);
+    if (out.back().p.n < per_batch && out.back().q.n < cap_slots) {
+      Open ob;
+      ob.idx = out.size() - 1;
+      ob.used.assign(words, 0ull);
+      for (int t = 0; t < no; ++t) ob.used[o[t] / 64] |= 1ull << (o[t] % 64);
+      open.push_back(ob);
+      if (open.size() > window) open.erase(open.begin());
+    }
+  }
+}
+
+static void schedule_for(const lace_plan* p,
+                         const std::vector<std::pair<int, int>>& pairs,
+                         int n_orb, int per_batch, std::vector<Batch>& out) {
+  if (p->gamma) build_slot_schedule(pairs, n_orb, per_batch, out);
+  else build_schedule(pairs, n_orb, per_batch, out);
 }
 
 // ------------------------------------------------------------------ API
@@ -517,36 +737,24 @@ static hipError_t enqueue_screen(const lace_plan* p, const CellDev& c, int n_orb
                             s_out, at(ws, L.part), pb, st);
 }
 
-// Packed slots of one batch for real orbitals: pairs of the same kind two
-// by two (the energy weight of a slot is then that of either pair).
-static QuadArgs to_quads(const PairArgs& b) {
-  QuadArgs q;
-  std::memset(&q, 0, sizeof(q));
-  int d[PMAX], o[PMAX], nd = 0, no = 0;
-  for (int k = 0; k < b.n; ++k) {
-    if (b.i[k] == b.j[k]) d[nd++] = k;
-    else o[no++] = k;
-  }
-  auto add = [&](int a, int c) {
-    q.i[q.n] = b.i[a];
-    q.j[q.n] = b.j[a];
-    q.k[q.n] = c >= 0 ? b.i[c] : -1;
-    q.l[q.n] = c >= 0 ? b.j[c] : -1;
-    ++q.n;
-  };
-  for (int k = 0; k < no; k += 2) add(o[k], k + 1 < no ? o[k + 1] : -1);
-  for (int k = 0; k < nd; k += 2) add(d[k], k + 1 < nd ? d[k + 1] : -1);
-  return q;
-}
-
 // Algorithmic bytes of one batch per pass (see lace_profile_read).
-static void batch_bytes(const lace_plan* p, const CellDev& c, const PairArgs& b,
+static void batch_bytes(const lace_plan* p, const CellDev& c, const Batch& bt,
                         double out[3]) {
   const double U = double(c.ng) * grid_bytes(p);
   const double G = double(c.ng) * orb_bytes(p);
-  double orbs = 0.0;
-  for (int k = 0; k < b.n; ++k) orbs += (b.i[k] == b.j[k]) ? 1.0 : 2.0;
-  const double slots = p->gamma ? to_quads(b).n : b.n;
+  double orbs = 0.0, slots = 0.0;
+  if (p->gamma) {
+    for (int q = 0; q < bt.q.n; ++q) {
+      const Slot sl{bt.q.i[q], bt.q.j[q], bt.q.k[q], bt.q.l[q], {-1, -1}};
+      int o[4];
+      orbs += slot_orbitals(sl, o);
+    }
+    slots = bt.q.n;
+  } else {
+    for (int k = 0; k < bt.p.n; ++k)
+      orbs += (bt.p.i[k] == bt.p.j[k]) ? 1.0 : 2.0;
+    slots = bt.p.n;
+  }
   out[0] = orbs * G + slots * U;
   out[1] = 2.0 * slots * U;
   out[2] = slots * U + 3.0 * orbs * G;
@@ -554,11 +762,12 @@ static void batch_bytes(const lace_plan* p, const CellDev& c, const PairArgs& b,
 
 // One batch of the pair pipeline (pairs, or packed slots for Gamma plans).
 static hipError_t enqueue_batch(const lace_plan* p, const CellDev& c,
-                                const PairArgs& b, const Layout& L, void* ws,
+                                const Batch& bt, const Layout& L, void* ws,
                                 double* epart, hipStream_t st, hipEvent_t* ev) {
   if (p->gamma)
-    return launch_quad_batch(c, p->fp64, to_quads(b), at(ws, L.psi),
-                             at(ws, L.w), at(ws, L.tmp), epart, st, ev);
+    return launch_quad_batch(c, p->fp64, bt.q, at(ws, L.psi), at(ws, L.w),
+                             at(ws, L.tmp), epart, st, ev);
+  const PairArgs& b = bt.p;
   if (ev)
     return launch_pair_batch_timed(c, p->fp64, b, at(ws, L.psi), at(ws, L.w),
                                    at(ws, L.tmp), epart, st, ev);
@@ -569,7 +778,7 @@ static hipError_t enqueue_batch(const lace_plan* p, const CellDev& c,
 // Pair pipeline over a schedule, energy reduction, W back to plane waves.
 // Requires the grid orbitals in the workspace.
 static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
-                                   const std::vector<PairArgs>& sched,
+                                   const std::vector<Batch>& sched,
                                    const Layout& L, void* ws, void* w_g,
                                    double* e_x, hipStream_t st, bool profile) {
   const bool fp64 = p->fp64;
@@ -594,7 +803,7 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
       if (!ev[0] || !ev[1] || !ev[2] || !ev[3]) return hipErrorOutOfMemory;
       Profile::Rec r;
       r.ev = first;
-      r.pairs = sched[b].n;
+      r.pairs = sched[b].p.n;
       batch_bytes(p, c, sched[b], r.bytes);
       pr.recs.push_back(r);
       e = enqueue_batch(p, c, sched[b], L, ws, epart, st, ev);
@@ -671,8 +880,8 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
       all_pairs(n_orb, pairs);
     }
   }
-  std::vector<PairArgs> sched;
-  build_schedule(pairs, n_orb, c.ppb, sched);
+  std::vector<Batch> sched;
+  schedule_for(p, pairs, n_orb, c.ppb, sched);
   e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true);
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();
@@ -740,10 +949,35 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
     if (i < 0 || j < i || j >= n_orb) return LACE_EINVAL;
     pairs.emplace_back(i, j);
   }
-  std::vector<PairArgs> sched;
+  std::vector<Batch> sched;
   std::vector<int32_t> bo;
   build_schedule(pairs, n_orb, per_batch, sched, &bo);
   for (int64_t k = 0; k < n_pairs; ++k) batch_of[k] = bo[k];
+  *n_batches = (int64_t)sched.size();
+  return LACE_OK;
+}
+
+int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
+                        int64_t n_pairs, int n_orb, int per_batch,
+                        int32_t* batch_of, int32_t* slot_of,
+                        int64_t* n_batches) {
+  if (!pair_i || !pair_j || !batch_of || !slot_of || !n_batches ||
+      n_pairs < 0 || n_orb < 1 || per_batch < 1 || per_batch > PMAX)
+    return LACE_EINVAL;
+  std::vector<std::pair<int, int>> pairs;
+  pairs.reserve(n_pairs);
+  for (int64_t k = 0; k < n_pairs; ++k) {
+    const int i = pair_i[k], j = pair_j[k];
+    if (i < 0 || j < i || j >= n_orb) return LACE_EINVAL;
+    pairs.emplace_back(i, j);
+  }
+  std::vector<Batch> sched;
+  std::vector<int32_t> bo, so;
+  build_slot_schedule(pairs, n_orb, per_batch, sched, &bo, &so);
+  for (int64_t k = 0; k < n_pairs; ++k) {
+    batch_of[k] = bo[k];
+    slot_of[k] = so[k];
+  }
   *n_batches = (int64_t)sched.size();
   return LACE_OK;
 }
@@ -783,10 +1017,11 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   std::vector<std::pair<int, int>> pairs;
   all_pairs(n_orb, pairs);
   {
-    std::vector<PairArgs> full;
+    std::vector<Batch> full;
     build_schedule(pairs, n_orb, PMAX, full);
     pairs.clear();
-    for (const auto& b : full) {
+    for (const auto& bt : full) {
+      const PairArgs& b = bt.p;
       for (int q = 0; q < b.n && pairs.size() < (size_t)(4 * PMAX); ++q)
         pairs.emplace_back(b.i[q], b.j[q]);
       if (pairs.size() >= (size_t)(4 * PMAX)) break;
@@ -806,8 +1041,8 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   for (auto& cd : cands) {
     c.ppb = cd.ppb;
     c.use_plane = cd.plane;
-    std::vector<PairArgs> sched;
-    build_schedule(pairs, n_orb, cd.ppb, sched);
+    std::vector<Batch> sched;
+    schedule_for(p, pairs, n_orb, cd.ppb, sched);
     double best = 1e30;
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       const bool fp = fp64;
@@ -934,7 +1169,7 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     }
   }
   if (e != hipSuccess) return LACE_EHIP;
-  std::vector<std::vector<PairArgs>> scheds(n_jobs);
+  std::vector<std::vector<Batch>> scheds(n_jobs);
   {
     std::vector<std::vector<double>> hs(n_jobs);
     for (int k = 0; k < n_jobs && e == hipSuccess; ++k) {
@@ -954,8 +1189,8 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
       if (jobs[k].s_thr > 0.0) kept_from_s(hs[k], jobs[k].n_orb, jobs[k].s_thr, pairs);
       else all_pairs(jobs[k].n_orb, pairs);
       jobs[k].n_kept = (int64_t)pairs.size();
-      build_schedule(pairs, jobs[k].n_orb, p->cells[jobs[k].cell].dev.ppb,
-                     scheds[k]);
+      schedule_for(p, pairs, jobs[k].n_orb, p->cells[jobs[k].cell].dev.ppb,
+                   scheds[k]);
     }
   }
   // phase 2: pair pipelines, back-transforms, ACE builds
@@ -994,10 +1229,15 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
                        (uint64_t)scheds[k].size()})
       hash_mix(key, v);
     uint64_t h = 1469598103934665603ull;
-    for (const auto& b : scheds[k])
-      for (int q = 0; q < b.n; ++q) {
-        h = (h ^ (uint64_t)(b.i[q] * 65536 + b.j[q] + 1)) * 1099511628211ull;
-      }
+    for (const auto& bt : scheds[k]) {
+      for (int q = 0; q < bt.p.n; ++q)
+        h = (h ^ (uint64_t)(bt.p.i[q] * 65536 + bt.p.j[q] + 1)) *
+            1099511628211ull;
+      for (int q = 0; q < bt.q.n; ++q)
+        for (int v : {bt.q.i[q], bt.q.j[q], bt.q.k[q], bt.q.l[q]})
+          h = (h ^ (uint64_t)(v + 2)) * 1099511628211ull;
+      h = (h ^ 0x9e3779b97f4a7c15ull) * 1099511628211ull;   // batch boundary
+    }
     hash_mix(key, h);
   }
   // the origin stream waits for phase 1 on every internal stream

@@ -39,6 +39,7 @@ SYMBOLS = (
     "lace_screen", "lace_apply_exchange", "lace_build_ace", "lace_apply_ace",
     "lace_fft3d", "lace_get_info", "lace_status_string",
     "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
+    "lace_schedule_slots",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
     "lace_autotune", "lace_check_real",
 )
@@ -110,6 +111,8 @@ def load(path: str = LIB_PATH):
                                     ctypes.POINTER(ctypes.c_double)]
     lib.lace_schedule_pairs.argtypes = [p_i32, p_i32, i64, i32, i32, p_i32,
                                         p_i64]
+    lib.lace_schedule_slots.argtypes = [p_i32, p_i32, i64, i32, i32, p_i32,
+                                        p_i32, p_i64]
     lib.lace_apply_exchange_batched.argtypes = [vp, ctypes.POINTER(LaceJob),
                                                 i32, i32, vp]
     lib.lace_set_tuning.argtypes = [vp, i32, i32, i32]
@@ -321,6 +324,24 @@ def lace_schedule_pairs(pairs, n_orb, per_batch):
                                       out.ctypes.data_as(P), ctypes.byref(nb)),
            "lace_schedule_pairs")
     return out, nb.value
+
+
+def lace_schedule_slots(pairs, n_orb, per_batch):
+    """Batch and slot of every pair for plans of real orbitals (host only).
+    Returns (batch_of, slot_of, n)."""
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    pi = np.ascontiguousarray(pr[:, 0])
+    pj = np.ascontiguousarray(pr[:, 1])
+    bo = np.empty(pr.shape[0], dtype=np.int32)
+    so = np.empty(pr.shape[0], dtype=np.int32)
+    nb = ctypes.c_int64(0)
+    P = ctypes.POINTER(ctypes.c_int32)
+    _check(load().lace_schedule_slots(pi.ctypes.data_as(P), pj.ctypes.data_as(P),
+                                      pr.shape[0], int(n_orb), int(per_batch),
+                                      bo.ctypes.data_as(P), so.ctypes.data_as(P),
+                                      ctypes.byref(nb)),
+           "lace_schedule_slots")
+    return bo, so, nb.value
 
 
 def _vp(t):

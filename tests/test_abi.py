@@ -130,3 +130,68 @@ def test_schedule_rejects_bad_pairs(lib):
         lace.lace_schedule_pairs([(0, 4)], 4, 4)
     with pytest.raises(lace.LaceError):
         lace.lace_schedule_pairs([(0, 1)], 4, 65)
+
+
+def _check_slots(pairs, n_orb, per_batch):
+    """Slot schedule of real-orbital plans: every pair placed once; a slot
+    holds one pair or two of the same kind; slots of one batch share no
+    orbital; batch capacities hold.  Returns (batches, slots, star slots)."""
+    bo, so, nb = lace.lace_schedule_slots(pairs, n_orb, per_batch)
+    assert bo.min() >= 0 and bo.max() == nb - 1 and so.min() >= 0
+    n_slots = n_star = 0
+    for b in range(nb):
+        ks = np.nonzero(bo == b)[0]
+        assert 1 <= len(ks) <= per_batch
+        slots = {}
+        for k in ks:
+            slots.setdefault(int(so[k]), []).append(tuple(pairs[k]))
+        assert sorted(slots) == list(range(len(slots)))
+        assert len(slots) <= (per_batch + 1) // 2
+        seen = []
+        for members in slots.values():
+            assert 1 <= len(members) <= 2
+            if len(members) == 2:
+                diag = [i == j for i, j in members]
+                assert diag[0] == diag[1], "pairs of different kinds packed"
+            orbs = {o for p in members for o in p}
+            if len(members) == 2 and not diag[0] and len(orbs) == 3:
+                n_star += 1
+            seen += sorted(orbs)
+        assert len(seen) == len(set(seen)), "orbital in two slots of a batch"
+        n_slots += len(slots)
+    return nb, n_slots, n_star
+
+
+@pytest.mark.parametrize("n_orb,per_batch", [(8, 4), (256, 64), (255, 32),
+                                             (33, 16), (128, 64), (5, 1)])
+def test_slot_schedule_complete_pair_set(lib, n_orb, per_batch):
+    pairs = [(i, j) for j in range(n_orb) for i in range(j + 1)]
+    nb, n_slots, n_star = _check_slots(pairs, n_orb, per_batch)
+    if per_batch == 1:
+        assert n_slots == len(pairs) and nb == len(pairs)
+        return
+    n_off = n_orb * (n_orb - 1) // 2
+    # almost every off-diagonal pair sits in a star slot
+    assert 2 * n_star >= 0.95 * n_off - n_orb
+    assert n_slots <= (len(pairs) + 1) // 2 + n_orb
+    if n_orb >= 128:   # batches nearly full
+        assert nb <= 1.1 * len(pairs) / per_batch + 8
+
+
+@pytest.mark.parametrize("keep", [0.7, 0.3])
+def test_slot_schedule_screened_pair_set(lib, keep):
+    rng = np.random.default_rng(int(keep * 10) + 1)
+    n_orb, per_batch = 256, 64
+    pairs = [(i, j) for j in range(n_orb) for i in range(j + 1)
+             if i == j or rng.random() < keep]
+    nb, n_slots, n_star = _check_slots(pairs, n_orb, per_batch)
+    n_off = sum(1 for i, j in pairs if i != j)
+    assert 2 * n_star >= 0.8 * n_off
+    assert nb <= 1.25 * len(pairs) / per_batch + 16
+
+
+def test_slot_schedule_rejects_bad_pairs(lib):
+    for pairs, n, pb in (([(2, 1)], 4, 4), ([(0, 4)], 4, 4), ([(0, 1)], 4, 65),
+                         ([(0, 1)], 4, 0)):
+        with pytest.raises(lace.LaceError):
+            lace.lace_schedule_slots(pairs, n, pb)
