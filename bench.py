@@ -230,8 +230,11 @@ def serving_rows(torch, seed, n_jobs):
 def pmc_sample(torch, seed):
     """Fixed small workload for counter collection: a plain 1 GiB device
     copy (the calibration of FETCH_SIZE / WRITE_SIZE), then one exchange
-    application over 128 off-diagonal pairs of the localized 120^3
-    workload (4 full batches of the pair pipeline)."""
+    application over 512 off-diagonal pairs of the localized 120^3
+    workload in the real-orbital mode: four rounds of a round-robin
+    tournament over the 256 orbitals, packed into star slots, 8 full
+    batches of the pair pipeline.  Prints the library's algorithmic bytes
+    per pass for the comparison with the counters."""
     import numpy as np
     import synth
     from paper_1801_09263_amd import lace
@@ -245,11 +248,17 @@ def pmc_sample(torch, seed):
     n_orb = inp["coeffs"].shape[0]
     sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA)
     sess.set_orbitals(inp["coeffs"])
-    # 128 disjoint-friendly pairs: two round-robin rounds of 64 each
-    pairs = [(i, i + 128) for i in range(128)]
+    lace.lace_set_tuning(sess.plan, 0, 64, 2)
+    m = n_orb - 1                       # n_orb even: rounds of n_orb / 2 pairs
+    pairs = [(i, j) for j in range(n_orb) for i in range(j)
+             if (i if j == m else ((i + j) * (n_orb // 2)) % m) < 4]
+    lace.lace_profile_enable(sess.plan, True)
     sess.apply_exchange(0.0, pairs=np.array(pairs))
     torch.cuda.synchronize()
-    print(json.dumps({"pmc_sample": "ok", "pairs": len(pairs)}), flush=True)
+    prof = lace.lace_profile_read(sess.plan)
+    print(json.dumps({"pmc_sample": "ok", "pairs": len(pairs),
+                      "launches": prof["launches"],
+                      "alg_bytes": prof["alg_bytes"]}), flush=True)
 
 
 def main():
@@ -268,6 +277,10 @@ def main():
                     help="skip the serving stream row")
     ap.add_argument("--serve-jobs", type=int, default=48,
                     help="jobs in the serving stream")
+    ap.add_argument("--tuning", default=None, metavar="PPB,MODE",
+                    help="fixed pipeline tuning (pairs per batch, xy schedule "
+                         "0 pencil / 1 plane / 2 half plane) instead of "
+                         "autotuning the main workload")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="small fixed run for hardware-counter passes: a "
                          "1 GiB copy (calibration) and 4 pair batches of "
@@ -297,10 +310,16 @@ def main():
     sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA, n_vec=n_orb)
     sess.set_orbitals(inp["coeffs"])
     real_dev = sess.check_real()
-    log(f"orbitals real to {real_dev:.1e}; autotuning the pair pipeline")
-    cands = lace.lace_autotune(sess.plan, 0, sess.psi, n_orb, sess.ws)
+    if args.tuning:
+        ppb, mode = (int(v) for v in args.tuning.split(","))
+        lace.lace_set_tuning(sess.plan, 0, ppb, mode)
+        log(f"orbitals real to {real_dev:.1e}; fixed tuning")
+    else:
+        log(f"orbitals real to {real_dev:.1e}; autotuning the pair pipeline")
+        cands = lace.lace_autotune(sess.plan, 0, sess.psi, n_orb, sess.ws)
+        log("candidates", cands)
     tuning = lace.lace_get_tuning(sess.plan, 0)
-    log("tuning", tuning, cands)
+    log("tuning", tuning)
     log(f"timing {args.steps} steps after {args.warmup} warmup")
     n_kept, t_step, prof = time_steps(torch, sess, inp["s_thr"], args.steps,
                                       args.warmup, profile=True)
