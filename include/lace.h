@@ -140,6 +140,31 @@ int lace_apply_exchange(lace_plan* plan, int cell, const void* psi_g,
                         double* e_x, int64_t* n_kept, void* ws,
                         size_t ws_bytes, lace_stream_t stream);
 
+/* W = K psi for occupied plus virtual orbitals (the band-gap setting of the
+ * silica results in Sec. 3: the projection space holds the occupied
+ * orbitals and a few virtual ones).  The exchange operator sums over the
+ * occupied orbitals only (Eq. (2)); the occupied pairs are screened with
+ * s_thr among themselves (Eq. (6)), and every integral that involves a
+ * virtual orbital is evaluated.  An occupied x virtual pair (i, v) adds
+ * -psi_i V_iv to W_v only and nothing to E_x.
+ *   psi_g   device, n_pw x (n_occ + n_virt) complex128, orthonormal, the
+ *           n_occ occupied orbitals first.
+ *   w_g     device, n_pw x (n_occ + n_virt) complex128 output.
+ *   e_x     device double (may be NULL): the exchange energy of the
+ *           occupied orbitals, as for lace_apply_exchange.
+ *   n_kept  host int64 (may be NULL): pair transforms run (kept occupied
+ *           pairs + n_occ n_virt).
+ * The workspace is that of n_orb = n_occ + n_virt.  lace_build_ace with
+ * n_orb = n_occ + n_virt then builds ACE on the whole projection space
+ * (its ex_tr then includes the virtual diagonal and is not E_x).  Same
+ * synchronization and errors as lace_apply_exchange (n_occ >= 1,
+ * n_virt >= 0). */
+int lace_apply_exchange_virtual(lace_plan* plan, int cell, const void* psi_g,
+                                int n_occ, int n_virt, double s_thr,
+                                void* w_g, double* e_x, int64_t* n_kept,
+                                void* ws, size_t ws_bytes,
+                                lace_stream_t stream);
+
 /* ACE projector from psi and W = K psi (Eqs. (3)-(5), (9)).
  *   m_out   device n_orb x n_orb complex128 (may be NULL): M = psi^H W.
  *   xi_g    device n_pw x n_orb complex128 output: xi = W L^{-H} with

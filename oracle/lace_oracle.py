@@ -42,7 +42,7 @@ __all__ = [
     "apply_exchange_to", "grid_to_pw", "exchange_matrix",
     "exchange_energy_trace", "exchange_energy_pairs", "symmetrize",
     "cholesky_neg", "NotPositiveDefinite", "projector", "apply_ace",
-    "run_path",
+    "run_path", "apply_exchange_virtual", "run_path_virtual",
 ]
 
 
@@ -309,3 +309,36 @@ def run_path(coeffs, miller, L, n, s_thr=0.0, rc=None, sym="avg",
     if want_grid:
         out.update(psi=psi, W=w, v=v)
     return out
+
+
+def apply_exchange_virtual(psi: np.ndarray, v: np.ndarray, n_occ: int,
+                           pairs=None) -> np.ndarray:
+    """W for the occupied orbitals psi[:n_occ] and the virtual ones after
+    them (the projection space of the band-gap runs in Sec. 3).  K sums
+    over the occupied orbitals only (Eq. (2)).  Occupied columns keep the
+    screened occupied pairs (Eqs. (7)-(8)); every integral that involves a
+    virtual orbital is evaluated, so a virtual column is K applied to that
+    function."""
+    w_occ = apply_exchange(psi[:n_occ], v, pairs)
+    w_virt = apply_exchange_to(psi[:n_occ], psi[n_occ:], v)
+    return np.concatenate([w_occ, w_virt])
+
+
+def run_path_virtual(coeffs, n_occ, miller, L, n, s_thr=0.0, rc=None,
+                     sym="avg"):
+    """``run_path`` on occupied plus virtual orbitals (occupied first):
+    screening among the occupied orbitals, W of all of them, M, Cholesky
+    and xi over the whole projection space; E_x from the occupied pairs."""
+    psi = orbitals_on_grid(coeffs, miller, L, n)
+    v = coulomb_kernel(L, n, rc)
+    s = overlap_of_moduli(psi[:n_occ], L)
+    pairs = kept_pairs(s, s_thr)
+    w = apply_exchange_virtual(psi, v, n_occ, pairs)
+    w_pw = grid_to_pw(w, miller, L)
+    m = exchange_matrix(coeffs, w_pw)
+    ex_pairs = exchange_energy_pairs(psi[:n_occ], v, L, pairs)
+    ms = symmetrize(m, sym)
+    chol = cholesky_neg(ms)
+    xi = projector(w_pw, chol)
+    return dict(S=s, pairs=pairs, W_pw=w_pw, M=m, Ms=ms, L=chol, xi=xi,
+                ex_pairs=ex_pairs, psi=psi, v=v)

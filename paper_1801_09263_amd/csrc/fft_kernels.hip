@@ -113,15 +113,19 @@ template <typename T> struct EpiAcc {
   int64_t gs;
   PairArgs pa;
   __device__ void prev(int g, int slot, Pre& r) const {
-    // a diagonal pair reads its orbital twice (from cache); stores decide
+    // a diagonal pair reads its orbital twice (from cache), and so does a
+    // one-sided pair its psi_i and W_j; the stores decide
     const int i = pa.i[slot], j = pa.j[slot];
+    const bool os = (pa.one_sided >> slot) & 1ull;
+    const int jj = os ? i : j, ii = os ? j : i;
     r.pi = ldv<C<T>, V>(psi + i * gs + g);
     r.wj = ldv<C<T>, V>(w + j * gs + g);
-    r.pj = ldv<C<T>, V>(psi + j * gs + g);
-    r.wi = ldv<C<T>, V>(w + i * gs + g);
+    r.pj = ldv<C<T>, V>(psi + jj * gs + g);
+    r.wi = ldv<C<T>, V>(w + ii * gs + g);
   }
   __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
     const int i = pa.i[slot], j = pa.j[slot];
+    const bool os = (pa.one_sided >> slot) & 1ull;
     Vec<C<T>, V> yj, yi;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -129,7 +133,7 @@ template <typename T> struct EpiAcc {
       yi.e[v] = sub<T>(r.wi.e[v], mulc<T>(r.pj.e[v], x[v]));
     }
     stv<C<T>, V>(w + j * gs + g, yj);
-    if (i != j) stv<C<T>, V>(w + i * gs + g, yi);
+    if (i != j && !os) stv<C<T>, V>(w + i * gs + g, yi);
   }
 };
 
@@ -159,6 +163,8 @@ template <typename T> struct QuadPre {
 // V = V_ij + i V_kl (both real):  W_j -= psi_i V_ij, W_i -= psi_j V_ij,
 // W_l -= psi_k V_kl, W_k -= psi_l V_kl (one update for a diagonal pair).
 // A star slot (k = i) folds both updates of the shared orbital into one.
+// A skipped W is neither updated nor read, nor is the orbital paired with
+// it: those loads repeat the pair's other orbital (served by the cache).
 template <typename T> struct EpiAccQuad {
   static constexpr int V = 16 / sizeof(T);
   static constexpr int CH = 2;
@@ -167,35 +173,44 @@ template <typename T> struct EpiAccQuad {
   T* __restrict__ w;
   int64_t gs;
   QuadArgs qa;
+  __device__ void flags(int slot, bool s[4]) const {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) s[t] = (qa.skip[t] >> slot) & 1ull;
+  }
   __device__ void prev(int g, int slot, Pre& r) const {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    bool sk[4];
+    flags(slot, sk);
     const int kk = k >= 0 ? k : i, ll = k >= 0 ? l : i;
-    r.pi = ldv<T, V>(psi + i * gs + g);
-    r.wj = ldv<T, V>(w + j * gs + g);
-    r.pj = ldv<T, V>(psi + j * gs + g);
-    r.wi = ldv<T, V>(w + i * gs + g);
-    r.pk = ldv<T, V>(psi + kk * gs + g);
-    r.wl = ldv<T, V>(w + ll * gs + g);
-    r.pl = ldv<T, V>(psi + ll * gs + g);
-    r.wk = ldv<T, V>(w + kk * gs + g);
+    r.pi = ldv<T, V>(psi + (sk[1] ? j : i) * gs + g);
+    r.wj = ldv<T, V>(w + (sk[1] ? i : j) * gs + g);
+    r.pj = ldv<T, V>(psi + (sk[0] ? i : j) * gs + g);
+    r.wi = ldv<T, V>(w + (sk[0] ? j : i) * gs + g);
+    r.pk = ldv<T, V>(psi + (sk[3] ? ll : kk) * gs + g);
+    r.wl = ldv<T, V>(w + (sk[3] ? kk : ll) * gs + g);
+    r.pl = ldv<T, V>(psi + (sk[2] ? kk : ll) * gs + g);
+    r.wk = ldv<T, V>(w + (sk[2] ? ll : kk) * gs + g);
   }
   __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    bool sk[4];
+    flags(slot, sk);
     const bool star = k == i;
+    const bool up_i = !sk[0] || (star && !sk[2]);
     Vec<T, V> yj, yi, yl, yk;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       yj.e[v] = r.wj.e[v] - r.pi.e[v] * x[v].x;
-      yi.e[v] = r.wi.e[v] - r.pj.e[v] * x[v].x;
+      yi.e[v] = r.wi.e[v] - (sk[0] ? T(0) : r.pj.e[v] * x[v].x);
       yl.e[v] = r.wl.e[v] - r.pk.e[v] * x[v].y;
       yk.e[v] = r.wk.e[v] - r.pl.e[v] * x[v].y;
-      if (star) yi.e[v] -= r.pl.e[v] * x[v].y;
+      if (star && !sk[2]) yi.e[v] -= r.pl.e[v] * x[v].y;
     }
-    stv<T, V>(w + j * gs + g, yj);
-    if (i != j) stv<T, V>(w + i * gs + g, yi);
+    if (!sk[1]) stv<T, V>(w + j * gs + g, yj);
+    if (i != j && up_i) stv<T, V>(w + i * gs + g, yi);
     if (k >= 0) {
-      stv<T, V>(w + l * gs + g, yl);
-      if (k != l && !star) stv<T, V>(w + k * gs + g, yk);
+      if (!sk[3]) stv<T, V>(w + l * gs + g, yl);
+      if (k != l && !star && !sk[2]) stv<T, V>(w + k * gs + g, yk);
     }
   }
 };
@@ -500,7 +515,8 @@ __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
     const double tot = block_sum<NT>(e[sl], red);
     if (threadIdx.x == 0 && sl < nsl) {
       const int slot = slot0 + sl;
-      const double wgt = (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
+      const double wgt = ((pa.one_sided >> slot) & 1ull) ? 0.0
+                         : (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
       epart[slot * ntiles + tile] += wgt * tot;
     }
     __syncthreads();   // red is reused by the next slot
@@ -695,6 +711,7 @@ template <typename T, int N> struct Engine {
     // energy weights: both pairs of a slot are of the same kind
     PairArgs pw;
     pw.n = cnt;
+    pw.one_sided = qa.one_sided;
     for (int q = 0; q < cnt; ++q) { pw.i[q] = qa.i[q]; pw.j[q] = qa.j[q]; }
     const int mode = (c.use_plane == 1 && !Cf::plane) ? 0 : c.use_plane;
     hipError_t err;

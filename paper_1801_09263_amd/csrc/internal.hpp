@@ -11,6 +11,9 @@ struct PairArgs {
   int n;
   int i[PMAX];
   int j[PMAX];
+  // bit q: pair q is one-sided, an occupied orbital i applied to a virtual
+  // orbital j: only W_j is updated and the pair adds nothing to E_x
+  uint64_t one_sided;
 };
 
 // Real (Gamma-point) orbitals: two pair densities of the same kind (both
@@ -22,6 +25,11 @@ constexpr int QMAX = PMAX / 2 + 1;
 struct QuadArgs {
   int n;
   int i[QMAX], j[QMAX], k[QMAX], l[QMAX];
+  // bit q of skip[0..3]: W_i, W_j, W_k, W_l of slot q is not updated (the
+  // occupied orbital of a one-sided pair); bit q of one_sided: the slot
+  // holds one-sided pairs and adds nothing to E_x
+  uint64_t skip[4];
+  uint64_t one_sided;
 };
 
 // Geometry and device tables of one cell, shared by all launchers.

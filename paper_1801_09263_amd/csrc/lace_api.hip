@@ -208,7 +208,8 @@ struct Batch {
 static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
                            int n_orb, int per_batch,
                            std::vector<Batch>& outb,
-                           std::vector<int32_t>* batch_of = nullptr) {
+                           std::vector<int32_t>* batch_of = nullptr,
+                           const std::vector<char>* one_sided = nullptr) {
   std::vector<PairArgs> out;
   const int nv = n_orb + (n_orb & 1);
   std::vector<int> order(pairs.size());
@@ -236,6 +237,7 @@ static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
       const bool uj = (ob.used[j / 64] >> (j % 64)) & 1ull;
       if (ui || uj) continue;
       PairArgs& b = out[ob.idx];
+      if (one_sided && (*one_sided)[k]) b.one_sided |= 1ull << b.n;
       b.i[b.n] = i; b.j[b.n] = j; ++b.n;
       if (batch_of) (*batch_of)[k] = (int32_t)ob.idx;
       ob.used[i / 64] |= 1ull << (i % 64);
@@ -248,6 +250,7 @@ static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
     PairArgs b;
     std::memset(&b, 0, sizeof(b));
     b.n = 1; b.i[0] = i; b.j[0] = j;
+    if (one_sided && (*one_sided)[k]) b.one_sided = 1ull;
     out.push_back(b);
     if (batch_of) (*batch_of)[k] = (int32_t)(out.size() - 1);
     if (per_batch > 1) {
@@ -281,6 +284,7 @@ static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
 struct Slot {
   int i, j, k, l;   // k = l = -1: a single pair; k = i: a star slot
   int pk[2];        // the slot's pairs (indices into the pair list, or -1)
+  bool os;          // one-sided pairs (occupied x virtual)
 };
 
 static int slot_orbitals(const Slot& s, int o[4]) {
@@ -299,6 +303,7 @@ static Slot make_slot(const std::vector<std::pair<int, int>>& pairs, int a,
   Slot s;
   s.pk[0] = a;
   s.pk[1] = b;
+  s.os = false;
   int i = pairs[a].first, j = pairs[a].second;
   if (b < 0) {
     s.i = i; s.j = j; s.k = s.l = -1;
@@ -359,29 +364,15 @@ static void trail_slots(const std::vector<std::pair<int, int>>& pairs,
     if (!done[e]) walk(pairs[e].first);
 }
 
-static void make_slots(const std::vector<std::pair<int, int>>& pairs,
-                       int n_orb, bool pack, std::vector<Slot>& slots) {
-  slots.clear();
-  if (!pack) {
-    for (size_t k = 0; k < pairs.size(); ++k)
-      slots.push_back(make_slot(pairs, (int)k, -1));
-    return;
-  }
+// Off-diagonal pairs of one kind (two-sided, or one-sided) into slots.
+static void star_slots(const std::vector<std::pair<int, int>>& pairs,
+                       std::vector<int> off, int n_orb, std::vector<char>& done,
+                       std::vector<Slot>& slots) {
   const int nv = n_orb + (n_orb & 1);
-  std::vector<int> off, diag, left, rest;
-  std::vector<int> round(pairs.size(), 0);
-  for (size_t k = 0; k < pairs.size(); ++k) {
-    if (pairs[k].first == pairs[k].second) {
-      diag.push_back((int)k);
-    } else {
-      off.push_back((int)k);
-      round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
-    }
-  }
+  std::vector<int> round(pairs.size(), 0), left, rest, group;
+  for (int k : off) round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
   std::stable_sort(off.begin(), off.end(),
                    [&](int a, int b) { return round[a] < round[b]; });
-  std::vector<int> group;
-  std::vector<char> done(pairs.size(), 0);
   for (size_t a = 0; a < off.size();) {
     const int g = round[off[a]] / 2;
     group.clear();
@@ -393,6 +384,31 @@ static void make_slots(const std::vector<std::pair<int, int>>& pairs,
   for (size_t t = 0; t < rest.size(); t += 2)
     slots.push_back(make_slot(pairs, rest[t],
                               t + 1 < rest.size() ? rest[t + 1] : -1));
+}
+
+static void make_slots(const std::vector<std::pair<int, int>>& pairs,
+                       int n_orb, bool pack, std::vector<Slot>& slots,
+                       const std::vector<char>* one_sided) {
+  slots.clear();
+  auto is_os = [&](int k) { return one_sided && (*one_sided)[k]; };
+  if (!pack) {
+    for (size_t k = 0; k < pairs.size(); ++k) {
+      slots.push_back(make_slot(pairs, (int)k, -1));
+      slots.back().os = is_os((int)k);
+    }
+    return;
+  }
+  std::vector<int> off, offo, diag;
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    if (is_os((int)k)) offo.push_back((int)k);
+    else if (pairs[k].first == pairs[k].second) diag.push_back((int)k);
+    else off.push_back((int)k);
+  }
+  std::vector<char> done(pairs.size(), 0);
+  star_slots(pairs, off, n_orb, done, slots);
+  const size_t first_os = slots.size();
+  star_slots(pairs, offo, n_orb, done, slots);
+  for (size_t t = first_os; t < slots.size(); ++t) slots[t].os = true;
   for (size_t t = 0; t < diag.size(); t += 2)
     slots.push_back(make_slot(pairs, diag[t],
                               t + 1 < diag.size() ? diag[t + 1] : -1));
@@ -405,10 +421,12 @@ static void build_slot_schedule(const std::vector<std::pair<int, int>>& pairs,
                                 int n_orb, int per_batch,
                                 std::vector<Batch>& out,
                                 std::vector<int32_t>* batch_of = nullptr,
-                                std::vector<int32_t>* slot_of = nullptr) {
+                                std::vector<int32_t>* slot_of = nullptr,
+                                const std::vector<char>* one_sided = nullptr,
+                                int n_occ = -1) {
   out.clear();
   std::vector<Slot> slots;
-  make_slots(pairs, n_orb, per_batch >= 2, slots);
+  make_slots(pairs, n_orb, per_batch >= 2, slots, one_sided);
   if (batch_of) batch_of->assign(pairs.size(), -1);
   if (slot_of) slot_of->assign(pairs.size(), -1);
   const int cap_slots = (per_batch + 1) / 2;
@@ -423,11 +441,18 @@ static void build_slot_schedule(const std::vector<std::pair<int, int>>& pairs,
     Batch& b = out[idx];
     const int q = b.q.n++;
     b.q.i[q] = sl.i; b.q.j[q] = sl.j; b.q.k[q] = sl.k; b.q.l[q] = sl.l;
+    if (sl.os) {   // the occupied orbital of a one-sided pair keeps its W
+      b.q.one_sided |= 1ull << q;
+      const int pos[4] = {sl.i, sl.j, sl.k, sl.l};
+      for (int t = 0; t < 4; ++t)
+        if (pos[t] >= 0 && pos[t] < n_occ) b.q.skip[t] |= 1ull << q;
+    }
     for (int t = 0; t < 2; ++t) {
       const int k = sl.pk[t];
       if (k < 0) continue;
       b.p.i[b.p.n] = pairs[k].first;
       b.p.j[b.p.n] = pairs[k].second;
+      if (sl.os) b.p.one_sided |= 1ull << b.p.n;
       ++b.p.n;
       if (batch_of) (*batch_of)[k] = (int32_t)idx;
       if (slot_of) (*slot_of)[k] = q;
@@ -468,11 +493,18 @@ static void build_slot_schedule(const std::vector<std::pair<int, int>>& pairs,
   }
 }
 
+// one_sided (optional): per pair, occupied x virtual; n_occ: orbitals
+// below it are occupied.
 static void schedule_for(const lace_plan* p,
                          const std::vector<std::pair<int, int>>& pairs,
-                         int n_orb, int per_batch, std::vector<Batch>& out) {
-  if (p->gamma) build_slot_schedule(pairs, n_orb, per_batch, out);
-  else build_schedule(pairs, n_orb, per_batch, out);
+                         int n_orb, int per_batch, std::vector<Batch>& out,
+                         const std::vector<char>* one_sided = nullptr,
+                         int n_occ = -1) {
+  if (p->gamma)
+    build_slot_schedule(pairs, n_orb, per_batch, out, nullptr, nullptr,
+                        one_sided, n_occ);
+  else
+    build_schedule(pairs, n_orb, per_batch, out, nullptr, one_sided);
 }
 
 // ------------------------------------------------------------------ API
@@ -742,22 +774,42 @@ static void batch_bytes(const lace_plan* p, const CellDev& c, const Batch& bt,
                         double out[3]) {
   const double U = double(c.ng) * grid_bytes(p);
   const double G = double(c.ng) * orb_bytes(p);
-  double orbs = 0.0, slots = 0.0;
+  // orbs: orbital grids read by pass A; orbs_c: orbital grids read by pass
+  // C plus twice the W grids it updates
+  double orbs = 0.0, orbs_c = 0.0, slots = 0.0;
   if (p->gamma) {
     for (int q = 0; q < bt.q.n; ++q) {
-      const Slot sl{bt.q.i[q], bt.q.j[q], bt.q.k[q], bt.q.l[q], {-1, -1}};
-      int o[4];
-      orbs += slot_orbitals(sl, o);
+      const int pos[4] = {bt.q.i[q], bt.q.j[q], bt.q.k[q], bt.q.l[q]};
+      const int mate[4] = {1, 0, 3, 2};
+      int all[4], upd[4], rd[4], na = 0, nu = 0, nr = 0;
+      auto add = [](int* set, int& n, int v) {
+        for (int t = 0; t < n; ++t) if (set[t] == v) return;
+        set[n++] = v;
+      };
+      for (int t = 0; t < 4; ++t) {
+        if (pos[t] < 0) continue;
+        add(all, na, pos[t]);
+        if (!((bt.q.skip[t] >> q) & 1ull)) {
+          add(upd, nu, pos[t]);
+          add(rd, nr, pos[mate[t]]);
+        }
+      }
+      orbs += na;
+      orbs_c += nr + 2 * nu;
     }
     slots = bt.q.n;
   } else {
-    for (int k = 0; k < bt.p.n; ++k)
-      orbs += (bt.p.i[k] == bt.p.j[k]) ? 1.0 : 2.0;
+    for (int k = 0; k < bt.p.n; ++k) {
+      const bool diag = bt.p.i[k] == bt.p.j[k];
+      const bool os = (bt.p.one_sided >> k) & 1ull;
+      orbs += diag ? 1.0 : 2.0;
+      orbs_c += (diag || os) ? 3.0 : 6.0;
+    }
     slots = bt.p.n;
   }
   out[0] = orbs * G + slots * U;
   out[1] = 2.0 * slots * U;
-  out[2] = slots * U + 3.0 * orbs * G;
+  out[2] = slots * U + orbs_c * G;
 }
 
 // One batch of the pair pipeline (pairs, or packed slots for Gamma plans).
@@ -882,6 +934,52 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   }
   std::vector<Batch> sched;
   schedule_for(p, pairs, n_orb, c.ppb, sched);
+  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true);
+  if (e != hipSuccess) return LACE_EHIP;
+  if (n_kept) *n_kept = (int64_t)pairs.size();
+  return LACE_OK;
+}
+
+int lace_apply_exchange_virtual(lace_plan* p, int cell, const void* psi_g,
+                                int n_occ, int n_virt, double s_thr, void* w_g,
+                                double* e_x, int64_t* n_kept, void* ws,
+                                size_t ws_bytes, lace_stream_t stream) {
+  if (n_occ < 1 || n_virt < 0) return LACE_EINVAL;
+  const int n_orb = n_occ + n_virt;
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_g || !w_g || !ws) return LACE_EINVAL;
+  if (!(s_thr >= 0.0 && s_thr < 1.0)) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  const CellDev& c = p->cells[cell].dev;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
+  if (e != hipSuccess) return LACE_EHIP;
+  // occupied pairs, screened among the occupied orbitals
+  std::vector<std::pair<int, int>> pairs;
+  if (s_thr > 0.0) {
+    double* s = reinterpret_cast<double*>(at(ws, L.s));
+    e = enqueue_screen(p, c, n_occ, L, ws, s, st);
+    if (e != hipSuccess) return LACE_EHIP;
+    std::vector<double> hs((size_t)n_occ * n_occ);
+    e = hipMemcpyAsync(hs.data(), s, sizeof(double) * hs.size(),
+                       hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return LACE_EHIP;
+    kept_from_s(hs, n_occ, s_thr, pairs);
+  } else {
+    all_pairs(n_occ, pairs);
+  }
+  // every occupied x virtual pair, one-sided
+  std::vector<char> os(pairs.size(), 0);
+  for (int v = n_occ; v < n_orb; ++v)
+    for (int i = 0; i < n_occ; ++i) {
+      pairs.emplace_back(i, v);
+      os.push_back(1);
+    }
+  std::vector<Batch> sched;
+  schedule_for(p, pairs, n_orb, c.ppb, sched, &os, n_occ);
   e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true);
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();

@@ -39,7 +39,7 @@ SYMBOLS = (
     "lace_screen", "lace_apply_exchange", "lace_build_ace", "lace_apply_ace",
     "lace_fft3d", "lace_get_info", "lace_status_string",
     "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
-    "lace_schedule_slots",
+    "lace_schedule_slots", "lace_apply_exchange_virtual",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
     "lace_autotune", "lace_check_real",
 )
@@ -97,6 +97,9 @@ def load(path: str = LIB_PATH):
                                         i64, vp, vp,
                                         ctypes.POINTER(ctypes.c_int64), vp, sz,
                                         vp]
+    lib.lace_apply_exchange_virtual.argtypes = [
+        vp, i32, vp, i32, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
+        sz, vp]
     lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
                                    sz, vp]
     lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
@@ -216,6 +219,21 @@ def lace_screen(plan, cell, psi_g, n_orb, s_out, ws, stream=None):
                               _ptr(s_out, torch.float64, "s_out"),
                               _ptr(ws, None, "ws"), ws.numel() * ws.element_size(),
                               _stream(stream)), "lace_screen")
+
+
+def lace_apply_exchange_virtual(plan, cell, psi_g, n_occ, n_virt, s_thr, w_g,
+                                e_x, ws, stream=None) -> int:
+    """W for n_occ occupied and n_virt virtual orbitals (occupied first).
+    Returns the number of pair transforms run."""
+    import torch
+    kept = ctypes.c_int64(0)
+    _check(load().lace_apply_exchange_virtual(
+        plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), int(n_occ),
+        int(n_virt), float(s_thr), _ptr(w_g, torch.complex128, "w_g"),
+        _ptr(e_x, torch.float64, "e_x"), ctypes.byref(kept),
+        _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)),
+        "lace_apply_exchange_virtual")
+    return kept.value
 
 
 def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,

@@ -46,10 +46,19 @@ class CellSession:
                          stream)
         return self.s
 
-    def apply_exchange(self, s_thr=0.0, pairs=None, stream=None):
-        self.n_kept = lace.lace_apply_exchange(
-            self.plan, 0, self.psi, self.n_orb, s_thr, pairs, self.w,
-            self.e_x, self.ws, stream)
+    def apply_exchange(self, s_thr=0.0, pairs=None, stream=None, n_occ=None):
+        """W = K psi.  With n_occ < n_orb the first n_occ orbitals are the
+        occupied ones and the rest virtual (pairs must then be None)."""
+        if n_occ is not None and n_occ < self.n_orb:
+            if pairs is not None:
+                raise ValueError("explicit pairs with virtual orbitals")
+            self.n_kept = lace.lace_apply_exchange_virtual(
+                self.plan, 0, self.psi, n_occ, self.n_orb - n_occ, s_thr,
+                self.w, self.e_x, self.ws, stream)
+        else:
+            self.n_kept = lace.lace_apply_exchange(
+                self.plan, 0, self.psi, self.n_orb, s_thr, pairs, self.w,
+                self.e_x, self.ws, stream)
         return self.w
 
     def build_ace(self, sym="avg", stream=None):

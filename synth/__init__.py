@@ -12,6 +12,7 @@ from .generators import (  # noqa: F401
     miller_sphere,
     random_orbitals,
     gaussian_orbitals,
+    virtual_orbitals,
     make_config_inputs,
     make_batch_cells,
     perturb_gaussian_params,

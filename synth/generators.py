@@ -146,6 +146,35 @@ def gaussian_orbitals(miller: np.ndarray, L: float, n_orb: int,
     return orbitals_from_params(miller, L, pos, widths)
 
 
+def virtual_orbitals(miller: np.ndarray, L: float, occ: np.ndarray,
+                     n_virt: int, rng: np.random.Generator,
+                     real: bool = True) -> np.ndarray:
+    """Delocalized functions orthonormal to each other and to the rows of
+    ``occ`` (n_occ, n_pw): random coefficients under the envelope
+    exp(-|G|^2 / 8), real functions (C_{-G} = conj(C_G)) when ``real``,
+    then twice: project out the occupied rows, Loewdin-orthonormalize."""
+    g = _g_vectors(miller, L)
+    env = np.exp(-np.einsum("ij,ij->i", g, g) / 8.0)
+    c = (rng.standard_normal((n_virt, miller.shape[0]))
+         + 1j * rng.standard_normal((n_virt, miller.shape[0]))) * env
+    if real:
+        where = {tuple(m): k for k, m in enumerate(miller.tolist())}
+        neg = np.array([where[(-a, -b, -d)] for a, b, d in miller.tolist()])
+        c = 0.5 * (c + np.conj(c[:, neg]))
+    for _ in range(2):
+        o = occ.conj() @ c.T                # o[a, v] = <occ_a | c_v>
+        if real:
+            o = o.real
+        c = c - o.T @ occ
+        s = c.conj() @ c.T
+        if real:
+            s = s.real
+        s = 0.5 * (s + s.conj().T)
+        w, u = np.linalg.eigh(s)
+        c = ((u * (1.0 / np.sqrt(w))) @ u.conj().T).T @ c
+    return np.ascontiguousarray(c)
+
+
 def perturb_gaussian_params(pos: np.ndarray, widths: np.ndarray,
                             rng: np.random.Generator):
     """One synthetic outer-iteration update: centres move by 0.02 z bohr and

@@ -1,0 +1,97 @@
+"""Occupied plus virtual orbitals (the band-gap projection space of the
+silica results, Sec. 3) through the C ABI against the oracle: occupied pairs
+screened, every occupied x virtual integral evaluated one-sided, ACE over
+the whole space."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+from paper_1801_09263_amd import lace  # noqa: E402
+from paper_1801_09263_amd.session import CellSession  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = lace.LACE_FP64, lace.LACE_FP32
+FP64G, FP32G = lace.LACE_FP64_GAMMA, lace.LACE_FP32_GAMMA
+TOL = {FP64: dict(w=1e-11, m=1e-11, xi=1e-10, ex=1e-12),
+       FP32: dict(w=1e-5, m=1e-5, xi=1e-4, ex=1e-5)}
+TOL[FP64G] = TOL[FP64]
+TOL[FP32G] = TOL[FP32]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def space():
+    L, n, ecut = 16.0, 32, 15.0
+    miller = synth.miller_sphere(L, ecut)
+    occ = synth.gaussian_orbitals(miller, L, 13, 7, synth.rng_for(95))
+    virt = synth.virtual_orbitals(miller, L, occ, 5, synth.rng_for(96))
+    return dict(L=L, n=n, miller=miller, coeffs=np.concatenate([occ, virt]),
+                n_occ=13)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, FP64G, FP32G],
+                         ids=["fp64", "fp32", "fp64g", "fp32g"])
+@pytest.mark.parametrize("s_thr", [0.0, 5e-3])
+def test_virtual_orbitals_against_oracle(space, prec, s_thr):
+    say(f"virtual orbitals prec={prec} s_thr={s_thr}")
+    tol = TOL[prec]
+    L, n, miller, coeffs = space["L"], space["n"], space["miller"], space["coeffs"]
+    n_occ = space["n_occ"]
+    n_orb = coeffs.shape[0]
+    res = O.run_path_virtual(coeffs, n_occ, miller, L, n, s_thr=s_thr)
+    s = CellSession(dict(L=L, n=n, miller=miller), n_orb, prec)
+    s.set_orbitals(coeffs)
+    if prec in (FP64G, FP32G):
+        assert s.check_real() <= 1e-14
+    s.apply_exchange(s_thr, n_occ=n_occ)
+    assert s.n_kept == len(res["pairs"]) + n_occ * (n_orb - n_occ)
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    assert s.info() == 0
+    w = s.w.cpu().numpy()
+    assert rel(w[:n_occ], res["W_pw"][:n_occ]) <= tol["w"]
+    assert rel(w[n_occ:], res["W_pw"][n_occ:]) <= tol["w"]
+    assert rel(s.m.cpu().numpy(), res["M"]) <= tol["m"]
+    assert rel(s.xi.cpu().numpy(), res["xi"]) <= tol["xi"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(res["ex_pairs"])
+    s.close()
+
+
+def test_virtual_with_no_virtuals_is_the_plain_call(space):
+    """n_virt = 0 runs exactly the occupied path: bitwise the same W."""
+    L, n, miller = space["L"], space["n"], space["miller"]
+    occ = space["coeffs"][:space["n_occ"]]
+    cell = dict(L=L, n=n, miller=miller)
+    a = CellSession(cell, occ.shape[0], FP32G)
+    a.set_orbitals(occ)
+    a.apply_exchange(5e-3)
+    b = CellSession(cell, occ.shape[0], FP32G)
+    b.set_orbitals(occ)
+    kept = lace.lace_apply_exchange_virtual(b.plan, 0, b.psi, occ.shape[0], 0,
+                                            5e-3, b.w, b.e_x, b.ws)
+    torch.cuda.synchronize()
+    assert kept == a.n_kept
+    assert torch.equal(a.w, b.w) and torch.equal(a.e_x, b.e_x)
+    a.close()
+    b.close()
+
+
+def test_virtual_rejects_bad_counts(space):
+    cell = dict(L=space["L"], n=space["n"], miller=space["miller"])
+    s = CellSession(cell, 4, FP32)
+    for n_occ, n_virt in ((0, 4), (2, -1), (3, 3)):
+        with pytest.raises(lace.LaceError):
+            lace.lace_apply_exchange_virtual(s.plan, 0, s.psi, n_occ, n_virt,
+                                             0.0, s.w, s.e_x, s.ws)
+    s.close()

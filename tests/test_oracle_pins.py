@@ -488,3 +488,79 @@ def test_planted_scale_error_breaks_plane_wave_pin(monkeypatch):
     coeffs[0, 3] = coeffs[1, 17] = 1.0
     res = O.run_path(coeffs, miller, L, n)
     assert res["ex_trace"] != pytest.approx(res["ex_pairs"], rel=1e-3)
+
+
+# ------------------------------------------------ virtual orbitals (Sec. 3)
+def test_virtual_plane_wave_closed_form():
+    """Occupied plane waves a, virtual plane waves b: K psi_b =
+    -(1/Omega) sum_a v(G_b - G_a) psi_b (the occupied sum only), so M is
+    diagonal over the whole projection space and E_x counts the occupied
+    block only."""
+    L, n, ecut = 8.0, 12, 4.0
+    miller = synth.miller_sphere(L, ecut)
+    rng = np.random.default_rng(13)
+    n_occ, n_virt = 4, 3
+    pick = rng.choice(len(miller), size=n_occ + n_virt, replace=False)
+    coeffs = np.zeros((n_occ + n_virt, len(miller)), complex)
+    coeffs[np.arange(n_occ + n_virt), pick] = 1.0
+    res = O.run_path_virtual(coeffs, n_occ, miller, L, n)
+    omega, rc = L ** 3, L / 2
+    m = miller[pick]
+    expect = np.zeros(n_occ + n_virt)
+    for b in range(n_occ + n_virt):
+        for a in range(n_occ):
+            d = signed(np.mod(m[b] - m[a], n), n)
+            gg = 2 * np.pi / L * np.sqrt(float(d @ d))
+            vv = (2 * np.pi * rc * rc if gg == 0 else
+                  4 * np.pi * (1 - np.cos(gg * rc)) / gg ** 2)
+            expect[b] -= vv / omega
+    assert np.abs(res["M"] - np.diag(expect)).max() <= 1e-13 * np.abs(
+        expect).max()
+    assert np.abs(res["W_pw"] - expect[:, None] * coeffs).max() <= 1e-13
+    assert res["ex_pairs"] == pytest.approx(0.5 * expect[:n_occ].sum(),
+                                            rel=1e-13)
+
+
+def test_virtual_ace_exact_on_projection_space(localized):
+    """Unscreened, ACE built on occupied + virtual orbitals reproduces K on
+    every one of them and lies above K elsewhere; the occupied block of M
+    is the occupied-only M; M is Hermitian negative definite."""
+    L, n, miller = localized["L"], localized["n"], localized["miller"]
+    occ = localized["coeffs"][:10]
+    virt = synth.virtual_orbitals(miller, L, occ, 4, synth.rng_for(91))
+    coeffs = np.concatenate([occ, virt])
+    res = O.run_path_virtual(coeffs, 10, miller, L, n)
+    y = O.apply_ace(res["xi"], coeffs)
+    assert np.linalg.norm(y - res["W_pw"]) <= 1e-12 * np.linalg.norm(
+        res["W_pw"])
+    m = res["M"]
+    assert np.abs(m - m.conj().T).max() <= 1e-13 * np.abs(m).max()
+    assert np.linalg.eigvalsh(0.5 * (m + m.conj().T)).max() < 0
+    occ_only = O.run_path(occ, miller, L, n)
+    assert np.abs(m[:10, :10] - occ_only["M"]).max() <= 1e-13 * np.abs(m).max()
+    assert res["ex_pairs"] == pytest.approx(occ_only["ex_pairs"], rel=1e-13)
+    # a function outside the projection space: ACE above K (Schur bound)
+    x = synth.virtual_orbitals(miller, L, coeffs, 1, synth.rng_for(92))
+    xg = O.orbitals_on_grid(x, miller, L, n)
+    kx = O.grid_to_pw(O.apply_exchange_to(res["psi"][:10], xg, res["v"]),
+                      miller, L)
+    gap = np.vdot(x[0], O.apply_ace(res["xi"], x)[0]).real - np.vdot(
+        x[0], kx[0]).real
+    assert gap > 1e-8
+
+
+def test_virtual_screening_keeps_every_virtual_integral(localized):
+    """With a threshold that drops occupied pairs, the virtual columns are
+    still the full K applied to them, and the occupied columns are those of
+    the screened occupied-only run."""
+    L, n, miller = localized["L"], localized["n"], localized["miller"]
+    occ = localized["coeffs"][:10]
+    virt = synth.virtual_orbitals(miller, L, occ, 2, synth.rng_for(93))
+    coeffs = np.concatenate([occ, virt])
+    s_thr = 5e-3
+    scr = O.run_path_virtual(coeffs, 10, miller, L, n, s_thr=s_thr)
+    full = O.run_path_virtual(coeffs, 10, miller, L, n)
+    occ_scr = O.run_path(occ, miller, L, n, s_thr=s_thr)
+    assert len(occ_scr["pairs"]) < 55
+    assert np.abs(scr["W_pw"][10:] - full["W_pw"][10:]).max() <= 1e-14
+    assert np.abs(scr["W_pw"][:10] - occ_scr["W_pw"]).max() <= 1e-14
