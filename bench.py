@@ -119,6 +119,55 @@ def time_exchange(torch, sess, s_thr):
     return sess.n_kept, time.perf_counter() - t0
 
 
+def ace_rows(torch, lace, sess, inp, seed, n_calls=8):
+    """FP64 matrix-core rows: apply_ace on n_b = 256 (16 N N_pw n_b flop per
+    call), M = psi^H W (8 N^2 N_pw flop), and lace_align (30 polar steps on
+    N x N plus two N_pw x N x N products)."""
+    import numpy as np
+    import synth
+    n, n_pw = sess.n_orb, sess.n_pw
+    x = sess.psi
+    y = torch.empty_like(x)
+    sess.apply_ace(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_calls):
+        sess.apply_ace(x, y)
+    torch.cuda.synchronize()
+    t_ace = (time.perf_counter() - t0) / n_calls
+    f_ace = 16.0 * n * n_pw * x.shape[0]
+    t0 = time.perf_counter()
+    for _ in range(n_calls):
+        sess.build_ace("avg")
+    torch.cuda.synchronize()
+    t_build = (time.perf_counter() - t0) / n_calls
+    f_m = 8.0 * n * n * n_pw
+    pos, wid = synth.gaussian_params(inp["L"], n, 128, synth.rng_for(2, 0, 0, 0, seed))
+    p2, w2 = synth.perturb_gaussian_params(pos, wid, synth.rng_for(2, 0, 0, 1, seed))
+    new = torch.tensor(synth.orbitals_from_params(inp["miller"], inp["L"], p2, w2),
+                       device="cuda")
+    out = torch.empty_like(new)
+    resid = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lace.lace_align(sess.plan, 0, new, sess.psi, n, out, resid, sess.ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_calls):
+        lace.lace_align(sess.plan, 0, new, sess.psi, n, out, resid, sess.ws)
+    torch.cuda.synchronize()
+    t_align = (time.perf_counter() - t0) / n_calls
+    moved = float(torch.linalg.norm(new - sess.psi) / np.sqrt(n))
+    left = float(torch.linalg.norm(out - sess.psi) / np.sqrt(n))
+    return dict(
+        apply_ace_n_b=int(x.shape[0]), apply_ace_ms=round(t_ace * 1e3, 3),
+        apply_ace_tflops=round(f_ace / t_ace / 1e12, 2),
+        apply_ace_frac_fp64_mfma=round(f_ace / t_ace / 1e12 / FP64_MFMA_PEAK_TFLOPS, 4),
+        build_ace_ms=round(t_build * 1e3, 3),
+        build_ace_tflops_m_gemm_only=round(f_m / t_build / 1e12, 2),
+        align_ms=round(t_align * 1e3, 3), align_resid=resid.item(),
+        align_rms_distance_before=round(moved, 4),
+        align_rms_distance_after=round(left, 4))
+
+
 def cpu_baseline(inp, n_sample_orb=12):
     """The oracle, as it stands, on a bounded sample of the same workload:
     the exchange among `n_sample_orb` orbitals spread over the cell (their
@@ -283,8 +332,8 @@ def main():
                          "autotuning the main workload")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="small fixed run for hardware-counter passes: a "
-                         "1 GiB copy (calibration) and 4 pair batches of "
-                         "the localized workload")
+                         "1 GiB copy (calibration) and 8 batches of star "
+                         "slots of the localized workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -359,6 +408,12 @@ def main():
         pipeline_GBs=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9, 1),
         pipeline_frac=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     )
+    # ACE algebra on the FP64 matrix cores: an inner loop of ACE
+    # applications to blocks of 256 functions (a Davidson-like solver's use
+    # of the operator between two exchange builds), the M = psi^H W product,
+    # and the alignment of a perturbed outer step's orbitals
+    ace = ace_rows(torch, lace, sess, inp, args.seed)
+    log("ace", ace)
     sess.close()
     del sess
     torch.cuda.empty_cache()
@@ -376,6 +431,37 @@ def main():
             step_ms=round(ts2 * 1e3, 1), pair_ffts_per_s=round(n2 / ts2, 1))
         s2.close()
         del s2
+        torch.cuda.empty_cache()
+        log("localized workload plus 10 virtual orbitals (real-orbital FP32)")
+        import numpy as np
+        n_v = 10
+        virt = synth.virtual_orbitals(inp["miller"], inp["L"], inp["coeffs"],
+                                      n_v, synth.rng_for(2, 0, 0, 1, args.seed))
+        s3 = CellSession(inp, n_orb + n_v, lace.LACE_FP32_GAMMA,
+                         n_vec=n_orb + n_v)
+        s3.set_orbitals(np.concatenate([inp["coeffs"], virt]))
+        lace.lace_set_tuning(s3.plan, 0, tuning[0], tuning[1])
+        y3 = torch.empty_like(s3.psi)
+        s3.apply_exchange(inp["s_thr"], n_occ=n_orb)
+        s3.build_ace("avg")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s3.apply_exchange(inp["s_thr"], n_occ=n_orb)
+        torch.cuda.synchronize()
+        t_ex3 = time.perf_counter() - t0
+        s3.build_ace("avg")
+        s3.apply_ace(s3.psi, y3)
+        torch.cuda.synchronize()
+        t_st3 = time.perf_counter() - t0
+        compare["lace_fp32_gamma_virtual10"] = dict(
+            occupied=n_orb, virtual=n_v, pairs=s3.n_kept,
+            occupied_pairs=s3.n_kept - n_orb * n_v,
+            exchange_ms=round(t_ex3 * 1e3, 1), step_ms=round(t_st3 * 1e3, 1),
+            pair_ffts_per_s=round(s3.n_kept / t_st3, 1),
+            cholesky_info=s3.info())
+        log("lace_fp32_gamma_virtual10", compare["lace_fp32_gamma_virtual10"])
+        s3.close()
+        del s3
         torch.cuda.empty_cache()
         log("plain unscreened 120^3 random orbitals (FP64 and FP32 pairs)")
         inp1 = synth.make_config_inputs(1, seed=args.seed)
@@ -445,6 +531,7 @@ def main():
         "roofline": roofline,
         "copy_GBs_measured": round(copy_gbs, 1),
         "compare": compare,
+        "ace": ace,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -165,6 +165,23 @@ int lace_apply_exchange_virtual(lace_plan* plan, int cell, const void* psi_g,
                                 void* ws, size_t ws_bytes,
                                 lace_stream_t stream);
 
+/* Orbital alignment, the aid to tight SCF convergence at the end of Sec. 2
+ * (align the orbitals of one iteration to those of the previous one).
+ * Reading: the unitary U that minimizes ||psi_new U - psi_old||_F (the
+ * orthogonal Procrustes problem) is the polar factor of
+ * A = psi_new^H psi_old; psi_out = psi_new U spans the space of psi_new.
+ * U is computed on the device by 30 Newton-Schulz steps
+ * X <- X (3 I - X^H X) / 2 from X_0 = A / b, b^2 >= the largest eigenvalue
+ * of A^H A (Gershgorin); singular values of A below ~1e-4 of the largest
+ * are not resolved (resid then stays large).
+ *   psi_new, psi_old  device, n_pw x n_orb complex128.
+ *   psi_out  device, n_pw x n_orb complex128, distinct from both inputs.
+ *   resid    device double (may be NULL): ||U^H U - I||_F / sqrt(n_orb).
+ * Workspace of n_orb.  Asynchronous.  Errors: EINVAL, ENOMEM, EHIP. */
+int lace_align(lace_plan* plan, int cell, const void* psi_new,
+               const void* psi_old, int n_orb, void* psi_out, double* resid,
+               void* ws, size_t ws_bytes, lace_stream_t stream);
+
 /* ACE projector from psi and W = K psi (Eqs. (3)-(5), (9)).
  *   m_out   device n_orb x n_orb complex128 (may be NULL): M = psi^H W.
  *   xi_g    device n_pw x n_orb complex128 output: xi = W L^{-H} with

@@ -43,6 +43,7 @@ __all__ = [
     "exchange_energy_trace", "exchange_energy_pairs", "symmetrize",
     "cholesky_neg", "NotPositiveDefinite", "projector", "apply_ace",
     "run_path", "apply_exchange_virtual", "run_path_virtual",
+    "align_orbitals",
 ]
 
 
@@ -342,3 +343,15 @@ def run_path_virtual(coeffs, n_occ, miller, L, n, s_thr=0.0, rc=None,
     xi = projector(w_pw, chol)
     return dict(S=s, pairs=pairs, W_pw=w_pw, M=m, Ms=ms, L=chol, xi=xi,
                 ex_pairs=ex_pairs, psi=psi, v=v)
+
+
+def align_orbitals(new: np.ndarray, old: np.ndarray) -> np.ndarray:
+    """Align orbitals to those of the previous iteration (the convergence
+    aid at the end of Sec. 2).  Reading: new U with U the unitary that
+    minimizes ||new U - old||_F, the polar factor of A = new^H old, taken
+    from the singular value decomposition A = P diag(s) Q^H as U = P Q^H.
+    Rows are orbitals; returns the aligned rows."""
+    a = np.conj(new) @ old.T              # a[x, y] = <new_x | old_y>
+    p, _, qh = np.linalg.svd(a)
+    u = p @ qh
+    return u.T @ new

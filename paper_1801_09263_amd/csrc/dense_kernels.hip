@@ -491,4 +491,78 @@ hipError_t launch_scale_c128(const void* x, int64_t n, double s, void* y,
   return hipGetLastError();
 }
 
+// Element-wise steps of the polar (Procrustes) iteration on n x n
+// complex128 row-major matrices: 0 out = conj(in); 1 out = *s * in;
+// 2 out = (3 I - in) / 2; 3 out = in^T.
+__global__ void k_polar_elem(int mode, const double2* in, int n,
+                             const double* s, double2* out) {
+  const int64_t nn = (int64_t)n * n;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const double f = (mode == 1) ? *s : 0.0;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nn;
+       e += stride) {
+    const int a = (int)(e / n), b = (int)(e % n);
+    const double2 x = in[e];
+    double2 y;
+    if (mode == 0) y = make_double2(x.x, -x.y);
+    else if (mode == 1) y = make_double2(f * x.x, f * x.y);
+    else if (mode == 2) y = make_double2(((a == b) ? 1.5 : 0.0) - 0.5 * x.x,
+                                         -0.5 * x.y);
+    else y = in[(int64_t)b * n + a];
+    out[e] = y;
+  }
+}
+
+// One workgroup on an n x n complex128 row-major B: mode 0 writes
+// 1 / sqrt(max_a sum_b |B_ab|) (a bound on the largest eigenvalue of a
+// Hermitian positive semidefinite B, by Gershgorin; 0 when B = 0), mode 1
+// writes ||B - I||_F / sqrt(n).
+__global__ void k_polar_norm(int mode, const double2* B, int n, double* out) {
+  __shared__ double red[4];
+  double t = 0.0;
+  for (int a = threadIdx.x; a < n; a += 256) {
+    double r = 0.0;
+    for (int b = 0; b < n; ++b) {
+      const double2 x = B[(int64_t)a * n + b];
+      if (mode == 0) {
+        r += sqrt(x.x * x.x + x.y * x.y);
+      } else {
+        const double re = x.x - (a == b ? 1.0 : 0.0);
+        r += re * re + x.y * x.y;
+      }
+    }
+    t = (mode == 0) ? fmax(t, r) : t + r;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double u = __shfl_xor(t, o, 64);
+    t = (mode == 0) ? fmax(t, u) : t + u;
+  }
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = red[0];
+    for (int w = 1; w < 4; ++w) v = (mode == 0) ? fmax(v, red[w]) : v + red[w];
+    *out = (mode == 0) ? (v > 0.0 ? 1.0 / sqrt(v) : 0.0) : sqrt(v / n);
+  }
+}
+
+hipError_t launch_polar_elem(int mode, const void* in, int n, const double* s,
+                             void* out, hipStream_t st) {
+  int64_t blocks = ((int64_t)n * n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_polar_elem, dim3((unsigned)blocks), dim3(256), 0, st,
+                     mode, static_cast<const double2*>(in), n, s,
+                     static_cast<double2*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_polar_norm(int mode, const void* B, int n, double* out,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_polar_norm, dim3(1), dim3(256), 0, st, mode,
+                     static_cast<const double2*>(B), n, out);
+  return hipGetLastError();
+}
+
 }  // namespace lace

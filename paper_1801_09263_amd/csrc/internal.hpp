@@ -137,4 +137,12 @@ hipError_t launch_trace_re(const void* M, int n, double factor, double* out,
 hipError_t launch_scale_c128(const void* x, int64_t n, double s, void* y,
                              hipStream_t st);
 
+// Polar-iteration helpers, n x n complex128 row-major.  elem: 0 conj,
+// 1 scale by *s, 2 (3 I - in) / 2, 3 transpose (out distinct from in).
+// norm: 0 Gershgorin scale 1 / sqrt(max row sum |B|), 1 ||B - I||_F / sqrt n.
+hipError_t launch_polar_elem(int mode, const void* in, int n, const double* s,
+                             void* out, hipStream_t st);
+hipError_t launch_polar_norm(int mode, const void* B, int n, double* out,
+                             hipStream_t st);
+
 }  // namespace lace

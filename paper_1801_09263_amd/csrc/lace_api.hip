@@ -84,7 +84,7 @@ static int hip_status(hipError_t e) { return e == hipSuccess ? LACE_OK : LACE_EH
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t psi, w, tmp, epart, s, part, mw, a, z, t, total;
+  size_t psi, w, tmp, epart, s, part, mw, a, z, t, u, total;
   int pairs_per_batch;
 };
 
@@ -121,6 +121,7 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.a = off; off += align_up(16 * (size_t)n_orb * n_orb);
   L.z = off; off += align_up(16 * (size_t)n_orb * std::max(n_orb, n_vec));
   L.t = off; off += align_up(16 * (size_t)n_orb * std::max(n_vec, 1));
+  L.u = off; off += align_up(16 * (size_t)n_orb * n_orb);
   L.total = off;
   return L;
 }
@@ -938,6 +939,59 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();
   return LACE_OK;
+}
+
+// Newton-Schulz steps of the polar factor; quadratic near convergence and
+// growing the smallest singular value by 3/2 per step before that, so 30
+// steps resolve singular values down to ~1e-4 of the largest.
+static constexpr int kAlignSteps = 30;
+
+int lace_align(lace_plan* p, int cell, const void* psi_new, const void* psi_old,
+               int n_orb, void* psi_out, double* resid, void* ws,
+               size_t ws_bytes, lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_new || !psi_old || !psi_out || !ws) return LACE_EINVAL;
+  if (psi_out == psi_new || psi_out == psi_old) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  const CellDev& c = p->cells[cell].dev;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int n = n_orb;
+  void* part = at(ws, L.part);
+  const int64_t pb = (int64_t)(L.mw - L.part);
+  void* g = at(ws, L.mw);     // G, later C and U
+  void* y0 = at(ws, L.a);     // Y = X^T, ping
+  void* y1 = at(ws, L.u);     // pong
+  void* b = at(ws, L.z);      // X^H X
+  double* sc = reinterpret_cast<double*>(at(ws, L.s));
+  // G[x][y] = <psi_old_x | psi_new_y> = conj(A[y][x]), A = psi_new^H psi_old;
+  // X_0 = A s, stored transposed: Y_0 = conj(G) s
+  hipError_t e = launch_gemm_ip_c128(psi_old, c.n_pw, n, psi_new, c.n_pw, n,
+                                     c.n_pw, 1.0, g, part, pb, st);
+  if (e == hipSuccess) e = launch_polar_elem(0, g, n, nullptr, y0, st);
+  if (e == hipSuccess)
+    e = launch_gemm_ip_c128(y0, n, n, y0, n, n, n, 1.0, b, part, pb, st);
+  if (e == hipSuccess) e = launch_polar_norm(0, b, n, sc, st);
+  if (e == hipSuccess) e = launch_polar_elem(1, y0, n, sc, y1, st);
+  void* cur = y1;
+  void* nxt = y0;
+  for (int it = 0; it < kAlignSteps && e == hipSuccess; ++it) {
+    // X <- X C, C = (3 I - X^H X) / 2: Y'[b][a] = sum_k Y[k][a] C[k][b]
+    e = launch_gemm_ip_c128(cur, n, n, cur, n, n, n, 1.0, b, part, pb, st);
+    if (e == hipSuccess) e = launch_polar_elem(2, b, n, nullptr, g, st);
+    if (e == hipSuccess) e = launch_gemm_tall(cur, n, n, n, g, n, nxt, n, st);
+    std::swap(cur, nxt);
+  }
+  if (e == hipSuccess && resid) {
+    e = launch_gemm_ip_c128(cur, n, n, cur, n, n, n, 1.0, b, part, pb, st);
+    if (e == hipSuccess) e = launch_polar_norm(1, b, n, resid, st);
+  }
+  // U = Y^T, psi_out_b = sum_a psi_new_a U[a][b]
+  if (e == hipSuccess) e = launch_polar_elem(3, cur, n, nullptr, g, st);
+  if (e == hipSuccess)
+    e = launch_gemm_tall(psi_new, c.n_pw, c.n_pw, n, g, n, psi_out, c.n_pw, st);
+  return hip_status(e);
 }
 
 int lace_apply_exchange_virtual(lace_plan* p, int cell, const void* psi_g,

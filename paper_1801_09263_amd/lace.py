@@ -39,7 +39,7 @@ SYMBOLS = (
     "lace_screen", "lace_apply_exchange", "lace_build_ace", "lace_apply_ace",
     "lace_fft3d", "lace_get_info", "lace_status_string",
     "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
-    "lace_schedule_slots", "lace_apply_exchange_virtual",
+    "lace_schedule_slots", "lace_apply_exchange_virtual", "lace_align",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
     "lace_autotune", "lace_check_real",
 )
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.lace_apply_exchange_virtual.argtypes = [
         vp, i32, vp, i32, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
         sz, vp]
+    lib.lace_align.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, sz, vp]
     lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
                                    sz, vp]
     lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
@@ -234,6 +235,18 @@ def lace_apply_exchange_virtual(plan, cell, psi_g, n_occ, n_virt, s_thr, w_g,
         _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)),
         "lace_apply_exchange_virtual")
     return kept.value
+
+
+def lace_align(plan, cell, psi_new, psi_old, n_orb, psi_out, resid, ws,
+               stream=None):
+    """psi_out = psi_new U, U the unitary closest to psi_new^H psi_old."""
+    import torch
+    _check(load().lace_align(
+        plan.handle, cell, _ptr(psi_new, torch.complex128, "psi_new"),
+        _ptr(psi_old, torch.complex128, "psi_old"), int(n_orb),
+        _ptr(psi_out, torch.complex128, "psi_out"),
+        _ptr(resid, torch.float64, "resid"), _ptr(ws, None, "ws"),
+        ws.numel() * ws.element_size(), _stream(stream)), "lace_align")
 
 
 def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,

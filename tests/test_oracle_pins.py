@@ -564,3 +564,57 @@ def test_virtual_screening_keeps_every_virtual_integral(localized):
     assert len(occ_scr["pairs"]) < 55
     assert np.abs(scr["W_pw"][10:] - full["W_pw"][10:]).max() <= 1e-14
     assert np.abs(scr["W_pw"][:10] - occ_scr["W_pw"]).max() <= 1e-14
+
+
+# ------------------------------------------------ alignment (end of Sec. 2)
+def _random_unitary(rng, n, real=False):
+    z = rng.standard_normal((n, n))
+    if not real:
+        z = z + 1j * rng.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def test_align_recovers_a_rotation(c0):
+    """new = old rotated by a unitary: aligning gives old back."""
+    inp, _ = c0
+    old = inp["coeffs"]
+    rot = _random_unitary(np.random.default_rng(21), old.shape[0])
+    new = rot.T @ old                     # new_a = sum_b rot[b, a] old_b
+    assert np.abs(O.align_orbitals(new, old) - old).max() <= 1e-13
+
+
+def test_align_is_the_closest_unitary_mix(c0):
+    """Procrustes optimality against random unitary mixes and the identity;
+    the result spans the space of new and is orthonormal."""
+    inp, _ = c0
+    old = inp["coeffs"]
+    rng = np.random.default_rng(22)
+    n = old.shape[0]
+    noise = 0.05 * (rng.standard_normal(old.shape)
+                    + 1j * rng.standard_normal(old.shape))
+    new, _ = np.linalg.qr((_random_unitary(rng, n).T @ old + noise).T)
+    new = new.T
+    out = O.align_orbitals(new, old)
+    best = np.linalg.norm(out - old)
+    for q in [np.eye(n)] + [_random_unitary(rng, n) for _ in range(20)]:
+        assert best <= np.linalg.norm(q.T @ new - old) + 1e-12
+    assert np.abs(np.conj(out) @ out.T - np.eye(n)).max() <= 1e-13
+    proj = np.conj(new) @ out.T           # out lies in span(new)
+    assert np.abs(proj.T @ new - out).max() <= 1e-12
+
+
+def test_align_keeps_real_orbitals_real(localized):
+    """Real orbitals rotated by a real orthogonal matrix align back with a
+    real orthogonal U (C_{-G} = conj(C_G) kept)."""
+    old = localized["coeffs"]
+    rng = np.random.default_rng(23)
+    rot = _random_unitary(rng, old.shape[0], real=True)
+    new = rot.T @ old + 1e-3 * (rot.T @ old)[::-1]
+    out = O.align_orbitals(new, old)
+    a = np.conj(new) @ old.T
+    assert np.abs(a.imag).max() <= 1e-13
+    miller = localized["miller"]
+    where = {tuple(m): k for k, m in enumerate(miller.tolist())}
+    neg = np.array([where[(-x, -y, -z)] for x, y, z in miller.tolist()])
+    assert np.abs(out[:, neg] - np.conj(out)).max() <= 1e-13
