@@ -141,7 +141,7 @@ int lace_apply_exchange(lace_plan* plan, int cell, const void* psi_g,
                         size_t ws_bytes, lace_stream_t stream);
 
 /* W = K psi for occupied plus virtual orbitals (the band-gap setting of the
- * silica results in Sec. 3: the projection space holds the occupied
+ * silica results in Sec. 4.1: the projection space holds the occupied
  * orbitals and a few virtual ones).  The exchange operator sums over the
  * occupied orbitals only (Eq. (2)); the occupied pairs are screened with
  * s_thr among themselves (Eq. (6)), and every integral that involves a

@@ -315,7 +315,7 @@ def run_path(coeffs, miller, L, n, s_thr=0.0, rc=None, sym="avg",
 def apply_exchange_virtual(psi: np.ndarray, v: np.ndarray, n_occ: int,
                            pairs=None) -> np.ndarray:
     """W for the occupied orbitals psi[:n_occ] and the virtual ones after
-    them (the projection space of the band-gap runs in Sec. 3).  K sums
+    them (the projection space of the band-gap runs in Sec. 4.1).  K sums
     over the occupied orbitals only (Eq. (2)).  Occupied columns keep the
     screened occupied pairs (Eqs. (7)-(8)); every integral that involves a
     virtual orbital is evaluated, so a virtual column is K applied to that

@@ -1,5 +1,5 @@
 """Occupied plus virtual orbitals (the band-gap projection space of the
-silica results, Sec. 3) through the C ABI against the oracle: occupied pairs
+silica results, Sec. 4.1) through the C ABI against the oracle: occupied pairs
 screened, every occupied x virtual integral evaluated one-sided, ACE over
 the whole space."""
 import numpy as np

@@ -490,7 +490,7 @@ def test_planted_scale_error_breaks_plane_wave_pin(monkeypatch):
     assert res["ex_trace"] != pytest.approx(res["ex_pairs"], rel=1e-3)
 
 
-# ------------------------------------------------ virtual orbitals (Sec. 3)
+# ---------------------------------------------- virtual orbitals (Sec. 4.1)
 def test_virtual_plane_wave_closed_form():
     """Occupied plane waves a, virtual plane waves b: K psi_b =
     -(1/Omega) sum_a v(G_b - G_a) psi_b (the occupied sum only), so M is
