@@ -251,8 +251,9 @@ int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
 
 /* Autotuner: times the pair pipeline of this cell on the given orbitals for
  * every candidate (pairs per batch 8, 16, 32, 64; half-plane, plane and
- * pencil schedules where they exist), over the same fixed set of pairs, and keeps
- * the fastest with lace_set_tuning.  Writes up to *n_cand candidates
+ * pencil schedules where they exist): each candidate schedules all pairs of
+ * the n_orb orbitals its own way and is timed on its first batches holding
+ * at least 256 pairs.  Keeps the fastest with lace_set_tuning.  Writes up to *n_cand candidates
  * (cand_ppb, cand_plane, cand_us_per_pair; host arrays, may be NULL) and
  * sets *n_cand to the number timed.  Synchronizes the stream.  The
  * workspace is the one of lace_workspace_size (W is overwritten). */

@@ -640,9 +640,9 @@ template <typename T, int N> struct Engine {
     EpiGrid<T> e1{g, NG, T(1)};
     EpiGrid<T> es{g, NG, scale};
     hipError_t err;
-    if (mode == 2) {
-      err = half<SIGN>(p, e1, count, tw, st);
-    } else if (Cf::plane && mode == 1) {
+    // In place, so never the half-plane form: its two workgroups of a plane
+    // would overwrite rows that the other one still reads.
+    if (Cf::plane && mode != 0) {
       err = plane<SIGN>(p, e1, count, tw, st);
     } else {
       err = xlines<SIGN>(p, e1, count, tw, st);

@@ -1165,20 +1165,11 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e != hipSuccess) return LACE_EHIP;
-  // fixed pair set: the first 4 * PMAX pairs in round-robin order
+  // every candidate schedules all pairs its own way and is timed on its
+  // first batches holding at least 4 * PMAX pairs: steady-state batches of
+  // that candidate's own schedule
   std::vector<std::pair<int, int>> pairs;
   all_pairs(n_orb, pairs);
-  {
-    std::vector<Batch> full;
-    build_schedule(pairs, n_orb, PMAX, full);
-    pairs.clear();
-    for (const auto& bt : full) {
-      const PairArgs& b = bt.p;
-      for (int q = 0; q < b.n && pairs.size() < (size_t)(4 * PMAX); ++q)
-        pairs.emplace_back(b.i[q], b.j[q]);
-      if (pairs.size() >= (size_t)(4 * PMAX)) break;
-    }
-  }
   struct Cand { int ppb, plane; double us; };
   std::vector<Cand> cands;
   const int ppbs[4] = {8, 16, 32, 64};
@@ -1195,6 +1186,11 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
     c.use_plane = cd.plane;
     std::vector<Batch> sched;
     schedule_for(p, pairs, n_orb, cd.ppb, sched);
+    int64_t timed_pairs = 0;
+    size_t nb = 0;
+    while (nb < sched.size() && timed_pairs < 4 * PMAX)
+      timed_pairs += sched[nb++].p.n;
+    sched.resize(nb);
     double best = 1e30;
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       const bool fp = fp64;
@@ -1209,7 +1205,7 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (rep > 0 && ms < best) best = ms;   // first repetition warms up
     }
-    cd.us = 1e3 * best / double(pairs.size());
+    cd.us = 1e3 * best / double(timed_pairs);
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
