@@ -121,8 +121,9 @@ def time_exchange(torch, sess, s_thr):
 
 def ace_rows(torch, lace, sess, inp, seed, n_calls=8):
     """FP64 matrix-core rows: apply_ace on n_b = 256 (16 N N_pw n_b flop per
-    call), M = psi^H W (8 N^2 N_pw flop), and lace_align (30 polar steps on
-    N x N plus two N_pw x N x N products)."""
+    call), M = psi^H W (8 N^2 N_pw flop), lace_align (30 polar steps on
+    N x N plus two N_pw x N x N products), and the SCDM localization of a
+    perturbed outer step's orbitals."""
     import numpy as np
     import synth
     n, n_pw = sess.n_orb, sess.n_pw
@@ -157,6 +158,14 @@ def ace_rows(torch, lace, sess, inp, seed, n_calls=8):
     t_align = (time.perf_counter() - t0) / n_calls
     moved = float(torch.linalg.norm(new - sess.psi) / np.sqrt(n))
     left = float(torch.linalg.norm(out - sess.psi) / np.sqrt(n))
+    # SCDM localization of the 256 orbitals (n_orb passes over the grids)
+    pts = torch.empty(n, dtype=torch.int32, device="cuda")
+    lace.lace_scdm(sess.plan, 0, new, n, out, pts, resid, sess.ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lace.lace_scdm(sess.plan, 0, new, n, out, pts, resid, sess.ws)
+    torch.cuda.synchronize()
+    t_scdm = time.perf_counter() - t0
     return dict(
         apply_ace_n_b=int(x.shape[0]), apply_ace_ms=round(t_ace * 1e3, 3),
         apply_ace_tflops=round(f_ace / t_ace / 1e12, 2),
@@ -165,7 +174,8 @@ def ace_rows(torch, lace, sess, inp, seed, n_calls=8):
         build_ace_tflops_m_gemm_only=round(f_m / t_build / 1e12, 2),
         align_ms=round(t_align * 1e3, 3), align_resid=resid.item(),
         align_rms_distance_before=round(moved, 4),
-        align_rms_distance_after=round(left, 4))
+        align_rms_distance_after=round(left, 4),
+        scdm_ms=round(t_scdm * 1e3, 2), scdm_resid=resid.item())
 
 
 def cpu_baseline(inp, n_sample_orb=12):

@@ -182,6 +182,27 @@ int lace_align(lace_plan* plan, int cell, const void* psi_new,
                const void* psi_old, int n_orb, void* psi_out, double* resid,
                void* ws, size_t ws_bytes, lace_stream_t stream);
 
+/* Localization by selected columns of the density matrix (SCDM; Sec. 2
+ * localizes the occupied manifold this way before screening; its modified
+ * version is not described, so this is the cited method itself).  The
+ * n_orb grid points r_k are picked greedily by column-pivoted QR of
+ * Psi^H on the grid (each pick maximizes the part of conj(psi(r)) outside
+ * the span of the earlier picks); the localized orbitals are the density
+ * matrix columns P(., r_k), Loewdin-orthonormalized:
+ * phi = psi U, U the polar factor of A, A[n][k] = conj(psi_n(r_k)).
+ * Picks use the plan's grids (FP32 or FP64) with FP64 sums; U comes from
+ * the Newton-Schulz iteration of lace_align.
+ *   psi_g   device, n_pw x n_orb complex128, orthonormal.
+ *   phi_g   device, n_pw x n_orb complex128 output (not psi_g).
+ *   points  device int32 [n_orb] (may be NULL): the picks in order, as flat
+ *           grid indices (z n + y) n + x.
+ *   resid   device double (may be NULL): ||U^H U - I||_F / sqrt(n_orb).
+ * n_orb <= 3072.  Workspace of n_orb.  Asynchronous (n_orb steps, each a
+ * pass over the orbital grids).  Errors: EINVAL, ENOMEM, EHIP. */
+int lace_scdm(lace_plan* plan, int cell, const void* psi_g, int n_orb,
+              void* phi_g, int32_t* points, double* resid, void* ws,
+              size_t ws_bytes, lace_stream_t stream);
+
 /* ACE projector from psi and W = K psi (Eqs. (3)-(5), (9)).
  *   m_out   device n_orb x n_orb complex128 (may be NULL): M = psi^H W.
  *   xi_g    device n_pw x n_orb complex128 output: xi = W L^{-H} with

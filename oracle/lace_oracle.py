@@ -43,7 +43,7 @@ __all__ = [
     "exchange_energy_trace", "exchange_energy_pairs", "symmetrize",
     "cholesky_neg", "NotPositiveDefinite", "projector", "apply_ace",
     "run_path", "apply_exchange_virtual", "run_path_virtual",
-    "align_orbitals",
+    "align_orbitals", "scdm_points", "scdm_given_points", "scdm",
 ]
 
 
@@ -355,3 +355,33 @@ def align_orbitals(new: np.ndarray, old: np.ndarray) -> np.ndarray:
     p, _, qh = np.linalg.svd(a)
     u = p @ qh
     return u.T @ new
+
+
+def scdm_points(psi: np.ndarray) -> np.ndarray:
+    """The grid points of the SCDM localization (Sec. 2, the cited selected
+    columns of the density matrix): the first N pivots of column-pivoted QR
+    (LAPACK's, through scipy) of Psi^H, whose column at point r is
+    conj(psi(r)).  Flat grid indices, in pivot order."""
+    nb = psi.shape[0]
+    a = np.conj(psi.reshape(nb, -1))
+    _, piv = scipy.linalg.qr(a, mode="r", pivoting=True)
+    return piv[:nb]
+
+
+def scdm_given_points(coeffs: np.ndarray, psi: np.ndarray,
+                      points) -> np.ndarray:
+    """Localized orbitals for given points: the density matrix columns
+    P(., r_k) = sum_n psi_n conj(psi_n(r_k)), Loewdin-orthonormalized, i.e.
+    psi U with U the polar factor (from an SVD) of A[n, k] =
+    conj(psi_n(r_k)).  Returns plane-wave coefficient rows."""
+    nb = psi.shape[0]
+    a = np.conj(psi.reshape(nb, -1)[:, np.asarray(points)])
+    p, _, qh = np.linalg.svd(a)
+    return (p @ qh).T @ coeffs
+
+
+def scdm(coeffs, miller, L, n):
+    """SCDM localization of the orbitals ``coeffs``: (coefficients, points)."""
+    psi = orbitals_on_grid(coeffs, miller, L, n)
+    pts = scdm_points(psi)
+    return scdm_given_points(coeffs, psi, pts), pts

@@ -145,4 +145,13 @@ hipError_t launch_polar_elem(int mode, const void* in, int n, const double* s,
 hipError_t launch_polar_norm(int mode, const void* B, int n, double* out,
                              hipStream_t st);
 
+// SCDM point selection on the workspace orbital grids (complex or real,
+// FP32 or FP64): n_orb greedy picks of column-pivoted QR of Psi^H into
+// points (device int32), then Y[k][n] = conj(psi_n(points[k])) (n_orb x n_orb
+// complex128 row-major).  d: ng doubles; scratch: scdm_scratch_bytes.
+int64_t scdm_scratch_bytes(int n_orb);
+hipError_t launch_scdm(bool fp64, bool real, const void* psi, int n_orb,
+                       int64_t ng, double* d, void* scratch, int32_t* points,
+                       void* Y, hipStream_t st);
+
 }  // namespace lace

@@ -84,7 +84,7 @@ static int hip_status(hipError_t e) { return e == hipSuccess ? LACE_OK : LACE_EH
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t psi, w, tmp, epart, s, part, mw, a, z, t, u, total;
+  size_t psi, w, tmp, epart, s, part, mw, a, z, t, u, dens, scdm, pts, total;
   int pairs_per_batch;
 };
 
@@ -122,6 +122,9 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.z = off; off += align_up(16 * (size_t)n_orb * std::max(n_orb, n_vec));
   L.t = off; off += align_up(16 * (size_t)n_orb * std::max(n_vec, 1));
   L.u = off; off += align_up(16 * (size_t)n_orb * n_orb);
+  L.dens = off; off += align_up(sizeof(double) * (size_t)c.ng);
+  L.scdm = off; off += align_up((size_t)scdm_scratch_bytes(n_orb));
+  L.pts = off; off += align_up(sizeof(int32_t) * (size_t)n_orb);
   L.total = off;
   return L;
 }
@@ -946,32 +949,21 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
 // steps resolve singular values down to ~1e-4 of the largest.
 static constexpr int kAlignSteps = 30;
 
-int lace_align(lace_plan* p, int cell, const void* psi_new, const void* psi_old,
-               int n_orb, void* psi_out, double* resid, void* ws,
-               size_t ws_bytes, lace_stream_t stream) {
-  int rc = check_common(p, cell, n_orb);
-  if (rc) return rc;
-  if (!psi_new || !psi_old || !psi_out || !ws) return LACE_EINVAL;
-  if (psi_out == psi_new || psi_out == psi_old) return LACE_EINVAL;
-  const Layout L = layout_for(p, cell, n_orb, 0);
-  if (ws_bytes < L.total) return LACE_ENOMEM;
-  const CellDev& c = p->cells[cell].dev;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int n = n_orb;
+// Polar factor U of an n x n complex matrix A, given Y_0 = A^T (row-major)
+// in the workspace's `a` block: X_0 = A s with s from a Gershgorin bound,
+// then X <- X (3 I - X^H X) / 2, kept transposed (Y = X^T).  Leaves U
+// (row-major) in the `mw` block; resid (device, may be NULL) gets
+// ||U^H U - I||_F / sqrt(n).
+static hipError_t enqueue_polar(const Layout& L, void* ws, int n, double* resid,
+                                hipStream_t st) {
   void* part = at(ws, L.part);
   const int64_t pb = (int64_t)(L.mw - L.part);
-  void* g = at(ws, L.mw);     // G, later C and U
-  void* y0 = at(ws, L.a);     // Y = X^T, ping
+  void* g = at(ws, L.mw);     // C, finally U
+  void* y0 = at(ws, L.a);     // Y, ping
   void* y1 = at(ws, L.u);     // pong
   void* b = at(ws, L.z);      // X^H X
   double* sc = reinterpret_cast<double*>(at(ws, L.s));
-  // G[x][y] = <psi_old_x | psi_new_y> = conj(A[y][x]), A = psi_new^H psi_old;
-  // X_0 = A s, stored transposed: Y_0 = conj(G) s
-  hipError_t e = launch_gemm_ip_c128(psi_old, c.n_pw, n, psi_new, c.n_pw, n,
-                                     c.n_pw, 1.0, g, part, pb, st);
-  if (e == hipSuccess) e = launch_polar_elem(0, g, n, nullptr, y0, st);
-  if (e == hipSuccess)
-    e = launch_gemm_ip_c128(y0, n, n, y0, n, n, n, 1.0, b, part, pb, st);
+  hipError_t e = launch_gemm_ip_c128(y0, n, n, y0, n, n, n, 1.0, b, part, pb, st);
   if (e == hipSuccess) e = launch_polar_norm(0, b, n, sc, st);
   if (e == hipSuccess) e = launch_polar_elem(1, y0, n, sc, y1, st);
   void* cur = y1;
@@ -987,10 +979,58 @@ int lace_align(lace_plan* p, int cell, const void* psi_new, const void* psi_old,
     e = launch_gemm_ip_c128(cur, n, n, cur, n, n, n, 1.0, b, part, pb, st);
     if (e == hipSuccess) e = launch_polar_norm(1, b, n, resid, st);
   }
-  // U = Y^T, psi_out_b = sum_a psi_new_a U[a][b]
-  if (e == hipSuccess) e = launch_polar_elem(3, cur, n, nullptr, g, st);
+  if (e == hipSuccess) e = launch_polar_elem(3, cur, n, nullptr, g, st);  // U = Y^T
+  return e;
+}
+
+int lace_align(lace_plan* p, int cell, const void* psi_new, const void* psi_old,
+               int n_orb, void* psi_out, double* resid, void* ws,
+               size_t ws_bytes, lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_new || !psi_old || !psi_out || !ws) return LACE_EINVAL;
+  if (psi_out == psi_new || psi_out == psi_old) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  const CellDev& c = p->cells[cell].dev;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int n = n_orb;
+  // G[x][y] = <psi_old_x | psi_new_y> = conj(A[y][x]), A = psi_new^H psi_old,
+  // so Y_0 = A^T = conj(G)
+  hipError_t e = launch_gemm_ip_c128(psi_old, c.n_pw, n, psi_new, c.n_pw, n,
+                                     c.n_pw, 1.0, at(ws, L.mw), at(ws, L.part),
+                                     (int64_t)(L.mw - L.part), st);
+  if (e == hipSuccess) e = launch_polar_elem(0, at(ws, L.mw), n, nullptr, at(ws, L.a), st);
+  if (e == hipSuccess) e = enqueue_polar(L, ws, n, resid, st);
+  // psi_out_b = sum_a psi_new_a U[a][b]
   if (e == hipSuccess)
-    e = launch_gemm_tall(psi_new, c.n_pw, c.n_pw, n, g, n, psi_out, c.n_pw, st);
+    e = launch_gemm_tall(psi_new, c.n_pw, c.n_pw, n, at(ws, L.mw), n, psi_out,
+                         c.n_pw, st);
+  return hip_status(e);
+}
+
+int lace_scdm(lace_plan* p, int cell, const void* psi_g, int n_orb,
+              void* phi_g, int32_t* points, double* resid, void* ws,
+              size_t ws_bytes, lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!psi_g || !phi_g || !ws || phi_g == psi_g) return LACE_EINVAL;
+  const CellDev& c = p->cells[cell].dev;
+  if ((int64_t)n_orb > c.ng || n_orb > 3072) return LACE_EINVAL;
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  if (ws_bytes < L.total) return LACE_ENOMEM;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t* pts = points ? points : reinterpret_cast<int32_t*>(at(ws, L.pts));
+  hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
+  if (e == hipSuccess)
+    e = launch_scdm(p->fp64, p->gamma, at(ws, L.psi), n_orb, c.ng,
+                    reinterpret_cast<double*>(at(ws, L.dens)), at(ws, L.scdm),
+                    pts, at(ws, L.a), st);
+  if (e == hipSuccess) e = enqueue_polar(L, ws, n_orb, resid, st);
+  // phi_k = sum_n psi_n U[n][k]
+  if (e == hipSuccess)
+    e = launch_gemm_tall(psi_g, c.n_pw, c.n_pw, n_orb, at(ws, L.mw), n_orb,
+                         phi_g, c.n_pw, st);
   return hip_status(e);
 }
 

@@ -1,0 +1,270 @@
+// Selected columns of the density matrix (SCDM) on the grid orbitals.
+//
+// The localization step of Sec. 2 picks N grid points r_k greedily: each
+// pick is the point where the column a_r = conj(psi(r)) of Psi^H (one
+// entry per orbital) has the largest part outside the span of the columns
+// already picked, i.e. column-pivoted QR of Psi^H.  The residual norms
+// d(r) = |a_r|^2 - sum_k |q_k^H a_r|^2 are kept on the device and
+// downdated after every pick with the new orthonormal direction q_k, so a
+// step reads the orbital grids once (a matrix-vector product over N_g
+// points) plus an argmax; no step returns to the host.
+//
+// Grids are the workspace's orbital grids in the plan precision: complex
+// (orbital-major, n^3 points each) or real (Gamma plans).  Sums and the
+// directions q_k are FP64.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace lace {
+
+template <typename T> struct GridVal;
+template <> struct GridVal<float2> {
+  __device__ static double2 get(const float2* g, int64_t i) {
+    const float2 v = g[i];
+    return make_double2(v.x, v.y);
+  }
+};
+template <> struct GridVal<double2> {
+  __device__ static double2 get(const double2* g, int64_t i) { return g[i]; }
+};
+template <> struct GridVal<float> {
+  __device__ static double2 get(const float* g, int64_t i) {
+    return make_double2(g[i], 0.0);
+  }
+};
+template <> struct GridVal<double> {
+  __device__ static double2 get(const double* g, int64_t i) {
+    return make_double2(g[i], 0.0);
+  }
+};
+
+// d(r) = sum_n |psi_n(r)|^2 (the diagonal of the density matrix)
+template <typename G>
+__global__ void k_scdm_density(const G* psi, int n_orb, int64_t ng, double* d) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < ng;
+       r += stride) {
+    double s = 0.0;
+    for (int n = 0; n < n_orb; ++n) {
+      const double2 v = GridVal<G>::get(psi, n * ng + r);
+      s += v.x * v.x + v.y * v.y;
+    }
+    d[r] = s;
+  }
+}
+
+// Block-wise argmax of d over [0, ng): the largest value, the smallest
+// index among equals.  Picked points hold -1 and are never chosen again.
+struct ArgMax {
+  double v;
+  int64_t i;
+};
+__device__ inline ArgMax better(ArgMax a, ArgMax b) {
+  if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+  return a;
+}
+
+template <int NT>
+__device__ inline ArgMax block_argmax(ArgMax m) {
+  __shared__ double sv[NT / 64];
+  __shared__ int64_t si[NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ArgMax t;
+    t.v = __shfl_xor(m.v, o, 64);
+    t.i = __shfl_xor(m.i, o, 64);
+    m = better(m, t);
+  }
+  if (threadIdx.x % 64 == 0) {
+    sv[threadIdx.x / 64] = m.v;
+    si[threadIdx.x / 64] = m.i;
+  }
+  __syncthreads();
+  m.v = sv[0];
+  m.i = si[0];
+  for (int w = 1; w < NT / 64; ++w) m = better(m, ArgMax{sv[w], si[w]});
+  return m;
+}
+
+constexpr int AM_NT = 256;
+constexpr int AM_BLOCKS = 1024;
+
+__global__ void k_argmax_partial(const double* d, int64_t ng, double* pv,
+                                 int64_t* pi) {
+  ArgMax m{-2.0, 0};
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t r = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; r < ng;
+       r += stride)
+    m = better(m, ArgMax{d[r], r});
+  m = block_argmax<AM_NT>(m);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = m.v;
+    pi[blockIdx.x] = m.i;
+  }
+}
+
+// Final argmax; records the point as pick k, marks it taken.
+__global__ void k_argmax_final(const double* pv, const int64_t* pi, int nparts,
+                               double* d, int32_t* points, int k) {
+  ArgMax m{-2.0, 0};
+  for (int b = threadIdx.x; b < nparts; b += AM_NT) m = better(m, ArgMax{pv[b], pi[b]});
+  m = block_argmax<AM_NT>(m);
+  if (threadIdx.x == 0) {
+    points[k] = (int32_t)m.i;
+    d[m.i] = -1.0;
+  }
+}
+
+// q_k: the picked column a = conj(psi(r_k)) made orthogonal to q_0..q_{k-1}
+// (classical Gram-Schmidt, twice) and normalized; Q row-major, q_m = Q[m][.].
+// One workgroup; scratch u holds n_orb doubles2, h holds k values.
+template <typename G, int NT>
+__global__ void k_scdm_direction(const G* psi, int n_orb, int64_t ng,
+                                 const int32_t* points, int k, double2* Q,
+                                 double2* u, double2* h) {
+  __shared__ double red[NT / 64];
+  const int64_t r = points[k];
+  for (int n = threadIdx.x; n < n_orb; n += NT) {
+    const double2 v = GridVal<G>::get(psi, n * ng + r);
+    u[n] = make_double2(v.x, -v.y);
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int m = threadIdx.x; m < k; m += NT) {   // h_m = q_m^H u
+      double2 s = make_double2(0.0, 0.0);
+      const double2* q = Q + (int64_t)m * n_orb;
+      for (int n = 0; n < n_orb; ++n) {
+        s.x += q[n].x * u[n].x + q[n].y * u[n].y;
+        s.y += q[n].x * u[n].y - q[n].y * u[n].x;
+      }
+      h[m] = s;
+    }
+    __syncthreads();
+    for (int n = threadIdx.x; n < n_orb; n += NT) {   // u -= sum_m q_m h_m
+      double2 s = u[n];
+      for (int m = 0; m < k; ++m) {
+        const double2 q = Q[(int64_t)m * n_orb + n];
+        s.x -= q.x * h[m].x - q.y * h[m].y;
+        s.y -= q.x * h[m].y + q.y * h[m].x;
+      }
+      u[n] = s;
+    }
+    __syncthreads();
+  }
+  double t = 0.0;
+  for (int n = threadIdx.x; n < n_orb; n += NT) t += u[n].x * u[n].x + u[n].y * u[n].y;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = t;
+  __syncthreads();
+  double nrm = 0.0;
+  for (int w = 0; w < NT / 64; ++w) nrm += red[w];
+  const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+  for (int n = threadIdx.x; n < n_orb; n += NT)
+    Q[(int64_t)k * n_orb + n] = make_double2(u[n].x * inv, u[n].y * inv);
+}
+
+// d(r) -= |q_k^H a_r|^2 = |sum_n q_kn psi_n(r)|^2 for points not yet taken.
+template <typename G, int NT>
+__global__ void k_scdm_downdate(const G* psi, int n_orb, int64_t ng,
+                                const double2* Q, int k, double* d) {
+  extern __shared__ double2 qs[];
+  for (int n = threadIdx.x; n < n_orb; n += NT) qs[n] = Q[(int64_t)k * n_orb + n];
+  __syncthreads();
+  const int64_t stride = int64_t(gridDim.x) * NT;
+  for (int64_t r = blockIdx.x * int64_t(NT) + threadIdx.x; r < ng; r += stride) {
+    double sx = 0.0, sy = 0.0;
+    for (int n = 0; n < n_orb; ++n) {
+      const double2 v = GridVal<G>::get(psi, n * ng + r);
+      sx += qs[n].x * v.x - qs[n].y * v.y;
+      sy += qs[n].x * v.y + qs[n].y * v.x;
+    }
+    const double old = d[r];
+    if (old >= 0.0) d[r] = fmax(old - (sx * sx + sy * sy), 0.0);
+  }
+}
+
+// Y[k][n] = conj(psi_n(r_k)): the picked columns of Psi^H, transposed.
+template <typename G>
+__global__ void k_scdm_gather(const G* psi, int n_orb, int64_t ng,
+                              const int32_t* points, double2* Y) {
+  const int64_t total = (int64_t)n_orb * n_orb;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += stride) {
+    const int k = (int)(e / n_orb), n = (int)(e % n_orb);
+    const double2 v = GridVal<G>::get(psi, n * ng + points[k]);
+    Y[e] = make_double2(v.x, -v.y);
+  }
+}
+
+template <typename G>
+static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
+                         double* pv, int64_t* pi, double2* Q, double2* u,
+                         double2* h, int32_t* points, double2* Y,
+                         hipStream_t st) {
+  constexpr int NT = 256;
+  int64_t blocks = (ng + NT - 1) / NT;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_scdm_density<G>, dim3((unsigned)blocks), dim3(NT), 0,
+                     st, psi, n_orb, ng, d);
+  hipError_t e = hipGetLastError();
+  const int parts = (int)std::min<int64_t>(AM_BLOCKS, (ng + AM_NT - 1) / AM_NT);
+  const size_t qlds = sizeof(double2) * (size_t)n_orb;
+  for (int k = 0; k < n_orb && e == hipSuccess; ++k) {
+    hipLaunchKernelGGL(k_argmax_partial, dim3(parts), dim3(AM_NT), 0, st, d,
+                       ng, pv, pi);
+    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(AM_NT), 0, st, pv, pi,
+                       parts, d, points, k);
+    hipLaunchKernelGGL((k_scdm_direction<G, 1024>), dim3(1), dim3(1024), 0, st,
+                       psi, n_orb, ng, points, k, Q, u, h);
+    if (k + 1 < n_orb)
+      hipLaunchKernelGGL((k_scdm_downdate<G, NT>), dim3((unsigned)blocks),
+                         dim3(NT), qlds, st, psi, n_orb, ng, Q, k, d);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    int64_t b2 = ((int64_t)n_orb * n_orb + NT - 1) / NT;
+    if (b2 > 2048) b2 = 2048;
+    hipLaunchKernelGGL(k_scdm_gather<G>, dim3((unsigned)b2), dim3(NT), 0, st,
+                       psi, n_orb, ng, points, Y);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+int64_t scdm_scratch_bytes(int n_orb) {
+  return (int64_t)AM_BLOCKS * (sizeof(double) + sizeof(int64_t)) +
+         (int64_t)sizeof(double2) * (2 * (int64_t)n_orb + (int64_t)n_orb * n_orb);
+}
+
+hipError_t launch_scdm(bool fp64, bool real, const void* psi, int n_orb,
+                       int64_t ng, double* d, void* scratch, int32_t* points,
+                       void* Y, hipStream_t st) {
+  if (n_orb > 48 * 1024 / (int)sizeof(double2)) return hipErrorInvalidValue;
+  char* p = static_cast<char*>(scratch);
+  double* pv = reinterpret_cast<double*>(p);
+  p += AM_BLOCKS * sizeof(double);
+  int64_t* pi = reinterpret_cast<int64_t*>(p);
+  p += AM_BLOCKS * sizeof(int64_t);
+  double2* u = reinterpret_cast<double2*>(p);
+  p += sizeof(double2) * n_orb;
+  double2* h = reinterpret_cast<double2*>(p);
+  p += sizeof(double2) * n_orb;
+  double2* Q = reinterpret_cast<double2*>(p);
+  double2* y = static_cast<double2*>(Y);
+  if (real)
+    return fp64 ? scdm_t(static_cast<const double*>(psi), n_orb, ng, d, pv, pi,
+                         Q, u, h, points, y, st)
+                : scdm_t(static_cast<const float*>(psi), n_orb, ng, d, pv, pi,
+                         Q, u, h, points, y, st);
+  return fp64 ? scdm_t(static_cast<const double2*>(psi), n_orb, ng, d, pv, pi,
+                       Q, u, h, points, y, st)
+              : scdm_t(static_cast<const float2*>(psi), n_orb, ng, d, pv, pi,
+                       Q, u, h, points, y, st);
+}
+
+}  // namespace lace

@@ -40,6 +40,7 @@ SYMBOLS = (
     "lace_fft3d", "lace_get_info", "lace_status_string",
     "lace_profile_enable", "lace_profile_read", "lace_schedule_pairs",
     "lace_schedule_slots", "lace_apply_exchange_virtual", "lace_align",
+    "lace_scdm",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
     "lace_autotune", "lace_check_real",
 )
@@ -101,6 +102,7 @@ def load(path: str = LIB_PATH):
         vp, i32, vp, i32, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
         sz, vp]
     lib.lace_align.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, sz, vp]
+    lib.lace_scdm.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
                                    sz, vp]
     lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
@@ -247,6 +249,18 @@ def lace_align(plan, cell, psi_new, psi_old, n_orb, psi_out, resid, ws,
         _ptr(psi_out, torch.complex128, "psi_out"),
         _ptr(resid, torch.float64, "resid"), _ptr(ws, None, "ws"),
         ws.numel() * ws.element_size(), _stream(stream)), "lace_align")
+
+
+def lace_scdm(plan, cell, psi_g, n_orb, phi_g, points, resid, ws,
+              stream=None):
+    """phi = SCDM-localized psi; points (int32 device tensor or None)."""
+    import torch
+    _check(load().lace_scdm(
+        plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), int(n_orb),
+        _ptr(phi_g, torch.complex128, "phi_g"),
+        _ptr(points, torch.int32, "points"), _ptr(resid, torch.float64, "resid"),
+        _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)),
+        "lace_scdm")
 
 
 def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,

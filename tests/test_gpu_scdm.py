@@ -1,0 +1,147 @@
+"""SCDM localization (Sec. 2) through the C ABI against the oracle: the
+greedy points (each pick checked to be a greedy choice given the earlier
+picks, and identical to LAPACK's pivots in FP64) and the localized
+orbitals for those points."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+from paper_1801_09263_amd import lace  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = lace.LACE_FP64, lace.LACE_FP32
+FP64G, FP32G = lace.LACE_FP64_GAMMA, lace.LACE_FP32_GAMMA
+IS64 = {FP64: True, FP32: False, FP64G: True, FP32G: False}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_scdm(cell, coeffs, prec):
+    n_orb = coeffs.shape[0]
+    plan = lace.lace_plan_create([cell], prec)
+    ws = torch.empty(lace.lace_workspace_size(plan, 0, n_orb, n_orb),
+                     dtype=torch.uint8, device="cuda")
+    psi = torch.tensor(coeffs, device="cuda")
+    phi = torch.empty_like(psi)
+    pts = torch.full((n_orb,), -1, dtype=torch.int32, device="cuda")
+    resid = torch.full((1,), -1.0, dtype=torch.float64, device="cuda")
+    lace.lace_scdm(plan, 0, psi, n_orb, phi, pts, resid, ws)
+    torch.cuda.synchronize()
+    plan.close()
+    return phi.cpu().numpy(), pts.cpu().numpy(), resid.item()
+
+
+def check_greedy(psi, picks, tol):
+    """Each pick has a residual norm within tol of the largest, given the
+    picks before it (FP64, from the oracle's grids)."""
+    nb = psi.shape[0]
+    a = np.conj(psi.reshape(nb, -1))
+    q = np.zeros((nb, 0), complex)
+    res = np.einsum("ij,ij->j", np.conj(a), a).real
+    taken = np.zeros(a.shape[1], bool)
+    worst = 1.0
+    for k, p in enumerate(picks):
+        cand = np.where(taken, -1.0, res)
+        worst = min(worst, cand[p] / cand.max())
+        assert cand[p] >= (1.0 - tol) * cand.max(), f"pick {k}"
+        u = a[:, p] - q @ (np.conj(q.T) @ a[:, p])
+        u /= np.linalg.norm(u)
+        q = np.concatenate([q, u[:, None]], axis=1)
+        res = res - np.abs(np.conj(u) @ a) ** 2
+        taken[p] = True
+    return worst
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    """16 localized real orbitals (8 centres, 16 bohr cell, 32^3) mixed by a
+    random rotation: delocalized, still real."""
+    L, n, ecut = 16.0, 32, 15.0
+    miller = synth.miller_sphere(L, ecut)
+    loc = synth.gaussian_orbitals(miller, L, 16, 8, synth.rng_for(90))
+    v, _ = np.linalg.qr(np.random.default_rng(73).standard_normal((16, 16)))
+    return dict(L=L, n=n, miller=miller), v.T @ loc
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, FP64G, FP32G],
+                         ids=["fp64", "fp32", "fp64g", "fp32g"])
+def test_scdm_against_oracle(mixed, prec):
+    cell, coeffs = mixed
+    say(f"scdm prec={prec}")
+    phi, pts, resid = run_scdm(cell, coeffs, prec)
+    psi = O.orbitals_on_grid(coeffs, cell["miller"], cell["L"], cell["n"])
+    tol = 1e-10 if IS64[prec] else 1e-3
+    worst = check_greedy(psi, pts, tol)
+    say(f"  worst pick ratio {worst:.8f}, resid {resid:.1e}")
+    if IS64[prec]:
+        assert list(pts) == list(O.scdm_points(psi))
+    ref = O.scdm_given_points(coeffs, psi, pts)
+    err = rel(phi, ref)
+    say(f"  phi rel err {err:.2e}")
+    assert err <= (1e-10 if IS64[prec] else 1e-5)
+    assert resid <= 1e-10
+
+
+def test_scdm_complex_orbitals_fp64():
+    inp = synth.make_config_inputs(0)
+    cell = dict(L=inp["L"], n=inp["n"], miller=inp["miller"])
+    phi, pts, resid = run_scdm(cell, inp["coeffs"], FP64)
+    psi = O.orbitals_on_grid(inp["coeffs"], inp["miller"], inp["L"], inp["n"])
+    assert list(pts) == list(O.scdm_points(psi))
+    assert rel(phi, O.scdm_given_points(inp["coeffs"], psi, pts)) <= 1e-10
+
+
+def test_scdm_full_size_relocalizes():
+    """The 256 localized orbitals of the 120^3 workload, mixed by a random
+    rotation, overlap strongly everywhere; after SCDM the overlaps of moduli
+    S_ij fall back to those of a localized set (SCDM orbitals carry the
+    orthonormalization tails of density-matrix columns, so they are not as
+    compact as the analytic Gaussians)."""
+    inp = synth.make_config_inputs(2)
+    cell = {k: inp[k] for k in ("L", "n", "miller")}
+    loc = inp["coeffs"]
+    v, _ = np.linalg.qr(np.random.default_rng(74).standard_normal((256, 256)))
+    mixed_c = v.T @ loc
+    phi, pts, resid = run_scdm(cell, mixed_c, FP32G)
+    say(f"full size: resid {resid:.1e}, distinct points {len(set(pts.tolist()))}")
+    assert resid <= 1e-10 and len(set(pts.tolist())) == 256
+    gram = np.conj(phi) @ phi.T
+    assert np.abs(gram - np.eye(256)).max() <= 1e-6
+
+    def overlaps(c):
+        plan = lace.lace_plan_create([cell], FP32G)
+        ws = torch.empty(lace.lace_workspace_size(plan, 0, 256, 256),
+                         dtype=torch.uint8, device="cuda")
+        s = torch.empty((256, 256), dtype=torch.float64, device="cuda")
+        lace.lace_screen(plan, 0, torch.tensor(c, device="cuda"), 256, s, ws)
+        torch.cuda.synchronize()
+        plan.close()
+        return s.cpu().numpy()[np.triu_indices(256, 1)]
+    s_loc, s_mix, s_scdm = overlaps(loc), overlaps(mixed_c), overlaps(phi)
+    for name, sv in (("localized", s_loc), ("mixed", s_mix), ("SCDM", s_scdm)):
+        say(f"  {name}: median S {np.median(sv):.2e}, "
+            + ", ".join(f"kept@{t:g} {(sv >= t).sum()}"
+                        for t in (1e-3, 1e-2, 3e-2, 1e-1)))
+    assert np.median(s_scdm) < 0.25 * np.median(s_mix)
+    assert (s_scdm >= 1e-2).sum() < 0.5 * (s_mix >= 1e-2).sum()
+
+
+def test_scdm_rejects_aliased_output(mixed):
+    cell, coeffs = mixed
+    plan = lace.lace_plan_create([cell], FP32)
+    ws = torch.empty(lace.lace_workspace_size(plan, 0, 16, 16),
+                     dtype=torch.uint8, device="cuda")
+    t = torch.tensor(coeffs, device="cuda")
+    with pytest.raises(lace.LaceError):
+        lace.lace_scdm(plan, 0, t, 16, t, None, None, ws)
+    plan.close()

@@ -618,3 +618,70 @@ def test_align_keeps_real_orbitals_real(localized):
     where = {tuple(m): k for k, m in enumerate(miller.tolist())}
     neg = np.array([where[(-x, -y, -z)] for x, y, z in miller.tolist()])
     assert np.abs(out[:, neg] - np.conj(out)).max() <= 1e-13
+
+
+# -------------------------------------------- SCDM localization (Sec. 2)
+def _greedy_points_brute(psi):
+    """Greedy picks by their definition: at each step the point whose column
+    conj(psi(r)) has the largest residual after least-squares projection on
+    the columns already picked."""
+    nb = psi.shape[0]
+    a = np.conj(psi.reshape(nb, -1))
+    picks = []
+    for _ in range(nb):
+        if picks:
+            b = a[:, picks]
+            coef, *_ = np.linalg.lstsq(b, a, rcond=None)
+            res = a - b @ coef
+        else:
+            res = a
+        norms = np.einsum("ij,ij->j", np.conj(res), res).real
+        norms[picks] = -1.0
+        picks.append(int(np.argmax(norms)))
+    return np.array(picks)
+
+
+def test_scdm_points_are_the_greedy_picks():
+    L, n, ecut = 8.0, 12, 4.0
+    miller = synth.miller_sphere(L, ecut)
+    coeffs = synth.random_orbitals(miller, L, 5, synth.rng_for(70))
+    psi = O.orbitals_on_grid(coeffs, miller, L, n)
+    assert list(O.scdm_points(psi)) == list(_greedy_points_brute(psi))
+
+
+def test_scdm_is_gauge_invariant(localized):
+    """Mixing the orbitals by any unitary changes neither the points nor the
+    localized orbitals (they depend on the density matrix only)."""
+    L, n, miller = localized["L"], localized["n"], localized["miller"]
+    coeffs = localized["coeffs"]
+    rng = np.random.default_rng(71)
+    z = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    v, _ = np.linalg.qr(z)
+    phi1, p1 = O.scdm(coeffs, miller, L, n)
+    phi2, p2 = O.scdm(v.T @ coeffs, miller, L, n)
+    assert list(p1) == list(p2)
+    assert np.abs(phi1 - phi2).max() <= 1e-12
+
+
+def test_scdm_localizes_mixed_localized_orbitals(localized):
+    """Localized orbitals mixed by a random rotation are delocalized (every
+    pair survives the screening); SCDM makes them local again, orthonormal
+    and spanning the same space."""
+    L, n, miller = localized["L"], localized["n"], localized["miller"]
+    coeffs = localized["coeffs"]
+    rng = np.random.default_rng(72)
+    v, _ = np.linalg.qr(rng.standard_normal((16, 16)))
+    mixed = v.T @ coeffs
+    s_thr = 5e-3
+    def kept(c):
+        return len(O.kept_pairs(O.overlap_of_moduli(
+            O.orbitals_on_grid(c, miller, L, n), L), s_thr))
+    k_loc, k_mix = kept(coeffs), kept(mixed)
+    phi, _ = O.scdm(mixed, miller, L, n)
+    k_scdm = kept(phi)
+    assert k_mix == 16 * 17 // 2
+    assert k_scdm < 0.8 * k_mix
+    assert abs(k_scdm - k_loc) <= 0.35 * k_loc
+    assert np.abs(np.conj(phi) @ phi.T - np.eye(16)).max() <= 1e-13
+    proj = np.conj(coeffs) @ phi.T
+    assert np.abs(proj.T @ coeffs - phi).max() <= 1e-12
