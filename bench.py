@@ -380,8 +380,8 @@ def main():
     tuning = lace.lace_get_tuning(sess.plan, 0)
     log("tuning", tuning)
     log(f"timing {args.steps} steps after {args.warmup} warmup")
-    n_kept, t_step, prof = time_steps(torch, sess, inp["s_thr"], args.steps,
-                                      args.warmup, profile=True)
+    n_kept, t_step, _ = time_steps(torch, sess, inp["s_thr"], args.steps,
+                                   args.warmup, profile=False)
     n_total = n_orb * (n_orb + 1) // 2
     e_x = sess.e_x.item()
     ex_tr = sess.ex_tr.item()
@@ -390,6 +390,15 @@ def main():
     value = n_kept / t_step
     log(f"step {t_step * 1e3:.1f} ms, kept {n_kept}/{n_total}, "
         f"exchange {t_exch * 1e3:.1f} ms")
+    # Per-pass kernel figures: the same steps again with the library's pass
+    # events on, which run the batches on the caller's stream one launch at a
+    # time (the timed steps let consecutive batches overlap on two streams),
+    # so each launch's duration is that kernel's own.  These are the last
+    # pair-pipeline launches of the run.
+    log(f"profiling {args.steps} more steps, launches serialized")
+    _, t_step_prof, prof = time_steps(torch, sess, inp["s_thr"], args.steps, 0,
+                                      profile=True)
+    log(f"profiled step {t_step_prof * 1e3:.1f} ms")
 
     # roofline of the dominant kernel of the pair pipeline
     rows = pass_roofline(prof)
@@ -415,6 +424,11 @@ def main():
         bytes_per_launch=rows[dom]["bytes_per_launch"],
         passes=[{k: (round(v, 3) if isinstance(v, float) else v)
                  for k, v in r.items()} for r in rows],
+        durations=("HIP events around each launch on the library's stream, "
+                   "in a profiled repeat of the timed steps that runs the "
+                   "launches one at a time; the timed steps overlap "
+                   "consecutive batches on two streams"),
+        exchange_GBs_overlapped=round(pipe_bytes / args.steps / t_exch / 1e9, 1),
         pipeline_GBs=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9, 1),
         pipeline_frac=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     )

@@ -655,7 +655,8 @@ template <typename T, int N> struct Engine {
   static hipError_t pair_batch(const CellDev& c, const PairArgs& pa,
                                const C<T>* psi, C<T>* w, C<T>* tmp,
                                double* epart, hipStream_t st,
-                               hipEvent_t* ev = nullptr) {
+                               hipEvent_t* ev = nullptr,
+                               const BatchSync* sy = nullptr) {
     const C<T>* tw = static_cast<const C<T>*>(c.tw);
     const int cnt = pa.n;
     ProPair<T> pp{psi, NG, pa};
@@ -685,6 +686,8 @@ template <typename T, int N> struct Engine {
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
+    if (sy && sy->wait_c && (err = hipStreamWaitEvent(st, sy->wait_c, 0)) != hipSuccess)
+      return err;
     // pass C
     if (mode == 2) {
       err = half<+1>(pt, ea, cnt, tw, st);
@@ -695,13 +698,15 @@ template <typename T, int N> struct Engine {
       if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
     }
     if (err == hipSuccess && ev) err = hipEventRecord(ev[3], st);
+    if (err == hipSuccess && sy && sy->done_c) err = hipEventRecord(sy->done_c, st);
     return err;
   }
 
   // Packed slots of real orbitals: same passes, real grids in and out.
   static hipError_t quad_batch(const CellDev& c, const QuadArgs& qa,
                                const T* psi, T* w, C<T>* tmp, double* epart,
-                               hipStream_t st, hipEvent_t* ev) {
+                               hipStream_t st, hipEvent_t* ev,
+                               const BatchSync* sy = nullptr) {
     const C<T>* tw = static_cast<const C<T>*>(c.tw);
     const int cnt = qa.n;
     ProQuad<T> pp{psi, NG, qa};
@@ -734,6 +739,8 @@ template <typename T, int N> struct Engine {
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
+    if (sy && sy->wait_c && (err = hipStreamWaitEvent(st, sy->wait_c, 0)) != hipSuccess)
+      return err;
     if (mode == 2) {
       err = half<+1>(pt, ea, cnt, tw, st);
     } else if (mode == 1) {
@@ -743,6 +750,7 @@ template <typename T, int N> struct Engine {
       if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
     }
     if (err == hipSuccess && ev) err = hipEventRecord(ev[3], st);
+    if (err == hipSuccess && sy && sy->done_c) err = hipEventRecord(sy->done_c, st);
     return err;
   }
 
@@ -870,13 +878,13 @@ template <typename T>
 static hipError_t pair_batch_t(const CellDev& c, const PairArgs& pa,
                                const void* psi, void* w, void* tmp,
                                double* epart, hipStream_t st,
-                               hipEvent_t* ev) {
+                               hipEvent_t* ev, const BatchSync* sy = nullptr) {
   switch (c.n) {
 #define X(NN)                                                          \
   case NN:                                                             \
     return Engine<T, NN>::pair_batch(c, pa, static_cast<const C<T>*>(psi), \
                                      static_cast<C<T>*>(w),            \
-                                     static_cast<C<T>*>(tmp), epart, st, ev);
+                                     static_cast<C<T>*>(tmp), epart, st, ev, sy);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -885,10 +893,11 @@ static hipError_t pair_batch_t(const CellDev& c, const PairArgs& pa,
 
 hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
                              const void* psi, void* w, void* tmp,
-                             double* epart, hipStream_t st) {
+                             double* epart, hipStream_t st,
+                             const BatchSync* sy) {
   if (pa.n <= 0) return hipSuccess;
-  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st, nullptr)
-              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st, nullptr);
+  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st, nullptr, sy)
+              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st, nullptr, sy);
 }
 
 hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
@@ -1042,13 +1051,14 @@ hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64,
 template <typename T>
 static hipError_t quad_batch_t(const CellDev& c, const QuadArgs& qa,
                                const void* psi, void* w, void* tmp,
-                               double* epart, hipStream_t st, hipEvent_t* ev) {
+                               double* epart, hipStream_t st, hipEvent_t* ev,
+                               const BatchSync* sy) {
   switch (c.n) {
 #define X(NN)                                                              \
   case NN:                                                                 \
     return Engine<T, NN>::quad_batch(c, qa, static_cast<const T*>(psi),    \
                                      static_cast<T*>(w),                   \
-                                     static_cast<C<T>*>(tmp), epart, st, ev);
+                                     static_cast<C<T>*>(tmp), epart, st, ev, sy);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -1057,10 +1067,11 @@ static hipError_t quad_batch_t(const CellDev& c, const QuadArgs& qa,
 
 hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
                              const void* psi, void* w, void* tmp,
-                             double* epart, hipStream_t st, hipEvent_t* ev) {
+                             double* epart, hipStream_t st, hipEvent_t* ev,
+                             const BatchSync* sy) {
   if (qa.n <= 0) return hipSuccess;
-  return fp64 ? quad_batch_t<double>(c, qa, psi, w, tmp, epart, st, ev)
-              : quad_batch_t<float>(c, qa, psi, w, tmp, epart, st, ev);
+  return fp64 ? quad_batch_t<double>(c, qa, psi, w, tmp, epart, st, ev, sy)
+              : quad_batch_t<float>(c, qa, psi, w, tmp, epart, st, ev, sy);
 }
 
 // per block: sum |C_m - conj C_{-m}|^2 and sum |C_m|^2 over its share

@@ -63,9 +63,16 @@ hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
                              void* w_pw, hipStream_t st);
 // One batch of pairs (no orbital used twice): forward, kernel multiply,
 // backward, accumulate into W; adds per-tile energy partials.
+// Cross-stream order of pass C: wait for wait_c before it, record done_c
+// after it (either may be null).
+struct BatchSync {
+  hipEvent_t wait_c;
+  hipEvent_t done_c;
+};
 hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
                              const void* psi, void* w, void* tmp,
-                             double* epart, hipStream_t st);
+                             double* epart, hipStream_t st,
+                             const BatchSync* sy = nullptr);
 // Same, with ev[0..3] recorded before pass A, between the passes and
 // after pass C.
 hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
@@ -87,7 +94,8 @@ hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64,
 // One batch of packed pair slots of real orbitals (no orbital twice).
 hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
                              const void* psi_real, void* w_real, void* tmp,
-                             double* epart, hipStream_t st, hipEvent_t* ev);
+                             double* epart, hipStream_t st, hipEvent_t* ev,
+                             const BatchSync* sy = nullptr);
 // Sum over orbitals of sum_m |C_m - conj(C_{-m})|^2 and sum_m |C_m|^2 into
 // part[2 * nblocks] (host reduces); returns the number of blocks used.
 hipError_t launch_real_check(const CellDev& c, const void* coeffs, int n_orb,

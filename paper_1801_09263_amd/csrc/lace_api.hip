@@ -109,9 +109,12 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   const size_t ob = p->gamma ? gb * ((n_orb + 1) / 2) : gb * n_orb;
   L.psi = off; off += align_up(ob);
   L.w = off; off += align_up(ob);
-  L.tmp = off; off += align_up(gb * PMAX);
+  // two pair buffers and two sets of energy partials: consecutive batches
+  // alternate between them, so that one batch's passes A and B can run
+  // while the previous batch's pass C still reads its buffer
+  L.tmp = off; off += align_up(gb * PMAX * 2);
   L.epart = off;
-  off += align_up(sizeof(double) * PMAX * energy_tiles(c.n, fp64));
+  off += align_up(sizeof(double) * PMAX * 2 * energy_tiles(c.n, fp64));
   L.s = off; off += align_up(sizeof(double) * n_orb * n_orb);
   int64_t part = gemm_ip_part_bytes(n_orb, n_orb, c.n_pw, true);
   part = std::max(part, gemm_ip_part_bytes(n_orb, n_orb, c.ng, false));
@@ -817,35 +820,62 @@ static void batch_bytes(const lace_plan* p, const CellDev& c, const Batch& bt,
 }
 
 // One batch of the pair pipeline (pairs, or packed slots for Gamma plans).
+// `lane` picks the pair buffer and the energy partials (0 or 1).
 static hipError_t enqueue_batch(const lace_plan* p, const CellDev& c,
                                 const Batch& bt, const Layout& L, void* ws,
-                                double* epart, hipStream_t st, hipEvent_t* ev) {
+                                int lane, hipStream_t st, hipEvent_t* ev,
+                                const BatchSync* sy = nullptr) {
+  void* tmp = at(ws, L.tmp + (size_t)lane * PMAX * c.ng * grid_bytes(p));
+  double* epart = reinterpret_cast<double*>(at(ws, L.epart)) +
+                  (size_t)lane * PMAX * energy_tiles(c.n, p->fp64);
   if (p->gamma)
     return launch_quad_batch(c, p->fp64, bt.q, at(ws, L.psi), at(ws, L.w),
-                             at(ws, L.tmp), epart, st, ev);
+                             tmp, epart, st, ev, sy);
   const PairArgs& b = bt.p;
   if (ev)
     return launch_pair_batch_timed(c, p->fp64, b, at(ws, L.psi), at(ws, L.w),
-                                   at(ws, L.tmp), epart, st, ev);
-  return launch_pair_batch(c, p->fp64, b, at(ws, L.psi), at(ws, L.w),
-                           at(ws, L.tmp), epart, st);
+                                   tmp, epart, st, ev);
+  return launch_pair_batch(c, p->fp64, b, at(ws, L.psi), at(ws, L.w), tmp,
+                           epart, st, sy);
 }
+
+static hipError_t ensure_streams(lace_plan* p, int k);
+static hipError_t link(lace_plan* p, hipStream_t from, hipStream_t to, int k);
 
 // Pair pipeline over a schedule, energy reduction, W back to plane waves.
 // Requires the grid orbitals in the workspace.
+// overlap: run consecutive batches on two internal streams (batch b on
+// lane b % 2): a batch's passes A and B overlap the previous batch's passes,
+// and its pass C waits for the previous pass C (they may share W grids), so
+// W is summed in batch order either way.  Profiled calls run on one stream.
 static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
                                    const std::vector<Batch>& sched,
                                    const Layout& L, void* ws, void* w_g,
-                                   double* e_x, hipStream_t st, bool profile) {
+                                   double* e_x, hipStream_t st, bool profile,
+                                   bool overlap = false) {
   const bool fp64 = p->fp64;
   void* w = at(ws, L.w);
   const int64_t ntiles = energy_tiles(c.n, fp64);
   double* epart = reinterpret_cast<double*>(at(ws, L.epart));
   hipError_t e = launch_zero(w, (int64_t)c.ng * n_orb * orb_bytes(p), st);
   if (e == hipSuccess)
-    e = launch_zero(epart, (int64_t)sizeof(double) * PMAX * ntiles, st);
+    e = launch_zero(epart, (int64_t)sizeof(double) * PMAX * 2 * ntiles, st);
   Profile& pr = p->prof;
   const bool timed = profile && pr.on;
+  const bool two = overlap && !timed && sched.size() > 1;
+  hipStream_t lane[2] = {st, st};
+  hipEvent_t cdone[2] = {nullptr, nullptr};
+  if (e == hipSuccess && two) {
+    e = ensure_streams(p, 2);
+    if (e == hipSuccess) {
+      lane[0] = p->streams[0];
+      lane[1] = p->streams[1];
+      cdone[0] = p->events[2];
+      cdone[1] = p->events[3];
+      e = link(p, st, lane[0], 0);
+      if (e == hipSuccess) e = link(p, st, lane[1], 1);
+    }
+  }
   if (e == hipSuccess && timed && pr.used + 4 * sched.size() > 65536) {
     // bound the number of outstanding events: fold what is recorded
     e = hipStreamSynchronize(st);
@@ -862,13 +892,21 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
       r.pairs = sched[b].p.n;
       batch_bytes(p, c, sched[b], r.bytes);
       pr.recs.push_back(r);
-      e = enqueue_batch(p, c, sched[b], L, ws, epart, st, ev);
+      e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), st, ev);
+    } else if (two) {
+      BatchSync sy{b > 0 ? cdone[(b - 1) % 2] : nullptr, cdone[b % 2]};
+      e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), lane[b % 2],
+                        nullptr, &sy);
     } else {
-      e = enqueue_batch(p, c, sched[b], L, ws, epart, st, nullptr);
+      e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), st, nullptr);
     }
   }
+  if (e == hipSuccess && two) {
+    e = link(p, lane[0], st, 0);
+    if (e == hipSuccess) e = link(p, lane[1], st, 1);
+  }
   if (e == hipSuccess && e_x)
-    e = launch_reduce_sum(epart, (int64_t)PMAX * ntiles,
+    e = launch_reduce_sum(epart, (int64_t)PMAX * 2 * ntiles,
                           -0.5 * c.omega / double(c.ng), e_x, st);
   if (e == hipSuccess) {
     if (p->gamma)  // the orbital grids are no longer needed: scratch
@@ -938,7 +976,7 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   }
   std::vector<Batch> sched;
   schedule_for(p, pairs, n_orb, c.ppb, sched);
-  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true);
+  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true, true);
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();
   return LACE_OK;
@@ -1074,7 +1112,7 @@ int lace_apply_exchange_virtual(lace_plan* p, int cell, const void* psi_g,
     }
   std::vector<Batch> sched;
   schedule_for(p, pairs, n_orb, c.ppb, sched, &os, n_occ);
-  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true);
+  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true, true);
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();
   return LACE_OK;
@@ -1233,12 +1271,9 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
     sched.resize(nb);
     double best = 1e30;
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-      const bool fp = fp64;
-      double* epart = reinterpret_cast<double*>(at(ws, L.epart));
       e = hipEventRecord(t0, st);
-      (void)fp;
       for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b)
-        e = enqueue_batch(p, c, sched[b], L, ws, epart, st, nullptr);
+        e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), st, nullptr);
       if (e == hipSuccess) e = hipEventRecord(t1, st);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
