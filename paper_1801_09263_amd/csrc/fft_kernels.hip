@@ -580,8 +580,9 @@ template <typename T, int N> struct Cfg {
   static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
   static constexpr int TX = (N % TX0 == 0) ? TX0 : ((N % 8 == 0) ? 8 : 4);
   static constexpr int NT_COLS = 256;
-  // z pass: pair slots per workgroup
-  static constexpr int SL = sizeof(T) == 4 ? 4 : 2;
+  // z pass: pair slots per workgroup (sharing one kernel-table tile); two
+  // measured fastest at 120^3 FP32 against one, four and eight
+  static constexpr int SL = 2;
   // x pencils: TY rows
   static constexpr int TY = (N % 8 == 0) ? 8 : 4;
   static constexpr int NT_X = 256;

@@ -387,3 +387,33 @@ def test_pair_passes_every_schedule(L, n, ecut, n_orb, prec, mode):
     assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(
         res["ex_pairs"])
     s.close()
+
+
+# ------------------------- two-stream batch pipeline = one stream, bitwise
+@pytest.mark.parametrize("prec", [FP32, FP32G, FP64G], ids=["fp32", "fp32g", "fp64g"])
+def test_overlapped_batches_match_one_stream(prec):
+    """An exchange call overlaps consecutive batches on two internal streams
+    (pass C ordered across them by events); with the pass profiler on it runs
+    every launch on the caller's stream.  W and E_x agree bitwise."""
+    say(f"overlap vs one stream prec={prec}")
+    L, n, ecut, n_orb = 12.0, 48, 20.0, 26
+    miller = synth.miller_sphere(L, ecut)
+    coeffs = synth.gaussian_orbitals(miller, L, n_orb, 13, synth.rng_for(79))
+    s = CellSession(dict(L=L, n=n, miller=miller), n_orb, prec)
+    lace.lace_set_tuning(s.plan, 0, 8, 2)     # many small batches
+    s.set_orbitals(coeffs)
+    s.apply_exchange(2e-3)
+    torch.cuda.synchronize()
+    w_ov, e_ov = s.w.clone(), s.e_x.clone()
+    lace.lace_profile_enable(s.plan, True)
+    s.apply_exchange(2e-3)
+    torch.cuda.synchronize()
+    prof = lace.lace_profile_read(s.plan)
+    lace.lace_profile_enable(s.plan, False)
+    assert prof["launches"][0] > 8
+    assert torch.equal(w_ov, s.w) and torch.equal(e_ov, s.e_x)
+    # and a second overlapped call reproduces the first
+    s.apply_exchange(2e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(w_ov, s.w) and torch.equal(e_ov, s.e_x)
+    s.close()
