@@ -417,3 +417,62 @@ def test_overlapped_batches_match_one_stream(prec):
     torch.cuda.synchronize()
     assert torch.equal(w_ov, s.w) and torch.equal(e_ov, s.e_x)
     s.close()
+
+
+# --------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("prec", [FP64, FP64G], ids=["fp64", "fp64g"])
+@pytest.mark.parametrize("n_orb", [1, 2, 3])
+def test_few_orbitals(c0, prec, n_orb):
+    """One, two and three orbitals: a lone diagonal pair, a packed slot with
+    a single pair left over."""
+    inp, _ = c0
+    coeffs = synth.gaussian_orbitals(inp["miller"], inp["L"], n_orb,
+                                     max(1, n_orb - 1), synth.rng_for(60, n_orb))
+    res = O.run_path(coeffs, inp["miller"], inp["L"], inp["n"])
+    s = CellSession(inp, n_orb, prec)
+    s.set_orbitals(coeffs)
+    s.apply_exchange(0.0)
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    assert s.n_kept == n_orb * (n_orb + 1) // 2
+    assert s.info() == 0
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= 1e-11
+    assert rel(s.xi.cpu().numpy(), res["xi"]) <= 1e-10
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= 1e-12 * abs(res["ex_pairs"])
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP32G], ids=["fp32", "fp32g"])
+def test_threshold_keeping_only_diagonal_pairs(localized, prec):
+    """S_ii = 1 and every S_ij < 1 off the diagonal: a threshold just below 1
+    keeps exactly the diagonal pairs."""
+    inp = localized
+    nb = inp["coeffs"].shape[0]
+    s_thr = 0.999
+    assert (inp["S"][~np.eye(nb, dtype=bool)] < s_thr).all()
+    res = O.run_path(inp["coeffs"], inp["miller"], inp["L"], inp["n"],
+                     pairs=[(i, i) for i in range(nb)])
+    s = CellSession(dict(L=inp["L"], n=inp["n"], miller=inp["miller"]), nb, prec)
+    s.set_orbitals(inp["coeffs"])
+    s.apply_exchange(s_thr)
+    torch.cuda.synchronize()
+    assert s.n_kept == nb
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= TOL[prec]["w"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= TOL[prec]["ex"] * abs(
+        res["ex_pairs"])
+    s.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, FP32G], ids=["fp32", "fp32g"])
+def test_empty_pair_list(c0, prec):
+    """An explicit empty pair list runs no pair: W = 0 and E_x = 0."""
+    inp, _ = c0
+    s = CellSession(inp, 8, prec)
+    s.set_orbitals(inp["coeffs"])
+    s.w.fill_(1.0)
+    s.e_x.fill_(1.0)
+    s.apply_exchange(0.0, pairs=np.zeros((0, 2), np.int32))
+    torch.cuda.synchronize()
+    assert s.n_kept == 0
+    assert float(s.w.abs().max()) == 0.0 and s.e_x.item() == 0.0
+    s.close()
