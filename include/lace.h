@@ -86,6 +86,14 @@ typedef struct {
   int64_t n_pw;          /* number of plane waves, >= 1 */
   const int32_t* miller; /* host, n_pw x 3 int32 (m_x, m_y, m_z) per plane
                             wave; every |m_d| < n / 2 and no duplicates */
+  double omega;          /* 0: the Coulomb interaction of Eq. (2), truncated
+                            at rc.  > 0: its short-range part
+                            erfc(omega r) / r, the screened exchange of the
+                            HSE functionals named in Sec. 3 (definition of
+                            Heyd, Scuseria and Ernzerhof, J. Chem. Phys. 118,
+                            8207 (2003)): v(G) = 4 pi (1 - exp(-|G|^2 /
+                            (4 omega^2))) / |G|^2, v(0) = pi / omega^2, no
+                            truncation (rc unused).  < 0 is EINVAL. */
 } lace_cell_desc;
 
 typedef struct lace_plan lace_plan; /* opaque */

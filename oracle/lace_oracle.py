@@ -96,13 +96,18 @@ def orbitals_on_grid(coeffs: np.ndarray, miller: np.ndarray, L: float,
     return out
 
 
-def coulomb_kernel(L: float, n: int, rc: float | None = None) -> np.ndarray:
+def coulomb_kernel(L: float, n: int, rc: float | None = None,
+                   omega: float = 0.0) -> np.ndarray:
     """v(G) on every frequency of the n^3 grid, indexed [z, y, x].
 
     Fourier transform of the Coulomb interaction e^2 / |r - r'| of Eq. (2)
     cut off at |r - r'| = R_c (default L / 2):
     v(G) = 8 pi sin^2(|G| R_c / 2) / |G|^2 (the same as
     4 pi (1 - cos |G| R_c) / |G|^2 without cancellation), v(0) = 2 pi R_c^2.
+    With omega > 0, the short-range part erfc(omega r) / r of the screened
+    hybrids (HSE, named in Sec. 3; Heyd, Scuseria and Ernzerhof's
+    definition), summed over all periodic images:
+    v(G) = 4 pi (1 - exp(-|G|^2 / (4 omega^2))) / |G|^2, v(0) = pi / omega^2.
     """
     rc = L / 2.0 if rc is None else float(rc)
     f = np.fft.fftfreq(n, d=1.0 / n)          # signed integer frequencies
@@ -111,6 +116,11 @@ def coulomb_kernel(L: float, n: int, rc: float | None = None) -> np.ndarray:
     gg = np.sqrt(gx * gx + gy * gy + gz * gz)
     v = np.empty_like(gg)
     nz = gg > 0
+    if omega > 0.0:
+        g2 = gg[nz] ** 2
+        v[nz] = -4.0 * np.pi * np.expm1(-g2 / (4.0 * omega * omega)) / g2
+        v[~nz] = np.pi / (omega * omega)
+        return v
     v[nz] = 8.0 * np.pi * np.sin(0.5 * gg[nz] * rc) ** 2 / gg[nz] ** 2
     v[~nz] = 2.0 * np.pi * rc * rc
     return v
@@ -288,12 +298,12 @@ def apply_ace(xi: np.ndarray, x: np.ndarray) -> np.ndarray:
 
 
 def run_path(coeffs, miller, L, n, s_thr=0.0, rc=None, sym="avg",
-             pairs=None, want_grid=False):
+             pairs=None, want_grid=False, omega=0.0):
     """The whole path on one cell: grid orbitals, screening, exchange,
     What, M, E_x (both routes), Cholesky, xi.  ``pairs`` overrides the
     screening decision when given."""
     psi = orbitals_on_grid(coeffs, miller, L, n)
-    v = coulomb_kernel(L, n, rc)
+    v = coulomb_kernel(L, n, rc, omega)
     s = overlap_of_moduli(psi, L)
     if pairs is None:
         pairs = kept_pairs(s, s_thr)

@@ -539,7 +539,8 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
   // validate everything before touching the device
   for (int ci = 0; ci < n_cells; ++ci) {
     const lace_cell_desc& d = cells[ci];
-    if (!(d.L > 0.0) || d.n_pw < 1 || !d.miller || !std::isfinite(d.L))
+    if (!(d.L > 0.0) || d.n_pw < 1 || !d.miller || !std::isfinite(d.L) ||
+        !(d.omega >= 0.0) || !std::isfinite(d.omega))
       return LACE_EINVAL;
     if (!grid_supported(d.n)) return LACE_EUNSUPPORTED;
     const int n = d.n;
@@ -603,7 +604,10 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
         negidx[m] = at_grid[x + (int64_t)n * (y + (int64_t)n * z)];
       }
     }
-    // kernel table v(G)/N_g: 8 pi sin^2(|G| rc / 2) / |G|^2, v(0) = 2 pi rc^2
+    // kernel table v(G)/N_g: truncated Coulomb 8 pi sin^2(|G| rc / 2) / |G|^2,
+    // v(0) = 2 pi rc^2; or, for omega > 0, the short-range erfc(omega r) / r:
+    // -4 pi expm1(-|G|^2 / (4 omega^2)) / |G|^2, v(0) = pi / omega^2
+    const double om = d.omega;
     std::vector<double> v(ng);
     const double g1 = 2.0 * M_PI / d.L;
     for (int z = 0; z < n; ++z)
@@ -613,7 +617,10 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
                        gz = g1 * signed_freq(z, n);
           const double gg2 = gx * gx + gy * gy + gz * gz;
           double val;
-          if (gg2 == 0.0) {
+          if (om > 0.0) {
+            val = gg2 == 0.0 ? M_PI / (om * om)
+                             : -4.0 * M_PI * std::expm1(-gg2 / (4.0 * om * om)) / gg2;
+          } else if (gg2 == 0.0) {
             val = 2.0 * M_PI * rc * rc;
           } else {
             const double s = std::sin(0.5 * std::sqrt(gg2) * rc);

@@ -60,7 +60,8 @@ class LaceError(RuntimeError):
 class CellDesc(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double), ("n", ctypes.c_int32),
                 ("rc", ctypes.c_double), ("n_pw", ctypes.c_int64),
-                ("miller", ctypes.POINTER(ctypes.c_int32))]
+                ("miller", ctypes.POINTER(ctypes.c_int32)),
+                ("omega", ctypes.c_double)]
 
 
 class LaceJob(ctypes.Structure):
@@ -189,7 +190,8 @@ class Plan:
 
 def lace_plan_create(cells, precision=LACE_FP64) -> Plan:
     """``cells``: list of dicts with L, n, miller (n_pw x 3 int array) and
-    optional rc."""
+    optional rc (Coulomb truncation) or omega (> 0: the short-range
+    erfc(omega r) / r interaction)."""
     lib = load()
     keep = []
     arr = (CellDesc * len(cells))()
@@ -199,6 +201,7 @@ def lace_plan_create(cells, precision=LACE_FP64) -> Plan:
         arr[k].L = float(c["L"])
         arr[k].n = int(c["n"])
         arr[k].rc = float(c.get("rc", 0.0) or 0.0)
+        arr[k].omega = float(c.get("omega", 0.0) or 0.0)
         arr[k].n_pw = int(m.shape[0])
         arr[k].miller = m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     h = ctypes.c_void_p()

@@ -476,3 +476,35 @@ def test_empty_pair_list(c0, prec):
     assert s.n_kept == 0
     assert float(s.w.abs().max()) == 0.0 and s.e_x.item() == 0.0
     s.close()
+
+
+# ---------------------------------------- screened (HSE-type) interaction
+@pytest.mark.parametrize("prec", [FP64, FP32, FP64G, FP32G],
+                         ids=["fp64", "fp32", "fp64g", "fp32g"])
+def test_screened_interaction(localized, prec):
+    """omega > 0 in the cell: the short-range erfc(omega r) / r kernel
+    (HSE's omega = 0.106 bohr^-1), screened pairs, whole ACE build."""
+    inp = localized
+    omega, s_thr = 0.106, 2e-3
+    tol = TOL[prec]
+    res = O.run_path(inp["coeffs"], inp["miller"], inp["L"], inp["n"],
+                     s_thr=s_thr, omega=omega)
+    cell = dict(L=inp["L"], n=inp["n"], miller=inp["miller"], omega=omega)
+    nb = inp["coeffs"].shape[0]
+    s = CellSession(cell, nb, prec)
+    s.set_orbitals(inp["coeffs"])
+    s.apply_exchange(s_thr, pairs=np.array(res["pairs"]))
+    s.build_ace("avg")
+    torch.cuda.synchronize()
+    assert s.info() == 0
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+    assert rel(s.xi.cpu().numpy(), res["xi"]) <= tol["xi"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(res["ex_pairs"])
+    s.close()
+
+
+def test_negative_omega_rejected(localized):
+    cell = dict(L=localized["L"], n=localized["n"], miller=localized["miller"],
+                omega=-1.0)
+    with pytest.raises(lace.LaceError):
+        lace.lace_plan_create([cell], FP32)

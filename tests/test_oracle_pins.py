@@ -455,8 +455,8 @@ def test_planted_bare_kernel_breaks_gaussian_pin(monkeypatch):
     import oracle.lace_oracle as mod
     real = mod.coulomb_kernel
 
-    def bare(L, n, rc=None):
-        v = real(L, n, rc)
+    def bare(L, n, rc=None, omega=0.0):
+        v = real(L, n, rc, omega)
         f = np.fft.fftfreq(n, d=1.0 / n) * 2 * np.pi / L
         gz, gy, gx = np.meshgrid(f, f, f, indexing="ij")
         g2 = gx ** 2 + gy ** 2 + gz ** 2
@@ -685,3 +685,25 @@ def test_scdm_localizes_mixed_localized_orbitals(localized):
     assert np.abs(np.conj(phi) @ phi.T - np.eye(16)).max() <= 1e-13
     proj = np.conj(coeffs) @ phi.T
     assert np.abs(proj.T @ coeffs - phi).max() <= 1e-12
+
+
+# ------------------------------- screened (HSE-type) kernel, closed form
+def test_screened_gaussian_self_exchange_closed_form():
+    """The short-range interaction erfc(omega r) / r: for one normalized
+    Gaussian orbital the self-energy of its density (width tau) is the bare
+    1 / (tau sqrt(pi)) minus the long-range part, the potential at its
+    centre of a Gaussian charge of variance 2 tau^2 + 1 / (2 omega^2)
+    (erf(omega r) / r is the potential of a Gaussian charge of variance
+    1 / (2 omega^2)).  Periodic images are below 1e-40 at omega = 0.5."""
+    L, n, ecut, sigma, omega = 20.0, 64, 40.0, 1.0, 0.5
+    miller = synth.miller_sphere(L, ecut)
+    c = gaussian_coeffs(miller, L, np.array([7.3, 9.1, 11.7]), sigma)[None]
+    res = O.run_path(c, miller, L, n, omega=omega)
+    tau = sigma / np.sqrt(2)
+    self_sr = 1.0 / (tau * np.sqrt(np.pi)) - np.sqrt(2.0 / np.pi) / np.sqrt(
+        2 * tau * tau + 1.0 / (2 * omega * omega))
+    assert res["ex_trace"] == pytest.approx(-0.5 * self_sr, rel=1e-10)
+    assert res["ex_pairs"] == pytest.approx(-0.5 * self_sr, rel=1e-10)
+    # screening only removes interaction: weaker than the bare kernel
+    bare = O.run_path(c, miller, L, n, rc=L / 2)
+    assert abs(res["ex_trace"]) < abs(bare["ex_trace"])
