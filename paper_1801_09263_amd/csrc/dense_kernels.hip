@@ -356,56 +356,152 @@ hipError_t launch_neg_sym(const void* M, int n, int mode, void* A,
 // Right-looking Cholesky A = L L^H in one workgroup (n <= a few thousand).
 // A is row-major complex128, overwritten by L (strict upper zeroed).
 // ------------------------------------------------------------------
-constexpr int CH_NT = 1024;
-__global__ __launch_bounds__(CH_NT) void k_cholesky(double2* A, int n,
-                                                    int32_t* info) {
+// Blocked right-looking Cholesky, panels of CB columns: factor the diagonal
+// block in LDS (one workgroup), solve the panel below it (one thread per
+// row), subtract the panel's outer product from the trailing matrix (an
+// MFMA GEMM into tmp, then a lower-triangle update).  The first failing
+// pivot is kept in info; later blocks see it and do nothing.
+constexpr int CB = 64;
+
+__global__ __launch_bounds__(256) void k_chol_diag(double2* A, int n, int k0,
+                                                   int kb, int32_t* info) {
+  __shared__ double2 a[CB][CB + 1];
   __shared__ int fail;
-  __shared__ double lkk;
   const int tid = threadIdx.x;
-  if (tid == 0) fail = 0;
+  for (int e = tid; e < kb * kb; e += 256) {
+    const int i = e / kb, j = e % kb;
+    a[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
+  }
+  if (tid == 0) fail = (*info != 0) ? -1 : 0;
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
+  if (fail) return;
+  for (int k = 0; k < kb; ++k) {
     if (tid == 0) {
-      const double d = A[(int64_t)k * n + k].x;
-      if (!(d > 0.0)) {
-        fail = k + 1;
-      } else {
-        lkk = sqrt(d);
-        A[(int64_t)k * n + k] = make_double2(lkk, 0.0);
-      }
+      const double d = a[k][k].x;
+      if (!(d > 0.0)) fail = k0 + k + 1;
+      else a[k][k] = make_double2(sqrt(d), 0.0);
     }
     __syncthreads();
     if (fail) break;
-    const double inv = 1.0 / lkk;
-    for (int i = k + 1 + tid; i < n; i += CH_NT) {
-      double2 v = A[(int64_t)i * n + k];
-      A[(int64_t)i * n + k] = make_double2(v.x * inv, v.y * inv);
-    }
+    const double inv = 1.0 / a[k][k].x;
+    for (int i = k + 1 + tid; i < kb; i += 256)
+      a[i][k] = make_double2(a[i][k].x * inv, a[i][k].y * inv);
     __syncthreads();
-    const int m = n - k - 1;
-    for (int64_t idx = tid; idx < (int64_t)m * m; idx += CH_NT) {
-      const int i = k + 1 + (int)(idx / m), j = k + 1 + (int)(idx % m);
+    const int m = kb - k - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
       if (j > i) continue;
-      const double2 li = A[(int64_t)i * n + k], lj = A[(int64_t)j * n + k];
-      double2 a = A[(int64_t)i * n + j];
-      // a -= li * conj(lj)
-      a.x -= li.x * lj.x + li.y * lj.y;
-      a.y -= li.y * lj.x - li.x * lj.y;
-      A[(int64_t)i * n + j] = a;
+      const double2 li = a[i][k], lj = a[j][k];
+      a[i][j].x -= li.x * lj.x + li.y * lj.y;
+      a[i][j].y -= li.y * lj.x - li.x * lj.y;
     }
     __syncthreads();
   }
-  for (int64_t e = tid; e < (int64_t)n * n; e += CH_NT) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (j > i) A[e] = make_double2(0.0, 0.0);
+  if (fail) {
+    if (tid == 0) *info = fail;
+    return;
   }
-  if (tid == 0) *info = fail;
+  for (int e = tid; e < kb * kb; e += 256) {
+    const int i = e / kb, j = e % kb;
+    if (j <= i) A[(int64_t)(k0 + i) * n + k0 + j] = a[i][j];
+  }
 }
 
-hipError_t launch_cholesky(void* A, int n, int32_t* info, hipStream_t st) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(CH_NT), 0, st,
-                     static_cast<double2*>(A), n, info);
-  return hipGetLastError();
+// Rows i >= k0 + kb of the panel: x L_kk^H = a, i.e. forward substitution
+// x_j = (a_j - sum_{m<j} x_m conj(L_jm)) / L_jj; one thread per row, 64 rows
+// per workgroup, the rows' solutions in LDS.
+constexpr int CP_ROWS = 64;
+__global__ __launch_bounds__(CP_ROWS) void k_chol_panel(double2* A, int n, int k0,
+                                                        int kb, const int32_t* info) {
+  __shared__ double2 l[CB][CB + 1];
+  __shared__ double2 xs[CP_ROWS][CB + 1];
+  for (int e = threadIdx.x; e < kb * kb; e += CP_ROWS) {
+    const int i = e / kb, j = e % kb;
+    l[i][j] = A[(int64_t)(k0 + i) * n + k0 + j];
+  }
+  __syncthreads();
+  if (*info != 0) return;
+  const int t = threadIdx.x;
+  const int i = k0 + kb + blockIdx.x * CP_ROWS + t;
+  if (i >= n) return;
+  double2* row = A + (int64_t)i * n + k0;
+  for (int j = 0; j < kb; ++j) {
+    double2 s = row[j];
+    for (int m = 0; m < j; ++m) {
+      const double2 L = l[j][m], x = xs[t][m];   // s -= x_m conj(L_jm)
+      s.x -= x.x * L.x + x.y * L.y;
+      s.y -= x.y * L.x - x.x * L.y;
+    }
+    const double inv = 1.0 / l[j][j].x;
+    xs[t][j] = make_double2(s.x * inv, s.y * inv);
+  }
+  for (int j = 0; j < kb; ++j) row[j] = xs[t][j];
+}
+
+__global__ void k_set_zero(int32_t* v) { *v = 0; }
+
+// A[i][j] -= T[j - off][i - off] for off <= j <= i < n (T = the GEMM output,
+// m x m with m = n - off).
+__global__ void k_chol_update(double2* A, int n, int off, const double2* T,
+                              const int32_t* info) {
+  if (*info != 0) return;
+  const int m = n - off;
+  const int64_t total = (int64_t)m * m;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += stride) {
+    const int i = (int)(e / m), j = (int)(e % m);
+    if (j > i) continue;
+    const double2 t = T[(int64_t)j * m + i];
+    double2& a = A[(int64_t)(off + i) * n + off + j];
+    a.x -= t.x;
+    a.y -= t.y;
+  }
+}
+
+__global__ void k_zero_upper(double2* A, int n) {
+  const int64_t total = (int64_t)n * n;
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += stride)
+    if ((int)(e % n) > (int)(e / n)) A[e] = make_double2(0.0, 0.0);
+}
+
+hipError_t launch_cholesky(void* Av, int n, int32_t* info, void* tmp,
+                           void* part, int64_t part_bytes, hipStream_t st) {
+  double2* A = static_cast<double2*>(Av);
+  hipLaunchKernelGGL(k_set_zero, dim3(1), dim3(1), 0, st, info);
+  hipError_t e = hipGetLastError();
+  for (int k0 = 0; k0 < n && e == hipSuccess; k0 += CB) {
+    const int kb = n - k0 < CB ? n - k0 : CB;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, n, k0, kb, info);
+    e = hipGetLastError();
+    const int off = k0 + kb, m = n - off;
+    if (e != hipSuccess || m <= 0) continue;
+    hipLaunchKernelGGL(k_chol_panel, dim3((m + CP_ROWS - 1) / CP_ROWS),
+                       dim3(CP_ROWS), 0, st, A, n, k0, kb, info);
+    e = hipGetLastError();
+    // T[a][b] = sum_t conj(L[off + a][k0 + t]) L[off + b][k0 + t]
+    if (e == hipSuccess)
+      e = launch_gemm_ip_c128(A + (int64_t)off * n + k0, n, m,
+                              A + (int64_t)off * n + k0, n, m, kb, 1.0, tmp,
+                              part, part_bytes, st);
+    if (e == hipSuccess) {
+      int64_t blocks = ((int64_t)m * m + 255) / 256;
+      if (blocks > 2048) blocks = 2048;
+      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)blocks), dim3(256), 0,
+                         st, A, n, off, static_cast<const double2*>(tmp), info);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) {
+    int64_t blocks = ((int64_t)n * n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)blocks), dim3(256), 0, st,
+                       A, n);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 // ------------------------------------------------------------------

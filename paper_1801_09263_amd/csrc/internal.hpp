@@ -134,8 +134,11 @@ hipError_t launch_gemm_tall(const void* X, int64_t ldx, int64_t M, int nk,
 // A <- -sym(M) (mode 0 avg, 1 upper, 2 lower), n x n complex128 row-major.
 hipError_t launch_neg_sym(const void* M, int n, int mode, void* A,
                           hipStream_t st);
-// In-place Cholesky A = L L^H (lower), info <- 0 or failing pivot + 1.
-hipError_t launch_cholesky(void* A, int n, int32_t* info, hipStream_t st);
+// In-place Cholesky A = L L^H (lower), info <- 0 or the first failing
+// pivot + 1.  tmp: (n - 64)^2 complex128 scratch; part: split-K
+// scratch of the trailing-update GEMMs.
+hipError_t launch_cholesky(void* A, int n, int32_t* info, void* tmp,
+                           void* part, int64_t part_bytes, hipStream_t st);
 // Z <- (L^{-1})^H, upper triangular, n x n row-major.
 hipError_t launch_trinv_adj(const void* L, int n, void* Z, hipStream_t st);
 // out <- factor * Re tr(M)

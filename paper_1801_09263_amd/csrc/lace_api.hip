@@ -937,7 +937,9 @@ static hipError_t enqueue_build_ace(const CellPlan& cp, int n_orb, int sym,
                                      (int64_t)(L.mw - L.part), st);
   if (e == hipSuccess && ex_tr) e = launch_trace_re(m, n_orb, 0.5, ex_tr, st);
   if (e == hipSuccess) e = launch_neg_sym(m, n_orb, sym, at(ws, L.a), st);
-  if (e == hipSuccess) e = launch_cholesky(at(ws, L.a), n_orb, cp.d_info, st);
+  if (e == hipSuccess)
+    e = launch_cholesky(at(ws, L.a), n_orb, cp.d_info, at(ws, L.u),
+                        at(ws, L.part), (int64_t)(L.mw - L.part), st);
   if (e == hipSuccess) e = launch_trinv_adj(at(ws, L.a), n_orb, at(ws, L.z), st);
   if (e == hipSuccess)
     e = launch_gemm_tall(w_g, c.n_pw, c.n_pw, n_orb, at(ws, L.z), n_orb, xi_g,
