@@ -1,10 +1,12 @@
 """Continuous-batching request loop for exchange jobs.
 
 A job is one set of orbitals on one cell size class that runs several outer
-iterations of the hybrid SCF loop: at each iteration the exchange is applied
-to the current orbitals, the ACE projector is rebuilt, and ACE is applied to
-the orbitals (the double loop of Sec. 2 of the paper, with the inner KS
-solve replaced by a precomputed orbital update).
+iterations of the hybrid SCF loop (the double loop of Sec. 2 of the paper,
+with the inner KS solve replaced by a precomputed orbital update): at each
+iteration the new orbitals are aligned to the previous iteration's (the
+convergence aid at the end of Sec. 2), the exchange is applied to them, the
+ACE projector is rebuilt, and ACE is applied `inner` times to the orbitals,
+as the inner solver would between two exchange builds.
 
 Requests arrive over time.  The admission controller admits them in arrival
 order while a worker slot is free and the sum of the admitted jobs' device
@@ -59,9 +61,12 @@ def job_footprint(plan, cell_index, n_orb, n_pw) -> int:
 
 class Server:
     def __init__(self, classes, precision=lace.LACE_FP32, n_slots=4,
-                 hbm_budget=None, keep_xi=False, device="cuda"):
+                 hbm_budget=None, keep_xi=False, device="cuda", inner=1,
+                 align=False):
         self.classes = classes
         self.precision = precision
+        self.inner = int(inner)
+        self.align = bool(align)
         self.n_slots = int(n_slots)
         self.keep_xi = keep_xi
         self.device = device
@@ -72,6 +77,8 @@ class Server:
         for k, c in enumerate(classes):
             n_pw = int(np.asarray(c.cell["miller"]).shape[0])
             c.footprint = job_footprint(self.plans[0], k, c.n_orb, n_pw)
+            if self.align:   # two more orbital sets: aligned, ping-pong
+                c.footprint += 2 * c.n_orb * n_pw * 16
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget = int(0.8 * free)
@@ -98,15 +105,25 @@ class Server:
             ex_tr = torch.empty(1, dtype=torch.float64, device=self.device)
             ws = torch.empty(lace.lace_workspace_size(plan, cell, n, n),
                              dtype=torch.uint8, device=self.device)
+            prev = None
+            if self.align and len(job.variants) > 1:
+                cur = torch.empty((n, n_pw), **z)
+                nxt = torch.empty((n, n_pw), **z)
             for step, v in enumerate(job.variants):
                 psi = c.pool[v]
+                if self.align and prev is not None:
+                    lace.lace_align(plan, cell, psi, prev, n, nxt, None, ws, st)
+                    psi = nxt
+                    cur, nxt = nxt, cur
                 kept = lace.lace_apply_exchange(
                     plan, cell, psi, n, c.cell.get("s_thr", 0.0), None, w,
                     ex[step:step + 1], ws, st)
                 lace.lace_build_ace(plan, cell, psi, w, n, "avg", xi, m,
                                     ex_tr, ws, st)
-                lace.lace_apply_ace(plan, cell, xi, n, psi, n, y, ws, st)
+                for _ in range(self.inner):
+                    lace.lace_apply_ace(plan, cell, xi, n, psi, n, y, ws, st)
                 job.kept.append(kept)
+                prev = psi
             st.synchronize()
         job.done = time.perf_counter() - t0
         job.e_x = ex.cpu().tolist()

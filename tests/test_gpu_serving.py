@@ -34,9 +34,13 @@ def make_jobs(n_jobs, rate, seed=5):
     return [Job(jid, t, cls, var) for jid, t, cls, var in spec]
 
 
-def test_results_same_alone_and_in_the_mix(classes):
-    say("serving: mix of 8 jobs on 3 slots vs each alone")
-    mix = Server(classes, lace.LACE_FP32, n_slots=3, keep_xi=True)
+@pytest.mark.parametrize("inner,align", [(1, False), (3, True)],
+                         ids=["plain", "aligned"])
+def test_results_same_alone_and_in_the_mix(classes, inner, align):
+    say(f"serving: mix of 8 jobs on 3 slots vs each alone (inner {inner}, "
+        f"align {align})")
+    mix = Server(classes, lace.LACE_FP32, n_slots=3, keep_xi=True,
+                 inner=inner, align=align)
     jobs = mix.run(make_jobs(8, rate=400.0))
     mix.close()
     assert all(j.done > j.admit >= j.arrival for j in jobs)
@@ -45,7 +49,8 @@ def test_results_same_alone_and_in_the_mix(classes):
                 if a.jid < b.jid and a.admit < b.done and b.admit < a.done)
     say(f"  overlapping job pairs: {overl}")
     assert overl > 0
-    alone = Server(classes, lace.LACE_FP32, n_slots=1, keep_xi=True)
+    alone = Server(classes, lace.LACE_FP32, n_slots=1, keep_xi=True,
+                   inner=inner, align=align)
     for j in jobs:
         solo = Job(j.jid, 0.0, j.cls, j.variants)
         alone.run([solo])
