@@ -719,7 +719,6 @@ int lace_screen(lace_plan* p, int cell, const void* psi_g, int n_orb,
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
   const CellDev& c = p->cells[cell].dev;
-  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e == hipSuccess) e = enqueue_screen(p, c, n_orb, L, ws, s_out, st);
@@ -964,7 +963,6 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   if (pair_i && !copy_pairs(pair_i, pair_j, n_pairs, n_orb, pairs))
     return LACE_EINVAL;
   const CellDev& c = p->cells[cell].dev;
-  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e != hipSuccess) return LACE_EHIP;
@@ -1365,7 +1363,6 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     for (int q = 0; q < k; ++q)
       if (jobs[q].ws == j.ws || jobs[q].w_g == j.w_g) return LACE_EINVAL;
   }
-  const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int ns = n_jobs < 8 ? n_jobs : 8;
   hipError_t e = ensure_streams(p, ns);
