@@ -568,25 +568,6 @@ hipError_t launch_trace_re(const void* M, int n, double factor, double* out,
   return hipGetLastError();
 }
 
-__global__ void k_scale_c128(const double2* x, int64_t n, double s,
-                             double2* y) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n;
-       e += stride)
-    y[e] = make_double2(s * x[e].x, s * x[e].y);
-}
-
-hipError_t launch_scale_c128(const void* x, int64_t n, double s, void* y,
-                             hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_scale_c128, dim3((unsigned)blocks), dim3(256), 0, st,
-                     static_cast<const double2*>(x), n, s,
-                     static_cast<double2*>(y));
-  return hipGetLastError();
-}
-
 // Element-wise steps of the polar (Procrustes) iteration on n x n
 // complex128 row-major matrices: 0 out = conj(in); 1 out = *s * in;
 // 2 out = (3 I - in) / 2; 3 out = in^T.

@@ -144,9 +144,6 @@ hipError_t launch_trinv_adj(const void* L, int n, void* Z, hipStream_t st);
 // out <- factor * Re tr(M)
 hipError_t launch_trace_re(const void* M, int n, double factor, double* out,
                            hipStream_t st);
-// y <- -x elementwise on n complex128 (scale copy)
-hipError_t launch_scale_c128(const void* x, int64_t n, double s, void* y,
-                             hipStream_t st);
 
 // Polar-iteration helpers, n x n complex128 row-major.  elem: 0 conj,
 // 1 scale by *s, 2 (3 I - in) / 2, 3 transpose (out distinct from in).
