@@ -137,24 +137,34 @@ template <typename T> struct EpiAcc {
   }
 };
 
-// Real orbitals, packed slot: value rho_ij + i rho_kl.
-template <typename T> struct ProQuad {
+// Real orbitals, packed slot: value rho_ij + i rho_kl.  STAR: every slot
+// of the launch is a star slot (k = i), whose three orbitals are read once.
+template <typename T, bool STAR = false> struct ProQuad {
   static constexpr int V = 16 / sizeof(T);
   const T* __restrict__ psi;
   int64_t gs;
   QuadArgs qa;
   __device__ void getv(int g, int slot, C<T>* out) const {
-    // a slot without a second pair reads orbital i twice and discards it
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
-    const bool two = k >= 0;
-    const int kk = two ? k : i, ll = two ? l : i;
-    const Vec<T, V> a = ldv<T, V>(psi + i * gs + g);
-    const Vec<T, V> b = ldv<T, V>(psi + j * gs + g);
-    const Vec<T, V> c = ldv<T, V>(psi + kk * gs + g);
-    const Vec<T, V> d = ldv<T, V>(psi + ll * gs + g);
+    if constexpr (STAR) {
+      const Vec<T, V> a = ldv<T, V>(psi + i * gs + g);
+      const Vec<T, V> b = ldv<T, V>(psi + j * gs + g);
+      const Vec<T, V> d = ldv<T, V>(psi + l * gs + g);
 #pragma unroll
-    for (int v = 0; v < V; ++v)
-      out[v] = mk<T>(a.e[v] * b.e[v], two ? c.e[v] * d.e[v] : T(0));
+      for (int v = 0; v < V; ++v)
+        out[v] = mk<T>(a.e[v] * b.e[v], a.e[v] * d.e[v]);
+    } else {
+      // a slot without a second pair reads orbital i twice and discards it
+      const bool two = k >= 0;
+      const int kk = two ? k : i, ll = two ? l : i;
+      const Vec<T, V> a = ldv<T, V>(psi + i * gs + g);
+      const Vec<T, V> b = ldv<T, V>(psi + j * gs + g);
+      const Vec<T, V> c = ldv<T, V>(psi + kk * gs + g);
+      const Vec<T, V> d = ldv<T, V>(psi + ll * gs + g);
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        out[v] = mk<T>(a.e[v] * b.e[v], two ? c.e[v] * d.e[v] : T(0));
+    }
   }
 };
 template <typename T> struct QuadPre {
@@ -162,10 +172,12 @@ template <typename T> struct QuadPre {
 };
 // V = V_ij + i V_kl (both real):  W_j -= psi_i V_ij, W_i -= psi_j V_ij,
 // W_l -= psi_k V_kl, W_k -= psi_l V_kl (one update for a diagonal pair).
-// A star slot (k = i) folds both updates of the shared orbital into one.
-// A skipped W is neither updated nor read, nor is the orbital paired with
-// it: those loads repeat the pair's other orbital (served by the cache).
-template <typename T> struct EpiAccQuad {
+// A star slot (k = i) folds both updates of the shared orbital into one;
+// when every slot of the launch is a star (STAR), psi_i and W_i are read
+// once.  A skipped W is neither updated nor read, nor is the orbital paired
+// with it: those loads repeat another orbital of the slot (served by the
+// cache).  The two W of the shared orbital of a star are skipped together.
+template <typename T, bool STAR = false> struct EpiAccQuad {
   static constexpr int V = 16 / sizeof(T);
   static constexpr int CH = 2;
   using Pre = QuadPre<T>;
@@ -181,36 +193,59 @@ template <typename T> struct EpiAccQuad {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
     bool sk[4];
     flags(slot, sk);
-    const int kk = k >= 0 ? k : i, ll = k >= 0 ? l : i;
-    r.pi = ldv<T, V>(psi + (sk[1] ? j : i) * gs + g);
-    r.wj = ldv<T, V>(w + (sk[1] ? i : j) * gs + g);
-    r.pj = ldv<T, V>(psi + (sk[0] ? i : j) * gs + g);
-    r.wi = ldv<T, V>(w + (sk[0] ? j : i) * gs + g);
-    r.pk = ldv<T, V>(psi + (sk[3] ? ll : kk) * gs + g);
-    r.wl = ldv<T, V>(w + (sk[3] ? kk : ll) * gs + g);
-    r.pl = ldv<T, V>(psi + (sk[2] ? kk : ll) * gs + g);
-    r.wk = ldv<T, V>(w + (sk[2] ? ll : kk) * gs + g);
+    if constexpr (STAR) {
+      r.pi = ldv<T, V>(psi + (sk[1] && sk[3] ? j : i) * gs + g);
+      r.wj = ldv<T, V>(w + (sk[1] ? i : j) * gs + g);
+      r.pj = ldv<T, V>(psi + (sk[0] ? i : j) * gs + g);
+      r.wi = ldv<T, V>(w + (sk[0] ? j : i) * gs + g);
+      r.pl = ldv<T, V>(psi + (sk[2] ? i : l) * gs + g);
+      r.wl = ldv<T, V>(w + (sk[3] ? i : l) * gs + g);
+    } else {
+      const int kk = k >= 0 ? k : i, ll = k >= 0 ? l : i;
+      r.pi = ldv<T, V>(psi + (sk[1] ? j : i) * gs + g);
+      r.wj = ldv<T, V>(w + (sk[1] ? i : j) * gs + g);
+      r.pj = ldv<T, V>(psi + (sk[0] ? i : j) * gs + g);
+      r.wi = ldv<T, V>(w + (sk[0] ? j : i) * gs + g);
+      r.pk = ldv<T, V>(psi + (sk[3] ? ll : kk) * gs + g);
+      r.wl = ldv<T, V>(w + (sk[3] ? kk : ll) * gs + g);
+      r.pl = ldv<T, V>(psi + (sk[2] ? kk : ll) * gs + g);
+      r.wk = ldv<T, V>(w + (sk[2] ? ll : kk) * gs + g);
+    }
   }
   __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
     const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
     bool sk[4];
     flags(slot, sk);
-    const bool star = k == i;
-    const bool up_i = !sk[0] || (star && !sk[2]);
-    Vec<T, V> yj, yi, yl, yk;
+    if constexpr (STAR) {
+      Vec<T, V> yj, yi, yl;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      yj.e[v] = r.wj.e[v] - r.pi.e[v] * x[v].x;
-      yi.e[v] = r.wi.e[v] - (sk[0] ? T(0) : r.pj.e[v] * x[v].x);
-      yl.e[v] = r.wl.e[v] - r.pk.e[v] * x[v].y;
-      yk.e[v] = r.wk.e[v] - r.pl.e[v] * x[v].y;
-      if (star && !sk[2]) yi.e[v] -= r.pl.e[v] * x[v].y;
-    }
-    if (!sk[1]) stv<T, V>(w + j * gs + g, yj);
-    if (i != j && up_i) stv<T, V>(w + i * gs + g, yi);
-    if (k >= 0) {
+      for (int v = 0; v < V; ++v) {
+        yj.e[v] = r.wj.e[v] - r.pi.e[v] * x[v].x;
+        yi.e[v] = r.wi.e[v] - (sk[0] ? T(0) : r.pj.e[v] * x[v].x);
+        yl.e[v] = r.wl.e[v] - r.pi.e[v] * x[v].y;
+        if (!sk[2]) yi.e[v] -= r.pl.e[v] * x[v].y;
+      }
+      if (!sk[1]) stv<T, V>(w + j * gs + g, yj);
+      if (!sk[0] || !sk[2]) stv<T, V>(w + i * gs + g, yi);
       if (!sk[3]) stv<T, V>(w + l * gs + g, yl);
-      if (k != l && !star && !sk[2]) stv<T, V>(w + k * gs + g, yk);
+    } else {
+      const bool star = k == i;
+      const bool up_i = !sk[0] || (star && !sk[2]);
+      Vec<T, V> yj, yi, yl, yk;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        yj.e[v] = r.wj.e[v] - r.pi.e[v] * x[v].x;
+        yi.e[v] = r.wi.e[v] - (sk[0] ? T(0) : r.pj.e[v] * x[v].x);
+        yl.e[v] = r.wl.e[v] - r.pk.e[v] * x[v].y;
+        yk.e[v] = r.wk.e[v] - r.pl.e[v] * x[v].y;
+        if (star && !sk[2]) yi.e[v] -= r.pl.e[v] * x[v].y;
+      }
+      if (!sk[1]) stv<T, V>(w + j * gs + g, yj);
+      if (i != j && up_i) stv<T, V>(w + i * gs + g, yi);
+      if (k >= 0) {
+        if (!sk[3]) stv<T, V>(w + l * gs + g, yl);
+        if (k != l && !star && !sk[2]) stv<T, V>(w + k * gs + g, yk);
+      }
     }
   }
 };
@@ -708,12 +743,22 @@ template <typename T, int N> struct Engine {
                                const T* psi, T* w, C<T>* tmp, double* epart,
                                hipStream_t st, hipEvent_t* ev,
                                const BatchSync* sy = nullptr) {
+    bool star = true;
+    for (int q = 0; q < qa.n; ++q) star = star && qa.k[q] == qa.i[q];
+    return star ? quad_run<true>(c, qa, psi, w, tmp, epart, st, ev, sy)
+                : quad_run<false>(c, qa, psi, w, tmp, epart, st, ev, sy);
+  }
+  template <bool STAR>
+  static hipError_t quad_run(const CellDev& c, const QuadArgs& qa,
+                             const T* psi, T* w, C<T>* tmp, double* epart,
+                             hipStream_t st, hipEvent_t* ev,
+                             const BatchSync* sy) {
     const C<T>* tw = static_cast<const C<T>*>(c.tw);
     const int cnt = qa.n;
-    ProQuad<T> pp{psi, NG, qa};
+    ProQuad<T, STAR> pp{psi, NG, qa};
     ProGrid<T> pt{tmp, NG};
     EpiGrid<T> et{tmp, NG, T(1)};
-    EpiAccQuad<T> ea{psi, w, NG, qa};
+    EpiAccQuad<T, STAR> ea{psi, w, NG, qa};
     // energy weights: both pairs of a slot are of the same kind
     PairArgs pw;
     pw.n = cnt;
