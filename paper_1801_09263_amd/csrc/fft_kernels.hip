@@ -482,10 +482,16 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // ---- pass B: z forward, x v(G)/N_g with energy partial, z backward ----
-// Workgroup (tile, group): TX columns of SL consecutive pair slots, one LDS
-// line per column and slot; the kernel-table tile is shared by the SL
-// slots.  Slots past the end of the batch load slot 0 (discarded) and are
-// neither stored nor summed.
+// Workgroup (tile, group): TX z columns of SL consecutive pair slots, one
+// LDS line per column and slot; the kernel-table tile is shared by the SL
+// slots.  A tile is TX consecutive points of the flattened xy plane (x + N
+// y), so that each z row of a tile is one whole 128-byte line even when TX
+// does not divide N.  Slots past the end of the batch load slot 0
+// (discarded) and are neither stored nor summed.
+template <int N, int TX>
+__device__ inline int zcol_index(int tile, int m) {
+  return tile * TX + m % TX + N * N * (m / TX);
+}
 template <typename T, int N, int TX, int SL, int NT>
 __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
                                               int64_t gs,
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
   // element m of the group: slot m / NE1, tile point m % NE1
   auto gidx = [tile, nsl, gs](int m) {
     const int sl = m / NE1;
-    return (sl < nsl ? sl : 0) * (int)gs + col_index<N, 2, TX>(tile, m % NE1);
+    return (sl < nsl ? sl : 0) * (int)gs + zcol_index<N, TX>(tile, m % NE1);
   };
   auto lds = [](int m) {
     const int sl = m / NE1, r = m % NE1;
@@ -524,7 +530,7 @@ __global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
 #pragma unroll
   for (int sl = 0; sl < SL; ++sl) e[sl] = 0.0;
   for (int m = threadIdx.x; m < NE1; m += NT) {
-    const T v = vtab[col_index<N, 2, TX>(tile, m)];
+    const T v = vtab[zcol_index<N, TX>(tile, m)];
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
       const int q = lds(sl * NE1 + m);
@@ -618,6 +624,10 @@ template <typename T, int N> struct Cfg {
   // z pass: pair slots per workgroup (sharing one kernel-table tile); two
   // measured fastest at 120^3 FP32 against one, four and eight
   static constexpr int SL = 2;
+  // z pass tiles: one 128-byte line of the flattened xy plane per z row
+  static constexpr int TXZ0 = 128 / (int)sizeof(C<T>);
+  static constexpr int TXZ = (N * N) % TXZ0 == 0 ? TXZ0 : TX;
+  static constexpr int NT_Z = (sizeof(T) == 4 && TXZ * SL * N >= 2048) ? 512 : 256;
   // x pencils: TY rows
   static constexpr int TY = (N % 8 == 0) ? 8 : 4;
   static constexpr int NT_X = 256;
@@ -714,10 +724,10 @@ template <typename T, int N> struct Engine {
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     // pass B
-    const int ntiles = N * (N / Cf::TX);
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::SL, Cf::NT_COLS>),
+    const int ntiles = (int)tiles();
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
-                       dim3(Cf::NT_COLS), 0, st, tmp, NG,
+                       dim3(Cf::NT_Z), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pa, epart, ntiles, tw);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -777,10 +787,10 @@ template <typename T, int N> struct Engine {
     }
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
-    const int ntiles = N * (N / Cf::TX);
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TX, Cf::SL, Cf::NT_COLS>),
+    const int ntiles = (int)tiles();
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
-                       dim3(Cf::NT_COLS), 0, st, tmp, NG,
+                       dim3(Cf::NT_Z), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pw, epart, ntiles, tw);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -800,7 +810,7 @@ template <typename T, int N> struct Engine {
     return err;
   }
 
-  static int64_t tiles() { return (int64_t)N * (N / Cf::TX); }
+  static int64_t tiles() { return (int64_t)N * N / Cf::TXZ; }
 };
 
 // ------------------------------------------------------ runtime dispatch
