@@ -195,12 +195,41 @@ def ace_rows(torch, lace, sess, inp, seed, n_calls=8):
         scdm_ms=round(t_scdm * 1e3, 2), scdm_resid=resid.item())
 
 
-def cpu_baseline(inp, n_sample_orb=12):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    the exchange among `n_sample_orb` orbitals spread over the cell (their
-    grid orbitals, screening among them, every kept ordered pair)."""
+# (psi, v, pairs) of the CPU sample, inherited by the forked workers
+_ORACLE_SAMPLE = None
+
+
+def _oracle_columns(cols):
+    """One worker's share of the CPU sample: W_j for the columns `cols`,
+    reduced to sum_j Re <psi_j, W_j> so that little crosses the pipe."""
     import numpy as np
     import oracle
+    psi, v, pairs = _ORACLE_SAMPLE
+    w = oracle.apply_exchange_columns(psi, v, pairs, cols)
+    return sum(float(np.vdot(psi[j], w[c]).real) for c, j in enumerate(cols))
+
+
+def host_cores() -> int:
+    """Cores this process may use, at most 16 (one GPU's share of a host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(inp, n_sample_orb=32):
+    """The oracle, as it stands, on a bounded sample of the same workload,
+    on the host's cores: grid orbitals of `n_sample_orb` orbitals spread over
+    the cell and screening among them in this process, then the W columns
+    of the kept pairs dealt to forked worker processes (balanced by their
+    number of ordered Poisson solves).  Must run before the GPU is touched:
+    the workers are forked."""
+    import multiprocessing as mp
+    import numpy as np
+    import oracle
+    global _ORACLE_SAMPLE
+    cores = host_cores()
     idx = np.linspace(0, inp["coeffs"].shape[0] - 1, n_sample_orb).astype(int)
     coeffs = inp["coeffs"][idx]
     t0 = time.perf_counter()
@@ -208,15 +237,31 @@ def cpu_baseline(inp, n_sample_orb=12):
     v = oracle.coulomb_kernel(inp["L"], inp["n"])
     s = oracle.overlap_of_moduli(psi, inp["L"])
     pairs = oracle.kept_pairs(s, inp["s_thr"])
-    oracle.apply_exchange(psi, v, pairs)
+    load = np.zeros(n_sample_orb, dtype=int)
+    for i, j in pairs:
+        load[j] += 1
+        if i != j:
+            load[i] += 1
+    shares = [[] for _ in range(cores)]
+    acc = [0] * cores
+    for j in sorted(range(n_sample_orb), key=lambda c: -load[c]):
+        k = acc.index(min(acc))
+        shares[k].append(j)
+        acc[k] += load[j]
+    shares = [sh for sh in shares if sh]
+    _ORACLE_SAMPLE = (psi, v, pairs)
+    with mp.get_context("fork").Pool(len(shares)) as pool:
+        pool.map(_oracle_columns, shares, chunksize=1)
     dt = time.perf_counter() - t0
-    return dict(value=len(pairs) / dt, unit="pair-FFTs/s", cores=1,
+    _ORACLE_SAMPLE = None
+    return dict(value=len(pairs) / dt, unit="pair-FFTs/s", cores=len(shares),
                 kind="oracle",
                 sample=(f"{n_sample_orb} of the 256 orbitals of the lace-120 "
-                        f"workload: grid orbitals, screening among them and "
-                        f"the {len(pairs)} kept pairs (each as two ordered "
-                        f"Poisson solves), numpy FFT, one thread; "
-                        f"{dt:.1f} s"))
+                        f"workload: grid orbitals and screening in one "
+                        f"process, then the {len(pairs)} kept pairs (each as "
+                        f"two ordered Poisson solves, {int(load.sum())} in "
+                        f"all) dealt by W column to {len(shares)} worker "
+                        f"processes, numpy FFT; {dt:.1f} s wall"))
 
 
 def batched_rows(torch, seed, steps):
@@ -381,9 +426,20 @@ def main():
               "the multi-GPU layout is described, not built", file=sys.stderr)
         sys.exit(2)
 
+    import synth
+
+    inp = cpu = None
+    if not args.pmc_sample:
+        log("generating the localized 120^3 workload")
+        inp = synth.make_config_inputs(2, seed=args.seed)
+        if not args.no_cpu:
+            # before torch and the GPU: the oracle's workers are forked
+            log("CPU oracle sample")
+            cpu = cpu_baseline(inp)
+            log("CPU oracle", cpu)
+
     import torch
 
-    import synth
     from paper_1801_09263_amd import lace
     from paper_1801_09263_amd.session import CellSession
 
@@ -394,8 +450,6 @@ def main():
         pmc_sample(torch, args.seed)
         return
 
-    log("generating the localized 120^3 workload")
-    inp = synth.make_config_inputs(2, seed=args.seed)
     n_orb = inp["coeffs"].shape[0]
     sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA, n_vec=n_orb)
     sess.set_orbitals(inp["coeffs"])
@@ -553,11 +607,6 @@ def main():
                              rate=args.serve_light_rate)
         serving = dict(oversubscribed=serving, sustained=light)
         log("serving at a sustained rate", light)
-
-    cpu = None
-    if not args.no_cpu:
-        log("CPU oracle sample")
-        cpu = cpu_baseline(inp)
 
     out = {
         "metric": "pair-FFTs/s + HBM roofline %, L-ACE vs plain FP64; "
