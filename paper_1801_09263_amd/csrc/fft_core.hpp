@@ -125,6 +125,40 @@ template <int SIGN, typename T> struct Dft<8, SIGN, T> {
   }
 };
 
+// Prime-factor (Good-Thomas) DFT of length R = A B with gcd(A, B) = 1.
+// Input n = (B a + A b) mod R and output k with k = ka (mod A), k = kb
+// (mod B) turn the length-R DFT into B-point DFTs over b followed by A-point
+// DFTs over a, with no twiddle factors between them.
+constexpr int inv_mod(int x, int m) {
+  for (int y = 1; y < m; ++y)
+    if ((x * y) % m == 1) return y;
+  return 1;
+}
+template <int A, int B, int SIGN, typename T> struct Pfa {
+  static constexpr int R = A * B;
+  static constexpr int EA = B * inv_mod(B % A, A);  // 1 mod A, 0 mod B
+  static constexpr int EB = A * inv_mod(A % B, B);  // 0 mod A, 1 mod B
+  __device__ static inline void run(C<T>* v) {
+    C<T> u[A][B];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) u[a][b] = v[(B * a + A * b) % R];
+      Dft<B, SIGN, T>::run(u[a]);
+    }
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) {
+      C<T> col[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) col[a] = u[a][kb];
+      Dft<A, SIGN, T>::run(col);
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) v[(EA * ka + EB * kb) % R] = col[ka];
+    }
+  }
+};
+template <int SIGN, typename T> struct Dft<15, SIGN, T> : Pfa<3, 5, SIGN, T> {};
+
 // ---------------------------------------------------------------------------
 // Radix plans for the supported lengths (product of the listed radices).
 // ---------------------------------------------------------------------------
@@ -143,11 +177,11 @@ LACE_PLAN(24, 2, 8, 3)
 LACE_PLAN(32, 2, 8, 4)
 LACE_PLAN(40, 2, 8, 5)
 LACE_PLAN(48, 3, 4, 4, 3)
-LACE_PLAN(60, 3, 4, 5, 3)
+LACE_PLAN(60, 2, 4, 15)
 LACE_PLAN(64, 2, 8, 8)
 LACE_PLAN(80, 3, 4, 4, 5)
 LACE_PLAN(96, 3, 8, 4, 3)
-LACE_PLAN(120, 3, 8, 5, 3)
+LACE_PLAN(120, 2, 8, 15)
 #undef LACE_PLAN
 
 template <int N, int S> struct StageP {  // product of radices before stage S

@@ -492,8 +492,9 @@ template <int N, int TX>
 __device__ inline int zcol_index(int tile, int m) {
   return tile * TX + m % TX + N * N * (m / TX);
 }
-template <typename T, int N, int TX, int SL, int NT>
-__global__ __launch_bounds__(NT) void k_zconv(C<T>* __restrict__ tmp,
+template <typename T, int N, int TX, int SL, int NT, int MINW>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
+void k_zconv(C<T>* __restrict__ tmp,
                                               int64_t gs,
                                               const T* __restrict__ vtab,
                                               PairArgs pa, double* epart,
@@ -628,6 +629,9 @@ template <typename T, int N> struct Cfg {
   static constexpr int TXZ0 = 128 / (int)sizeof(C<T>);
   static constexpr int TXZ = (N * N) % TXZ0 == 0 ? TXZ0 : TX;
   static constexpr int NT_Z = (sizeof(T) == 4 && TXZ * SL * N >= 2048) ? 512 : 256;
+  // waves per SIMD to budget registers for: four 512-thread workgroups of
+  // 31 KiB LDS per CU at 120^3 FP32
+  static constexpr int W_Z = sizeof(T) == 4 ? 8 : 4;
   // x pencils: TY rows
   static constexpr int TY = (N % 8 == 0) ? 8 : 4;
   static constexpr int NT_X = 256;
@@ -725,7 +729,7 @@ template <typename T, int N> struct Engine {
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     // pass B
     const int ntiles = (int)tiles();
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z>),
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z, Cf::W_Z>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
                        dim3(Cf::NT_Z), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pa, epart, ntiles, tw);
@@ -788,7 +792,7 @@ template <typename T, int N> struct Engine {
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     const int ntiles = (int)tiles();
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z>),
+    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z, Cf::W_Z>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
                        dim3(Cf::NT_Z), 0, st, tmp, NG,
                        static_cast<const T*>(c.vtab), pw, epart, ntiles, tw);
