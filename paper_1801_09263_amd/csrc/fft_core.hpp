@@ -157,6 +157,9 @@ template <int A, int B, int SIGN, typename T> struct Pfa {
     }
   }
 };
+template <int SIGN, typename T> struct Dft<6, SIGN, T> : Pfa<2, 3, SIGN, T> {};
+template <int SIGN, typename T> struct Dft<10, SIGN, T> : Pfa<2, 5, SIGN, T> {};
+template <int SIGN, typename T> struct Dft<12, SIGN, T> : Pfa<3, 4, SIGN, T> {};
 template <int SIGN, typename T> struct Dft<15, SIGN, T> : Pfa<3, 5, SIGN, T> {};
 
 // ---------------------------------------------------------------------------
@@ -169,18 +172,18 @@ template <int N> struct Plan;
     static constexpr int r[NS] = {__VA_ARGS__};                  \
   };
 LACE_PLAN(4, 1, 4)
-LACE_PLAN(6, 2, 3, 2)
+LACE_PLAN(6, 1, 6)
 LACE_PLAN(8, 1, 8)
-LACE_PLAN(12, 2, 4, 3)
+LACE_PLAN(12, 1, 12)
 LACE_PLAN(16, 2, 4, 4)
 LACE_PLAN(24, 2, 8, 3)
 LACE_PLAN(32, 2, 8, 4)
 LACE_PLAN(40, 2, 8, 5)
-LACE_PLAN(48, 3, 4, 4, 3)
+LACE_PLAN(48, 2, 4, 12)
 LACE_PLAN(60, 2, 4, 15)
 LACE_PLAN(64, 2, 8, 8)
-LACE_PLAN(80, 3, 4, 4, 5)
-LACE_PLAN(96, 3, 8, 4, 3)
+LACE_PLAN(80, 2, 8, 10)
+LACE_PLAN(96, 2, 8, 12)
 LACE_PLAN(120, 2, 8, 15)
 #undef LACE_PLAN
 
