@@ -1,5 +1,6 @@
-"""GPU checks at the full 120^3 sizes, in the launch configuration the
-benchmark times (32 pairs per batch, the same kernels).
+"""GPU checks at the full 120^3 sizes, with the kernels the benchmark times
+(and, in the column test, its launch configuration: 64 pairs per batch,
+half-plane passes).
 
 The oracle cannot run all 65,536 ordered Poisson solves of a full exchange
 in test time, so full-size parity is checked on sampled outputs it can
@@ -112,6 +113,55 @@ def test_gamma_full_step_matches_complex_path(lace120):
     assert rel(b["w"], a["w"]) <= 2e-6
     assert rel(b["m"], a["m"]) <= 2e-6
     assert rel(b["xi"], a["xi"]) <= 1e-4
+
+
+def test_gamma_full_step_columns_against_oracle(lace120):
+    """The timed configuration itself: the whole screened real-orbital FP32
+    step at 120^3, 64 pairs per batch, half-plane passes (full batches of
+    star slots).  Two whole columns W_j, over every partner i the oracle
+    keeps for j, against the oracle's W_j; the GPU's S column against the
+    oracle's.  The GPU's grid orbitals are FP32: their rounding gives each
+    S a relative error of a few 1e-8 (S_jj reads 1 + 4e-8), and the FP32
+    transform's error, absolute at about 1e-7 of the largest grid values,
+    shows in the small entries as a few 1e-9.  S is compared to 2e-7
+    relative plus 1e-8 absolute, and a column with an entry within that
+    band of S_thr (where the two could keep different pairs) is skipped for
+    the next one."""
+    inp = lace120
+    n_orb = inp["coeffs"].shape[0]
+    s = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA, n_vec=n_orb)
+    s.set_orbitals(inp["coeffs"])
+    lace.lace_set_tuning(s.plan, 0, 64, 2)
+    s.apply_exchange(inp["s_thr"])
+    torch.cuda.synchronize()
+    w_gpu = s.w.cpu().numpy()
+    s_gpu = s.screen().cpu().numpy()
+    say(f"  GPU kept {s.n_kept} pairs")
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    say("  oracle grid orbitals")
+    psi = O.orbitals_on_grid(inp["coeffs"], inp["miller"], inp["L"], inp["n"])
+    v = O.coulomb_kernel(inp["L"], inp["n"])
+    thr = inp["s_thr"]
+    done = 0
+    for j in (37, 131, 203, 250):
+        col = np.array([O.overlap_of_moduli(psi[[i, j]], inp["L"])[0, 1]
+                        for i in range(n_orb)])
+        if np.any(np.abs(col - thr) <= 2e-7 * thr + 1e-8):
+            say(f"  column {j}: borderline entry, skipped")
+            continue
+        assert np.all(np.abs(s_gpu[:, j] - col) <= 2e-7 * np.abs(col) + 1e-8)
+        pairs = [(min(i, j), max(i, j)) for i in range(n_orb) if col[i] >= thr]
+        w_ref = O.grid_to_pw(O.apply_exchange_columns(psi, v, pairs, [j]),
+                             inp["miller"], inp["L"])[0]
+        err = rel(w_gpu[j], w_ref)
+        say(f"  column {j}: {len(pairs)} kept partners, W rel err {err:.2e}")
+        assert err <= 1e-5
+        done += 1
+        if done == 2:
+            break
+    assert done == 2
 
 
 def test_sampled_pairs_full_size_plain(plain120):
