@@ -31,62 +31,94 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
 // MODE 2: real, op = |.| of double2 inputs
 // MODE 3, 4: real, op = |.| of float / double inputs (real grids)
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 output,
-// each wave a 32 x 32 block (2 x 2 MFMA tiles).  K staged through LDS in
-// chunks of 16 with coalesced row loads.
+// each wave a 32 x 32 block (2 x 2 MFMA tiles).  K is staged through LDS
+// in chunks of KC (32 real, 16 complex) with coalesced row loads; the
+// next chunk's loads are issued before the current chunk's MFMAs, so
+// their latency hides behind the matrix work.  SYM (A = B): only the
+// tiles on and above the diagonal are computed; the reduction mirrors.
 // ------------------------------------------------------------------
-constexpr int IP_T = 64, IP_KC = 16;
+constexpr int IP_T = 64;
+template <int MODE> struct IpKc { static constexpr int value = MODE == 0 ? 16 : 32; };
+constexpr int IP_KC_MAX = 32;
 
+// Element loads: load() fetches the raw element (zero when out of range)
+// and conv() turns it into the operand, so a prefetched element is not
+// waited for until it is converted, at its LDS store.
 template <int MODE> struct IpLoad;
 template <> struct IpLoad<0> {
-  __device__ static inline void get(const void* p, int64_t off, double& re,
-                                    double& im) {
-    const double2 v = static_cast<const double2*>(p)[off];
+  using Raw = double2;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const double2*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return make_double2(0.0, 0.0); }
+  __device__ static inline void conv(Raw v, double& re, double& im) {
     re = v.x; im = v.y;
   }
 };
 template <> struct IpLoad<1> {
-  __device__ static inline void get(const void* p, int64_t off, double& re,
-                                    double& im) {
-    const float2 v = static_cast<const float2*>(p)[off];
+  using Raw = float2;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const float2*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return make_float2(0.f, 0.f); }
+  __device__ static inline void conv(Raw v, double& re, double& im) {
     const double x = v.x, y = v.y;
     re = sqrt(x * x + y * y); im = 0.0;
   }
 };
 template <> struct IpLoad<2> {
-  __device__ static inline void get(const void* p, int64_t off, double& re,
-                                    double& im) {
-    const double2 v = static_cast<const double2*>(p)[off];
+  using Raw = double2;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const double2*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return make_double2(0.0, 0.0); }
+  __device__ static inline void conv(Raw v, double& re, double& im) {
     re = sqrt(v.x * v.x + v.y * v.y); im = 0.0;
   }
 };
-
 template <> struct IpLoad<3> {
-  __device__ static inline void get(const void* p, int64_t off, double& re,
-                                    double& im) {
-    re = fabs(double(static_cast<const float*>(p)[off])); im = 0.0;
+  using Raw = float;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const float*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return 0.f; }
+  __device__ static inline void conv(Raw v, double& re, double& im) {
+    re = fabs(double(v)); im = 0.0;
   }
 };
 template <> struct IpLoad<4> {
-  __device__ static inline void get(const void* p, int64_t off, double& re,
-                                    double& im) {
-    re = fabs(static_cast<const double*>(p)[off]); im = 0.0;
+  using Raw = double;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const double*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return 0.0; }
+  __device__ static inline void conv(Raw v, double& re, double& im) {
+    re = fabs(v); im = 0.0;
   }
 };
 
-template <int MODE>
+template <int MODE, bool SYM>
 __global__ __launch_bounds__(256) void k_gemm_ip(const void* A, int64_t lda,
                                                  int na, const void* B,
                                                  int64_t ldb, int nb,
                                                  int64_t K, int64_t kchunk,
                                                  double* part) {
   constexpr bool CPLX = (MODE == 0);
-  __shared__ double sAr[IP_T][IP_KC + 1];
-  __shared__ double sBr[IP_T][IP_KC + 1];
-  __shared__ double sAi[CPLX ? IP_T : 1][IP_KC + 1];
-  __shared__ double sBi[CPLX ? IP_T : 1][IP_KC + 1];
+  constexpr int KC = IpKc<MODE>::value;
+  constexpr int PT = IP_T * KC / 256;   // elements per thread and matrix
+  __shared__ double sAr[IP_T][KC + 1];
+  __shared__ double sBr[IP_T][KC + 1];
+  __shared__ double sAi[CPLX ? IP_T : 1][KC + 1];
+  __shared__ double sBi[CPLX ? IP_T : 1][KC + 1];
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
   const int wa = w % 2, wb = w / 2;
-  const int a0 = blockIdx.x * IP_T, b0 = blockIdx.y * IP_T;
+  int ta = blockIdx.x, tb = blockIdx.y;
+  if (SYM) {   // blockIdx.x enumerates the tile pairs ta <= tb, column by column
+    ta = blockIdx.x;
+    tb = 0;
+    while (ta > tb) { ta -= tb + 1; ++tb; }
+  }
+  const int a0 = ta * IP_T, b0 = tb * IP_T;
   const int64_t kb = blockIdx.z * kchunk;
   int64_t ke = kb + kchunk;
   if (ke > K) ke = K;
@@ -100,35 +132,47 @@ __global__ __launch_bounds__(256) void k_gemm_ip(const void* A, int64_t lda,
       accI[p][q] = d4{0, 0, 0, 0};
     }
 
-  for (int64_t k0 = kb; k0 < ke; k0 += IP_KC) {
+  using L = IpLoad<MODE>;
+  typename L::Raw xa[PT], xb[PT];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < (IP_T * IP_KC) / 256; ++e) {
+    for (int e = 0; e < PT; ++e) {
       const int idx = tid + e * 256;
-      const int r = idx / IP_KC, kk = idx % IP_KC;
+      const int r = idx / KC, kk = idx % KC;
       const int64_t k = k0 + kk;
-      double re = 0.0, im = 0.0;
-      if (a0 + r < na && k < ke) IpLoad<MODE>::get(A, (a0 + r) * lda + k, re, im);
+      xa[e] = (a0 + r < na && k < ke) ? L::load(A, (a0 + r) * lda + k) : L::zero();
+      xb[e] = (b0 + r < nb && k < ke) ? L::load(B, (b0 + r) * ldb + k) : L::zero();
+    }
+  };
+  fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / KC, kk = idx % KC;
+      double re, im;
+      L::conv(xa[e], re, im);
       sAr[r][kk] = re;
       if (CPLX) sAi[r][kk] = im;
-      re = 0.0; im = 0.0;
-      if (b0 + r < nb && k < ke) IpLoad<MODE>::get(B, (b0 + r) * ldb + k, re, im);
+      L::conv(xb[e], re, im);
       sBr[r][kk] = re;
       if (CPLX) sBi[r][kk] = im;
     }
     __syncthreads();
+    if (k0 + KC < ke) fetch(k0 + KC);
 #pragma unroll
-    for (int ks = 0; ks < IP_KC / 4; ++ks) {
+    for (int ks = 0; ks < KC / 4; ++ks) {
       const int kk = ks * 4 + lane / 16;
       double ar[2], ai[2], br[2], bi[2];
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const int ra = wa * 32 + p * 16 + lane % 16;
-        const int rb = wb * 32 + p * 16 + lane % 16;
-        ar[p] = sAr[ra][kk];
-        br[p] = sBr[rb][kk];
+        const int rra = wa * 32 + p * 16 + lane % 16;
+        const int rrb = wb * 32 + p * 16 + lane % 16;
+        ar[p] = sAr[rra][kk];
+        br[p] = sBr[rrb][kk];
         if (CPLX) {
-          ai[p] = sAi[ra][kk];
-          bi[p] = sBi[rb][kk];
+          ai[p] = sAi[rra][kk];
+          bi[p] = sBi[rrb][kk];
         }
       }
 #pragma unroll
@@ -166,14 +210,21 @@ __global__ __launch_bounds__(256) void k_gemm_ip(const void* A, int64_t lda,
       }
 }
 
-// out[e] = scale * sum_z part[z][e], fixed order over z
+// out[e] = scale * sum_z part[z][e], fixed order over z.  sym_nb > 0: a
+// real sym_nb x sym_nb result of which only the tiles on and above the
+// diagonal were computed; an element below reads its mirror.
 __global__ void k_splitk_reduce(const double* part, int64_t nel, int nsplit,
-                                double scale, double* out) {
+                                double scale, double* out, int sym_nb) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nel;
        e += stride) {
+    int64_t src = e;
+    if (sym_nb > 0) {
+      const int64_t a = e / sym_nb, b = e % sym_nb;
+      if (a / IP_T > b / IP_T) src = b * sym_nb + a;
+    }
     double t = 0.0;
-    for (int z = 0; z < nsplit; ++z) t += part[(int64_t)z * nel + e];
+    for (int z = 0; z < nsplit; ++z) t += part[(int64_t)z * nel + src];
     out[e] = scale * t;
   }
 }
@@ -183,15 +234,17 @@ struct SplitPlan {
   int64_t kchunk;
 };
 
+// Split K so that about 1024 workgroups run.  The chunk is a multiple of
+// the largest KC, which keeps the partial layout the same for every mode.
 static SplitPlan split_plan(int na, int nb, int64_t K) {
   const int64_t tiles = (int64_t)((na + IP_T - 1) / IP_T) * ((nb + IP_T - 1) / IP_T);
   int64_t want = (1024 + tiles - 1) / tiles;
-  const int64_t maxs = (K + IP_KC - 1) / IP_KC;
+  const int64_t maxs = (K + IP_KC_MAX - 1) / IP_KC_MAX;
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
   int64_t chunk = (K + want - 1) / want;
-  chunk = ((chunk + IP_KC - 1) / IP_KC) * IP_KC;
-  if (chunk < IP_KC) chunk = IP_KC;
+  chunk = ((chunk + IP_KC_MAX - 1) / IP_KC_MAX) * IP_KC_MAX;
+  if (chunk < IP_KC_MAX) chunk = IP_KC_MAX;
   SplitPlan sp;
   sp.kchunk = chunk;
   sp.nsplit = (int)((K + chunk - 1) / chunk);
@@ -204,18 +257,22 @@ int64_t gemm_ip_part_bytes(int na, int nb, int64_t K, bool complex_out) {
   return (int64_t)sp.nsplit * na * nb * (complex_out ? 16 : 8);
 }
 
-template <int MODE>
+// SYM: B is A (na = nb), the result is symmetric.
+template <int MODE, bool SYM = false>
 static hipError_t gemm_ip(const void* A, int64_t lda, int na, const void* B,
                           int64_t ldb, int nb, int64_t K, double scale,
                           double* out, void* part, int64_t part_bytes,
                           hipStream_t st) {
+  static_assert(!SYM || MODE != 0, "symmetric only for real results");
   const SplitPlan sp = split_plan(na, nb, K);
   const bool cplx = (MODE == 0);
   if ((int64_t)sp.nsplit * na * nb * (cplx ? 16 : 8) > part_bytes)
     return hipErrorInvalidValue;
-  dim3 grid((na + IP_T - 1) / IP_T, (nb + IP_T - 1) / IP_T, sp.nsplit);
-  hipLaunchKernelGGL((k_gemm_ip<MODE>), grid, dim3(256), 0, st, A, lda, na, B,
-                     ldb, nb, K, sp.kchunk, static_cast<double*>(part));
+  if (SYM && (A != B || na != nb || lda != ldb)) return hipErrorInvalidValue;
+  const int ta = (na + IP_T - 1) / IP_T, tb = (nb + IP_T - 1) / IP_T;
+  dim3 grid(SYM ? ta * (ta + 1) / 2 : ta, SYM ? 1 : tb, sp.nsplit);
+  hipLaunchKernelGGL((k_gemm_ip<MODE, SYM>), grid, dim3(256), 0, st, A, lda,
+                     na, B, ldb, nb, K, sp.kchunk, static_cast<double*>(part));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int64_t nel = (int64_t)na * nb * (cplx ? 2 : 1);
@@ -223,7 +280,7 @@ static hipError_t gemm_ip(const void* A, int64_t lda, int na, const void* B,
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const double*>(part), nel, sp.nsplit, scale,
-                     out);
+                     out, SYM ? nb : 0);
   return hipGetLastError();
 }
 
@@ -238,20 +295,20 @@ hipError_t launch_gemm_ip_c128(const void* A, int64_t lda, int na,
 hipError_t launch_gemm_ip_abs(bool fp64, const void* A, int64_t lda, int na,
                               int64_t K, double scale, double* out, void* part,
                               int64_t part_bytes, hipStream_t st) {
-  return fp64 ? gemm_ip<2>(A, lda, na, A, lda, na, K, scale, out, part,
-                           part_bytes, st)
-              : gemm_ip<1>(A, lda, na, A, lda, na, K, scale, out, part,
-                           part_bytes, st);
+  return fp64 ? gemm_ip<2, true>(A, lda, na, A, lda, na, K, scale, out, part,
+                                 part_bytes, st)
+              : gemm_ip<1, true>(A, lda, na, A, lda, na, K, scale, out, part,
+                                 part_bytes, st);
 }
 
 hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
                                    int na, int64_t K, double scale,
                                    double* out, void* part, int64_t part_bytes,
                                    hipStream_t st) {
-  return fp64 ? gemm_ip<4>(A, lda, na, A, lda, na, K, scale, out, part,
-                           part_bytes, st)
-              : gemm_ip<3>(A, lda, na, A, lda, na, K, scale, out, part,
-                           part_bytes, st);
+  return fp64 ? gemm_ip<4, true>(A, lda, na, A, lda, na, K, scale, out, part,
+                                 part_bytes, st)
+              : gemm_ip<3, true>(A, lda, na, A, lda, na, K, scale, out, part,
+                                 part_bytes, st);
 }
 
 // ------------------------------------------------------------------
