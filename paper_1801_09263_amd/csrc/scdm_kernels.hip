@@ -120,51 +120,92 @@ __global__ void k_argmax_final(const double* pv, const int64_t* pi, int nparts,
 
 // q_k: the picked column a = conj(psi(r_k)) made orthogonal to q_0..q_{k-1}
 // (classical Gram-Schmidt, twice) and normalized; Q row-major, q_m = Q[m][.].
-// One workgroup; scratch u holds n_orb doubles2, h holds k values.
+// One workgroup.  The column u lives in LDS; h_m = q_m^H u is one wave per
+// m (lanes along n, coalesced rows of Q, shuffle sum) into the scratch h;
+// u -= sum_m q_m h_m splits the m sum over ngrp thread groups when n_orb
+// is small, their partial sums added in LDS.  Dynamic LDS: n_orb double2
+// for u plus, when ngrp > 1, ngrp * n_orb for the partials.
+__device__ inline double2 wave_sum2(double2 v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  return v;
+}
+
 template <typename G, int NT>
-__global__ void k_scdm_direction(const G* psi, int n_orb, int64_t ng,
-                                 const int32_t* points, int k, double2* Q,
-                                 double2* u, double2* h) {
+__global__ __launch_bounds__(NT) void k_scdm_direction(
+    const G* psi, int n_orb, int64_t ng, const int32_t* points, int k,
+    double2* Q, double2* h, int ngrp) {
+  extern __shared__ double2 lds[];
+  double2* us = lds;
+  double2* part = lds + n_orb;
   __shared__ double red[NT / 64];
+  const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64;
   const int64_t r = points[k];
-  for (int n = threadIdx.x; n < n_orb; n += NT) {
+  for (int n = tid; n < n_orb; n += NT) {
     const double2 v = GridVal<G>::get(psi, n * ng + r);
-    u[n] = make_double2(v.x, -v.y);
+    us[n] = make_double2(v.x, -v.y);
   }
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    for (int m = threadIdx.x; m < k; m += NT) {   // h_m = q_m^H u
-      double2 s = make_double2(0.0, 0.0);
+    for (int m = wv; m < k; m += NT / 64) {   // h_m = q_m^H u
       const double2* q = Q + (int64_t)m * n_orb;
-      for (int n = 0; n < n_orb; ++n) {
-        s.x += q[n].x * u[n].x + q[n].y * u[n].y;
-        s.y += q[n].x * u[n].y - q[n].y * u[n].x;
+      double2 sm = make_double2(0.0, 0.0);
+      for (int n = lane; n < n_orb; n += 64) {
+        const double2 a = q[n], b = us[n];
+        sm.x += a.x * b.x + a.y * b.y;
+        sm.y += a.x * b.y - a.y * b.x;
       }
-      h[m] = s;
+      sm = wave_sum2(sm);
+      if (lane == 0) h[m] = sm;
     }
     __syncthreads();
-    for (int n = threadIdx.x; n < n_orb; n += NT) {   // u -= sum_m q_m h_m
-      double2 s = u[n];
-      for (int m = 0; m < k; ++m) {
-        const double2 q = Q[(int64_t)m * n_orb + n];
-        s.x -= q.x * h[m].x - q.y * h[m].y;
-        s.y -= q.x * h[m].y + q.y * h[m].x;
+    if (ngrp > 1) {   // thread (g, n): partial over m = g, g + ngrp, ...
+      if (tid < ngrp * n_orb) {
+        const int n = tid % n_orb, g = tid / n_orb;
+        double2 sm = make_double2(0.0, 0.0);
+        for (int m = g; m < k; m += ngrp) {
+          const double2 a = Q[(int64_t)m * n_orb + n], hm = h[m];
+          sm.x += a.x * hm.x - a.y * hm.y;
+          sm.y += a.x * hm.y + a.y * hm.x;
+        }
+        part[g * n_orb + n] = sm;
       }
-      u[n] = s;
+      __syncthreads();
+      for (int n = tid; n < n_orb; n += NT) {
+        double2 sm = us[n];
+        for (int g = 0; g < ngrp; ++g) {
+          sm.x -= part[g * n_orb + n].x;
+          sm.y -= part[g * n_orb + n].y;
+        }
+        us[n] = sm;
+      }
+    } else {
+      for (int n = tid; n < n_orb; n += NT) {   // u -= sum_m q_m h_m
+        double2 sm = us[n];
+        for (int m = 0; m < k; ++m) {
+          const double2 a = Q[(int64_t)m * n_orb + n], hm = h[m];
+          sm.x -= a.x * hm.x - a.y * hm.y;
+          sm.y -= a.x * hm.y + a.y * hm.x;
+        }
+        us[n] = sm;
+      }
     }
     __syncthreads();
   }
   double t = 0.0;
-  for (int n = threadIdx.x; n < n_orb; n += NT) t += u[n].x * u[n].x + u[n].y * u[n].y;
+  for (int n = tid; n < n_orb; n += NT) t += us[n].x * us[n].x + us[n].y * us[n].y;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = t;
+  if (lane == 0) red[wv] = t;
   __syncthreads();
   double nrm = 0.0;
   for (int w = 0; w < NT / 64; ++w) nrm += red[w];
   const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-  for (int n = threadIdx.x; n < n_orb; n += NT)
-    Q[(int64_t)k * n_orb + n] = make_double2(u[n].x * inv, u[n].y * inv);
+  for (int n = tid; n < n_orb; n += NT)
+    Q[(int64_t)k * n_orb + n] = make_double2(us[n].x * inv, us[n].y * inv);
 }
 
 // d(r) -= |q_k^H a_r|^2 = |sum_n q_kn psi_n(r)|^2 for points not yet taken.
@@ -203,10 +244,12 @@ __global__ void k_scdm_gather(const G* psi, int n_orb, int64_t ng,
 
 template <typename G>
 static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
-                         double* pv, int64_t* pi, double2* Q, double2* u,
-                         double2* h, int32_t* points, double2* Y,
-                         hipStream_t st) {
+                         double* pv, int64_t* pi, double2* Q, double2* h,
+                         int32_t* points, double2* Y, hipStream_t st) {
   constexpr int NT = 256;
+  constexpr int DIR_NT = 1024;
+  const int ngrp = n_orb <= DIR_NT / 2 ? DIR_NT / n_orb : 1;
+  const size_t dir_lds = sizeof(double2) * (size_t)n_orb * (ngrp > 1 ? 1 + ngrp : 1);
   int64_t blocks = (ng + NT - 1) / NT;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_scdm_density<G>, dim3((unsigned)blocks), dim3(NT), 0,
@@ -219,8 +262,8 @@ static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
                        ng, pv, pi);
     hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(AM_NT), 0, st, pv, pi,
                        parts, d, points, k);
-    hipLaunchKernelGGL((k_scdm_direction<G, 1024>), dim3(1), dim3(1024), 0, st,
-                       psi, n_orb, ng, points, k, Q, u, h);
+    hipLaunchKernelGGL((k_scdm_direction<G, DIR_NT>), dim3(1), dim3(DIR_NT),
+                       dir_lds, st, psi, n_orb, ng, points, k, Q, h, ngrp);
     if (k + 1 < n_orb)
       hipLaunchKernelGGL((k_scdm_downdate<G, NT>), dim3((unsigned)blocks),
                          dim3(NT), qlds, st, psi, n_orb, ng, Q, k, d);
@@ -238,7 +281,7 @@ static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
 
 int64_t scdm_scratch_bytes(int n_orb) {
   return (int64_t)AM_BLOCKS * (sizeof(double) + sizeof(int64_t)) +
-         (int64_t)sizeof(double2) * (2 * (int64_t)n_orb + (int64_t)n_orb * n_orb);
+         (int64_t)sizeof(double2) * ((int64_t)n_orb + (int64_t)n_orb * n_orb);
 }
 
 hipError_t launch_scdm(bool fp64, bool real, const void* psi, int n_orb,
@@ -250,21 +293,19 @@ hipError_t launch_scdm(bool fp64, bool real, const void* psi, int n_orb,
   p += AM_BLOCKS * sizeof(double);
   int64_t* pi = reinterpret_cast<int64_t*>(p);
   p += AM_BLOCKS * sizeof(int64_t);
-  double2* u = reinterpret_cast<double2*>(p);
-  p += sizeof(double2) * n_orb;
   double2* h = reinterpret_cast<double2*>(p);
   p += sizeof(double2) * n_orb;
   double2* Q = reinterpret_cast<double2*>(p);
   double2* y = static_cast<double2*>(Y);
   if (real)
     return fp64 ? scdm_t(static_cast<const double*>(psi), n_orb, ng, d, pv, pi,
-                         Q, u, h, points, y, st)
+                         Q, h, points, y, st)
                 : scdm_t(static_cast<const float*>(psi), n_orb, ng, d, pv, pi,
-                         Q, u, h, points, y, st);
+                         Q, h, points, y, st);
   return fp64 ? scdm_t(static_cast<const double2*>(psi), n_orb, ng, d, pv, pi,
-                       Q, u, h, points, y, st)
+                       Q, h, points, y, st)
               : scdm_t(static_cast<const float2*>(psi), n_orb, ng, d, pv, pi,
-                       Q, u, h, points, y, st);
+                       Q, h, points, y, st);
 }
 
 }  // namespace lace
