@@ -90,7 +90,7 @@ __device__ inline ArgMax block_argmax(ArgMax m) {
 }
 
 constexpr int AM_NT = 256;
-constexpr int AM_BLOCKS = 1024;
+constexpr int AM_BLOCKS = 4096;
 
 __global__ void k_argmax_partial(const double* d, int64_t ng, double* pv,
                                  int64_t* pi) {
@@ -153,6 +153,7 @@ __global__ __launch_bounds__(NT) void k_scdm_direction(
     for (int m = wv; m < k; m += NT / 64) {   // h_m = q_m^H u
       const double2* q = Q + (int64_t)m * n_orb;
       double2 sm = make_double2(0.0, 0.0);
+#pragma unroll 4
       for (int n = lane; n < n_orb; n += 64) {
         const double2 a = q[n], b = us[n];
         sm.x += a.x * b.x + a.y * b.y;
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(NT) void k_scdm_direction(
       if (tid < ngrp * n_orb) {
         const int n = tid % n_orb, g = tid / n_orb;
         double2 sm = make_double2(0.0, 0.0);
+#pragma unroll 8
         for (int m = g; m < k; m += ngrp) {
           const double2 a = Q[(int64_t)m * n_orb + n], hm = h[m];
           sm.x += a.x * hm.x - a.y * hm.y;
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(NT) void k_scdm_direction(
     } else {
       for (int n = tid; n < n_orb; n += NT) {   // u -= sum_m q_m h_m
         double2 sm = us[n];
+#pragma unroll 8
         for (int m = 0; m < k; ++m) {
           const double2 a = Q[(int64_t)m * n_orb + n], hm = h[m];
           sm.x -= a.x * hm.x - a.y * hm.y;
@@ -208,23 +211,80 @@ __global__ __launch_bounds__(NT) void k_scdm_direction(
     Q[(int64_t)k * n_orb + n] = make_double2(us[n].x * inv, us[n].y * inv);
 }
 
-// d(r) -= |q_k^H a_r|^2 = |sum_n q_kn psi_n(r)|^2 for points not yet taken.
-template <typename G, int NT>
-__global__ void k_scdm_downdate(const G* psi, int n_orb, int64_t ng,
-                                const double2* Q, int k, double* d) {
+// d(r) -= |q_k^H a_r|^2 = |sum_n q_kn psi_n(r)|^2 for points not yet taken,
+// fused with the next pick's block-wise argmax (written to pv, pi as
+// k_argmax_partial does).  A thread takes VW consecutive points, one
+// 16-byte load per orbital (VW = 1 when n_g is not a multiple of the
+// vector width); the sum over orbitals runs in orbital order for every
+// point, as in a scalar loop.
+template <typename G, int VW> struct GridVec {
+  G v[VW];
+};
+template <typename G, int VW>
+__device__ inline GridVec<G, VW> ldgrid(const G* p) {
+  GridVec<G, VW> r;
+  if constexpr (VW * sizeof(G) == 16) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    __builtin_memcpy(&r, &t, 16);
+  } else {
+#pragma unroll
+    for (int e = 0; e < VW; ++e) r.v[e] = p[e];
+  }
+  return r;
+}
+template <typename G> struct Cpx;
+template <> struct Cpx<float> {
+  __device__ static double2 of(float v) { return make_double2(v, 0.0); }
+};
+template <> struct Cpx<double> {
+  __device__ static double2 of(double v) { return make_double2(v, 0.0); }
+};
+template <> struct Cpx<float2> {
+  __device__ static double2 of(float2 v) { return make_double2(v.x, v.y); }
+};
+template <> struct Cpx<double2> {
+  __device__ static double2 of(double2 v) { return v; }
+};
+
+template <typename G, int VW>
+__global__ __launch_bounds__(AM_NT) void k_scdm_downdate(
+    const G* psi, int n_orb, int64_t ng, const double2* Q, int k, double* d,
+    double* pv, int64_t* pi) {
   extern __shared__ double2 qs[];
-  for (int n = threadIdx.x; n < n_orb; n += NT) qs[n] = Q[(int64_t)k * n_orb + n];
+  for (int n = threadIdx.x; n < n_orb; n += AM_NT) qs[n] = Q[(int64_t)k * n_orb + n];
   __syncthreads();
-  const int64_t stride = int64_t(gridDim.x) * NT;
-  for (int64_t r = blockIdx.x * int64_t(NT) + threadIdx.x; r < ng; r += stride) {
-    double sx = 0.0, sy = 0.0;
+  ArgMax m{-2.0, 0};
+  const int64_t stride = int64_t(gridDim.x) * AM_NT * VW;
+  for (int64_t r0 = (blockIdx.x * int64_t(AM_NT) + threadIdx.x) * VW; r0 < ng;
+       r0 += stride) {
+    double sx[VW], sy[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) sx[e] = sy[e] = 0.0;
     for (int n = 0; n < n_orb; ++n) {
-      const double2 v = GridVal<G>::get(psi, n * ng + r);
-      sx += qs[n].x * v.x - qs[n].y * v.y;
-      sy += qs[n].x * v.y + qs[n].y * v.x;
+      const GridVec<G, VW> g = ldgrid<G, VW>(psi + n * ng + r0);
+      const double2 q = qs[n];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const double2 v = Cpx<G>::of(g.v[e]);
+        sx[e] += q.x * v.x - q.y * v.y;
+        sy[e] += q.x * v.y + q.y * v.x;
+      }
     }
-    const double old = d[r];
-    if (old >= 0.0) d[r] = fmax(old - (sx * sx + sy * sy), 0.0);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const double old = d[r0 + e];
+      double nv = old;
+      if (old >= 0.0) {
+        nv = fmax(old - (sx[e] * sx[e] + sy[e] * sy[e]), 0.0);
+        d[r0 + e] = nv;
+      }
+      m = better(m, ArgMax{nv, r0 + e});
+    }
+  }
+  m = block_argmax<AM_NT>(m);
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = m.v;
+    pi[blockIdx.x] = m.i;
   }
 }
 
@@ -255,18 +315,27 @@ static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
   hipLaunchKernelGGL(k_scdm_density<G>, dim3((unsigned)blocks), dim3(NT), 0,
                      st, psi, n_orb, ng, d);
   hipError_t e = hipGetLastError();
-  const int parts = (int)std::min<int64_t>(AM_BLOCKS, (ng + AM_NT - 1) / AM_NT);
+  constexpr int VW = 16 / (int)sizeof(G);
+  const bool vec = ng % VW == 0;
+  // one vector of points per downdate thread where the partials allow
+  const int64_t per_block = (int64_t)AM_NT * (vec ? VW : 1);
+  const int parts = (int)std::min<int64_t>(AM_BLOCKS, (ng + per_block - 1) / per_block);
   const size_t qlds = sizeof(double2) * (size_t)n_orb;
+  hipLaunchKernelGGL(k_argmax_partial, dim3(parts), dim3(AM_NT), 0, st, d, ng,
+                     pv, pi);
   for (int k = 0; k < n_orb && e == hipSuccess; ++k) {
-    hipLaunchKernelGGL(k_argmax_partial, dim3(parts), dim3(AM_NT), 0, st, d,
-                       ng, pv, pi);
     hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(AM_NT), 0, st, pv, pi,
                        parts, d, points, k);
     hipLaunchKernelGGL((k_scdm_direction<G, DIR_NT>), dim3(1), dim3(DIR_NT),
                        dir_lds, st, psi, n_orb, ng, points, k, Q, h, ngrp);
-    if (k + 1 < n_orb)
-      hipLaunchKernelGGL((k_scdm_downdate<G, NT>), dim3((unsigned)blocks),
-                         dim3(NT), qlds, st, psi, n_orb, ng, Q, k, d);
+    if (k + 1 < n_orb) {   // downdate, and the next pick's partial argmax
+      if (vec)
+        hipLaunchKernelGGL((k_scdm_downdate<G, VW>), dim3(parts), dim3(AM_NT),
+                           qlds, st, psi, n_orb, ng, Q, k, d, pv, pi);
+      else
+        hipLaunchKernelGGL((k_scdm_downdate<G, 1>), dim3(parts), dim3(AM_NT),
+                           qlds, st, psi, n_orb, ng, Q, k, d, pv, pi);
+    }
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
