@@ -100,6 +100,51 @@ template <typename T> struct EpiGrid {
     stv<C<T>, V>(buf + slot * gs + g, y);
   }
 };
+// Two real grids packed as one complex grid: value W_{2p} + i W_{2p+1}
+// (zero imaginary part for a last odd grid).  Reads 16 bytes per grid.
+template <typename T> struct ProPackReal {
+  static constexpr int V = 16 / sizeof(T);
+  const T* __restrict__ w;
+  int64_t gs;
+  int n_real;
+  __device__ void getv(int g, int slot, C<T>* out) const {
+    const int a = 2 * slot;
+    const bool two = a + 1 < n_real;   // uniform over the workgroup
+    const Vec<T, V> x = ldv<T, V>(w + a * gs + g);
+    Vec<T, V> y;
+    if (two) {
+      y = ldv<T, V>(w + (a + 1) * gs + g);
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) y.e[v] = T(0);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = mk<T>(x.e[v], y.e[v]);
+  }
+};
+// The inverse: scale * (Re, Im) into the real grids 2p and 2p + 1.
+template <typename T> struct EpiSplitReal {
+  static constexpr int V = 16 / sizeof(T);
+  static constexpr int CH = 4;
+  using Pre = NoPre;
+  T* __restrict__ psi;
+  int64_t gs;
+  int n_real;
+  T scale;
+  __device__ void prev(int, int, Pre&) const {}
+  __device__ void putv(int g, int slot, const C<T>* x, const Pre&) const {
+    const int a = 2 * slot;
+    Vec<T, V> re, im;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      re.e[v] = x[v].x * scale;
+      im.e[v] = x[v].y * scale;
+    }
+    stv<T, V>(psi + a * gs + g, re);
+    if (a + 1 < n_real) stv<T, V>(psi + (a + 1) * gs + g, im);
+  }
+};
+
 template <typename T> struct AccPre {
   Vec<C<T>, 16 / sizeof(C<T>)> pi, pj, wi, wj;
 };
@@ -456,6 +501,8 @@ __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
   __shared__ C<T> s[TX * LS];
   __shared__ C<T> tw[N];
   constexpr int NTILES = N * (N / TX);
+  static_assert(TX % Pro::V == 0 && TX % Epi::V == 0,
+                "vectors must not cross a tile row");
   const int lg = xcd_logical(blockIdx.x, NTILES * nslots);
   const int tile = lg / nslots, slot = lg % nslots;
   load_tw<T, N, NT>(tw, tw_g);
@@ -682,24 +729,44 @@ template <typename T, int N> struct Engine {
     return hipGetLastError();
   }
 
-  // in-place transform of `count` grids, optional scale on the last pass
-  template <int SIGN>
-  static hipError_t fft3d(C<T>* g, int count, T scale, const C<T>* tw,
-                          int mode, hipStream_t st) {
+  // Transform of `count` grids held in g between the passes: the first
+  // pass reads through `first`, the last one (z) writes through `last`.
+  template <int SIGN, class ProF, class EpiL>
+  static hipError_t fft3d_io(ProF first, EpiL last, C<T>* g, int count,
+                             const C<T>* tw, int mode, hipStream_t st) {
     ProGrid<T> p{g, NG};
     EpiGrid<T> e1{g, NG, T(1)};
-    EpiGrid<T> es{g, NG, scale};
     hipError_t err;
     // In place, so never the half-plane form: its two workgroups of a plane
     // would overwrite rows that the other one still reads.
     if (Cf::plane && mode != 0) {
-      err = plane<SIGN>(p, e1, count, tw, st);
+      err = plane<SIGN>(first, e1, count, tw, st);
     } else {
-      err = xlines<SIGN>(p, e1, count, tw, st);
+      err = xlines<SIGN>(first, e1, count, tw, st);
       if (err == hipSuccess) err = cols<1, SIGN>(p, e1, count, tw, st);
     }
-    if (err == hipSuccess) err = cols<2, SIGN>(p, es, count, tw, st);
+    if (err == hipSuccess) err = cols<2, SIGN>(p, last, count, tw, st);
     return err;
+  }
+  // in-place transform of `count` grids, optional scale on the last pass
+  template <int SIGN>
+  static hipError_t fft3d(C<T>* g, int count, T scale, const C<T>* tw,
+                          int mode, hipStream_t st) {
+    return fft3d_io<SIGN>(ProGrid<T>{g, NG}, EpiGrid<T>{g, NG, scale}, g,
+                          count, tw, mode, st);
+  }
+  // real grids to packed pairs: inverse transform, split into 2 real grids
+  static hipError_t to_real(C<T>* g, int count, T scale, T* psi, int n_real,
+                            const C<T>* tw, int mode, hipStream_t st) {
+    return fft3d_io<+1>(ProGrid<T>{g, NG},
+                        EpiSplitReal<T>{psi, NG, n_real, scale}, g, count, tw,
+                        mode, st);
+  }
+  // packed pairs of real grids: forward transform into g
+  static hipError_t from_real(const T* w, int n_real, C<T>* g, int count,
+                              const C<T>* tw, int mode, hipStream_t st) {
+    return fft3d_io<-1>(ProPackReal<T>{w, NG, n_real},
+                        EpiGrid<T>{g, NG, T(1)}, g, count, tw, mode, st);
   }
 
   static hipError_t pair_batch(const CellDev& c, const PairArgs& pa,
@@ -995,36 +1062,6 @@ __global__ void k_scatter_pairs(const double2* coeffs, int64_t n_pw,
   }
 }
 
-// psi_{2p} <- Re z_p, psi_{2p+1} <- Im z_p
-template <typename T>
-__global__ void k_split_real(const C<T>* z, int64_t gs, T* psi, int n_orb) {
-  const int npair = (n_orb + 1) / 2;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  const int64_t total = gs * npair;
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
-       k += stride) {
-    const int64_t p = k / gs, g = k % gs;
-    const C<T> v = z[k];
-    psi[(2 * p) * gs + g] = v.x;
-    if (2 * p + 1 < n_orb) psi[(2 * p + 1) * gs + g] = v.y;
-  }
-}
-
-// z_p <- W_{2p} + i W_{2p+1}
-template <typename T>
-__global__ void k_pack_real(const T* w, int64_t gs, int n_orb, C<T>* z) {
-  const int npair = (n_orb + 1) / 2;
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  const int64_t total = gs * npair;
-  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < total;
-       k += stride) {
-    const int64_t p = k / gs, g = k % gs;
-    const T a = w[(2 * p) * gs + g];
-    const T b = (2 * p + 1 < n_orb) ? w[(2 * p + 1) * gs + g] : T(0);
-    z[k] = mk<T>(a, b);
-  }
-}
-
 // Unpack two real transforms: with Z = F[W_a + i W_b],
 // F[W_a](G) = (Z(G) + conj Z(-G)) / 2, F[W_b](G) = (Z(G) - conj Z(-G)) / 2i.
 template <typename T>
@@ -1066,12 +1103,19 @@ static hipError_t orb_to_grid_real_t(const CellDev& c, const void* coeffs,
                      dim3(256), 0, st, static_cast<const double2*>(coeffs),
                      c.n_pw, c.gidx, static_cast<C<T>*>(scratch), c.ng, n_orb);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  err = fft3d_t<T>(c, +1, scratch, npair, T(1.0 / std::sqrt(c.omega)), st);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_split_real<T>), dim3(grid_for(c.ng * npair)), dim3(256),
-                     0, st, static_cast<const C<T>*>(scratch), c.ng,
-                     static_cast<T*>(psi), n_orb);
-  return hipGetLastError();
+  const T scale = T(1.0 / std::sqrt(c.omega));
+  C<T>* z = static_cast<C<T>*>(scratch);
+  T* out = static_cast<T*>(psi);
+  const C<T>* tw = static_cast<const C<T>*>(c.tw);
+  switch (c.n) {
+#define X(NN)                                                               \
+  case NN:                                                                  \
+    return Engine<T, NN>::to_real(z, npair, scale, out, n_orb, tw,          \
+                                  c.use_plane, st);
+    LACE_SIZES(X)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_orbitals_to_grid_real(const CellDev& c, bool fp64,
@@ -1086,12 +1130,19 @@ template <typename T>
 static hipError_t grid_to_pw_real_t(const CellDev& c, const void* w, int n_orb,
                                     void* scratch, void* w_pw, hipStream_t st) {
   const int npair = (n_orb + 1) / 2;
-  hipLaunchKernelGGL((k_pack_real<T>), dim3(grid_for(c.ng * npair)), dim3(256),
-                     0, st, static_cast<const T*>(w), c.ng, n_orb,
-                     static_cast<C<T>*>(scratch));
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  err = fft3d_t<T>(c, -1, scratch, npair, T(1), st);
+  C<T>* z = static_cast<C<T>*>(scratch);
+  const C<T>* tw = static_cast<const C<T>*>(c.tw);
+  hipError_t err = hipErrorInvalidValue;
+  switch (c.n) {
+#define X(NN)                                                               \
+  case NN:                                                                  \
+    err = Engine<T, NN>::from_real(static_cast<const T*>(w), n_orb, z,      \
+                                   npair, tw, c.use_plane, st);             \
+    break;
+    LACE_SIZES(X)
+#undef X
+    default: break;
+  }
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_gather_pairs<T>), dim3(grid_for(c.n_pw * npair)),
                      dim3(256), 0, st, static_cast<const C<T>*>(scratch), c.ng,
