@@ -260,6 +260,33 @@ struct StagesFrom<T, N, -1, NL, NT, SIGN, LF, TWS> {
   __device__ static inline void run(C<T>*, int, int, const C<T>*) {}
 };
 
+// Stages S .. E-1 of the plan, in plan order.
+template <typename T, int N, int S, int E, int NL, int NT, int SIGN, bool LF,
+          int TWS>
+struct StagesRange {
+  __device__ static inline void run(C<T>* s, int ls, int es, const C<T>* tw) {
+    if constexpr (S < E) {
+      lds_stage<T, N, Plan<N>::r[S], StageP<N, S>::value, NL, NT, SIGN, LF,
+                TWS>(s, ls, es, tw);
+      StagesRange<T, N, S + 1, E, NL, NT, SIGN, LF, TWS>::run(s, ls, es, tw);
+    }
+  }
+};
+
+// The plan in reverse order, from stage index S down to 0: radix r[S] after
+// the radices r[S+1..] already applied (P = N / (r[0] ... r[S])).  The
+// reversed plan is an equally valid self-sorting Stockham factorization.
+template <typename T, int N, int S, int NL, int NT, int SIGN, bool LF, int TWS>
+struct StagesReversed {
+  __device__ static inline void run(C<T>* s, int ls, int es, const C<T>* tw) {
+    if constexpr (S >= 0) {
+      lds_stage<T, N, Plan<N>::r[S], N / StageP<N, S + 1>::value, NL, NT, SIGN,
+                LF, TWS>(s, ls, es, tw);
+      StagesReversed<T, N, S - 1, NL, NT, SIGN, LF, TWS>::run(s, ls, es, tw);
+    }
+  }
+};
+
 // NL length-N transforms in LDS.  Caller must __syncthreads() after filling
 // s; the call ends with a barrier.  The twiddle table holds the roots of a
 // length N * TWS transform.

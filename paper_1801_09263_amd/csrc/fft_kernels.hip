@@ -570,25 +570,65 @@ void k_zconv(C<T>* __restrict__ tmp,
     const int sl = m / NE1, r = m % NE1;
     return (sl * TX + r % TX) * LS + r / TX;
   };
+  // The forward transform's last stage (radix RL), the kernel multiply
+  // with the energy sum, and the inverse transform's first stage run in
+  // registers: the inverse takes the plan in reverse order, whose first
+  // stage (radix RL, no twiddles) reads exactly the RL outputs that a
+  // thread holds after the forward's last stage.
+  constexpr int NLN = SL * TX;                 // LDS lines
+  constexpr int NST = Plan<N>::nst;
+  constexpr int RL = Plan<N>::r[NST - 1];
+  constexpr int PL = N / RL;                   // butterflies per line
+  constexpr int BF = NLN * PL;
+  constexpr int NBF = (BF + NT - 1) / NT;
+  static_assert(NT % NLN == 0, "a thread keeps one line (one slot)");
+  const int line = threadIdx.x % NLN, col = line % TX, my_sl = line / TX;
   ProGrid<T> pro{g, 0};
   stage_in<T, NE, NT>(s, pro, 0, gidx, lds);
   __syncthreads();
-  lds_fft<T, N, SL * TX, NT, -1, true>(s, LS, 1, tw);
-  double e[SL];
+  StagesRange<T, N, 0, NST - 1, NLN, NT, -1, true, 1>::run(s, LS, 1, tw);
+  C<T> x[NBF][RL];
 #pragma unroll
-  for (int sl = 0; sl < SL; ++sl) e[sl] = 0.0;
-  for (int m = threadIdx.x; m < NE1; m += NT) {
-    const T v = vtab[zcol_index<N, TX>(tile, m)];
+  for (int b = 0; b < NBF; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if (BF % NT == 0 || idx < BF) {
+      const int i = idx / NLN;
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int q = lds(sl * NE1 + m);
-      const C<T> r = s[q];
-      e[sl] += double(v) * (double(r.x) * double(r.x) + double(r.y) * double(r.y));
-      s[q] = scl<T>(r, v);
+      for (int t = 0; t < RL; ++t) x[b][t] = s[line * LS + i + t * PL];
     }
   }
   __syncthreads();
-  lds_fft<T, N, SL * TX, NT, +1, true>(s, LS, 1, tw);
+  double e = 0.0;
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int idx = threadIdx.x + b * NT;
+    if (BF % NT == 0 || idx < BF) {
+      const int i = idx / NLN;
+      if (PL > 1) {   // twiddles of the forward's last stage (k = i < PL)
+#pragma unroll
+        for (int t = 1; t < RL; ++t) x[b][t] = mul<T>(x[b][t], tw[t * i]);
+      }
+      T vt[RL];   // kernel values at frequencies i + t PL of the z line
+#pragma unroll
+      for (int t = 0; t < RL; ++t)
+        vt[t] = vtab[zcol_index<N, TX>(tile, col + TX * (i + t * PL))];
+      Dft<RL, -1, T>::run(x[b]);
+      T eb = T(0);   // the butterfly's RL terms in the transform precision
+#pragma unroll
+      for (int t = 0; t < RL; ++t) {
+        const C<T> r = x[b][t];
+        const T v = vt[t];
+        eb += v * (r.x * r.x + r.y * r.y);
+        x[b][t] = scl<T>(r, v);
+      }
+      e += double(eb);   // partial sums accumulated in FP64
+      Dft<RL, +1, T>::run(x[b]);
+#pragma unroll
+      for (int t = 0; t < RL; ++t) s[line * LS + i * RL + t] = x[b][t];
+    }
+  }
+  __syncthreads();
+  StagesReversed<T, N, NST - 2, NLN, NT, +1, true, 1>::run(s, LS, 1, tw);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int mv = threadIdx.x + q * NT;
@@ -601,7 +641,7 @@ void k_zconv(C<T>* __restrict__ tmp,
   }
 #pragma unroll
   for (int sl = 0; sl < SL; ++sl) {
-    const double tot = block_sum<NT>(e[sl], red);
+    const double tot = block_sum<NT>(my_sl == sl ? e : 0.0, red);
     if (threadIdx.x == 0 && sl < nsl) {
       const int slot = slot0 + sl;
       const double wgt = ((pa.one_sided >> slot) & 1ull) ? 0.0
@@ -676,9 +716,10 @@ template <typename T, int N> struct Cfg {
   static constexpr int TXZ0 = 128 / (int)sizeof(C<T>);
   static constexpr int TXZ = (N * N) % TXZ0 == 0 ? TXZ0 : TX;
   static constexpr int NT_Z = (sizeof(T) == 4 && TXZ * SL * N >= 2048) ? 512 : 256;
-  // waves per SIMD to budget registers for: four 512-thread workgroups of
-  // 31 KiB LDS per CU at 120^3 FP32
-  static constexpr int W_Z = sizeof(T) == 4 ? 8 : 4;
+  // waves per SIMD to budget registers for: three 512-thread workgroups
+  // per CU in FP32 (80 VGPRs, what the fused radix-15 middle stage needs
+  // without spilling; measured faster than four with spills)
+  static constexpr int W_Z = sizeof(T) == 4 ? 6 : 4;
   // x pencils: TY rows
   static constexpr int TY = (N % 8 == 0) ? 8 : 4;
   static constexpr int NT_X = 256;
