@@ -389,6 +389,46 @@ def test_pair_passes_every_schedule(L, n, ecut, n_orb, prec, mode):
     s.close()
 
 
+# ------------------------------------ every supported grid size, pair passes
+_EVERY_SIZE = {}
+
+
+def _every_size_case(n):
+    """Cell of L = n/2 bohr, Ecut 4.5 Ha (sphere radius about n/4 grid
+    points), five real orthonormal orbitals; the oracle's plain-ACE path."""
+    if n not in _EVERY_SIZE:
+        L = n / 2.0
+        miller = synth.miller_sphere(L, 4.5)
+        assert np.abs(miller).max() < n / 2
+        coeffs = synth.virtual_orbitals(
+            miller, L, np.zeros((0, miller.shape[0]), complex), 5,
+            synth.rng_for(79, n))
+        _EVERY_SIZE[n] = (L, miller, coeffs, O.run_path(coeffs, miller, L, n))
+    return _EVERY_SIZE[n]
+
+
+@pytest.mark.parametrize("prec", [FP32G, FP32, FP64G],
+                         ids=["fp32g", "fp32", "fp64g"])
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 80, 96, 120])
+def test_pair_pipeline_every_grid_size(n, prec):
+    """Every supported grid through the pair passes against the oracle:
+    single-stage radix plans (8, 12), two-stage plans with the prime-factor
+    radices (48 = 4 x 12, 60 = 4 x 15, 80 = 8 x 10, 96 = 8 x 12,
+    120 = 8 x 15), and the z pass whose middle stage runs in registers;
+    complex and packed real orbitals (an odd count)."""
+    L, miller, coeffs, res = _every_size_case(n)
+    say(f"every size n={n} prec={prec}")
+    tol = TOL[prec]
+    s = CellSession(dict(L=L, n=n, miller=miller), coeffs.shape[0], prec)
+    s.set_orbitals(coeffs)
+    s.apply_exchange(0.0)
+    torch.cuda.synchronize()
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(
+        res["ex_pairs"])
+    s.close()
+
+
 # ------------------------- two-stream batch pipeline = one stream, bitwise
 @pytest.mark.parametrize("prec", [FP32, FP32G, FP64G], ids=["fp32", "fp32g", "fp64g"])
 def test_overlapped_batches_match_one_stream(prec):
