@@ -316,15 +316,24 @@ hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
 // Workgroup 256 threads: 64 rows m (one 16-row block per wave) x 64
 // columns b (4 MFMA tiles per wave).  X is read straight from global
 // memory (16 consecutive m per k row per wave), Z is small and cached.
+// The operands of the next 4-wide k step are loaded before the current
+// step's MFMAs.  The flat workgroup id is remapped so that the column
+// blocks of one row block run back to back on one XCD and share its
+// rows of X in that XCD's L2.
 // ------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gemm_tall(const double2* X,
                                                    int64_t ldx, int64_t M,
                                                    int nk, const double2* Z,
                                                    int nb, double2* Y,
-                                                   int64_t ldy) {
+                                                   int64_t ldy, int nbb) {
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
-  const int64_t m0 = (int64_t)blockIdx.x * 64 + w * 16;
-  const int b0 = blockIdx.y * 64;
+  // XCD-aware remap of the flat id: XCD x (ids x, x + 8, ...) takes the
+  // logical range [x per, (x + 1) per); a ragged tail keeps its id
+  const int total = gridDim.x, per = total / 8;
+  const int bid = blockIdx.x;
+  const int lg = bid < per * 8 ? (bid % 8) * per + bid / 8 : bid;
+  const int64_t m0 = (int64_t)(lg / nbb) * 64 + w * 16;
+  const int b0 = (lg % nbb) * 64;
   d4 accR[4], accI[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -332,19 +341,31 @@ __global__ __launch_bounds__(256) void k_gemm_tall(const double2* X,
     accI[q] = d4{0, 0, 0, 0};
   }
   const int64_t m = m0 + lane % 16;
-  for (int k0 = 0; k0 < nk; k0 += 4) {
+  double2 xn, zn[4];
+  auto fetch = [&](int k0) {
     const int k = k0 + lane / 16;
-    double2 x = make_double2(0.0, 0.0);
-    if (k < nk && m < M) x = X[(int64_t)k * ldx + m];
+    xn = make_double2(0.0, 0.0);
+    if (k < nk && m < M) xn = X[(int64_t)k * ldx + m];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int b = b0 + q * 16 + lane % 16;
-      double2 z = make_double2(0.0, 0.0);
-      if (k < nk && b < nb) z = Z[(int64_t)k * nb + b];
-      accR[q] = mfma(x.x, z.x, accR[q]);
-      accR[q] = mfma(-x.y, z.y, accR[q]);
-      accI[q] = mfma(x.x, z.y, accI[q]);
-      accI[q] = mfma(x.y, z.x, accI[q]);
+      zn[q] = make_double2(0.0, 0.0);
+      if (k < nk && b < nb) zn[q] = Z[(int64_t)k * nb + b];
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < nk; k0 += 4) {
+    const double2 x = xn;
+    double2 z[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) z[q] = zn[q];
+    if (k0 + 4 < nk) fetch(k0 + 4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      accR[q] = mfma(x.x, z[q].x, accR[q]);
+      accR[q] = mfma(-x.y, z[q].y, accR[q]);
+      accI[q] = mfma(x.x, z[q].y, accI[q]);
+      accI[q] = mfma(x.y, z[q].x, accI[q]);
     }
   }
 #pragma unroll
@@ -362,11 +383,13 @@ __global__ __launch_bounds__(256) void k_gemm_tall(const double2* X,
 hipError_t launch_gemm_tall(const void* X, int64_t ldx, int64_t M, int nk,
                             const void* Z, int nb, void* Y, int64_t ldy,
                             hipStream_t st) {
-  dim3 grid((unsigned)((M + 63) / 64), (nb + 63) / 64);
-  hipLaunchKernelGGL(k_gemm_tall, grid, dim3(256), 0, st,
+  const int nbb = (nb + 63) / 64;
+  const int64_t blocks = ((M + 63) / 64) * nbb;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const double2*>(X), ldx, M, nk,
                      static_cast<const double2*>(Z), nb,
-                     static_cast<double2*>(Y), ldy);
+                     static_cast<double2*>(Y), ldy, nbb);
   return hipGetLastError();
 }
 
