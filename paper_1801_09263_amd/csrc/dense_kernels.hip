@@ -315,17 +315,21 @@ hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
 // Tall GEMM  Y[b][m] = sum_k X[k][m] Z[k][b]  (complex, no conjugation).
 // Workgroup 256 threads: 64 rows m (one 16-row block per wave) x 64
 // columns b (4 MFMA tiles per wave).  X is read straight from global
-// memory (16 consecutive m per k row per wave), Z is small and cached.
-// The operands of the next 4-wide k step are loaded before the current
-// step's MFMAs.  The flat workgroup id is remapped so that the column
+// memory (16 consecutive m per k row per wave); the workgroup's columns of
+// Z are staged through LDS in chunks of TALL_KC k, read once per
+// workgroup instead of once per wave.  The next chunk's X and Z are
+// loaded before the current chunk's MFMAs.  The flat workgroup id is remapped so that the column
 // blocks of one row block run back to back on one XCD and share its
 // rows of X in that XCD's L2.
 // ------------------------------------------------------------------
+constexpr int TALL_KC = 16;
 __global__ __launch_bounds__(256) void k_gemm_tall(const double2* X,
                                                    int64_t ldx, int64_t M,
                                                    int nk, const double2* Z,
                                                    int nb, double2* Y,
                                                    int64_t ldy, int nbb) {
+  // Z chunk [TALL_KC][64] in LDS, rows padded by one element
+  __shared__ double2 zs[TALL_KC][64 + 1];
   const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
   // XCD-aware remap of the flat id: XCD x (ids x, x + 8, ...) takes the
   // logical range [x per, (x + 1) per); a ragged tail keeps its id
@@ -341,32 +345,48 @@ __global__ __launch_bounds__(256) void k_gemm_tall(const double2* X,
     accI[q] = d4{0, 0, 0, 0};
   }
   const int64_t m = m0 + lane % 16;
-  double2 xn, zn[4];
+  constexpr int ZPT = TALL_KC * 64 / 256;   // Z elements per thread and chunk
+  double2 xn[TALL_KC / 4], zn[ZPT];
   auto fetch = [&](int k0) {
-    const int k = k0 + lane / 16;
-    xn = make_double2(0.0, 0.0);
-    if (k < nk && m < M) xn = X[(int64_t)k * ldx + m];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = b0 + q * 16 + lane % 16;
-      zn[q] = make_double2(0.0, 0.0);
-      if (k < nk && b < nb) zn[q] = Z[(int64_t)k * nb + b];
+    for (int s4 = 0; s4 < TALL_KC / 4; ++s4) {
+      const int k = k0 + s4 * 4 + lane / 16;
+      xn[s4] = make_double2(0.0, 0.0);
+      if (k < nk && m < M) xn[s4] = X[(int64_t)k * ldx + m];
+    }
+#pragma unroll
+    for (int e = 0; e < ZPT; ++e) {
+      const int idx = tid + e * 256, kk = idx / 64, bb = idx % 64;
+      const int k = k0 + kk, b = b0 + bb;
+      zn[e] = make_double2(0.0, 0.0);
+      if (k < nk && b < nb) zn[e] = Z[(int64_t)k * nb + b];
     }
   };
   fetch(0);
-  for (int k0 = 0; k0 < nk; k0 += 4) {
-    const double2 x = xn;
-    double2 z[4];
+  for (int k0 = 0; k0 < nk; k0 += TALL_KC) {
+    double2 x[TALL_KC / 4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) z[q] = zn[q];
-    if (k0 + 4 < nk) fetch(k0 + 4);
+    for (int s4 = 0; s4 < TALL_KC / 4; ++s4) x[s4] = xn[s4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      accR[q] = mfma(x.x, z[q].x, accR[q]);
-      accR[q] = mfma(-x.y, z[q].y, accR[q]);
-      accI[q] = mfma(x.x, z[q].y, accI[q]);
-      accI[q] = mfma(x.y, z[q].x, accI[q]);
+    for (int e = 0; e < ZPT; ++e) {
+      const int idx = tid + e * 256;
+      zs[idx / 64][idx % 64] = zn[e];
     }
+    __syncthreads();
+    if (k0 + TALL_KC < nk) fetch(k0 + TALL_KC);
+#pragma unroll
+    for (int s4 = 0; s4 < TALL_KC / 4; ++s4) {
+      const int kk = s4 * 4 + lane / 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 z = zs[kk][q * 16 + lane % 16];
+        accR[q] = mfma(x[s4].x, z.x, accR[q]);
+        accR[q] = mfma(-x[s4].y, z.y, accR[q]);
+        accI[q] = mfma(x[s4].x, z.y, accI[q]);
+        accI[q] = mfma(x[s4].y, z.x, accI[q]);
+      }
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
