@@ -376,7 +376,7 @@ def pmc_sample(torch, seed):
     y.copy_(x)
     torch.cuda.synchronize()
     del x, y
-    inp = synth.make_config_inputs(2, seed=seed)
+    inp = synth.make_inputs("lace-120", seed=seed)
     n_orb = inp["coeffs"].shape[0]
     sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA)
     sess.set_orbitals(inp["coeffs"])
@@ -431,7 +431,7 @@ def main():
     inp = cpu = None
     if not args.pmc_sample:
         log("generating the localized 120^3 workload")
-        inp = synth.make_config_inputs(2, seed=args.seed)
+        inp = synth.make_inputs("lace-120", seed=args.seed)
         if not args.no_cpu:
             # before torch and the GPU: the oracle's workers are forked
             log("CPU oracle sample")
@@ -573,7 +573,7 @@ def main():
         del s3
         torch.cuda.empty_cache()
         log("plain unscreened 120^3 random orbitals (FP64 and FP32 pairs)")
-        inp1 = synth.make_config_inputs(1, seed=args.seed)
+        inp1 = synth.make_inputs("plain-ace-120", seed=args.seed)
         for name, prec in (("plain_fp64", lace.LACE_FP64),
                            ("plain_fp32", lace.LACE_FP32)):
             s1 = CellSession(inp1, n_orb, prec, n_vec=n_orb)

@@ -6,14 +6,14 @@ none of the exchange arithmetic, and both the CPU oracle and the GPU path
 consume what it produces.
 """
 from .generators import (  # noqa: F401
-    CONFIGS,
+    WORKLOADS,
     BATCH_CLASSES,
     rng_for,
     miller_sphere,
     random_orbitals,
     gaussian_orbitals,
     virtual_orbitals,
-    make_config_inputs,
+    make_inputs,
     make_batch_cells,
     perturb_gaussian_params,
     gaussian_params,

@@ -1,7 +1,7 @@
 """Seeded generators for the synthetic workloads.
 
-Every random draw goes through ``rng_for(config, cell, job, step, seed)`` so
-that a given (config, cell, job, step, seed) tuple always yields the same
+Every random draw goes through ``rng_for(stream, cell, job, step, seed)`` so
+that a given (stream, cell, job, step, seed) tuple always yields the same
 arrays.  Coefficient arrays are returned orbital-major: shape
 ``(n_orb, n_pw)``, C-contiguous complex128, i.e. the column-major
 ``n_pw x n_orb`` matrix whose column ``j`` holds orbital ``j``.
@@ -18,14 +18,15 @@ from __future__ import annotations
 
 import numpy as np
 
-# Workload definitions (sizes in bohr / Hartree).
-CONFIGS = {
-    0: dict(name="plain-ace-24", L=10.0, n=24, ecut=15.0, n_orb=8,
-            kind="random", s_thr=0.0),
-    1: dict(name="plain-ace-120", L=23.5, n=120, ecut=40.0, n_orb=256,
-            kind="random", s_thr=0.0),
-    2: dict(name="lace-120", L=23.5, n=120, ecut=40.0, n_orb=256,
-            kind="gaussian", n_centers=128, s_thr=1e-3),
+# Single-cell workloads by name (sizes in bohr / Hartree); `stream` selects
+# the workload's own random stream.
+WORKLOADS = {
+    "plain-ace-24": dict(stream=0, L=10.0, n=24, ecut=15.0, n_orb=8,
+                         kind="random", s_thr=0.0),
+    "plain-ace-120": dict(stream=1, L=23.5, n=120, ecut=40.0, n_orb=256,
+                          kind="random", s_thr=0.0),
+    "lace-120": dict(stream=2, L=23.5, n=120, ecut=40.0, n_orb=256,
+                     kind="gaussian", n_centers=128, s_thr=1e-3),
 }
 # Batched multi-cell workload: (L, n, n_orb); 4 cells of each class.
 BATCH_CLASSES = [(12.0, 48, 32), (16.0, 64, 64), (20.0, 80, 96), (24.0, 96, 128)]
@@ -33,11 +34,11 @@ BATCH_ECUT = 40.0
 BATCH_S_THR = 1e-3
 
 
-def rng_for(config: int, cell: int = 0, job: int = 0, step: int = 0,
+def rng_for(stream: int, cell: int = 0, job: int = 0, step: int = 0,
             seed: int = 0) -> np.random.Generator:
-    """Independent stream per (config, cell, job, step, seed)."""
+    """Independent stream per (stream, cell, job, step, seed)."""
     return np.random.default_rng(
-        np.random.SeedSequence([int(config), int(cell), int(job), int(step),
+        np.random.SeedSequence([int(stream), int(cell), int(job), int(step),
                                 int(seed)]))
 
 
@@ -184,19 +185,19 @@ def perturb_gaussian_params(pos: np.ndarray, widths: np.ndarray,
     return pos + dp, widths * dw
 
 
-def make_config_inputs(config: int, seed: int = 0, cell: int = 0):
-    """Inputs of a single-cell workload: dict with L, n, ecut, miller,
-    coeffs (n_orb, n_pw), s_thr, rc."""
-    cfg = CONFIGS[config]
+def make_inputs(name: str, seed: int = 0, cell: int = 0):
+    """Inputs of the single-cell workload `name` (a key of WORKLOADS): dict
+    with name, L, n, ecut, miller, coeffs (n_orb, n_pw), s_thr, rc."""
+    cfg = WORKLOADS[name]
     L, n, ecut = cfg["L"], cfg["n"], cfg["ecut"]
     miller = miller_sphere(L, ecut)
-    rng = rng_for(config, cell, 0, 0, seed)
+    rng = rng_for(cfg["stream"], cell, 0, 0, seed)
     if cfg["kind"] == "random":
         coeffs = random_orbitals(miller, L, cfg["n_orb"], rng)
     else:
         coeffs = gaussian_orbitals(miller, L, cfg["n_orb"], cfg["n_centers"],
                                    rng)
-    return dict(name=cfg["name"], L=L, n=n, ecut=ecut, miller=miller,
+    return dict(name=name, L=L, n=n, ecut=ecut, miller=miller,
                 coeffs=coeffs, s_thr=cfg["s_thr"], rc=L / 2.0)
 
 

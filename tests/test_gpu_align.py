@@ -48,7 +48,7 @@ def run_align(cell, new, old, prec=lace.LACE_FP64):
 
 @pytest.fixture(scope="module")
 def small():
-    inp = synth.make_config_inputs(0)
+    inp = synth.make_inputs("plain-ace-24")
     return dict(L=inp["L"], n=inp["n"], miller=inp["miller"]), inp["coeffs"]
 
 

@@ -35,13 +35,13 @@ def say(*a):
 @pytest.fixture(scope="module")
 def lace120():
     say("generating localized 120^3 inputs")
-    return synth.make_config_inputs(2)
+    return synth.make_inputs("lace-120")
 
 
 @pytest.fixture(scope="module")
 def plain120():
     say("generating plain 120^3 inputs")
-    return synth.make_config_inputs(1)
+    return synth.make_inputs("plain-ace-120")
 
 
 def sampled_pair_parity(inp, prec, tol):

@@ -158,7 +158,7 @@ def test_cholesky_and_projector_on_known_matrix():
 # --------------------------------------------------- 24^3 plain ACE (c0)
 @pytest.fixture(scope="module")
 def c0():
-    inp = synth.make_config_inputs(0)
+    inp = synth.make_inputs("plain-ace-24")
     res = O.run_path(inp["coeffs"], inp["miller"], inp["L"], inp["n"])
     return inp, res
 

@@ -93,7 +93,7 @@ def test_scdm_against_oracle(mixed, prec):
 
 
 def test_scdm_complex_orbitals_fp64():
-    inp = synth.make_config_inputs(0)
+    inp = synth.make_inputs("plain-ace-24")
     cell = dict(L=inp["L"], n=inp["n"], miller=inp["miller"])
     phi, pts, resid = run_scdm(cell, inp["coeffs"], FP64)
     psi = O.orbitals_on_grid(inp["coeffs"], inp["miller"], inp["L"], inp["n"])
@@ -107,7 +107,7 @@ def test_scdm_full_size_relocalizes():
     S_ij fall back to those of a localized set (SCDM orbitals carry the
     orthonormalization tails of density-matrix columns, so they are not as
     compact as the analytic Gaussians)."""
-    inp = synth.make_config_inputs(2)
+    inp = synth.make_inputs("lace-120")
     cell = {k: inp[k] for k in ("L", "n", "miller")}
     loc = inp["coeffs"]
     v, _ = np.linalg.qr(np.random.default_rng(74).standard_normal((256, 256)))

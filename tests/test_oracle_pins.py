@@ -61,7 +61,7 @@ def gauss_self_coulomb(tau, rc):
 
 @pytest.fixture(scope="module")
 def c0():
-    inp = synth.make_config_inputs(0)
+    inp = synth.make_inputs("plain-ace-24")
     res = O.run_path(inp["coeffs"], inp["miller"], inp["L"], inp["n"],
                      want_grid=True)
     return inp, res
@@ -428,7 +428,7 @@ def test_localized_generator_orthonormal_real(localized):
 
 # ------------------------------------------------- planted mistakes bite
 def _c0_small():
-    inp = synth.make_config_inputs(0)
+    inp = synth.make_inputs("plain-ace-24")
     return inp["coeffs"][:4], inp["miller"], inp["L"], inp["n"]
 
 
