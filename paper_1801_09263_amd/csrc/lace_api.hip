@@ -75,6 +75,7 @@ struct lace_plan {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;   // fork/join events, no timing
   hipStream_t origin = nullptr;     // capture stream of the batched call
+  hipEvent_t s_ready = nullptr;     // screened exchange: S copied to the host
   GraphCache graph;
 };
 
@@ -328,17 +329,28 @@ static Slot make_slot(const std::vector<std::pair<int, int>>& pairs, int a,
 // Trail decomposition of the off-diagonal pairs `edges`: consecutive pairs
 // of each walk become star slots, the last pair of an odd walk goes to
 // `left`.  Walks start at orbitals with an odd number of unused pairs.
+// Adjacency buffers of trail_slots, reused across its calls.
+struct TrailWork {
+  std::vector<int> off, rem, cur, adj;
+};
+
 static void trail_slots(const std::vector<std::pair<int, int>>& pairs,
                         const std::vector<int>& edges, int n_orb,
                         std::vector<char>& done, std::vector<Slot>& slots,
-                        std::vector<int>& left) {
-  std::vector<int> off(n_orb + 1, 0), rem(n_orb, 0);
+                        std::vector<int>& left, TrailWork& tw) {
+  std::vector<int>& off = tw.off;
+  std::vector<int>& rem = tw.rem;
+  std::vector<int>& cur = tw.cur;
+  std::vector<int>& adj = tw.adj;
+  off.assign(n_orb + 1, 0);
+  rem.resize(n_orb);
   for (int e : edges) {
     ++off[pairs[e].first + 1];
     ++off[pairs[e].second + 1];
   }
   for (int v = 0; v < n_orb; ++v) off[v + 1] += off[v];
-  std::vector<int> adj(off[n_orb]), cur(off.begin(), off.end() - 1);
+  adj.resize(off[n_orb]);
+  cur.assign(off.begin(), off.end() - 1);
   for (int e : edges)
     for (int v : {pairs[e].first, pairs[e].second}) adj[cur[v]++] = e;
   for (int v = 0; v < n_orb; ++v) {
@@ -377,17 +389,24 @@ static void star_slots(const std::vector<std::pair<int, int>>& pairs,
                        std::vector<Slot>& slots) {
   const int nv = n_orb + (n_orb & 1);
   std::vector<int> round(pairs.size(), 0), left, rest, group;
-  for (int k : off) round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
-  std::stable_sort(off.begin(), off.end(),
-                   [&](int a, int b) { return round[a] < round[b]; });
+  // stable counting sort of the pairs by round (rounds are < nv)
+  std::vector<int> start(nv + 1, 0), sorted(off.size());
+  for (int k : off) {
+    round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
+    ++start[round[k] + 1];
+  }
+  for (int r = 0; r < nv; ++r) start[r + 1] += start[r];
+  for (int k : off) sorted[start[round[k]]++] = k;
+  off.swap(sorted);
+  TrailWork tw;
   for (size_t a = 0; a < off.size();) {
     const int g = round[off[a]] / 2;
     group.clear();
     while (a < off.size() && round[off[a]] / 2 == g) group.push_back(off[a++]);
-    trail_slots(pairs, group, n_orb, done, slots, left);
+    trail_slots(pairs, group, n_orb, done, slots, left, tw);
   }
   for (int e : left) done[e] = 0;
-  trail_slots(pairs, left, n_orb, done, slots, rest);
+  trail_slots(pairs, left, n_orb, done, slots, rest, tw);
   for (size_t t = 0; t < rest.size(); t += 2)
     slots.push_back(make_slot(pairs, rest[t],
                               t + 1 < rest.size() ? rest[t + 1] : -1));
@@ -689,6 +708,7 @@ int lace_plan_destroy(lace_plan* p) {
   if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
   if (p->graph.graph) (void)hipGraphDestroy(p->graph.graph);
   for (auto ev : p->events) (void)hipEventDestroy(ev);
+  if (p->s_ready) (void)hipEventDestroy(p->s_ready);
   for (auto st : p->streams) (void)hipStreamDestroy(st);
   if (p->origin) (void)hipStreamDestroy(p->origin);
   delete p;
@@ -854,18 +874,28 @@ static hipError_t link(lace_plan* p, hipStream_t from, hipStream_t to, int k);
 // lane b % 2): a batch's passes A and B overlap the previous batch's passes,
 // and its pass C waits for the previous pass C (they may share W grids), so
 // W is summed in batch order either way.  Profiled calls run on one stream.
+// W and the energy partials start at zero.
+static hipError_t enqueue_exchange_zero(const lace_plan* p, const CellDev& c,
+                                        int n_orb, const Layout& L, void* ws,
+                                        hipStream_t st) {
+  const int64_t ntiles = energy_tiles(c.n, p->fp64);
+  hipError_t e = launch_zero(at(ws, L.w), (int64_t)c.ng * n_orb * orb_bytes(p), st);
+  if (e == hipSuccess)
+    e = launch_zero(at(ws, L.epart), (int64_t)sizeof(double) * PMAX * 2 * ntiles, st);
+  return e;
+}
+
+// zeroed: the caller has already enqueued enqueue_exchange_zero on st.
 static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
                                    const std::vector<Batch>& sched,
                                    const Layout& L, void* ws, void* w_g,
                                    double* e_x, hipStream_t st, bool profile,
-                                   bool overlap = false) {
+                                   bool overlap = false, bool zeroed = false) {
   const bool fp64 = p->fp64;
   void* w = at(ws, L.w);
   const int64_t ntiles = energy_tiles(c.n, fp64);
   double* epart = reinterpret_cast<double*>(at(ws, L.epart));
-  hipError_t e = launch_zero(w, (int64_t)c.ng * n_orb * orb_bytes(p), st);
-  if (e == hipSuccess)
-    e = launch_zero(epart, (int64_t)sizeof(double) * PMAX * 2 * ntiles, st);
+  hipError_t e = zeroed ? hipSuccess : enqueue_exchange_zero(p, c, n_orb, L, ws, st);
   Profile& pr = p->prof;
   const bool timed = profile && pr.on;
   const bool two = overlap && !timed && sched.size() > 1;
@@ -966,6 +996,7 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e != hipSuccess) return LACE_EHIP;
+  bool zeroed = false;
   if (!pair_i) {
     if (s_thr > 0.0) {
       double* s = reinterpret_cast<double*>(at(ws, L.s));
@@ -974,8 +1005,15 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
       std::vector<double> hs((size_t)n_orb * n_orb);
       e = hipMemcpyAsync(hs.data(), s, sizeof(double) * hs.size(),
                          hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e == hipSuccess && !p->s_ready)
+        e = hipEventCreateWithFlags(&p->s_ready, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(p->s_ready, st);
+      // the device clears W while the host builds the pair list and the
+      // schedule
+      if (e == hipSuccess) e = enqueue_exchange_zero(p, c, n_orb, L, ws, st);
+      if (e == hipSuccess) e = hipEventSynchronize(p->s_ready);
       if (e != hipSuccess) return LACE_EHIP;
+      zeroed = true;
       kept_from_s(hs, n_orb, s_thr, pairs);
     } else {
       all_pairs(n_orb, pairs);
@@ -983,7 +1021,8 @@ int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
   }
   std::vector<Batch> sched;
   schedule_for(p, pairs, n_orb, c.ppb, sched);
-  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true, true);
+  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true, true,
+                       zeroed);
   if (e != hipSuccess) return LACE_EHIP;
   if (n_kept) *n_kept = (int64_t)pairs.size();
   return LACE_OK;
