@@ -429,6 +429,33 @@ def test_pair_pipeline_every_grid_size(n, prec):
     s.close()
 
 
+# ---------------------- screening product over several (ragged) tiles
+@pytest.mark.parametrize("prec", [FP64, FP32, FP64G, FP32G],
+                         ids=["fp64", "fp32", "fp64g", "fp32g"])
+def test_screening_matrix_ragged_tiles(prec):
+    """S = dV |psi|^T |psi| with 150 orbitals: three 64-wide tiles per side,
+    the last one ragged, of which only those on and above the diagonal are
+    computed and the rest mirrored; complex and real grids."""
+    L, n, n_orb = 10.0, 24, 150
+    miller = synth.miller_sphere(L, 15.0)
+    rng = synth.rng_for(81, n)
+    if prec in (FP64G, FP32G):
+        coeffs = synth.virtual_orbitals(
+            miller, L, np.zeros((0, miller.shape[0]), complex), n_orb, rng)
+    else:
+        coeffs = synth.random_orbitals(miller, L, n_orb, rng)
+    psi = O.orbitals_on_grid(coeffs, miller, L, n)
+    ref = O.overlap_of_moduli(psi, L)
+    say(f"screening n_orb={n_orb} prec={prec}")
+    sess = CellSession(dict(L=L, n=n, miller=miller), n_orb, prec)
+    sess.set_orbitals(coeffs)
+    got = sess.screen().cpu().numpy()
+    torch.cuda.synchronize()
+    sess.close()
+    assert np.array_equal(got, got.T)
+    assert rel(got, ref) <= TOL[prec]["s"]
+
+
 # ------------------------- two-stream batch pipeline = one stream, bitwise
 @pytest.mark.parametrize("prec", [FP32, FP32G, FP64G], ids=["fp32", "fp32g", "fp64g"])
 def test_overlapped_batches_match_one_stream(prec):
