@@ -486,6 +486,13 @@ __device__ inline int col_index(int tile, int m) {
   const int x = xt * TX + xx;
   return AXIS == 1 ? x + N * (e + N * f) : x + N * (f + N * e);
 }
+// z pencils: a tile is TX consecutive points of the flattened xy plane
+// (x + N y), so each z row of a tile is TX contiguous points even where TX
+// does not divide N.
+template <int N, int TX>
+__device__ inline int zcol_index(int tile, int m) {
+  return tile * TX + m % TX + N * N * (m / TX);
+}
 template <int N, int TX>
 __device__ inline int col_lds(int m) {
   return (m % TX) * Pad<N>::LS + m / TX;
@@ -500,13 +507,18 @@ __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
   constexpr int LS = Pad<N>::LS;
   __shared__ C<T> s[TX * LS];
   __shared__ C<T> tw[N];
-  constexpr int NTILES = N * (N / TX);
+  // y pencils: TX adjacent x of one row; z pencils: flattened xy tiles
+  constexpr int NTILES = AXIS == 2 ? N * N / TX : N * (N / TX);
+  static_assert(AXIS == 2 ? (N * N) % TX == 0 : N % TX == 0, "tile width");
   static_assert(TX % Pro::V == 0 && TX % Epi::V == 0,
                 "vectors must not cross a tile row");
   const int lg = xcd_logical(blockIdx.x, NTILES * nslots);
   const int tile = lg / nslots, slot = lg % nslots;
   load_tw<T, N, NT>(tw, tw_g);
-  auto idx = [tile](int m) { return col_index<N, AXIS, TX>(tile, m); };
+  auto idx = [tile](int m) {
+    if constexpr (AXIS == 2) return zcol_index<N, TX>(tile, m);
+    else return col_index<N, AXIS, TX>(tile, m);
+  };
   auto lds = [](int m) { return col_lds<N, TX>(m); };
   stage_in<T, TX * N, NT>(s, pro, slot, idx, lds);
   __syncthreads();
@@ -535,10 +547,6 @@ __device__ inline double block_sum(double v, double* red) {
 // y), so that each z row of a tile is one whole 128-byte line even when TX
 // does not divide N.  Slots past the end of the batch load slot 0
 // (discarded) and are neither stored nor summed.
-template <int N, int TX>
-__device__ inline int zcol_index(int tile, int m) {
-  return tile * TX + m % TX + N * N * (m / TX);
-}
 template <typename T, int N, int TX, int SL, int NT, int MINW>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_zconv(C<T>* __restrict__ tmp,
@@ -720,6 +728,10 @@ template <typename T, int N> struct Cfg {
   // per CU in FP32 (80 VGPRs, what the fused radix-15 middle stage needs
   // without spilling; measured faster than four with spills)
   static constexpr int W_Z = sizeof(T) == 4 ? 6 : 4;
+  // z pencils of the 3D transforms: 256 bytes of complex points per z row
+  // (128 bytes of each real grid when the last pass splits into real grids)
+  static constexpr int TXC20 = 256 / (int)sizeof(C<T>);
+  static constexpr int TXC2 = (N * N) % TXC20 == 0 ? TXC20 : TXZ;
   // x pencils: TY rows
   static constexpr int TY = (N % 8 == 0) ? 8 : 4;
   static constexpr int NT_X = 256;
@@ -764,9 +776,11 @@ template <typename T, int N> struct Engine {
   template <int AXIS, int SIGN, class Pro, class Epi>
   static hipError_t cols(Pro p, Epi e, int count, const C<T>* tw,
                          hipStream_t st) {
-    hipLaunchKernelGGL((k_cols<T, N, AXIS, Cf::TX, Cf::NT_COLS, SIGN, Pro, Epi>),
-                       dim3(N * (N / Cf::TX) * count), dim3(Cf::NT_COLS), 0,
-                       st, p, e, tw, count);
+    constexpr int TXC = AXIS == 2 ? Cf::TXC2 : Cf::TX;
+    constexpr int ntiles = AXIS == 2 ? N * N / TXC : N * (N / TXC);
+    hipLaunchKernelGGL((k_cols<T, N, AXIS, TXC, Cf::NT_COLS, SIGN, Pro, Epi>),
+                       dim3(ntiles * count), dim3(Cf::NT_COLS), 0, st, p, e,
+                       tw, count);
     return hipGetLastError();
   }
 
