@@ -786,15 +786,19 @@ template <typename T, int N> struct Engine {
 
   // Transform of `count` grids held in g between the passes: the first
   // pass reads through `first`, the last one (z) writes through `last`.
+  // oop: `first` reads memory other than g, so the first pass may take the
+  // half-plane form (in place, its two workgroups of a plane would
+  // overwrite rows that the other one still reads).
   template <int SIGN, class ProF, class EpiL>
   static hipError_t fft3d_io(ProF first, EpiL last, C<T>* g, int count,
-                             const C<T>* tw, int mode, hipStream_t st) {
+                             const C<T>* tw, int mode, hipStream_t st,
+                             bool oop = false) {
     ProGrid<T> p{g, NG};
     EpiGrid<T> e1{g, NG, T(1)};
     hipError_t err;
-    // In place, so never the half-plane form: its two workgroups of a plane
-    // would overwrite rows that the other one still reads.
-    if (Cf::plane && mode != 0) {
+    if (oop && mode == 2) {
+      err = half<SIGN>(first, e1, count, tw, st);
+    } else if (Cf::plane && mode != 0) {
       err = plane<SIGN>(first, e1, count, tw, st);
     } else {
       err = xlines<SIGN>(first, e1, count, tw, st);
@@ -810,18 +814,20 @@ template <typename T, int N> struct Engine {
     return fft3d_io<SIGN>(ProGrid<T>{g, NG}, EpiGrid<T>{g, NG, scale}, g,
                           count, tw, mode, st);
   }
-  // real grids to packed pairs: inverse transform, split into 2 real grids
-  static hipError_t to_real(C<T>* g, int count, T scale, T* psi, int n_real,
-                            const C<T>* tw, int mode, hipStream_t st) {
-    return fft3d_io<+1>(ProGrid<T>{g, NG},
+  // packed pairs in src to real grids: inverse transform through g (a
+  // buffer apart from src), split into 2 real grids per pair in psi
+  static hipError_t to_real(const C<T>* src, C<T>* g, int count, T scale,
+                            T* psi, int n_real, const C<T>* tw, int mode,
+                            hipStream_t st) {
+    return fft3d_io<+1>(ProGrid<T>{src, NG},
                         EpiSplitReal<T>{psi, NG, n_real, scale}, g, count, tw,
-                        mode, st);
+                        mode, st, true);
   }
   // packed pairs of real grids: forward transform into g
   static hipError_t from_real(const T* w, int n_real, C<T>* g, int count,
                               const C<T>* tw, int mode, hipStream_t st) {
     return fft3d_io<-1>(ProPackReal<T>{w, NG, n_real},
-                        EpiGrid<T>{g, NG, T(1)}, g, count, tw, mode, st);
+                        EpiGrid<T>{g, NG, T(1)}, g, count, tw, mode, st, true);
   }
 
   static hipError_t pair_batch(const CellDev& c, const PairArgs& pa,
@@ -1151,12 +1157,16 @@ template <typename T>
 static hipError_t orb_to_grid_real_t(const CellDev& c, const void* coeffs,
                                      int n_orb, void* psi, void* scratch,
                                      hipStream_t st) {
+  // the packed coefficients go to the psi buffer (npair complex grids, the
+  // bytes of n_orb real ones), are transformed through scratch, and come
+  // back to psi as real grids
   const int npair = (n_orb + 1) / 2;
-  hipError_t err = launch_zero(scratch, (int64_t)npair * c.ng * sizeof(C<T>), st);
+  C<T>* zin = static_cast<C<T>*>(psi);
+  hipError_t err = launch_zero(zin, (int64_t)npair * c.ng * sizeof(C<T>), st);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_scatter_pairs<T>), dim3(grid_for(c.n_pw * npair)),
                      dim3(256), 0, st, static_cast<const double2*>(coeffs),
-                     c.n_pw, c.gidx, static_cast<C<T>*>(scratch), c.ng, n_orb);
+                     c.n_pw, c.gidx, zin, c.ng, n_orb);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   const T scale = T(1.0 / std::sqrt(c.omega));
   C<T>* z = static_cast<C<T>*>(scratch);
@@ -1165,7 +1175,7 @@ static hipError_t orb_to_grid_real_t(const CellDev& c, const void* coeffs,
   switch (c.n) {
 #define X(NN)                                                               \
   case NN:                                                                  \
-    return Engine<T, NN>::to_real(z, npair, scale, out, n_orb, tw,          \
+    return Engine<T, NN>::to_real(zin, z, npair, scale, out, n_orb, tw,     \
                                   c.use_plane, st);
     LACE_SIZES(X)
 #undef X

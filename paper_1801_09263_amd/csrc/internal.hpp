@@ -81,7 +81,9 @@ hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
                                    hipStream_t st, hipEvent_t* ev);
 // ---- real (Gamma-point) orbitals: real grids, packed complex transforms
 // psi_real (n_orb real grids) <- real parts of Omega^{-1/2} B[C]; two
-// orbitals per complex transform in `scratch` (ceil(n_orb/2) complex grids).
+// orbitals per complex transform.  psi_real must hold ceil(n_orb/2) complex
+// grids (it first receives the packed coefficients); the transform passes
+// through `scratch` (as many complex grids, apart from psi_real).
 hipError_t launch_orbitals_to_grid_real(const CellDev& c, bool fp64,
                                         const void* coeffs, int n_orb,
                                         void* psi_real, void* scratch,
