@@ -293,6 +293,51 @@ def test_explicit_pairs_rejected_when_invalid(c0):
     s.close()
 
 
+@pytest.mark.parametrize("prec", [FP32, lace.LACE_FP32_GAMMA],
+                         ids=["fp32", "fp32g"])
+def test_argument_errors(prec):
+    """Short workspaces, thresholds outside [0, 1), a cell that does not
+    exist and an empty orbital set are rejected before any device work; the
+    session stays usable and then gives the oracle's W (real orbitals, so
+    that both the complex and the real-orbital plans apply)."""
+    L, n, n_orb = 10.0, 24, 8
+    miller = synth.miller_sphere(L, 15.0)
+    coeffs = synth.virtual_orbitals(
+        miller, L, np.zeros((0, miller.shape[0]), complex), n_orb,
+        synth.rng_for(82, n))
+    res = O.run_path(coeffs, miller, L, n)
+    inp = dict(L=L, n=n, miller=miller, coeffs=coeffs)
+    s = CellSession(inp, n_orb, prec, n_vec=4)
+    s.set_orbitals(inp["coeffs"])
+    short = s.ws[: s.ws.numel() // 2]
+
+    def code_of(call):
+        with pytest.raises(lace.LaceError) as ei:
+            call()
+        return ei.value.code
+
+    y = torch.empty((4, s.n_pw), dtype=torch.complex128, device="cuda")
+    assert code_of(lambda: lace.lace_apply_exchange(
+        s.plan, 0, s.psi, n_orb, 0.0, None, s.w, s.e_x, short)) == lace.LACE_ENOMEM
+    assert code_of(lambda: lace.lace_build_ace(
+        s.plan, 0, s.psi, s.w, n_orb, "avg", s.xi, s.m, s.ex_tr, short)) == lace.LACE_ENOMEM
+    assert code_of(lambda: lace.lace_apply_ace(
+        s.plan, 0, s.xi, n_orb, s.psi[:4], 4, y, short)) == lace.LACE_ENOMEM
+    assert code_of(lambda: lace.lace_screen(
+        s.plan, 0, s.psi, n_orb, s.s, short)) == lace.LACE_ENOMEM
+    for bad in (-0.1, 1.0, float("nan")):
+        assert code_of(lambda: s.apply_exchange(bad)) == lace.LACE_EINVAL
+    assert code_of(lambda: lace.lace_apply_exchange(
+        s.plan, 1, s.psi, n_orb, 0.0, None, s.w, s.e_x, s.ws)) == lace.LACE_EINVAL
+    assert code_of(lambda: lace.lace_apply_exchange(
+        s.plan, 0, s.psi, 0, 0.0, None, s.w, s.e_x, s.ws)) == lace.LACE_EINVAL
+    # after the rejections the same session still computes the right W
+    s.apply_exchange(0.0)
+    torch.cuda.synchronize()
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= TOL[FP32]["w"]
+    s.close()
+
+
 def test_deterministic_repeat(c0):
     """Same inputs, same schedule: bitwise identical W and E_x."""
     inp, _ = c0
