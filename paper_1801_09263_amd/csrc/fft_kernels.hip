@@ -717,17 +717,20 @@ template <typename T, int N> struct Cfg {
   static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
   static constexpr int TX = (N % TX0 == 0) ? TX0 : ((N % 8 == 0) ? 8 : 4);
   static constexpr int NT_COLS = 256;
-  // z pass: pair slots per workgroup (sharing one kernel-table tile); two
-  // measured fastest at 120^3 FP32 against one, four and eight
-  static constexpr int SL = 2;
-  // z pass tiles: one 128-byte line of the flattened xy plane per z row
-  static constexpr int TXZ0 = 128 / (int)sizeof(C<T>);
-  static constexpr int TXZ = (N * N) % TXZ0 == 0 ? TXZ0 : TX;
-  static constexpr int NT_Z = (sizeof(T) == 4 && TXZ * SL * N >= 2048) ? 512 : 256;
-  // waves per SIMD to budget registers for: three 512-thread workgroups
-  // per CU in FP32 (80 VGPRs, what the fused radix-15 middle stage needs
-  // without spilling; measured faster than four with spills)
-  static constexpr int W_Z = sizeof(T) == 4 ? 6 : 4;
+  // z pass: tiles of 256 bytes of the flattened xy plane per z row, one
+  // pair slot per workgroup of 256 threads.  Measured at 120^3 FP32 (32
+  // slots): 188 us, against 204 us for 128-byte tiles with two slots per
+  // 512 threads, 198 us for 256-byte tiles with two slots, 200 us with 512
+  // threads.
+  static constexpr int SL = 1;
+  static constexpr int TXZ0 = 256 / (int)sizeof(C<T>);
+  static constexpr int TXZ = (N * N) % TXZ0 == 0 ? TXZ0
+                             : (N * N) % (TXZ0 / 2) == 0 ? TXZ0 / 2 : TX;
+  static constexpr int NT_Z = 256;
+  // waves per SIMD to budget registers for (the fused middle stage in
+  // registers needs up to 120 VGPRs at 120^3 FP32, more in FP64, without
+  // spilling)
+  static constexpr int W_Z = sizeof(T) == 4 ? 4 : 3;
   // z pencils of the 3D transforms: 256 bytes of complex points per z row
   // (128 bytes of each real grid when the last pass splits into real grids)
   static constexpr int TXC20 = 256 / (int)sizeof(C<T>);
