@@ -452,19 +452,24 @@ def _every_size_case(n):
     return _EVERY_SIZE[n]
 
 
+@pytest.mark.parametrize("sched", ["auto", "half"])
 @pytest.mark.parametrize("prec", [FP32G, FP32, FP64G],
                          ids=["fp32g", "fp32", "fp64g"])
 @pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 80, 96, 120])
-def test_pair_pipeline_every_grid_size(n, prec):
+def test_pair_pipeline_every_grid_size(n, prec, sched):
     """Every supported grid through the pair passes against the oracle:
     single-stage radix plans (8, 12), two-stage plans with the prime-factor
     radices (48 = 4 x 12, 60 = 4 x 15, 80 = 8 x 10, 96 = 8 x 12,
     120 = 8 x 15), and the z pass whose middle stage runs in registers;
-    complex and packed real orbitals (an odd count)."""
+    complex and packed real orbitals (an odd count).  "half" forces the
+    half-plane schedule, whose forward xy pass splits the plane in time and
+    whose z pass combines the halves over paired tiles, at every size."""
     L, miller, coeffs, res = _every_size_case(n)
-    say(f"every size n={n} prec={prec}")
+    say(f"every size n={n} prec={prec} sched={sched}")
     tol = TOL[prec]
     s = CellSession(dict(L=L, n=n, miller=miller), coeffs.shape[0], prec)
+    if sched == "half":
+        assert set_schedule(s.plan, 2)
     s.set_orbitals(coeffs)
     s.apply_exchange(0.0)
     torch.cuda.synchronize()
