@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -34,11 +35,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_of(text: str) -> str:
+    """C++ source without comments, blank lines and trailing blanks."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the pass kernels' code (comments left out): the stored HBM
+    counter figures hold for exactly this code."""
     h = hashlib.sha256()
     for f in ("fft_core.hpp", "fft_kernels.hip", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1801_09263_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1801_09263_amd", "csrc", f)) as fh:
+            h.update(code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -566,14 +566,15 @@ __device__ inline double block_sum(double v, double* red) {
 // Workgroup (tile, group): TX z columns of SL consecutive pair slots, one
 // LDS line per column and slot; the kernel-table tile is shared by the SL
 // slots.  A tile is TX consecutive points of the flattened xy plane (x + N
-// y), so that each z row of a tile is one whole 128-byte line even when TX
-// does not divide N.  Slots past the end of the batch load slot 0
-// (discarded) and are neither stored nor summed.
+// y), so that each z row of a tile is one contiguous piece (256 bytes for
+// the tile widths in use) even when TX does not divide N.  Slots past the
+// end of the batch load slot 0 (discarded) and are neither stored nor
+// summed.
 //
 // DIT: the xy pass left the decimation-in-time halves E (rows < N/2) and
-// O (rows >= N/2) of each plane; tiles pair them (zcol_dit), and the
-// loads form the plane's transform X_k = E_k + w^k O_k, X_{k+N/2} =
-// E_k - w^k O_k before the z transform.  Both sit where the natural layout
+// O (rows >= N/2) of each plane; tiles pair them (zcol_dit: two pieces of
+// TX/2 points per z row), and the loads form the plane's transform X_k =
+// E_k + w^k O_k, X_{k+N/2} = E_k - w^k O_k before the z transform.  Both sit where the natural layout
 // keeps them, so the kernel table, the stores and the next pass are those
 // of the plain layout.
 template <typename T, int N, int TX, int SL, int NT, int MINW, int ORDER = 0,
