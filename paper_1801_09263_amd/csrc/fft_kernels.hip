@@ -405,13 +405,17 @@ __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
 // input; the remap puts them on one XCD, back to back, so the second read
 // is served by that XCD's L2.  The epilogue is pointwise: the interleaved
 // row order of the result costs nothing.
-// DIT: decimation in time instead.  Half h reads only the rows y = 2m + h
-// and writes its length-N by length-H transform (E for h = 0, O for h = 1)
-// to rows hH .. hH + H - 1; the plane's transform is E_k +- w^k O_k, left
-// to the next pass (the z pass), which reads both anyway.  Each workgroup
-// then loads half the rows it loads in the frequency split.
+// SPLIT 1: decimation in time instead.  Half h reads only the rows
+// y = 2m + h and writes its length-N by length-H transform (E for h = 0, O
+// for h = 1) to rows hH .. hH + H - 1; the plane's transform is
+// E_k +- w^k O_k, left to the next pass (the z pass), which reads both
+// anyway.  Each workgroup then loads half the rows it loads in the
+// frequency split.
+// SPLIT 2: the frequency split with a and b already formed by the previous
+// pass (the z pass) and stored as rows 0 .. H - 1 (a) and H .. N - 1 (b):
+// half h reads only its own contiguous half plane.
 template <typename T, int N, int NT, int MINW, int SIGN, class Pro, class Epi,
-          bool DIT = false>
+          int SPLIT = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
   constexpr int H = N / 2;
@@ -433,8 +437,10 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
     const int mv = threadIdx.x + q * NT;
     if (q < NVH / NT || mv < NVH) {
       const int m0 = mv * V;
-      if constexpr (DIT) {
+      if constexpr (SPLIT == 1) {
         pro.getv(base + (2 * (m0 / N) + half) * N + m0 % N, slot, f1[q]);
+      } else if constexpr (SPLIT == 2) {
+        pro.getv(base + half * H * N + m0, slot, f1[q]);
       } else {
         pro.getv(base + m0, slot, f1[q]);
         pro.getv(base + H * N + m0, slot, f2[q]);
@@ -453,7 +459,7 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         C<T> r;
-        if (DIT) r = f1[q][v];
+        if (SPLIT != 0) r = f1[q][v];
         else if (half == 0) r = add<T>(f1[q][v], f2[q][v]);
         else r = mul<T>(sub<T>(f1[q][v], f2[q][v]), w);
         s[lds(m0 + v)] = r;
@@ -464,7 +470,7 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
   lds_fft<T, N, H, NT, SIGN, true>(s, LS, 1, tw);          // x: H rows
   lds_fft<T, H, N, NT, SIGN, true, 2>(s, 1, LS, tw);       // y: N columns
   auto out = [base, half](int m) {
-    if constexpr (DIT) return base + half * H * N + m;
+    if constexpr (SPLIT == 1) return base + half * H * N + m;
     else return base + (2 * (m / N) + half) * N + m % N;
   };
   stage_out<T, H * N, NT>(s, epi, slot, out, lds);
@@ -573,10 +579,14 @@ __device__ inline double block_sum(double v, double* red) {
 //
 // DIT: the xy pass left the decimation-in-time halves E (rows < N/2) and
 // O (rows >= N/2) of each plane; tiles pair them (zcol_dit: two pieces of
-// TX/2 points per z row), and the loads form the plane's transform X_k =
-// E_k + w^k O_k, X_{k+N/2} = E_k - w^k O_k before the z transform.  Both sit where the natural layout
-// keeps them, so the kernel table, the stores and the next pass are those
-// of the plain layout.
+// TX/2 points per z row), and the loads form the plane's transform
+// X_k = E_k + w^k O_k, X_{k+N/2} = E_k - w^k O_k before the z transform,
+// in the places the natural layout gives them (so the kernel table is read
+// as in that layout).  The stores form the inverse xy pass's frequency
+// split in the same places: a_k = Y_k + Y_{k+N/2} in row k and
+// b_k = (Y_k - Y_{k+N/2}) w^-k in row k + N/2, Y the result of the inverse
+// z transform, so that each half of the inverse xy pass reads only its own
+// half plane (its SPLIT 2 form).
 template <typename T, int N, int TX, int SL, int NT, int MINW, int ORDER = 0,
           bool DIT = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
@@ -632,17 +642,16 @@ void k_zconv(C<T>* __restrict__ tmp,
   static_assert(NT % NLN == 0, "a thread keeps one line (one slot)");
   const int line = threadIdx.x % NLN, col = line % TX, my_sl = line / TX;
   ProGrid<T> pro{g, 0};
+  // DIT element pairs (column c < TX/2, column c + TX/2) of each z row
+  constexpr int HC = TX / 2;
+  constexpr int NVP = NE / 2 / V;
+  constexpr int PP = (NVP + NT - 1) / NT;
+  static_assert(!DIT || (TX % 2 == 0 && HC % V == 0), "paired tile width");
+  auto lo = [](int mp) {   // pair element -> element of the low column
+    const int sl = mp / (NE1 / 2), r = mp % (NE1 / 2);
+    return sl * NE1 + (r / HC) * TX + r % HC;
+  };
   if constexpr (DIT) {
-    // element pairs (column c < TX/2, column c + TX/2) of each z row
-    constexpr int HC = TX / 2;
-    constexpr int NP = NE / 2;
-    constexpr int NVP = NP / V;
-    constexpr int PP = (NVP + NT - 1) / NT;
-    static_assert(TX % 2 == 0 && HC % V == 0, "paired tile width");
-    auto lo = [](int mp) {   // pair element -> element of the low column
-      const int sl = mp / (NE1 / 2), r = mp % (NE1 / 2);
-      return sl * NE1 + (r / HC) * TX + r % HC;
-    };
     C<T> fe[PP][V], fo[PP][V];
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
@@ -716,14 +725,35 @@ void k_zconv(C<T>* __restrict__ tmp,
   }
   __syncthreads();
   StagesReversed<T, N, NST - 2, NLN, NT, +1, true, 1>::run(s, LS, 1, tw);
+  if constexpr (DIT) {
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int mv = threadIdx.x + q * NT;
-    if ((q < NV / NT || mv < NV) && (mv * V) / NE1 < nsl) {
-      Vec<C<T>, V> y;
+    for (int q = 0; q < PP; ++q) {
+      const int mv = threadIdx.x + q * NT;
+      if ((q < NVP / NT || mv < NVP) && (mv * V) / (NE1 / 2) < nsl) {
+        const int m = lo(mv * V);
+        Vec<C<T>, V> ya, yb;
 #pragma unroll
-      for (int v = 0; v < V; ++v) y.e[v] = s[lds(mv * V + v)];
-      stv<C<T>, V>(g + gidx(mv * V), y);
+        for (int v = 0; v < V; ++v) {
+          const C<T> a = s[lds(m + v)], b = s[lds(m + v + HC)];
+          C<T> w = tw[(tile * HC + (m + v) % TX) / N];
+          w.y = -w.y;
+          ya.e[v] = add<T>(a, b);
+          yb.e[v] = mul<T>(sub<T>(a, b), w);
+        }
+        stv<C<T>, V>(g + gidx(m), ya);
+        stv<C<T>, V>(g + gidx(m + HC), yb);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int mv = threadIdx.x + q * NT;
+      if ((q < NV / NT || mv < NV) && (mv * V) / NE1 < nsl) {
+        Vec<C<T>, V> y;
+#pragma unroll
+        for (int v = 0; v < V; ++v) y.e[v] = s[lds(mv * V + v)];
+        stv<C<T>, V>(g + gidx(mv * V), y);
+      }
     }
   }
 #pragma unroll
@@ -839,17 +869,19 @@ template <typename T, int N> struct Engine {
   // two half planes fit the 160 KiB of LDS of a CU
   static constexpr int W_HALF =
       (N / 2 * (N + 1) + N) * (int)sizeof(C<T>) * 2 <= 160 * 1024 ? 4 : 2;
-  template <int SIGN, bool DIT = false, class Pro, class Epi>
+  template <int SIGN, int SPLIT = 0, class Pro, class Epi>
   static hipError_t half(Pro p, Epi e, int count, const C<T>* tw,
                          hipStream_t st) {
-    hipLaunchKernelGGL((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi, DIT>),
+    hipLaunchKernelGGL((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi, SPLIT>),
                        dim3(2 * N * count), dim3(NT_HALF), 0, st, p, e, tw,
                        count);
     return hipGetLastError();
   }
   // The pair passes' forward xy pass over half planes splits in time and
   // leaves the combination to the z pass (measured at 120^3 FP32, 32 star
-  // slots: 206 us against 219-224 us for the split in frequency).
+  // slots: 206 us against 219-224 us for the split in frequency); the z
+  // pass also forms the inverse pass's frequency split, so that each of
+  // its halves reads only its half plane.
   static constexpr bool XY_DIT = N % 2 == 0 && Cf::TXZ % 2 == 0 &&
                               (Cf::TXZ / 2) % ProGrid<T>::V == 0;
   template <bool D>
@@ -944,7 +976,7 @@ template <typename T, int N> struct Engine {
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     // pass A
     if (mode == 2) {
-      err = half<-1, XY_DIT>(pp, et, cnt, tw, st);
+      err = half<-1, XY_DIT ? 1 : 0>(pp, et, cnt, tw, st);
     } else if (mode == 1) {
       err = plane<-1>(pp, et, cnt, tw, st);
     } else {
@@ -963,7 +995,7 @@ template <typename T, int N> struct Engine {
       return err;
     // pass C
     if (mode == 2) {
-      err = half<+1>(pt, ea, cnt, tw, st);
+      err = half<+1, XY_DIT ? 2 : 0>(pt, ea, cnt, tw, st);
     } else if (mode == 1) {
       err = plane<+1>(pt, ea, cnt, tw, st);
     } else {
@@ -1005,7 +1037,7 @@ template <typename T, int N> struct Engine {
     hipError_t err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     if (mode == 2) {
-      err = half<-1, XY_DIT>(pp, et, cnt, tw, st);
+      err = half<-1, XY_DIT ? 1 : 0>(pp, et, cnt, tw, st);
     } else if (mode == 1) {
       err = plane<-1>(pp, et, cnt, tw, st);
     } else {
@@ -1022,7 +1054,7 @@ template <typename T, int N> struct Engine {
     if (sy && sy->wait_c && (err = hipStreamWaitEvent(st, sy->wait_c, 0)) != hipSuccess)
       return err;
     if (mode == 2) {
-      err = half<+1>(pt, ea, cnt, tw, st);
+      err = half<+1, XY_DIT ? 2 : 0>(pt, ea, cnt, tw, st);
     } else if (mode == 1) {
       err = plane<+1>(pt, ea, cnt, tw, st);
     } else {
