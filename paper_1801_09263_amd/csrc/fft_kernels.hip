@@ -641,6 +641,15 @@ void k_zconv(C<T>* __restrict__ tmp,
   constexpr int NBF = (BF + NT - 1) / NT;
   static_assert(NT % NLN == 0, "a thread keeps one line (one slot)");
   const int line = threadIdx.x % NLN, col = line % TX, my_sl = line / TX;
+  // The kernel table holds one octant, 0 <= kx, ky, kz <= N/2 (v depends on
+  // |G| only and the cell is cubic): 1/8 of the grid, small enough to stay
+  // in L2 while every slot of the launch reads it.  Octant row of this
+  // line's xy point:
+  constexpr int VH = N / 2 + 1;
+  const int vxy = [&] {
+    const int p = zcol(tile, col), lx = p % N, ly = p / N;
+    return (ly <= N - ly ? ly : N - ly) * VH + (lx <= N - lx ? lx : N - lx);
+  }();
   ProGrid<T> pro{g, 0};
   // DIT element pairs (column c < TX/2, column c + TX/2) of each z row
   constexpr int HC = TX / 2;
@@ -706,8 +715,10 @@ void k_zconv(C<T>* __restrict__ tmp,
       }
       T vt[RL];   // kernel values at frequencies i + t PL of the z line
 #pragma unroll
-      for (int t = 0; t < RL; ++t)
-        vt[t] = vtab[zcol(tile, col + TX * (i + t * PL))];
+      for (int t = 0; t < RL; ++t) {
+        const int kz = i + t * PL;
+        vt[t] = vtab[(kz <= N - kz ? kz : N - kz) * (VH * VH) + vxy];
+      }
       Dft<RL, -1, T>::run(x[b]);
       T eb = T(0);   // the butterfly's RL terms in the transform precision
 #pragma unroll

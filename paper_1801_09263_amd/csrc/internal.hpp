@@ -39,7 +39,9 @@ struct CellDev {
   int64_t n_pw;
   double L, rc, omega;
   const int32_t* gidx;  // n_pw linear grid indices (x + n (y + n z))
-  const void* vtab;     // ng kernel values v(G) / ng in the plan precision
+  const void* vtab;     // v(G) / ng in the plan precision for one octant,
+                        // 0 <= kx, ky, kz <= n/2, index (kz (n/2+1) + ky)
+                        // (n/2+1) + kx (v depends on |G| only; cubic cell)
   const void* tw;       // n twiddles exp(-2 pi i m / n), plan precision
   const int32_t* negidx;  // n_pw: position of -m in the Miller list (Gamma)
   int ppb;              // pairs per batch (1..PMAX)

@@ -656,7 +656,17 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
     }
     hipError_t e = hipSuccess;
     e = hipMalloc(&cp.d_gidx, sizeof(int32_t) * d.n_pw);
-    if (e == hipSuccess) e = hipMalloc(&cp.d_vtab, (fp64 ? 8 : 4) * (size_t)ng);
+    // the device keeps one octant of the table (0 <= kx, ky, kz <= n/2):
+    // v depends on the squares of the signed frequencies only, so the
+    // entry at k and at n - k is the same value
+    const int vh = n / 2 + 1;
+    const int64_t nv = (int64_t)vh * vh * vh;
+    std::vector<double> voct((size_t)nv);
+    for (int z = 0; z < vh; ++z)
+      for (int y = 0; y < vh; ++y)
+        for (int x = 0; x < vh; ++x)
+          voct[(size_t)((z * vh + y) * vh + x)] = v[x + (int64_t)n * (y + (int64_t)n * z)];
+    if (e == hipSuccess) e = hipMalloc(&cp.d_vtab, (fp64 ? 8 : 4) * (size_t)nv);
     if (e == hipSuccess) e = hipMalloc(&cp.d_tw, (fp64 ? 16 : 8) * (size_t)n);
     if (e == hipSuccess) e = hipMalloc(&cp.d_info, sizeof(int32_t));
     if (e == hipSuccess && gamma) {
@@ -670,14 +680,14 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
                     hipMemcpyHostToDevice);
     if (e == hipSuccess) {
       if (fp64) {
-        e = hipMemcpy(cp.d_vtab, v.data(), 8 * (size_t)ng, hipMemcpyHostToDevice);
+        e = hipMemcpy(cp.d_vtab, voct.data(), 8 * (size_t)nv, hipMemcpyHostToDevice);
         if (e == hipSuccess)
           e = hipMemcpy(cp.d_tw, tw.data(), 16 * (size_t)n, hipMemcpyHostToDevice);
       } else {
-        std::vector<float> vf(ng), twf(2 * n);
-        for (int64_t k = 0; k < ng; ++k) vf[k] = static_cast<float>(v[k]);
+        std::vector<float> vf((size_t)nv), twf(2 * n);
+        for (int64_t k = 0; k < nv; ++k) vf[k] = static_cast<float>(voct[k]);
         for (int k = 0; k < 2 * n; ++k) twf[k] = static_cast<float>(tw[k]);
-        e = hipMemcpy(cp.d_vtab, vf.data(), 4 * (size_t)ng, hipMemcpyHostToDevice);
+        e = hipMemcpy(cp.d_vtab, vf.data(), 4 * (size_t)nv, hipMemcpyHostToDevice);
         if (e == hipSuccess)
           e = hipMemcpy(cp.d_tw, twf.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
       }
