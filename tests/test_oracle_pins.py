@@ -162,6 +162,22 @@ def test_kernel_table_properties(c0):
     assert np.allclose(v, kernel_direct(L, n, rc), rtol=1e-12, atol=1e-12)
 
 
+@pytest.mark.parametrize("n", [8, 12, 60, 120])
+@pytest.mark.parametrize("omega", [0.0, 0.2])
+def test_kernel_table_octant_determines_it(n, omega):
+    """In a cubic cell v depends on |G| only, so the table is unchanged,
+    bit for bit, under k -> n - k along each axis: the octant
+    0 <= kx, ky, kz <= n/2, (n/2 + 1)^3 values, determines the whole table
+    (the device keeps only that octant)."""
+    v = O.coulomb_kernel(9.0, n, omega=omega)
+    fold = np.minimum(np.arange(n), n - np.arange(n))
+    assert fold.max() == n // 2
+    octant = v[: n // 2 + 1, : n // 2 + 1, : n // 2 + 1]
+    rebuilt = octant[np.ix_(fold, fold, fold)]
+    assert np.array_equal(rebuilt, v)
+    assert np.array_equal(rebuilt.astype(np.float32), v.astype(np.float32))
+
+
 # --------------------------------------------------- T3 plane-wave orbitals
 def test_plane_wave_orbitals_closed_form():
     """psi_j = Omega^{-1/2} exp(i G_j r): V_ij = v(G_j - G_i) rho_ij, so
