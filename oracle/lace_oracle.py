@@ -40,7 +40,8 @@ __all__ = [
     "coulomb_kernel", "overlap_of_moduli", "kept_pairs", "pair_potential",
     "pair_energy", "apply_exchange", "apply_exchange_columns",
     "apply_exchange_to", "grid_to_pw", "exchange_matrix",
-    "exchange_energy_trace", "exchange_energy_pairs", "symmetrize",
+    "exchange_energy_trace", "exchange_energy_pairs",
+    "exchange_integrals_columns", "symmetrize",
     "cholesky_neg", "NotPositiveDefinite", "projector", "apply_ace",
     "run_path", "apply_exchange_virtual", "run_path_virtual",
     "align_orbitals", "scdm_points", "scdm_given_points", "scdm",
@@ -252,6 +253,24 @@ def exchange_energy_pairs(psi: np.ndarray, v: np.ndarray, L: float,
             if keep[i, j]:
                 e += pair_energy(psi[i], psi[j], v, L)
     return -0.5 * e
+
+
+def exchange_integrals_columns(psi: np.ndarray, v: np.ndarray, L: float,
+                               pairs, cols) -> np.ndarray:
+    """For each listed column j: sum over i with (i, j) kept of (ij|ji),
+    every integral from its own pair density (the terms of
+    ``exchange_energy_pairs``, grouped by column so that columns can be
+    computed apart).  E_x = -(1/2) times the sum over all columns."""
+    nb = psi.shape[0]
+    keep = (np.ones((nb, nb), dtype=bool) if pairs is None
+            else _kept_lookup(pairs, nb))
+    cols = list(cols)
+    out = np.zeros(len(cols))
+    for c, j in enumerate(cols):
+        for i in range(nb):
+            if keep[i, j]:
+                out[c] += pair_energy(psi[i], psi[j], v, L)
+    return out
 
 
 def symmetrize(m: np.ndarray, mode: str = "avg") -> np.ndarray:

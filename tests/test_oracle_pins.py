@@ -435,6 +435,82 @@ def test_symmetrizations_agree_on_hermitian(c0):
         assert np.abs(O.symmetrize(m, mode) - a).max() <= 1e-15 * np.abs(m).max()
 
 
+def test_symmetrization_keeps_the_named_triangle():
+    """Sec. 2, text after Eq. (10): 'upper' copies the upper triangle of M'
+    (entries M'_jk = <psi_j|K|psi_k> with j < k) into the lower one, 'lower'
+    the lower triangle into the upper one, 'avg' averages M' with its
+    adjoint.  On a non-Hermitian complex M' the kept triangle must come back
+    unchanged, the other one as its mirror image, and the diagonal real."""
+    rng = np.random.default_rng(31)
+    n = 7
+    m = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    iu = np.triu_indices(n, 1)
+    il = np.tril_indices(n, -1)
+    up = O.symmetrize(m, "upper")
+    assert np.array_equal(up[iu], m[iu])
+    assert np.array_equal(up.T[iu], np.conj(m[iu]))
+    lo = O.symmetrize(m, "lower")
+    assert np.array_equal(lo[il], m[il])
+    assert np.array_equal(lo.T[il], np.conj(m[il]))
+    # the two modes disagree off the diagonal when M' is not Hermitian
+    assert np.abs(up - lo).max() > 0.1
+    av = O.symmetrize(m, "avg")
+    for a in range(n):
+        for b in range(n):
+            if a != b:
+                want = 0.5 * (m[a, b] + np.conj(m[b, a]))
+                assert abs(av[a, b] - want) <= 1e-15 * abs(want) + 1e-300
+    for out in (up, lo, av):
+        assert np.array_equal(np.diag(out), np.diag(m).real.astype(complex))
+
+
+def test_scdm_orbitals_are_the_loewdin_polar_factor(localized):
+    """The SCDM orbitals are the density-matrix columns Loewdin-
+    orthonormalized: with D_k = P(., r_k) = sum_n psi_n conj(psi_n(r_k))
+    (built here by a plain loop over the orbitals) and Phi the returned set,
+    D = Phi H with H = Phi^H D Hermitian positive definite (the polar
+    decomposition, unique for full-rank D), so no other orthonormal set is
+    closer to D in the Frobenius norm: Gram-Schmidt (QR) of D and random
+    unitary mixes of Phi all lie further away."""
+    L, n, miller = localized["L"], localized["n"], localized["miller"]
+    coeffs = localized["coeffs"]
+    psi = localized["psi"]
+    nb = coeffs.shape[0]
+    pts = O.scdm_points(psi)
+    phi = O.scdm_given_points(coeffs, psi, pts)
+    flat = psi.reshape(nb, -1)
+    d = np.zeros_like(coeffs)
+    for k, r in enumerate(pts):
+        for m in range(nb):
+            d[k] += coeffs[m] * np.conj(flat[m, r])
+    assert np.abs(np.conj(phi) @ phi.T - np.eye(nb)).max() <= 1e-12
+    h = np.conj(phi) @ d.T             # h[a, b] = <phi_a | D_b>
+    assert np.abs(h - h.conj().T).max() <= 1e-12 * np.abs(h).max()
+    assert np.linalg.eigvalsh(0.5 * (h + h.conj().T)).min() > 0
+    assert np.abs(phi.T @ h - d.T).max() <= 1e-12 * np.abs(d).max()
+    best = np.linalg.norm(phi - d)
+    q, _ = np.linalg.qr(d.T)
+    assert np.linalg.norm(q.T - d) > best * (1 + 1e-6)
+    rng = np.random.default_rng(73)
+    for _ in range(20):
+        z = rng.standard_normal((nb, nb)) + 1j * rng.standard_normal((nb, nb))
+        u, _ = np.linalg.qr(z)
+        u = np.linalg.qr(np.eye(nb) + 0.05 * (u - np.eye(nb)))[0]
+        assert np.linalg.norm(u.T @ phi - d) > best
+
+
+def test_exchange_integral_columns_sum_to_the_energy(localized):
+    """The per-column integral sums of the screened energy add up to
+    -2 E_x of the kept ordered pairs."""
+    loc = localized
+    pairs = O.kept_pairs(loc["S"], 2e-3)
+    cols = O.exchange_integrals_columns(loc["psi"], loc["v"], loc["L"], pairs,
+                                        range(loc["psi"].shape[0]))
+    ex = O.exchange_energy_pairs(loc["psi"], loc["v"], loc["L"], pairs)
+    assert -0.5 * cols.sum() == pytest.approx(ex, rel=1e-13)
+    assert np.all(cols > 0)
+
+
 def test_localized_generator_orthonormal_real(localized):
     c = localized["coeffs"]
     assert np.abs(c.conj() @ c.T - np.eye(16)).max() < 1e-12
