@@ -31,8 +31,10 @@
  * Errors.  Every call returns an int status: LACE_OK (0) or a negative code.
  * Argument, shape and workspace errors are detected on the host before any
  * device work is enqueued.  A failed Cholesky factorization (M_s not
- * negative definite) is a device-side event recorded in the plan's info
- * word and read with lace_get_info.  HIP runtime errors map to LACE_EHIP.
+ * negative definite) is a device-side event recorded in an info word that
+ * belongs to the call (a device int32 the caller passes, else the first
+ * word of the call's workspace, read with lace_get_info).  HIP runtime
+ * errors map to LACE_EHIP.
  *
  * Streams.  Work is enqueued on the given stream (0 = null stream) and is
  * asynchronous, except where a call says it synchronizes.  A plan must be
@@ -216,12 +218,18 @@ int lace_scdm(lace_plan* plan, int cell, const void* psi_g, int n_orb,
  *   xi_g    device n_pw x n_orb complex128 output: xi = W L^{-H} with
  *           -M_s = L L^H, L lower triangular with positive diagonal.
  *   ex_tr   device double (may be NULL): (1/2) Re tr M.
- * A non-positive-definite -M_s sets the cell's info word (read with
- * lace_get_info); xi is then undefined.  Asynchronous. */
+ *   info    device int32 (may be NULL): 0 when the Cholesky factorization
+ *           succeeds, else k + 1 for the first non-positive pivot k; xi is
+ *           then undefined.  NULL writes the word into the workspace
+ *           instead (its first 4 bytes), where lace_get_info reads it.
+ *           Each call clears and sets only its own word, so builds on
+ *           different streams with different workspaces (or info words)
+ *           never see each other's failures.
+ * Asynchronous. */
 int lace_build_ace(lace_plan* plan, int cell, const void* psi_g,
                    const void* w_g, int n_orb, lace_sym sym, void* xi_g,
-                   void* m_out, double* ex_tr, void* ws, size_t ws_bytes,
-                   lace_stream_t stream);
+                   void* m_out, double* ex_tr, int32_t* info, void* ws,
+                   size_t ws_bytes, lace_stream_t stream);
 
 /* y = -xi (xi^H x): the compressed exchange applied to n_vec functions.
  * xi_g device n_pw x n_orb, x_g device n_pw x n_vec, y_g device
@@ -247,6 +255,8 @@ typedef struct {
   void* xi_g;            /* device n_pw x n_orb, or NULL: no ACE build */
   void* m_out;           /* device n_orb x n_orb complex128, may be NULL */
   double* ex_tr;         /* device, may be NULL */
+  int32_t* info;         /* device int32, may be NULL (then the job's
+                            workspace word): Cholesky info of the ACE build */
   void* ws;              /* device workspace of this job */
   size_t ws_bytes;
 } lace_job;
@@ -298,11 +308,14 @@ int lace_autotune(lace_plan* plan, int cell, const void* psi_g, int n_orb,
 int lace_fft3d(lace_plan* plan, int cell, int direction, void* grids,
                int count, lace_stream_t stream);
 
-/* Info word of the last lace_build_ace on this cell: 0 if the Cholesky
- * factorization succeeded, else k + 1 for the first non-positive pivot k.
- * Synchronizes the device.  Returns LACE_OK when the word is 0 and
- * LACE_ENOTPD when it is not (*info_host is filled in both cases). */
-int lace_get_info(lace_plan* plan, int cell, int32_t* info_host);
+/* Info word kept in a workspace: that of the last lace_build_ace (or
+ * batched job) that used workspace `ws` with info == NULL: 0 if the
+ * Cholesky factorization succeeded, else k + 1 for the first non-positive
+ * pivot k.  Synchronizes `stream` (the stream of that call) only, then
+ * copies the word.  Returns LACE_OK when the word is 0 and LACE_ENOTPD when
+ * it is not (*info_host is filled in both cases); EINVAL for NULL
+ * pointers, EHIP. */
+int lace_get_info(const void* ws, lace_stream_t stream, int32_t* info_host);
 
 /* Host only, no device work: the batch schedule lace_apply_exchange uses.
  * The n_pairs unordered pairs (host arrays, 0 <= i <= j < n_orb) are

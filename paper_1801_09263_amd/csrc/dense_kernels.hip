@@ -271,14 +271,14 @@ static hipError_t gemm_ip(const void* A, int64_t lda, int na, const void* B,
   if (SYM && (A != B || na != nb || lda != ldb)) return hipErrorInvalidValue;
   const int ta = (na + IP_T - 1) / IP_T, tb = (nb + IP_T - 1) / IP_T;
   dim3 grid(SYM ? ta * (ta + 1) / 2 : ta, SYM ? 1 : tb, sp.nsplit);
-  hipLaunchKernelGGL((k_gemm_ip<MODE, SYM>), grid, dim3(256), 0, st, A, lda,
+  LACE_LAUNCH((k_gemm_ip<MODE, SYM>), grid, dim3(256), 0, st, A, lda,
                      na, B, ldb, nb, K, sp.kchunk, static_cast<double*>(part));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int64_t nel = (int64_t)na * nb * (cplx ? 2 : 1);
   int64_t blocks = (nel + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
+  LACE_LAUNCH(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const double*>(part), nel, sp.nsplit, scale,
                      out, SYM ? nb : 0);
   return hipGetLastError();
@@ -406,7 +406,7 @@ hipError_t launch_gemm_tall(const void* X, int64_t ldx, int64_t M, int nk,
   const int nbb = (nb + 63) / 64;
   const int64_t blocks = ((M + 63) / 64) * nbb;
   if (blocks > INT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemm_tall, dim3((unsigned)blocks), dim3(256), 0, st,
+  LACE_LAUNCH(k_gemm_tall, dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const double2*>(X), ldx, M, nk,
                      static_cast<const double2*>(Z), nb,
                      static_cast<double2*>(Y), ldy, nbb);
@@ -446,7 +446,7 @@ hipError_t launch_neg_sym(const void* M, int n, int mode, void* A,
   const int64_t total = (int64_t)n * n;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_neg_sym, dim3((unsigned)blocks), dim3(256), 0, st,
+  LACE_LAUNCH(k_neg_sym, dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const double2*>(M), n, mode,
                      static_cast<double2*>(A));
   return hipGetLastError();
@@ -570,15 +570,15 @@ __global__ void k_zero_upper(double2* A, int n) {
 hipError_t launch_cholesky(void* Av, int n, int32_t* info, void* tmp,
                            void* part, int64_t part_bytes, hipStream_t st) {
   double2* A = static_cast<double2*>(Av);
-  hipLaunchKernelGGL(k_set_zero, dim3(1), dim3(1), 0, st, info);
+  LACE_LAUNCH(k_set_zero, dim3(1), dim3(1), 0, st, info);
   hipError_t e = hipGetLastError();
   for (int k0 = 0; k0 < n && e == hipSuccess; k0 += CB) {
     const int kb = n - k0 < CB ? n - k0 : CB;
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, A, n, k0, kb, info);
+    LACE_LAUNCH(k_chol_diag, dim3(1), dim3(256), 0, st, A, n, k0, kb, info);
     e = hipGetLastError();
     const int off = k0 + kb, m = n - off;
     if (e != hipSuccess || m <= 0) continue;
-    hipLaunchKernelGGL(k_chol_panel, dim3((m + CP_ROWS - 1) / CP_ROWS),
+    LACE_LAUNCH(k_chol_panel, dim3((m + CP_ROWS - 1) / CP_ROWS),
                        dim3(CP_ROWS), 0, st, A, n, k0, kb, info);
     e = hipGetLastError();
     // T[a][b] = sum_t conj(L[off + a][k0 + t]) L[off + b][k0 + t]
@@ -589,7 +589,7 @@ hipError_t launch_cholesky(void* Av, int n, int32_t* info, void* tmp,
     if (e == hipSuccess) {
       int64_t blocks = ((int64_t)m * m + 255) / 256;
       if (blocks > 2048) blocks = 2048;
-      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)blocks), dim3(256), 0,
+      LACE_LAUNCH(k_chol_update, dim3((unsigned)blocks), dim3(256), 0,
                          st, A, n, off, static_cast<const double2*>(tmp), info);
       e = hipGetLastError();
     }
@@ -597,7 +597,7 @@ hipError_t launch_cholesky(void* Av, int n, int32_t* info, void* tmp,
   if (e == hipSuccess) {
     int64_t blocks = ((int64_t)n * n + 255) / 256;
     if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL(k_zero_upper, dim3((unsigned)blocks), dim3(256), 0, st,
+    LACE_LAUNCH(k_zero_upper, dim3((unsigned)blocks), dim3(256), 0, st,
                        A, n);
     e = hipGetLastError();
   }
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(64) void k_trinv_adj(const double2* L, int n,
 }
 
 hipError_t launch_trinv_adj(const void* L, int n, void* Z, hipStream_t st) {
-  hipLaunchKernelGGL(k_trinv_adj, dim3(n), dim3(64), n * sizeof(double2), st,
+  LACE_LAUNCH(k_trinv_adj, dim3(n), dim3(64), n * sizeof(double2), st,
                      static_cast<const double2*>(L), n,
                      static_cast<double2*>(Z));
   return hipGetLastError();
@@ -663,7 +663,7 @@ __global__ void k_trace_re(const double2* M, int n, double factor,
 
 hipError_t launch_trace_re(const void* M, int n, double factor, double* out,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_trace_re, dim3(1), dim3(256), 0, st,
+  LACE_LAUNCH(k_trace_re, dim3(1), dim3(256), 0, st,
                      static_cast<const double2*>(M), n, factor, out);
   return hipGetLastError();
 }
@@ -729,7 +729,7 @@ hipError_t launch_polar_elem(int mode, const void* in, int n, const double* s,
   int64_t blocks = ((int64_t)n * n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_polar_elem, dim3((unsigned)blocks), dim3(256), 0, st,
+  LACE_LAUNCH(k_polar_elem, dim3((unsigned)blocks), dim3(256), 0, st,
                      mode, static_cast<const double2*>(in), n, s,
                      static_cast<double2*>(out));
   return hipGetLastError();
@@ -737,7 +737,7 @@ hipError_t launch_polar_elem(int mode, const void* in, int n, const double* s,
 
 hipError_t launch_polar_norm(int mode, const void* B, int n, double* out,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_polar_norm, dim3(1), dim3(256), 0, st, mode,
+  LACE_LAUNCH(k_polar_norm, dim3(1), dim3(256), 0, st, mode,
                      static_cast<const double2*>(B), n, out);
   return hipGetLastError();
 }

@@ -868,7 +868,7 @@ template <typename T, int N> struct Engine {
   static hipError_t plane(Pro p, Epi e, int count, const C<T>* tw,
                           hipStream_t st) {
     if constexpr (Cf::plane) {
-      hipLaunchKernelGGL((k_plane<T, N, Cf::NT_PLANE, SIGN, Pro, Epi>),
+      LACE_LAUNCH((k_plane<T, N, Cf::NT_PLANE, SIGN, Pro, Epi>),
                          dim3(N, count), dim3(Cf::NT_PLANE), 0, st, p, e, tw);
       return hipGetLastError();
     } else {
@@ -883,7 +883,7 @@ template <typename T, int N> struct Engine {
   template <int SIGN, int SPLIT = 0, class Pro, class Epi>
   static hipError_t half(Pro p, Epi e, int count, const C<T>* tw,
                          hipStream_t st) {
-    hipLaunchKernelGGL((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi, SPLIT>),
+    LACE_LAUNCH((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi, SPLIT>),
                        dim3(2 * N * count), dim3(NT_HALF), 0, st, p, e, tw,
                        count);
     return hipGetLastError();
@@ -900,7 +900,7 @@ template <typename T, int N> struct Engine {
                           double* epart, int cnt, const C<T>* tw,
                           hipStream_t st) {
     const int ntiles = (int)tiles();
-    hipLaunchKernelGGL((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z, Cf::W_Z, 1, D>),
+    LACE_LAUNCH((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z, Cf::W_Z, 1, D>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
                        dim3(Cf::NT_Z), 0, st, tmp, NG, vtab, pa, epart,
                        ntiles, tw);
@@ -909,7 +909,7 @@ template <typename T, int N> struct Engine {
   template <int SIGN, class Pro, class Epi>
   static hipError_t xlines(Pro p, Epi e, int count, const C<T>* tw,
                            hipStream_t st) {
-    hipLaunchKernelGGL((k_xlines<T, N, Cf::TY, Cf::NT_X, SIGN, Pro, Epi>),
+    LACE_LAUNCH((k_xlines<T, N, Cf::TY, Cf::NT_X, SIGN, Pro, Epi>),
                        dim3(N * N / Cf::TY, count), dim3(Cf::NT_X), 0, st, p,
                        e, tw);
     return hipGetLastError();
@@ -919,7 +919,7 @@ template <typename T, int N> struct Engine {
                          hipStream_t st) {
     constexpr int TXC = AXIS == 2 ? Cf::TXC2 : Cf::TX;
     constexpr int ntiles = AXIS == 2 ? N * N / TXC : N * (N / TXC);
-    hipLaunchKernelGGL((k_cols<T, N, AXIS, TXC, Cf::NT_COLS, SIGN, Pro, Epi>),
+    LACE_LAUNCH((k_cols<T, N, AXIS, TXC, Cf::NT_COLS, SIGN, Pro, Epi>),
                        dim3(ntiles * count), dim3(Cf::NT_COLS), 0, st, p, e,
                        tw, count);
     return hipGetLastError();
@@ -1142,12 +1142,12 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st) {
   if (n16 > 0) {
     int64_t blocks = (n16 + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st,
+    LACE_LAUNCH(k_zero, dim3((unsigned)blocks), dim3(256), 0, st,
                        static_cast<uint4*>(p), n16);
   }
   const int64_t rem = bytes - n16 * 16;
   if (rem > 0)
-    hipLaunchKernelGGL(k_zero_tail, dim3(1), dim3(64), 0, st,
+    LACE_LAUNCH(k_zero_tail, dim3(1), dim3(64), 0, st,
                        static_cast<unsigned char*>(p) + n16 * 16, rem);
   return hipGetLastError();
 }
@@ -1161,7 +1161,7 @@ static hipError_t orb_to_grid_t(const CellDev& c, const void* coeffs,
   const int64_t total = c.n_pw * n_orb;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)blocks), dim3(256), 0, st,
+  LACE_LAUNCH((k_scatter<T>), dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const double2*>(coeffs), c.n_pw, c.gidx,
                      static_cast<C<T>*>(psi), c.ng, n_orb);
   err = hipGetLastError();
@@ -1184,7 +1184,7 @@ static hipError_t grid_to_pw_t(const CellDev& c, void* w, int n_orb,
   const int64_t total = c.n_pw * n_orb;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)blocks), dim3(256), 0, st,
+  LACE_LAUNCH((k_gather<T>), dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<const C<T>*>(w), c.ng, c.gidx, c.n_pw, n_orb,
                      std::sqrt(c.omega) / double(c.ng),
                      static_cast<double2*>(w_pw));
@@ -1234,7 +1234,7 @@ hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
 
 hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,
                              double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, part, count,
+  LACE_LAUNCH(k_reduce_sum, dim3(1), dim3(256), 0, st, part, count,
                      factor, out);
   return hipGetLastError();
 }
@@ -1299,7 +1299,7 @@ static hipError_t orb_to_grid_real_t(const CellDev& c, const void* coeffs,
   C<T>* zin = static_cast<C<T>*>(psi);
   hipError_t err = launch_zero(zin, (int64_t)npair * c.ng * sizeof(C<T>), st);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_scatter_pairs<T>), dim3(grid_for(c.n_pw * npair)),
+  LACE_LAUNCH((k_scatter_pairs<T>), dim3(grid_for(c.n_pw * npair)),
                      dim3(256), 0, st, static_cast<const double2*>(coeffs),
                      c.n_pw, c.gidx, zin, c.ng, n_orb);
   if ((err = hipGetLastError()) != hipSuccess) return err;
@@ -1344,7 +1344,7 @@ static hipError_t grid_to_pw_real_t(const CellDev& c, const void* w, int n_orb,
     default: break;
   }
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_gather_pairs<T>), dim3(grid_for(c.n_pw * npair)),
+  LACE_LAUNCH((k_gather_pairs<T>), dim3(grid_for(c.n_pw * npair)),
                      dim3(256), 0, st, static_cast<const C<T>*>(scratch), c.ng,
                      c.gidx, c.negidx, c.n_pw, n_orb,
                      std::sqrt(c.omega) / double(c.ng),
@@ -1422,7 +1422,7 @@ hipError_t launch_real_check(const CellDev& c, const void* coeffs, int n_orb,
   unsigned nb = grid_for(c.n_pw * n_orb);
   if (nb > 1024) nb = 1024;
   *nblocks = (int)nb;
-  hipLaunchKernelGGL(k_real_check, dim3(nb), dim3(256), 0, st,
+  LACE_LAUNCH(k_real_check, dim3(nb), dim3(256), 0, st,
                      static_cast<const double2*>(coeffs), c.n_pw, n_orb,
                      c.negidx, part);
   return hipGetLastError();

@@ -3,7 +3,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 namespace lace {
+
+// First-launch guard.  Before a kernel is launched for the first time on a
+// device, the runtime loads the library's code object and looks the kernel
+// up.  resolve_kernel does that lookup (hipFuncGetAttributes) under one
+// process-wide mutex and marks the kernel resolved on the current device,
+// so first launches from several host threads (one plan per thread) never
+// run the lookup concurrently; later launches only test a bit.
+hipError_t resolve_kernel(const void* kernel, std::atomic<uint64_t>& done);
+template <auto K> struct KernelOnce {
+  static inline std::atomic<uint64_t> done{0};   // bit d: resolved on device d
+};
+template <auto K> inline hipError_t resolved() {
+  return resolve_kernel(reinterpret_cast<const void*>(K), KernelOnce<K>::done);
+}
 
 constexpr int PMAX = 64;  // pairs per batch (kernel-argument table)
 
@@ -167,3 +183,13 @@ hipError_t launch_scdm(bool fp64, bool real, const void* psi, int n_orb,
                        void* Y, hipStream_t st);
 
 }  // namespace lace
+
+// Every kernel launch of the library: the first-launch guard, then the
+// launch.  Used inside functions that return hipError_t (a failed guard
+// returns its error).
+#define LACE_LAUNCH(K, ...)                                        \
+  do {                                                             \
+    const hipError_t lace_resolve_err_ = ::lace::resolved<K>();    \
+    if (lace_resolve_err_ != hipSuccess) return lace_resolve_err_; \
+    hipLaunchKernelGGL(K, __VA_ARGS__);                            \
+  } while (0)

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -14,6 +15,23 @@
 #include "lace.h"
 
 using namespace lace;
+
+// First-launch guard of every kernel (internal.hpp): the lookup runs under
+// this one mutex, once per kernel and device.
+hipError_t lace::resolve_kernel(const void* kernel, std::atomic<uint64_t>& done) {
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = d < 64 ? (1ull << d) : 0ull;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  static std::mutex m;
+  std::lock_guard<std::mutex> lock(m);
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  hipFuncAttributes attr;
+  e = hipFuncGetAttributes(&attr, kernel);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+  return e;
+}
 
 namespace {
 
@@ -23,7 +41,6 @@ struct CellPlan {
   int32_t* d_negidx = nullptr;
   void* d_vtab = nullptr;
   void* d_tw = nullptr;
-  int32_t* d_info = nullptr;
 };
 
 int default_pairs_per_batch(int n) {
@@ -85,7 +102,8 @@ static int hip_status(hipError_t e) { return e == hipSuccess ? LACE_OK : LACE_EH
 static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t psi, w, tmp, epart, s, part, mw, a, z, t, u, dens, scdm, pts, total;
+  size_t info, psi, w, tmp, epart, s, part, mw, a, z, t, u, dens, scdm, pts,
+      total;
   int pairs_per_batch;
 };
 
@@ -103,6 +121,9 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.pairs_per_batch = c.ppb;
   const size_t gb = (size_t)c.ng * grid_bytes(p);
   size_t off = 0;
+  // the Cholesky info word of builds that pass no info pointer: first, so
+  // that lace_get_info finds it without the layout
+  L.info = off; off += 256;
   // pair buffer and energy partials sized for the largest batch, so that
   // one workspace serves every tuning of the cell
   // orbital and W grids; for real orbitals these hold n_orb real grids and
@@ -154,8 +175,7 @@ static void free_cell(CellPlan& c) {
   c.d_negidx = nullptr;
   if (c.d_vtab) (void)hipFree(c.d_vtab);
   if (c.d_tw) (void)hipFree(c.d_tw);
-  if (c.d_info) (void)hipFree(c.d_info);
-  c.d_gidx = nullptr; c.d_vtab = nullptr; c.d_tw = nullptr; c.d_info = nullptr;
+  c.d_gidx = nullptr; c.d_vtab = nullptr; c.d_tw = nullptr;
 }
 
 // Next free profiling event (created on first use).
@@ -534,7 +554,7 @@ static void schedule_for(const lace_plan* p,
 }
 
 // ------------------------------------------------------------------ API
-extern "C" {
+// The entry points keep the C linkage of their declarations in lace.h.
 
 const char* lace_status_string(int s) {
   switch (s) {
@@ -668,7 +688,6 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
           voct[(size_t)((z * vh + y) * vh + x)] = v[x + (int64_t)n * (y + (int64_t)n * z)];
     if (e == hipSuccess) e = hipMalloc(&cp.d_vtab, (fp64 ? 8 : 4) * (size_t)nv);
     if (e == hipSuccess) e = hipMalloc(&cp.d_tw, (fp64 ? 16 : 8) * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc(&cp.d_info, sizeof(int32_t));
     if (e == hipSuccess && gamma) {
       e = hipMalloc(&cp.d_negidx, sizeof(int32_t) * d.n_pw);
       if (e == hipSuccess)
@@ -691,10 +710,6 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
         if (e == hipSuccess)
           e = hipMemcpy(cp.d_tw, twf.data(), 8 * (size_t)n, hipMemcpyHostToDevice);
       }
-    }
-    if (e == hipSuccess) {
-      int32_t zero = 0;
-      e = hipMemcpy(cp.d_info, &zero, sizeof(zero), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
       for (auto& c2 : p->cells) free_cell(c2);
@@ -964,11 +979,12 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
 }
 
 // M, E_x trace, -M_s, Cholesky, Z = L^{-H}, xi = W Z.
+// info: the call's Cholesky info word (device), or NULL for the workspace's.
 static hipError_t enqueue_build_ace(const CellPlan& cp, int n_orb, int sym,
                                     const Layout& L, void* ws,
                                     const void* psi_g, const void* w_g,
                                     void* xi_g, void* m_out, double* ex_tr,
-                                    hipStream_t st) {
+                                    int32_t* info, hipStream_t st) {
   const CellDev& c = cp.dev;
   void* m = m_out ? m_out : at(ws, L.mw);
   hipError_t e = launch_gemm_ip_c128(psi_g, c.n_pw, n_orb, w_g, c.n_pw, n_orb,
@@ -977,7 +993,9 @@ static hipError_t enqueue_build_ace(const CellPlan& cp, int n_orb, int sym,
   if (e == hipSuccess && ex_tr) e = launch_trace_re(m, n_orb, 0.5, ex_tr, st);
   if (e == hipSuccess) e = launch_neg_sym(m, n_orb, sym, at(ws, L.a), st);
   if (e == hipSuccess)
-    e = launch_cholesky(at(ws, L.a), n_orb, cp.d_info, at(ws, L.u),
+    e = launch_cholesky(at(ws, L.a), n_orb,
+                        info ? info : reinterpret_cast<int32_t*>(at(ws, L.info)),
+                        at(ws, L.u),
                         at(ws, L.part), (int64_t)(L.mw - L.part), st);
   if (e == hipSuccess) e = launch_trinv_adj(at(ws, L.a), n_orb, at(ws, L.z), st);
   if (e == hipSuccess)
@@ -1176,7 +1194,7 @@ int lace_apply_exchange_virtual(lace_plan* p, int cell, const void* psi_g,
 
 int lace_build_ace(lace_plan* p, int cell, const void* psi_g, const void* w_g,
                    int n_orb, lace_sym sym, void* xi_g, void* m_out,
-                   double* ex_tr, void* ws, size_t ws_bytes,
+                   double* ex_tr, int32_t* info, void* ws, size_t ws_bytes,
                    lace_stream_t stream) {
   int rc = check_common(p, cell, n_orb);
   if (rc) return rc;
@@ -1186,7 +1204,7 @@ int lace_build_ace(lace_plan* p, int cell, const void* psi_g, const void* w_g,
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
   return hip_status(enqueue_build_ace(p->cells[cell], n_orb, (int)sym, L, ws,
-                                      psi_g, w_g, xi_g, m_out, ex_tr,
+                                      psi_g, w_g, xi_g, m_out, ex_tr, info,
                                       static_cast<hipStream_t>(stream)));
 }
 
@@ -1410,7 +1428,9 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     lay[k] = layout_for(p, j.cell, j.n_orb, 0);
     if (j.ws_bytes < lay[k].total) return LACE_ENOMEM;
     for (int q = 0; q < k; ++q)
-      if (jobs[q].ws == j.ws || jobs[q].w_g == j.w_g) return LACE_EINVAL;
+      if (jobs[q].ws == j.ws || jobs[q].w_g == j.w_g ||
+          (j.info && jobs[q].info == j.info))
+        return LACE_EINVAL;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int ns = n_jobs < 8 ? n_jobs : 8;
@@ -1482,7 +1502,7 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
                            j.e_x, js, false);
       if (r == hipSuccess && j.xi_g)
         r = enqueue_build_ace(cp, j.n_orb, j.sym, lay[k], j.ws, j.psi_g, j.w_g,
-                              j.xi_g, j.m_out, j.ex_tr, js);
+                              j.xi_g, j.m_out, j.ex_tr, j.info, js);
     }
     return r;
   };
@@ -1502,7 +1522,8 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
                        (uint64_t)j.n_orb, (uint64_t)(uintptr_t)j.w_g,
                        (uint64_t)(uintptr_t)j.e_x, (uint64_t)j.sym,
                        (uint64_t)(uintptr_t)j.xi_g, (uint64_t)(uintptr_t)j.m_out,
-                       (uint64_t)(uintptr_t)j.ex_tr, (uint64_t)(uintptr_t)j.ws,
+                       (uint64_t)(uintptr_t)j.ex_tr, (uint64_t)(uintptr_t)j.info,
+                       (uint64_t)(uintptr_t)j.ws,
                        (uint64_t)on[k], (uint64_t)c.ppb, (uint64_t)c.use_plane,
                        (uint64_t)scheds[k].size()})
       hash_mix(key, v);
@@ -1602,16 +1623,15 @@ int lace_check_real(lace_plan* p, int cell, const void* psi_g, int n_orb,
   return LACE_OK;
 }
 
-int lace_get_info(lace_plan* p, int cell, int32_t* info_host) {
-  if (!p || !info_host || cell < 0 || cell >= (int)p->cells.size())
-    return LACE_EINVAL;
-  if (hipDeviceSynchronize() != hipSuccess) return LACE_EHIP;
+int lace_get_info(const void* ws, lace_stream_t stream, int32_t* info_host) {
+  if (!ws || !info_host) return LACE_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
   int32_t v = 0;
-  if (hipMemcpy(&v, p->cells[cell].d_info, sizeof(v), hipMemcpyDeviceToHost) !=
-      hipSuccess)
-    return LACE_EHIP;
+  // the word sits at offset 0 of every workspace layout
+  hipError_t e = hipMemcpyAsync(&v, ws, sizeof(v), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return LACE_EHIP;
   *info_host = v;
   return v == 0 ? LACE_OK : LACE_ENOTPD;
 }
 
-}  // extern "C"

@@ -312,7 +312,7 @@ static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
   const size_t dir_lds = sizeof(double2) * (size_t)n_orb * (ngrp > 1 ? 1 + ngrp : 1);
   int64_t blocks = (ng + NT - 1) / NT;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_scdm_density<G>, dim3((unsigned)blocks), dim3(NT), 0,
+  LACE_LAUNCH(k_scdm_density<G>, dim3((unsigned)blocks), dim3(NT), 0,
                      st, psi, n_orb, ng, d);
   hipError_t e = hipGetLastError();
   constexpr int VW = 16 / (int)sizeof(G);
@@ -321,19 +321,19 @@ static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
   const int64_t per_block = (int64_t)AM_NT * (vec ? VW : 1);
   const int parts = (int)std::min<int64_t>(AM_BLOCKS, (ng + per_block - 1) / per_block);
   const size_t qlds = sizeof(double2) * (size_t)n_orb;
-  hipLaunchKernelGGL(k_argmax_partial, dim3(parts), dim3(AM_NT), 0, st, d, ng,
+  LACE_LAUNCH(k_argmax_partial, dim3(parts), dim3(AM_NT), 0, st, d, ng,
                      pv, pi);
   for (int k = 0; k < n_orb && e == hipSuccess; ++k) {
-    hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(AM_NT), 0, st, pv, pi,
+    LACE_LAUNCH(k_argmax_final, dim3(1), dim3(AM_NT), 0, st, pv, pi,
                        parts, d, points, k);
-    hipLaunchKernelGGL((k_scdm_direction<G, DIR_NT>), dim3(1), dim3(DIR_NT),
+    LACE_LAUNCH((k_scdm_direction<G, DIR_NT>), dim3(1), dim3(DIR_NT),
                        dir_lds, st, psi, n_orb, ng, points, k, Q, h, ngrp);
     if (k + 1 < n_orb) {   // downdate, and the next pick's partial argmax
       if (vec)
-        hipLaunchKernelGGL((k_scdm_downdate<G, VW>), dim3(parts), dim3(AM_NT),
+        LACE_LAUNCH((k_scdm_downdate<G, VW>), dim3(parts), dim3(AM_NT),
                            qlds, st, psi, n_orb, ng, Q, k, d, pv, pi);
       else
-        hipLaunchKernelGGL((k_scdm_downdate<G, 1>), dim3(parts), dim3(AM_NT),
+        LACE_LAUNCH((k_scdm_downdate<G, 1>), dim3(parts), dim3(AM_NT),
                            qlds, st, psi, n_orb, ng, Q, k, d, pv, pi);
     }
     e = hipGetLastError();
@@ -341,7 +341,7 @@ static hipError_t scdm_t(const G* psi, int n_orb, int64_t ng, double* d,
   if (e == hipSuccess) {
     int64_t b2 = ((int64_t)n_orb * n_orb + NT - 1) / NT;
     if (b2 > 2048) b2 = 2048;
-    hipLaunchKernelGGL(k_scdm_gather<G>, dim3((unsigned)b2), dim3(NT), 0, st,
+    LACE_LAUNCH(k_scdm_gather<G>, dim3((unsigned)b2), dim3(NT), 0, st,
                        psi, n_orb, ng, points, Y);
     e = hipGetLastError();
   }

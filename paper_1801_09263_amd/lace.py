@@ -70,7 +70,8 @@ class LaceJob(ctypes.Structure):
                 ("w_g", ctypes.c_void_p), ("e_x", ctypes.c_void_p),
                 ("n_kept", ctypes.c_int64), ("sym", ctypes.c_int32),
                 ("xi_g", ctypes.c_void_p), ("m_out", ctypes.c_void_p),
-                ("ex_tr", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+                ("ex_tr", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("ws", ctypes.c_void_p),
                 ("ws_bytes", ctypes.c_size_t)]
 
 
@@ -105,10 +106,10 @@ def load(path: str = LIB_PATH):
     lib.lace_align.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, sz, vp]
     lib.lace_scdm.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
-                                   sz, vp]
+                                   vp, sz, vp]
     lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
     lib.lace_fft3d.argtypes = [vp, i32, i32, vp, i32, vp]
-    lib.lace_get_info.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
+    lib.lace_get_info.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lace_profile_enable.argtypes = [vp, i32]
     p_i64 = ctypes.POINTER(ctypes.c_int64)
     lib.lace_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -159,6 +160,19 @@ def _ptr(t, dtype=None, what="buffer"):
     if dtype is not None and t.dtype != dtype:
         raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _n_pw(plan, cell):
+    if not 0 <= int(cell) < len(plan.cells):
+        return 0     # the library rejects the cell index itself
+    return int(np.asarray(plan.cells[int(cell)]["miller"]).shape[0])
+
+
+def _need(t, count, what):
+    """The C ABI receives raw pointers and cannot see a tensor's size: an
+    undersized buffer is rejected here, before the call."""
+    if t is not None and t.numel() < count:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {count}")
 
 
 def _stream(stream):
@@ -220,6 +234,8 @@ def lace_workspace_size(plan: Plan, cell: int, n_orb: int, n_vec: int = 0):
 
 def lace_screen(plan, cell, psi_g, n_orb, s_out, ws, stream=None):
     import torch
+    _need(psi_g, n_orb * _n_pw(plan, cell), "psi_g")
+    _need(s_out, n_orb * n_orb, "s_out")
     _check(load().lace_screen(plan.handle, cell,
                               _ptr(psi_g, torch.complex128, "psi_g"), n_orb,
                               _ptr(s_out, torch.float64, "s_out"),
@@ -232,6 +248,10 @@ def lace_apply_exchange_virtual(plan, cell, psi_g, n_occ, n_virt, s_thr, w_g,
     """W for n_occ occupied and n_virt virtual orbitals (occupied first).
     Returns the number of pair transforms run."""
     import torch
+    n = (int(n_occ) + int(n_virt)) * _n_pw(plan, cell)
+    _need(psi_g, n, "psi_g")
+    _need(w_g, n, "w_g")
+    _need(e_x, 1, "e_x")
     kept = ctypes.c_int64(0)
     _check(load().lace_apply_exchange_virtual(
         plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), int(n_occ),
@@ -246,6 +266,11 @@ def lace_align(plan, cell, psi_new, psi_old, n_orb, psi_out, resid, ws,
                stream=None):
     """psi_out = psi_new U, U the unitary closest to psi_new^H psi_old."""
     import torch
+    n = n_orb * _n_pw(plan, cell)
+    for t, name in ((psi_new, "psi_new"), (psi_old, "psi_old"),
+                    (psi_out, "psi_out")):
+        _need(t, n, name)
+    _need(resid, 1, "resid")
     _check(load().lace_align(
         plan.handle, cell, _ptr(psi_new, torch.complex128, "psi_new"),
         _ptr(psi_old, torch.complex128, "psi_old"), int(n_orb),
@@ -258,6 +283,11 @@ def lace_scdm(plan, cell, psi_g, n_orb, phi_g, points, resid, ws,
               stream=None):
     """phi = SCDM-localized psi; points (int32 device tensor or None)."""
     import torch
+    n = n_orb * _n_pw(plan, cell)
+    _need(psi_g, n, "psi_g")
+    _need(phi_g, n, "phi_g")
+    _need(points, n_orb, "points")
+    _need(resid, 1, "resid")
     _check(load().lace_scdm(
         plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), int(n_orb),
         _ptr(phi_g, torch.complex128, "phi_g"),
@@ -271,6 +301,9 @@ def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,
     """``pairs``: None (screen with s_thr) or an (n, 2) int array of
     unordered pairs i <= j.  Returns the number of pairs run."""
     import torch
+    _need(psi_g, n_orb * _n_pw(plan, cell), "psi_g")
+    _need(w_g, n_orb * _n_pw(plan, cell), "w_g")
+    _need(e_x, 1, "e_x")
     if pairs is None:
         pi = pj = None
         npairs = 0
@@ -292,20 +325,34 @@ def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,
 
 
 def lace_build_ace(plan, cell, psi_g, w_g, n_orb, sym, xi_g, m_out, ex_tr, ws,
-                   stream=None):
+                   stream=None, info=None):
+    """``info``: optional int32 device tensor (one element) that receives
+    the Cholesky info word of this call; None keeps it in the workspace
+    (read with ``lace_get_info(ws, stream)``)."""
     import torch
+    n = n_orb * _n_pw(plan, cell)
+    for t, name in ((psi_g, "psi_g"), (w_g, "w_g"), (xi_g, "xi_g")):
+        _need(t, n, name)
+    _need(m_out, n_orb * n_orb, "m_out")
+    _need(ex_tr, 1, "ex_tr")
+    _need(info, 1, "info")
     mode = SYM_MODES[sym] if isinstance(sym, str) else int(sym)
     _check(load().lace_build_ace(
         plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"),
         _ptr(w_g, torch.complex128, "w_g"), n_orb, mode,
         _ptr(xi_g, torch.complex128, "xi_g"),
         _ptr(m_out, torch.complex128, "m_out"),
-        _ptr(ex_tr, torch.float64, "ex_tr"), _ptr(ws, None, "ws"),
+        _ptr(ex_tr, torch.float64, "ex_tr"),
+        _ptr(info, torch.int32, "info"), _ptr(ws, None, "ws"),
         ws.numel() * ws.element_size(), _stream(stream)), "lace_build_ace")
 
 
 def lace_apply_ace(plan, cell, xi_g, n_orb, x_g, n_vec, y_g, ws, stream=None):
     import torch
+    n_pw = _n_pw(plan, cell)
+    _need(xi_g, n_orb * n_pw, "xi_g")
+    _need(x_g, n_vec * n_pw, "x_g")
+    _need(y_g, n_vec * n_pw, "y_g")
     _check(load().lace_apply_ace(
         plan.handle, cell, _ptr(xi_g, torch.complex128, "xi_g"), n_orb,
         _ptr(x_g, torch.complex128, "x_g"), n_vec,
@@ -314,14 +361,24 @@ def lace_apply_ace(plan, cell, xi_g, n_orb, x_g, n_vec, y_g, ws, stream=None):
 
 
 def lace_fft3d(plan, cell, direction, grids, count, stream=None):
+    if 0 <= int(cell) < len(plan.cells) and grids is not None:
+        n = int(plan.cells[int(cell)]["n"])
+        point = 16 if plan.precision in (LACE_FP64, LACE_FP64_GAMMA) else 8
+        need = int(count) * n ** 3 * point
+        if grids.numel() * grids.element_size() < need:
+            raise ValueError(f"grids holds {grids.numel() * grids.element_size()}"
+                             f" bytes, needs {need}")
     _check(load().lace_fft3d(plan.handle, cell, int(direction),
                              _ptr(grids, None, "grids"), int(count),
                              _stream(stream)), "lace_fft3d")
 
 
-def lace_get_info(plan, cell) -> int:
+def lace_get_info(ws, stream=None) -> int:
+    """Cholesky info word of the last ACE build that used workspace ``ws``
+    without an info tensor (synchronizes ``stream``)."""
     info = ctypes.c_int32(0)
-    code = load().lace_get_info(plan.handle, cell, ctypes.byref(info))
+    code = load().lace_get_info(_ptr(ws, None, "ws"), _stream(stream),
+                                ctypes.byref(info))
     if code not in (LACE_OK, LACE_ENOTPD):
         _check(code, "lace_get_info")
     return info.value
@@ -349,6 +406,7 @@ def lace_profile_read(plan):
 def lace_check_real(plan, cell, psi_g, n_orb, ws, stream=None) -> float:
     """Relative deviation of the orbitals from C_{-G} = conj(C_G)."""
     import torch
+    _need(psi_g, n_orb * _n_pw(plan, cell), "psi_g")
     out = ctypes.c_double(0.0)
     _check(load().lace_check_real(plan.handle, cell,
                                   _ptr(psi_g, torch.complex128, "psi_g"),
@@ -403,6 +461,12 @@ def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
     import torch
     arr = (LaceJob * len(jobs))()
     for k, j in enumerate(jobs):
+        n_orb, n_pw = int(j["n_orb"]), _n_pw(plan, j.get("cell", 0))
+        for name in ("psi_g", "w_g", "xi_g"):
+            _need(j.get(name), n_orb * n_pw, name)
+        _need(j.get("m_out"), n_orb * n_orb, "m_out")
+        for name in ("e_x", "ex_tr", "info"):
+            _need(j.get(name), 1, name)
         for name in ("psi_g", "w_g", "xi_g", "m_out"):
             t = j.get(name)
             if t is not None:
@@ -411,6 +475,8 @@ def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
             t = j.get(name)
             if t is not None:
                 _ptr(t, torch.float64, name)
+        if j.get("info") is not None:
+            _ptr(j["info"], torch.int32, "info")
         _ptr(j["ws"], None, "ws")
         arr[k].cell = int(j.get("cell", 0))
         arr[k].psi_g = _vp(j["psi_g"])
@@ -423,6 +489,7 @@ def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
         arr[k].xi_g = _vp(j.get("xi_g"))
         arr[k].m_out = _vp(j.get("m_out"))
         arr[k].ex_tr = _vp(j.get("ex_tr"))
+        arr[k].info = _vp(j.get("info"))
         arr[k].ws = _vp(j["ws"])
         arr[k].ws_bytes = j["ws"].numel() * j["ws"].element_size()
     _check(load().lace_apply_exchange_batched(
@@ -448,6 +515,7 @@ def lace_autotune(plan, cell, psi_g, n_orb, ws, stream=None):
     """Time every pipeline candidate on this cell, keep the fastest.
     Returns a list of (pairs_per_batch, use_plane, us_per_pair)."""
     import torch
+    _need(psi_g, n_orb * _n_pw(plan, cell), "psi_g")
     cap = 16
     ppb = (ctypes.c_int * cap)()
     pl = (ctypes.c_int * cap)()

@@ -51,6 +51,7 @@ class Job:
     slot: int = -1
     e_x: list = dataclasses.field(default_factory=list)
     kept: list = dataclasses.field(default_factory=list)
+    info: list = dataclasses.field(default_factory=list)
     xi_host: object = None
 
 
@@ -103,6 +104,9 @@ class Server:
             ex = torch.zeros(len(job.variants), dtype=torch.float64,
                              device=self.device)
             ex_tr = torch.empty(1, dtype=torch.float64, device=self.device)
+            # Cholesky info word of each outer step's ACE build
+            info = torch.zeros(len(job.variants), dtype=torch.int32,
+                               device=self.device)
             ws = torch.empty(lace.lace_workspace_size(plan, cell, n, n),
                              dtype=torch.uint8, device=self.device)
             prev = None
@@ -119,7 +123,7 @@ class Server:
                     plan, cell, psi, n, c.cell.get("s_thr", 0.0), None, w,
                     ex[step:step + 1], ws, st)
                 lace.lace_build_ace(plan, cell, psi, w, n, "avg", xi, m,
-                                    ex_tr, ws, st)
+                                    ex_tr, ws, st, info=info[step:step + 1])
                 for _ in range(self.inner):
                     lace.lace_apply_ace(plan, cell, xi, n, psi, n, y, ws, st)
                 job.kept.append(kept)
@@ -127,9 +131,13 @@ class Server:
             st.synchronize()
         job.done = time.perf_counter() - t0
         job.e_x = ex.cpu().tolist()
+        job.info = info.cpu().tolist()
         if self.keep_xi:
             job.xi_host = xi.cpu().numpy()
-        del w, xi, y, m, ex, ex_tr, ws
+        del w, xi, y, m, ex, ex_tr, ws, info
+        if any(job.info):
+            raise lace.LaceError(lace.LACE_ENOTPD,
+                                 f"job {job.jid}: ACE build (info {job.info})")
 
     def _worker(self, slot, inbox, outbox, t0):
         while True:

@@ -70,8 +70,10 @@ class CellSession:
         return lace.lace_check_real(self.plan, 0, self.psi, self.n_orb,
                                     self.ws, stream)
 
-    def info(self) -> int:
-        return lace.lace_get_info(self.plan, 0)
+    def info(self, stream=None) -> int:
+        """Cholesky info word of the last build_ace (synchronizes the
+        stream)."""
+        return lace.lace_get_info(self.ws, stream)
 
     def apply_ace(self, x, y=None, stream=None):
         n_vec = x.shape[0]

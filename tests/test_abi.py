@@ -69,13 +69,13 @@ def test_null_arguments_rejected(lib):
     assert lib.lace_apply_exchange(None, 0, None, 8, 0.0, None, None, 0, None,
                                    None, None, None, 0, None) == lace.LACE_EINVAL
     assert lib.lace_build_ace(None, 0, None, None, 8, 0, None, None, None,
-                              None, 0, None) == lace.LACE_EINVAL
+                              None, None, 0, None) == lace.LACE_EINVAL
     assert lib.lace_apply_ace(None, 0, None, 8, None, 1, None, None, 0,
                               None) == lace.LACE_EINVAL
     assert lib.lace_fft3d(None, 0, -1, None, 1, None) == lace.LACE_EINVAL
     assert lib.lace_screen(None, 0, None, 8, None, None, 0, None) == lace.LACE_EINVAL
     info = ctypes.c_int32()
-    assert lib.lace_get_info(None, 0, ctypes.byref(info)) == lace.LACE_EINVAL
+    assert lib.lace_get_info(None, None, ctypes.byref(info)) == lace.LACE_EINVAL
     assert lib.lace_plan_destroy(None) == lace.LACE_OK
 
 
@@ -195,3 +195,33 @@ def test_slot_schedule_rejects_bad_pairs(lib):
                          ([(0, 1)], 4, 0)):
         with pytest.raises(lace.LaceError):
             lace.lace_schedule_slots(pairs, n, pb)
+
+
+def test_binding_rejects_undersized_buffers():
+    """The C ABI receives bare pointers, so the binding checks every
+    buffer's element count against the cell's plane-wave count and the
+    orbital count before it calls the library."""
+    torch = pytest.importorskip("torch")
+    miller = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0],
+                       [0, -1, 0]], np.int32)
+    plan = lace.Plan(None, [dict(L=10.0, n=24, miller=miller)], lace.LACE_FP32)
+    ok = torch.zeros((4, 5), dtype=torch.complex128)
+    short = torch.zeros((3, 5), dtype=torch.complex128)
+    ws = torch.zeros(16, dtype=torch.uint8)
+    m = torch.zeros((4, 4), dtype=torch.complex128)
+    calls = [
+        lambda: lace.lace_apply_exchange(plan, 0, short, 4, 0.0, None, ok,
+                                         None, ws),
+        lambda: lace.lace_apply_exchange(plan, 0, ok, 4, 0.0, None, short,
+                                         None, ws),
+        lambda: lace.lace_build_ace(plan, 0, ok, ok, 4, "avg", short, m, None,
+                                    ws),
+        lambda: lace.lace_build_ace(plan, 0, ok, ok, 4, "avg", ok, m[:3], None,
+                                    ws),
+        lambda: lace.lace_apply_ace(plan, 0, ok, 4, ok, 4, short, ws),
+        lambda: lace.lace_align(plan, 0, ok, short, 4, ok, None, ws),
+        lambda: lace.lace_screen(plan, 0, ok, 4, torch.zeros(15), ws),
+    ]
+    for call in calls:
+        with pytest.raises(ValueError):
+            call()
