@@ -112,7 +112,6 @@ def run_step(sess, s_thr, y):
     sess.apply_exchange(s_thr)
     sess.build_ace("avg")
     sess.apply_ace(sess.psi, y)
-    return sess.n_kept
 
 
 def time_steps(torch, sess, s_thr, steps, warmup, profile=False):
@@ -125,11 +124,11 @@ def time_steps(torch, sess, s_thr, steps, warmup, profile=False):
         lace.lace_profile_enable(sess.plan, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    n_kept = 0
     for _ in range(steps):
-        n_kept = run_step(sess, s_thr, y)
+        run_step(sess, s_thr, y)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    n_kept = sess.n_kept
     prof = None
     if profile:
         prof = lace.lace_profile_read(sess.plan)

@@ -130,24 +130,36 @@ int lace_screen(lace_plan* plan, int cell, const void* psi_g, int n_orb,
 
 /* W = K psi restricted to the kept pairs (Eq. (2) truncated by
  * Eqs. (6)-(8)).
- *   psi_g   device, n_pw x n_orb complex128, orthonormal orbitals.
+ *   psi_g   device, n_pw x n_orb complex128, orthonormal orbitals
+ *           (1 <= n_orb <= 4096; also for the virtual, batched and
+ *           autotuning calls).
  *   s_thr   screening threshold in [0, 1): an unordered pair (i, j) is kept
- *           when S_ij >= s_thr; s_thr = 0 keeps every pair (plain ACE).
- *   pair_i, pair_j  optional host int32 arrays of n_pairs unordered pairs
- *           (0 <= i <= j < n_orb, no repeats) that override the screening;
- *           pass NULL/NULL/0 to screen with s_thr.
+ *           when S_ij >= s_thr (Eq. (6)); s_thr = 0 keeps every pair (plain
+ *           ACE).
+ *   pair_i, pair_j  optional device int32 arrays of n_pairs unordered pairs
+ *           (0 <= i <= j < n_orb) that replace the screening; pass
+ *           NULL/NULL/0 to screen with s_thr.  A pair out of range or with
+ *           i > j is dropped and a repeat runs once (n_kept then differs
+ *           from n_pairs).
  *   w_g     device, n_pw x n_orb complex128 output (K psi on the sphere).
  *   e_x     device double output (may be NULL): exchange energy
  *           -(1/2) sum over kept ordered pairs of (ij|ji), summed in FP64
  *           from the pair densities.
- *   n_kept  host int64 output (may be NULL): number of unordered pairs run.
- * With screening (pair_i == NULL and s_thr > 0) the call synchronizes the
- * stream once to read S back and build the pair schedule on the host;
- * otherwise it is asynchronous.  Errors: EINVAL, ENOMEM (workspace), EHIP. */
+ *   n_kept  device int64 output (may be NULL): unordered pairs run.
+ *   kept    device int32 output (may be NULL; written only when the call
+ *           screens, pair_i == NULL), room for n_orb (n_orb + 1) int32:
+ *           the kept pairs (i, j), i <= j, as consecutive int32 couples,
+ *           column by column (j ascending), i ascending within a column;
+ *           n_kept of them.
+ * The screening decision, the pair list and the batch schedule are made on
+ * the device; the call is asynchronous (it enqueues as many pipeline
+ * launches as a schedule of any pair set can need; those past the end of
+ * this schedule return at once).  Errors: EINVAL, ENOMEM (workspace),
+ * EHIP. */
 int lace_apply_exchange(lace_plan* plan, int cell, const void* psi_g,
                         int n_orb, double s_thr, const int32_t* pair_i,
                         const int32_t* pair_j, int64_t n_pairs, void* w_g,
-                        double* e_x, int64_t* n_kept, void* ws,
+                        double* e_x, int64_t* n_kept, int32_t* kept, void* ws,
                         size_t ws_bytes, lace_stream_t stream);
 
 /* W = K psi for occupied plus virtual orbitals (the band-gap setting of the
@@ -162,13 +174,13 @@ int lace_apply_exchange(lace_plan* plan, int cell, const void* psi_g,
  *   w_g     device, n_pw x (n_occ + n_virt) complex128 output.
  *   e_x     device double (may be NULL): the exchange energy of the
  *           occupied orbitals, as for lace_apply_exchange.
- *   n_kept  host int64 (may be NULL): pair transforms run (kept occupied
+ *   n_kept  device int64 (may be NULL): pair transforms run (kept occupied
  *           pairs + n_occ n_virt).
  * The workspace is that of n_orb = n_occ + n_virt.  lace_build_ace with
  * n_orb = n_occ + n_virt then builds ACE on the whole projection space
- * (its ex_tr then includes the virtual diagonal and is not E_x).  Same
- * synchronization and errors as lace_apply_exchange (n_occ >= 1,
- * n_virt >= 0). */
+ * (its ex_tr then includes the virtual diagonal and is not E_x).
+ * Asynchronous, like lace_apply_exchange.  Errors: EINVAL (n_occ < 1,
+ * n_virt < 0, ...), ENOMEM, EHIP. */
 int lace_apply_exchange_virtual(lace_plan* plan, int cell, const void* psi_g,
                                 int n_occ, int n_virt, double s_thr,
                                 void* w_g, double* e_x, int64_t* n_kept,
@@ -242,7 +254,7 @@ int lace_apply_ace(lace_plan* plan, int cell, const void* xi_g, int n_orb,
  * ACE build) of one set of orbitals on one cell of the plan.  Fields are as
  * in lace_apply_exchange / lace_build_ace; each job brings its own
  * workspace (sized by lace_workspace_size for its cell and n_orb) because
- * jobs run concurrently.  n_kept is an output, written by the call. */
+ * jobs run concurrently. */
 typedef struct {
   int32_t cell;
   const void* psi_g;     /* device n_pw x n_orb complex128 */
@@ -250,7 +262,7 @@ typedef struct {
   double s_thr;          /* [0, 1) */
   void* w_g;             /* device n_pw x n_orb complex128, output */
   double* e_x;           /* device, may be NULL */
-  int64_t n_kept;        /* output: pairs run */
+  int64_t* n_kept;       /* device int64, may be NULL: pairs run */
   int32_t sym;           /* lace_sym, used when xi_g != NULL */
   void* xi_g;            /* device n_pw x n_orb, or NULL: no ACE build */
   void* m_out;           /* device n_orb x n_orb complex128, may be NULL */
@@ -266,15 +278,16 @@ typedef struct {
 /* Several independent exchange applications (and ACE builds) at once, on
  * cells of any supported sizes: the multi-cell batching of the same method.
  * Jobs are spread over the plan's internal streams (forked from and joined
- * back to `stream`), so small cells overlap on the device.  Grid orbitals
- * and screening run first; if any job screens (s_thr > 0) the call
- * synchronizes once to build all pair schedules on the host.  With
- * LACE_BATCH_GRAPH, the pair pipelines, W back-transforms and ACE builds of
- * all jobs are captured in one HIP graph that is cached on the plan and
- * replayed while the jobs, their pair lists and buffers stay the same.
- * Results are identical to running each job alone (same kernels, same
- * schedule, same summation order).  Errors: EINVAL (a bad job), ENOMEM (a
- * job workspace too small), EHIP. */
+ * back to `stream`), so small cells overlap on the device.  Every step of
+ * every job (grid orbitals, screening, pair list and schedule, pair
+ * pipeline, W back-transform, ACE build) runs on the device; the call is
+ * asynchronous.  With LACE_BATCH_GRAPH all of it is captured in one HIP
+ * graph, cached on the plan and replayed while the jobs' buffers, counts,
+ * thresholds and the plan's tuning stay the same (a replay screens the
+ * orbitals the buffers then hold).  Results are identical to running each
+ * job alone (same kernels, same schedule, same summation order).  Errors:
+ * EINVAL (a bad job, two jobs sharing a workspace, W or info word),
+ * ENOMEM (a job workspace too small), EHIP. */
 int lace_apply_exchange_batched(lace_plan* plan, lace_job* jobs, int n_jobs,
                                 int flags, lace_stream_t stream);
 
@@ -317,32 +330,47 @@ int lace_fft3d(lace_plan* plan, int cell, int direction, void* grids,
  * pointers, EHIP. */
 int lace_get_info(const void* ws, lace_stream_t stream, int32_t* info_host);
 
-/* Host only, no device work: the batch schedule lace_apply_exchange uses.
- * The n_pairs unordered pairs (host arrays, 0 <= i <= j < n_orb) are
- * grouped into batches of at most per_batch (1..64) pairs in which no
- * orbital appears twice; batch_of[k] (host, n_pairs int32) receives the
- * batch of pair k and *n_batches the number of batches.  Pairs are ordered
- * by their round in a round-robin tournament over the orbitals, whose rounds
- * are sets of disjoint pairs. */
+/* Host only, no device work: the batch schedule that lace_apply_exchange
+ * builds on the device for plans of complex orbitals, computed the same way
+ * on the host (the results are identical).  The n_pairs unordered pairs
+ * (host arrays, 0 <= i <= j < n_orb <= 4096, no repeats) are grouped into
+ * batches of at most per_batch (1..64) pairs in which no orbital appears
+ * twice; batch_of[k] (host, n_pairs int32) receives the batch of pair k and
+ * *n_batches the number of batches.  Pairs are taken round by round of a
+ * round-robin tournament over the orbitals (every round a set of disjoint
+ * pairs) and placed first-fit into a window of eight open batches. */
 int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int64_t* n_batches);
 
-/* Host only, no device work: the schedule lace_apply_exchange uses on plans
- * of real orbitals (LACE_*_GAMMA), where two pair densities share one
- * complex transform, a slot.  Same arguments as lace_schedule_pairs, plus
- * slot_of[k] (host, n_pairs int32), the slot of pair k within its batch.
- * A slot holds one or two pairs of the same kind (both diagonal or both
- * off-diagonal); two off-diagonal pairs of a slot share an orbital where the
- * pair set allows it, so the slot reads and updates three orbital grids
+/* Host only, no device work: the schedule lace_apply_exchange builds on the
+ * device for plans of real orbitals (LACE_*_GAMMA), where two pair
+ * densities share one complex transform, a slot; computed the same way on
+ * the host.  Same arguments as lace_schedule_pairs, plus slot_of[k] (host,
+ * n_pairs int32), the slot of pair k within its batch.  A slot holds one or
+ * two pairs of the same kind (both diagonal or both off-diagonal); two
+ * off-diagonal pairs of a slot share an orbital where the pair set allows
+ * it (a star slot), so the slot reads and updates three orbital grids
  * instead of four (the pair products are those inside the integrals of
- * Eqs. (2) and (8)).  No orbital
- * appears in two slots of one batch; a batch holds at most per_batch pairs
- * and (per_batch + 1) / 2 slots. */
+ * Eqs. (2) and (8)).  Stars come from the cycle that two consecutive rounds
+ * of the round robin form, then from left-over pairs meeting at an orbital.
+ * No orbital appears in two slots of one batch; a batch holds at most
+ * per_batch pairs and (per_batch + 1) / 2 slots. */
 int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int32_t* slot_of,
                         int64_t* n_batches);
+
+/* The schedule the last exchange call on workspace `ws` (cell, n_orb of
+ * that call) built on the device, read back: for each of the n_pairs given
+ * unordered pairs (host arrays) its batch and slot (-1 when the schedule
+ * does not hold it), and the number of batches.  Synchronizes `stream`.
+ * For tests and inspection.  Errors: EINVAL, EHIP. */
+int lace_read_schedule(const lace_plan* plan, int cell, int n_orb,
+                       const void* ws, lace_stream_t stream,
+                       const int32_t* pair_i, const int32_t* pair_j,
+                       int64_t n_pairs, int32_t* batch_of, int32_t* slot_of,
+                       int64_t* n_batches);
 
 /* Kernel timing of the pair pipeline of lace_apply_exchange, for
  * roofline measurement.  While enabled, every batch of the pipeline is
@@ -350,8 +378,10 @@ int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
  *   0  pass A: pair product + forward transform along x and y,
  *   1  pass B: forward z transform, kernel multiply, backward z transform,
  *   2  pass C: backward transform along y and x + accumulation into W.
- * lace_profile_enable(plan, 1) clears the totals and starts recording,
- * (plan, 0) stops.  lace_profile_read synchronizes the device and returns
+ * While enabled, an exchange call reads its schedule back (synchronizing
+ * the stream) and launches only the batches it holds, one at a time on the
+ * call's stream.  lace_profile_enable(plan, 1) clears the totals and starts
+ * recording, (plan, 0) stops.  lace_profile_read synchronizes the device and returns
  * per pass: total milliseconds ms[3], launches (batches) launches[3], pairs
  * processed pairs[3], and algorithmic HBM bytes alg_bytes[3].  With U the
  * bytes of one complex grid, G those of one orbital grid (U, or U/2 for

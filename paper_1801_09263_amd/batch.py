@@ -31,10 +31,10 @@ class MultiCell:
                 xi_g=torch.zeros((n, n_pw), **z),
                 m_out=torch.zeros((n, n), **z),
                 e_x=torch.zeros(1, dtype=torch.float64, device=device),
+                n_kept=torch.zeros(1, dtype=torch.int64, device=device),
                 ex_tr=torch.zeros(1, dtype=torch.float64, device=device),
                 ws=torch.empty(nbytes, dtype=torch.uint8, device=device),
                 sym="avg"))
-        self.n_kept = [0] * len(cells)
 
     def set_orbitals(self, k, coeffs):
         self.jobs[k]["psi_g"].copy_(torch.as_tensor(
@@ -44,10 +44,15 @@ class MultiCell:
         jobs = self.jobs if build_ace else [
             {k: v for k, v in j.items() if k not in ("xi_g", "m_out", "ex_tr")}
             for j in self.jobs]
-        self.n_kept = lace.lace_apply_exchange_batched(self.plan, jobs,
-                                                       graph=graph,
-                                                       stream=stream)
+        lace.lace_apply_exchange_batched(self.plan, jobs, graph=graph,
+                                         stream=stream)
         return self.n_kept
+
+    @property
+    def n_kept(self):
+        """Pairs run per job by the last call (synchronizes the device)."""
+        torch.cuda.synchronize()
+        return [int(j["n_kept"].item()) for j in self.jobs]
 
     def autotune(self, k, stream=None):
         j = self.jobs[k]

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "liblace.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["lace_api.hip", "fft_kernels.hip", "dense_kernels.hip",
-           "scdm_kernels.hip"]
+           "scdm_kernels.hip", "screen_kernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -13,7 +13,9 @@
 //           W_j -= psi_i V_ij and, for i != j, W_i -= psi_j conj(V_ij)
 //           (V_ji = conj(V_ij) because v is real and even in G).
 // Pairs inside a batch share no orbital, so pass C needs no atomics and the
-// accumulation order is fixed by the host schedule.
+// accumulation order is fixed by the schedule.  Batches are read from a
+// table in device memory; the launches are sized for a batch's capacity and
+// every kernel reads the batch's own slot count.
 #include "fft_core.hpp"
 #include "internal.hpp"
 
@@ -62,7 +64,16 @@ __device__ inline void stv(E* p, const Vec<E, V>& r) {
 
 struct NoPre {};
 
+// Functor traits.  TABLE: the functor reads a batch of the pair pipeline
+// from device memory (bt) and knows its slot count; DYN: the batch says
+// whether every slot is a star slot, and the kernel takes the star or the
+// general form of the functor for the whole workgroup (as_star).
+#define LACE_PLAIN_FUNCTOR              \
+  static constexpr bool TABLE = false; \
+  static constexpr bool DYN = false;
+
 template <typename T> struct ProGrid {
+  LACE_PLAIN_FUNCTOR
   static constexpr int V = 16 / sizeof(C<T>);
   const C<T>* __restrict__ buf;
   int64_t gs;
@@ -75,17 +86,20 @@ template <typename T> struct ProGrid {
 // rho = conj(psi_i) psi_j
 template <typename T> struct ProPair {
   static constexpr int V = 16 / sizeof(C<T>);
+  static constexpr bool TABLE = true;
+  static constexpr bool DYN = false;
   const C<T>* __restrict__ psi;
   int64_t gs;
-  PairArgs pa;
+  const BatchDev* __restrict__ bt;
   __device__ void getv(int g, int slot, C<T>* out) const {
-    const Vec<C<T>, V> a = ldv<C<T>, V>(psi + pa.i[slot] * gs + g);
-    const Vec<C<T>, V> b = ldv<C<T>, V>(psi + pa.j[slot] * gs + g);
+    const Vec<C<T>, V> a = ldv<C<T>, V>(psi + bt->i[slot] * gs + g);
+    const Vec<C<T>, V> b = ldv<C<T>, V>(psi + bt->j[slot] * gs + g);
 #pragma unroll
     for (int v = 0; v < V; ++v) out[v] = cmul<T>(a.e[v], b.e[v]);
   }
 };
 template <typename T> struct EpiGrid {
+  LACE_PLAIN_FUNCTOR
   static constexpr int V = 16 / sizeof(C<T>);
   static constexpr int CH = 4;   // vectors per chunk of in-flight loads
   using Pre = NoPre;
@@ -103,6 +117,7 @@ template <typename T> struct EpiGrid {
 // Two real grids packed as one complex grid: value W_{2p} + i W_{2p+1}
 // (zero imaginary part for a last odd grid).  Reads 16 bytes per grid.
 template <typename T> struct ProPackReal {
+  LACE_PLAIN_FUNCTOR
   static constexpr int V = 16 / sizeof(T);
   const T* __restrict__ w;
   int64_t gs;
@@ -124,6 +139,7 @@ template <typename T> struct ProPackReal {
 };
 // The inverse: scale * (Re, Im) into the real grids 2p and 2p + 1.
 template <typename T> struct EpiSplitReal {
+  LACE_PLAIN_FUNCTOR
   static constexpr int V = 16 / sizeof(T);
   static constexpr int CH = 4;
   using Pre = NoPre;
@@ -152,16 +168,18 @@ template <typename T> struct AccPre {
 template <typename T> struct EpiAcc {
   static constexpr int V = 16 / sizeof(C<T>);
   static constexpr int CH = 4;
+  static constexpr bool TABLE = true;
+  static constexpr bool DYN = false;
   using Pre = AccPre<T>;
   const C<T>* __restrict__ psi;
   C<T>* __restrict__ w;
   int64_t gs;
-  PairArgs pa;
+  const BatchDev* __restrict__ bt;
   __device__ void prev(int g, int slot, Pre& r) const {
     // a diagonal pair reads its orbital twice (from cache), and so does a
     // one-sided pair its psi_i and W_j; the stores decide
-    const int i = pa.i[slot], j = pa.j[slot];
-    const bool os = (pa.one_sided >> slot) & 1ull;
+    const int i = bt->i[slot], j = bt->j[slot];
+    const bool os = (bt->one_sided >> slot) & 1ull;
     const int jj = os ? i : j, ii = os ? j : i;
     r.pi = ldv<C<T>, V>(psi + i * gs + g);
     r.wj = ldv<C<T>, V>(w + j * gs + g);
@@ -169,8 +187,8 @@ template <typename T> struct EpiAcc {
     r.wi = ldv<C<T>, V>(w + ii * gs + g);
   }
   __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
-    const int i = pa.i[slot], j = pa.j[slot];
-    const bool os = (pa.one_sided >> slot) & 1ull;
+    const int i = bt->i[slot], j = bt->j[slot];
+    const bool os = (bt->one_sided >> slot) & 1ull;
     Vec<C<T>, V> yj, yi;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -186,11 +204,13 @@ template <typename T> struct EpiAcc {
 // of the launch is a star slot (k = i), whose three orbitals are read once.
 template <typename T, bool STAR = false> struct ProQuad {
   static constexpr int V = 16 / sizeof(T);
+  static constexpr bool TABLE = true;
+  static constexpr bool DYN = false;
   const T* __restrict__ psi;
   int64_t gs;
-  QuadArgs qa;
+  const BatchDev* __restrict__ bt;
   __device__ void getv(int g, int slot, C<T>* out) const {
-    const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    const int i = bt->i[slot], j = bt->j[slot], k = bt->k[slot], l = bt->l[slot];
     if constexpr (STAR) {
       const Vec<T, V> a = ldv<T, V>(psi + i * gs + g);
       const Vec<T, V> b = ldv<T, V>(psi + j * gs + g);
@@ -225,17 +245,19 @@ template <typename T> struct QuadPre {
 template <typename T, bool STAR = false> struct EpiAccQuad {
   static constexpr int V = 16 / sizeof(T);
   static constexpr int CH = 2;
+  static constexpr bool TABLE = true;
+  static constexpr bool DYN = false;
   using Pre = QuadPre<T>;
   const T* __restrict__ psi;
   T* __restrict__ w;
   int64_t gs;
-  QuadArgs qa;
+  const BatchDev* __restrict__ bt;
   __device__ void flags(int slot, bool s[4]) const {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) s[t] = (qa.skip[t] >> slot) & 1ull;
+    for (int t = 0; t < 4; ++t) s[t] = (bt->skip[t] >> slot) & 1ull;
   }
   __device__ void prev(int g, int slot, Pre& r) const {
-    const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    const int i = bt->i[slot], j = bt->j[slot], k = bt->k[slot], l = bt->l[slot];
     bool sk[4];
     flags(slot, sk);
     if constexpr (STAR) {
@@ -258,7 +280,7 @@ template <typename T, bool STAR = false> struct EpiAccQuad {
     }
   }
   __device__ void putv(int g, int slot, const C<T>* x, const Pre& r) const {
-    const int i = qa.i[slot], j = qa.j[slot], k = qa.k[slot], l = qa.l[slot];
+    const int i = bt->i[slot], j = bt->j[slot], k = bt->k[slot], l = bt->l[slot];
     bool sk[4];
     flags(slot, sk);
     if constexpr (STAR) {
@@ -294,6 +316,67 @@ template <typename T, bool STAR = false> struct EpiAccQuad {
     }
   }
 };
+
+// The batch decides between the star and the general form (DYN): the
+// kernel branches once, at its top, into the whole body of either form, so
+// each form keeps its own load schedule (a branch inside the load functions
+// serialized a thread's loads).
+template <typename T> struct ProQuadD {
+  static constexpr int V = 16 / sizeof(T);
+  static constexpr bool TABLE = true;
+  static constexpr bool DYN = true;
+  const T* __restrict__ psi;
+  int64_t gs;
+  const BatchDev* __restrict__ bt;
+  template <bool S> __device__ ProQuad<T, S> form() const { return {psi, gs, bt}; }
+};
+template <typename T> struct EpiAccQuadD {
+  static constexpr int V = 16 / sizeof(T);
+  static constexpr int CH = 2;
+  static constexpr bool TABLE = true;
+  static constexpr bool DYN = true;
+  using Pre = QuadPre<T>;
+  const T* __restrict__ psi;
+  T* __restrict__ w;
+  int64_t gs;
+  const BatchDev* __restrict__ bt;
+  template <bool S> __device__ EpiAccQuad<T, S> form() const { return {psi, w, gs, bt}; }
+};
+
+template <bool S, class F> __device__ inline auto as_star(const F& f) {
+  if constexpr (F::DYN) return f.template form<S>();
+  else return f;
+}
+
+// Slots of the launch: the batch's own count for table functors, else the
+// host's count.
+template <class Pro, class Epi>
+__device__ inline int active_slots(const Pro& pro, const Epi& epi, int host) {
+  if constexpr (Pro::TABLE) {
+    const int n = pro.bt->n;
+    return n < host ? n : host;
+  } else if constexpr (Epi::TABLE) {
+    const int n = epi.bt->n;
+    return n < host ? n : host;
+  } else {
+    return host;
+  }
+}
+
+// Run body(pro', epi') with the star or the general form of dynamic functors.
+template <class Pro, class Epi, class Body>
+__device__ __forceinline__ void with_form(const Pro& pro, const Epi& epi,
+                                          Body&& body) {
+  if constexpr (Pro::DYN || Epi::DYN) {
+    int star;
+    if constexpr (Pro::DYN) star = pro.bt->star;
+    else star = epi.bt->star;
+    if (star) body(as_star<true>(pro), as_star<true>(epi));
+    else body(as_star<false>(pro), as_star<false>(epi));
+  } else {
+    body(pro, epi);
+  }
+}
 
 template <typename T, int N, int NT>
 __device__ inline void load_tw(C<T>* tw, const C<T>* tw_g) {
@@ -378,20 +461,23 @@ template <int N> struct Pad { static constexpr int LS = N + 1; };
 // ------------------------------------------- xy-plane pass (whole plane)
 template <typename T, int N, int NT, int SIGN, class Pro, class Epi>
 __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
-                                              const C<T>* tw_g) {
+                                              const C<T>* tw_g, int nslots) {
   constexpr int LS = Pad<N>::LS;
   __shared__ C<T> s[N * LS];
   __shared__ C<T> tw[N];
   const int z = blockIdx.x, slot = blockIdx.y;
+  if (slot >= active_slots(pro, epi, nslots)) return;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = z * N * N;
   auto idx = [base](int m) { return base + m; };
   auto lds = [](int m) { return (m / N) * LS + m % N; };  // row y, col x
-  stage_in<T, N * N, NT>(s, pro, slot, idx, lds);
-  __syncthreads();
-  lds_fft<T, N, N, NT, SIGN, true>(s, LS, 1, tw);  // along x: lines = rows
-  lds_fft<T, N, N, NT, SIGN, true>(s, 1, LS, tw);  // along y: lines = columns
-  stage_out<T, N * N, NT>(s, epi, slot, idx, lds);
+  with_form(pro, epi, [&](const auto& pf, const auto& ef) {
+    stage_in<T, N * N, NT>(s, pf, slot, idx, lds);
+    __syncthreads();
+    lds_fft<T, N, N, NT, SIGN, true>(s, LS, 1, tw);  // along x: lines = rows
+    lds_fft<T, N, N, NT, SIGN, true>(s, 1, LS, tw);  // along y: lines = columns
+    stage_out<T, N * N, NT>(s, ef, slot, idx, lds);
+  });
 }
 
 // ------------------------------ xy plane in two halves (half the LDS)
@@ -426,11 +512,14 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
   static_assert((H * N) % V == 0 && N % V == 0, "vector width");
   __shared__ C<T> s[H * LS];
   __shared__ C<T> tw[N];
-  const int lg = xcd_logical(blockIdx.x, 2 * N * nslots);
+  const int ns = active_slots(pro, epi, nslots);
+  if ((int)blockIdx.x >= 2 * N * ns) return;
+  const int lg = xcd_logical(blockIdx.x, 2 * N * ns);
   const int half = lg & 1, zs = lg >> 1;
   const int z = zs % N, slot = zs / N;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = z * N * N;
+  with_form(pro, epi, [&](const auto& pf, const auto& ef) {
   C<T> f1[PER][V], f2[PER][V];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
@@ -438,12 +527,12 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
     if (q < NVH / NT || mv < NVH) {
       const int m0 = mv * V;
       if constexpr (SPLIT == 1) {
-        pro.getv(base + (2 * (m0 / N) + half) * N + m0 % N, slot, f1[q]);
+        pf.getv(base + (2 * (m0 / N) + half) * N + m0 % N, slot, f1[q]);
       } else if constexpr (SPLIT == 2) {
-        pro.getv(base + half * H * N + m0, slot, f1[q]);
+        pf.getv(base + half * H * N + m0, slot, f1[q]);
       } else {
-        pro.getv(base + m0, slot, f1[q]);
-        pro.getv(base + H * N + m0, slot, f2[q]);
+        pf.getv(base + m0, slot, f1[q]);
+        pf.getv(base + H * N + m0, slot, f2[q]);
       }
     }
   }
@@ -473,25 +562,29 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
     if constexpr (SPLIT == 1) return base + half * H * N + m;
     else return base + (2 * (m / N) + half) * N + m % N;
   };
-  stage_out<T, H * N, NT>(s, epi, slot, out, lds);
+  stage_out<T, H * N, NT>(s, ef, slot, out, lds);
+  });
 }
 
 // ---------------------------------------------- x pencils: TY whole rows
 template <typename T, int N, int TY, int NT, int SIGN, class Pro, class Epi>
 __global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
-                                               const C<T>* tw_g) {
+                                               const C<T>* tw_g, int nslots) {
   constexpr int LS = Pad<N>::LS;
   __shared__ C<T> s[TY * LS];
   __shared__ C<T> tw[N];
   const int slot = blockIdx.y;
+  if (slot >= active_slots(pro, epi, nslots)) return;
   load_tw<T, N, NT>(tw, tw_g);
   const int base = blockIdx.x * TY * N;
   auto idx = [base](int m) { return base + m; };
   auto lds = [](int m) { return (m / N) * LS + m % N; };
-  stage_in<T, TY * N, NT>(s, pro, slot, idx, lds);
-  __syncthreads();
-  lds_fft<T, N, TY, NT, SIGN, true>(s, LS, 1, tw);
-  stage_out<T, TY * N, NT>(s, epi, slot, idx, lds);
+  with_form(pro, epi, [&](const auto& pf, const auto& ef) {
+    stage_in<T, TY * N, NT>(s, pf, slot, idx, lds);
+    __syncthreads();
+    lds_fft<T, N, TY, NT, SIGN, true>(s, LS, 1, tw);
+    stage_out<T, TY * N, NT>(s, ef, slot, idx, lds);
+  });
 }
 
 // ---------------------- y or z pencils: TX adjacent x columns, whole axis
@@ -540,18 +633,22 @@ __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
   static_assert(AXIS == 2 ? (N * N) % TX == 0 : N % TX == 0, "tile width");
   static_assert(TX % Pro::V == 0 && TX % Epi::V == 0,
                 "vectors must not cross a tile row");
-  const int lg = xcd_logical(blockIdx.x, NTILES * nslots);
-  const int tile = lg / nslots, slot = lg % nslots;
+  const int ns = active_slots(pro, epi, nslots);
+  if ((int)blockIdx.x >= NTILES * ns) return;
+  const int lg = xcd_logical(blockIdx.x, NTILES * ns);
+  const int tile = lg / ns, slot = lg % ns;
   load_tw<T, N, NT>(tw, tw_g);
   auto idx = [tile](int m) {
     if constexpr (AXIS == 2) return zcol_index<N, TX>(tile, m);
     else return col_index<N, AXIS, TX>(tile, m);
   };
   auto lds = [](int m) { return col_lds<N, TX>(m); };
-  stage_in<T, TX * N, NT>(s, pro, slot, idx, lds);
-  __syncthreads();
-  lds_fft<T, N, TX, NT, SIGN, true>(s, LS, 1, tw);
-  stage_out<T, TX * N, NT>(s, epi, slot, idx, lds);
+  with_form(pro, epi, [&](const auto& pf, const auto& ef) {
+    stage_in<T, TX * N, NT>(s, pf, slot, idx, lds);
+    __syncthreads();
+    lds_fft<T, N, TX, NT, SIGN, true>(s, LS, 1, tw);
+    stage_out<T, TX * N, NT>(s, ef, slot, idx, lds);
+  });
 }
 
 template <int NT>
@@ -590,11 +687,9 @@ __device__ inline double block_sum(double v, double* red) {
 template <typename T, int N, int TX, int SL, int NT, int MINW, int ORDER = 0,
           bool DIT = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
-void k_zconv(C<T>* __restrict__ tmp,
-                                              int64_t gs,
-                                              const T* __restrict__ vtab,
-                                              PairArgs pa, double* epart,
-                                              int ntiles, const C<T>* tw_g) {
+void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
+             const BatchDev* __restrict__ bt, double* epart, int ntiles,
+             const C<T>* tw_g) {
   constexpr int LS = Pad<N>::LS;
   constexpr int NE1 = TX * N;          // points of one slot's tile
   constexpr int NE = SL * NE1;
@@ -604,7 +699,9 @@ void k_zconv(C<T>* __restrict__ tmp,
   __shared__ C<T> s[SL * TX * LS];
   __shared__ C<T> tw[N];
   __shared__ double red[NT / 64];
-  const int ngroups = (pa.n + SL - 1) / SL;
+  const int nslots = bt->n;
+  const int ngroups = (nslots + SL - 1) / SL;
+  if ((int)blockIdx.x >= ntiles * ngroups) return;
   const int lg = xcd_logical(blockIdx.x, ntiles * ngroups);
   // ORDER 0: all slot groups of a tile together; 1: slot-group-major, the
   // last group first, so that the z pass ends on the slot that pass C
@@ -612,7 +709,7 @@ void k_zconv(C<T>* __restrict__ tmp,
   // 0 at 120^3 FP32)
   const int tile = ORDER == 0 ? lg / ngroups : lg % ntiles;
   const int slot0 = (ORDER == 0 ? lg % ngroups : ngroups - 1 - lg / ntiles) * SL;
-  const int nsl = min(SL, pa.n - slot0);
+  const int nsl = min(SL, nslots - slot0);
   load_tw<T, N, NT>(tw, tw_g);
   C<T>* g = tmp + slot0 * gs;
   // element m of the group: slot m / NE1, tile point m % NE1
@@ -772,8 +869,8 @@ void k_zconv(C<T>* __restrict__ tmp,
     const double tot = block_sum<NT>(my_sl == sl ? e : 0.0, red);
     if (threadIdx.x == 0 && sl < nsl) {
       const int slot = slot0 + sl;
-      const double wgt = ((pa.one_sided >> slot) & 1ull) ? 0.0
-                         : (pa.i[slot] == pa.j[slot]) ? 1.0 : 2.0;
+      const double wgt = ((bt->one_sided >> slot) & 1ull) ? 0.0
+                         : (bt->i[slot] == bt->j[slot]) ? 1.0 : 2.0;
       epart[slot * ntiles + tile] += wgt * tot;
     }
     __syncthreads();   // red is reused by the next slot
@@ -869,7 +966,8 @@ template <typename T, int N> struct Engine {
                           hipStream_t st) {
     if constexpr (Cf::plane) {
       LACE_LAUNCH((k_plane<T, N, Cf::NT_PLANE, SIGN, Pro, Epi>),
-                         dim3(N, count), dim3(Cf::NT_PLANE), 0, st, p, e, tw);
+                         dim3(N, count), dim3(Cf::NT_PLANE), 0, st, p, e, tw,
+                         count);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -896,13 +994,13 @@ template <typename T, int N> struct Engine {
   static constexpr bool XY_DIT = N % 2 == 0 && Cf::TXZ % 2 == 0 &&
                               (Cf::TXZ / 2) % ProGrid<T>::V == 0;
   template <bool D>
-  static hipError_t zpass(C<T>* tmp, const T* vtab, const PairArgs& pa,
+  static hipError_t zpass(C<T>* tmp, const T* vtab, const BatchDev* bt,
                           double* epart, int cnt, const C<T>* tw,
                           hipStream_t st) {
     const int ntiles = (int)tiles();
     LACE_LAUNCH((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z, Cf::W_Z, 1, D>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
-                       dim3(Cf::NT_Z), 0, st, tmp, NG, vtab, pa, epart,
+                       dim3(Cf::NT_Z), 0, st, tmp, NG, vtab, bt, epart,
                        ntiles, tw);
     return hipGetLastError();
   }
@@ -911,7 +1009,7 @@ template <typename T, int N> struct Engine {
                            hipStream_t st) {
     LACE_LAUNCH((k_xlines<T, N, Cf::TY, Cf::NT_X, SIGN, Pro, Epi>),
                        dim3(N * N / Cf::TY, count), dim3(Cf::NT_X), 0, st, p,
-                       e, tw);
+                       e, tw, count);
     return hipGetLastError();
   }
   template <int AXIS, int SIGN, class Pro, class Epi>
@@ -971,110 +1069,73 @@ template <typename T, int N> struct Engine {
                         EpiGrid<T>{g, NG, T(1)}, g, count, tw, mode, st, true);
   }
 
-  static hipError_t pair_batch(const CellDev& c, const PairArgs& pa,
-                               const C<T>* psi, C<T>* w, C<T>* tmp,
-                               double* epart, hipStream_t st,
-                               hipEvent_t* ev = nullptr,
-                               const BatchSync* sy = nullptr) {
+  // One batch of the pair pipeline, read from bt; the grids are sized for
+  // cap slots.  Complex orbitals: ProPair / EpiAcc; real orbitals: packed
+  // slots (ProQuadD / EpiAccQuadD, star or general form per batch).
+  template <class ProA, class EpiC>
+  static hipError_t run_batch(const CellDev& c, ProA pa_, EpiC ec,
+                              const BatchDev* bt, int cap, C<T>* tmp,
+                              double* epart, hipStream_t st, hipEvent_t* ev,
+                              const BatchSync* sy) {
     const C<T>* tw = static_cast<const C<T>*>(c.tw);
-    const int cnt = pa.n;
-    ProPair<T> pp{psi, NG, pa};
     ProGrid<T> pt{tmp, NG};
     EpiGrid<T> et{tmp, NG, T(1)};
-    EpiAcc<T> ea{psi, w, NG, pa};
-    hipError_t err;
     const int mode = (c.use_plane == 1 && !Cf::plane) ? 0 : c.use_plane;
+    hipError_t err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     // pass A
     if (mode == 2) {
-      err = half<-1, XY_DIT ? 1 : 0>(pp, et, cnt, tw, st);
+      err = half<-1, XY_DIT ? 1 : 0>(pa_, et, cap, tw, st);
     } else if (mode == 1) {
-      err = plane<-1>(pp, et, cnt, tw, st);
+      err = plane<-1>(pa_, et, cap, tw, st);
     } else {
-      err = xlines<-1>(pp, et, cnt, tw, st);
-      if (err == hipSuccess) err = cols<1, -1>(pt, et, cnt, tw, st);
+      err = xlines<-1>(pa_, et, cap, tw, st);
+      if (err == hipSuccess) err = cols<1, -1>(pt, EpiGridT{tmp, NG, T(1), bt}, cap, tw, st);
     }
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     // pass B
     const T* vtab = static_cast<const T*>(c.vtab);
-    err = mode == 2 ? zpass<XY_DIT>(tmp, vtab, pa, epart, cnt, tw, st)
-                    : zpass<false>(tmp, vtab, pa, epart, cnt, tw, st);
+    err = mode == 2 ? zpass<XY_DIT>(tmp, vtab, bt, epart, cap, tw, st)
+                    : zpass<false>(tmp, vtab, bt, epart, cap, tw, st);
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
     if (sy && sy->wait_c && (err = hipStreamWaitEvent(st, sy->wait_c, 0)) != hipSuccess)
       return err;
     // pass C
     if (mode == 2) {
-      err = half<+1, XY_DIT ? 2 : 0>(pt, ea, cnt, tw, st);
+      err = half<+1, XY_DIT ? 2 : 0>(pt, ec, cap, tw, st);
     } else if (mode == 1) {
-      err = plane<+1>(pt, ea, cnt, tw, st);
+      err = plane<+1>(pt, ec, cap, tw, st);
     } else {
-      err = cols<1, +1>(pt, et, cnt, tw, st);
-      if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
+      err = cols<1, +1>(pt, EpiGridT{tmp, NG, T(1), bt}, cap, tw, st);
+      if (err == hipSuccess) err = xlines<+1>(pt, ec, cap, tw, st);
     }
     if (err == hipSuccess && ev) err = hipEventRecord(ev[3], st);
     if (err == hipSuccess && sy && sy->done_c) err = hipEventRecord(sy->done_c, st);
     return err;
   }
+  // Grid-to-grid step of the pencil schedule between the pair passes: the
+  // pair buffer in and out, limited to the batch's slots.
+  struct EpiGridT : EpiGrid<T> {
+    static constexpr bool TABLE = true;
+    const BatchDev* __restrict__ bt;
+    EpiGridT(C<T>* b, int64_t g, T s, const BatchDev* t) : EpiGrid<T>{b, g, s}, bt(t) {}
+  };
 
-  // Packed slots of real orbitals: same passes, real grids in and out.
-  static hipError_t quad_batch(const CellDev& c, const QuadArgs& qa,
+  static hipError_t pair_batch(const CellDev& c, const BatchDev* bt, int cap,
+                               const C<T>* psi, C<T>* w, C<T>* tmp,
+                               double* epart, hipStream_t st, hipEvent_t* ev,
+                               const BatchSync* sy) {
+    return run_batch(c, ProPair<T>{psi, NG, bt}, EpiAcc<T>{psi, w, NG, bt}, bt,
+                     cap, tmp, epart, st, ev, sy);
+  }
+  static hipError_t quad_batch(const CellDev& c, const BatchDev* bt, int cap,
                                const T* psi, T* w, C<T>* tmp, double* epart,
                                hipStream_t st, hipEvent_t* ev,
-                               const BatchSync* sy = nullptr) {
-    bool star = true;
-    for (int q = 0; q < qa.n; ++q) star = star && qa.k[q] == qa.i[q];
-    return star ? quad_run<true>(c, qa, psi, w, tmp, epart, st, ev, sy)
-                : quad_run<false>(c, qa, psi, w, tmp, epart, st, ev, sy);
-  }
-  template <bool STAR>
-  static hipError_t quad_run(const CellDev& c, const QuadArgs& qa,
-                             const T* psi, T* w, C<T>* tmp, double* epart,
-                             hipStream_t st, hipEvent_t* ev,
-                             const BatchSync* sy) {
-    const C<T>* tw = static_cast<const C<T>*>(c.tw);
-    const int cnt = qa.n;
-    ProQuad<T, STAR> pp{psi, NG, qa};
-    ProGrid<T> pt{tmp, NG};
-    EpiGrid<T> et{tmp, NG, T(1)};
-    EpiAccQuad<T, STAR> ea{psi, w, NG, qa};
-    // energy weights: both pairs of a slot are of the same kind
-    PairArgs pw;
-    pw.n = cnt;
-    pw.one_sided = qa.one_sided;
-    for (int q = 0; q < cnt; ++q) { pw.i[q] = qa.i[q]; pw.j[q] = qa.j[q]; }
-    const int mode = (c.use_plane == 1 && !Cf::plane) ? 0 : c.use_plane;
-    hipError_t err;
-    if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
-    if (mode == 2) {
-      err = half<-1, XY_DIT ? 1 : 0>(pp, et, cnt, tw, st);
-    } else if (mode == 1) {
-      err = plane<-1>(pp, et, cnt, tw, st);
-    } else {
-      err = xlines<-1>(pp, et, cnt, tw, st);
-      if (err == hipSuccess) err = cols<1, -1>(pt, et, cnt, tw, st);
-    }
-    if (err != hipSuccess) return err;
-    if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
-    const T* vtab = static_cast<const T*>(c.vtab);
-    err = mode == 2 ? zpass<XY_DIT>(tmp, vtab, pw, epart, cnt, tw, st)
-                    : zpass<false>(tmp, vtab, pw, epart, cnt, tw, st);
-    if (err != hipSuccess) return err;
-    if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
-    if (sy && sy->wait_c && (err = hipStreamWaitEvent(st, sy->wait_c, 0)) != hipSuccess)
-      return err;
-    if (mode == 2) {
-      err = half<+1, XY_DIT ? 2 : 0>(pt, ea, cnt, tw, st);
-    } else if (mode == 1) {
-      err = plane<+1>(pt, ea, cnt, tw, st);
-    } else {
-      err = cols<1, +1>(pt, et, cnt, tw, st);
-      if (err == hipSuccess) err = xlines<+1>(pt, ea, cnt, tw, st);
-    }
-    if (err == hipSuccess && ev) err = hipEventRecord(ev[3], st);
-    if (err == hipSuccess && sy && sy->done_c) err = hipEventRecord(sy->done_c, st);
-    return err;
+                               const BatchSync* sy) {
+    return run_batch(c, ProQuadD<T>{psi, NG, bt}, EpiAccQuadD<T>{psi, w, NG, bt},
+                     bt, cap, tmp, epart, st, ev, sy);
   }
 
   static int64_t tiles() { return (int64_t)N * N / Cf::TXZ; }
@@ -1198,15 +1259,15 @@ hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
 }
 
 template <typename T>
-static hipError_t pair_batch_t(const CellDev& c, const PairArgs& pa,
+static hipError_t pair_batch_t(const CellDev& c, const BatchDev* bt, int cap,
                                const void* psi, void* w, void* tmp,
                                double* epart, hipStream_t st,
-                               hipEvent_t* ev, const BatchSync* sy = nullptr) {
+                               hipEvent_t* ev, const BatchSync* sy) {
   switch (c.n) {
-#define X(NN)                                                          \
-  case NN:                                                             \
-    return Engine<T, NN>::pair_batch(c, pa, static_cast<const C<T>*>(psi), \
-                                     static_cast<C<T>*>(w),            \
+#define X(NN)                                                               \
+  case NN:                                                                  \
+    return Engine<T, NN>::pair_batch(c, bt, cap, static_cast<const C<T>*>(psi), \
+                                     static_cast<C<T>*>(w),                 \
                                      static_cast<C<T>*>(tmp), epart, st, ev, sy);
     LACE_SIZES(X)
 #undef X
@@ -1214,22 +1275,13 @@ static hipError_t pair_batch_t(const CellDev& c, const PairArgs& pa,
   }
 }
 
-hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
-                             const void* psi, void* w, void* tmp,
-                             double* epart, hipStream_t st,
+hipError_t launch_pair_batch(const CellDev& c, bool fp64, const BatchDev* bt,
+                             int cap, const void* psi, void* w, void* tmp,
+                             double* epart, hipStream_t st, hipEvent_t* ev,
                              const BatchSync* sy) {
-  if (pa.n <= 0) return hipSuccess;
-  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st, nullptr, sy)
-              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st, nullptr, sy);
-}
-
-hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
-                                   const PairArgs& pa, const void* psi,
-                                   void* w, void* tmp, double* epart,
-                                   hipStream_t st, hipEvent_t* ev) {
-  if (pa.n <= 0) return hipSuccess;
-  return fp64 ? pair_batch_t<double>(c, pa, psi, w, tmp, epart, st, ev)
-              : pair_batch_t<float>(c, pa, psi, w, tmp, epart, st, ev);
+  if (cap <= 0 || cap > PMAX) return hipErrorInvalidValue;
+  return fp64 ? pair_batch_t<double>(c, bt, cap, psi, w, tmp, epart, st, ev, sy)
+              : pair_batch_t<float>(c, bt, cap, psi, w, tmp, epart, st, ev, sy);
 }
 
 hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,
@@ -1360,15 +1412,15 @@ hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64,
 }
 
 template <typename T>
-static hipError_t quad_batch_t(const CellDev& c, const QuadArgs& qa,
+static hipError_t quad_batch_t(const CellDev& c, const BatchDev* bt, int cap,
                                const void* psi, void* w, void* tmp,
                                double* epart, hipStream_t st, hipEvent_t* ev,
                                const BatchSync* sy) {
   switch (c.n) {
-#define X(NN)                                                              \
-  case NN:                                                                 \
-    return Engine<T, NN>::quad_batch(c, qa, static_cast<const T*>(psi),    \
-                                     static_cast<T*>(w),                   \
+#define X(NN)                                                                \
+  case NN:                                                                   \
+    return Engine<T, NN>::quad_batch(c, bt, cap, static_cast<const T*>(psi), \
+                                     static_cast<T*>(w),                     \
                                      static_cast<C<T>*>(tmp), epart, st, ev, sy);
     LACE_SIZES(X)
 #undef X
@@ -1376,13 +1428,13 @@ static hipError_t quad_batch_t(const CellDev& c, const QuadArgs& qa,
   }
 }
 
-hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
-                             const void* psi, void* w, void* tmp,
+hipError_t launch_quad_batch(const CellDev& c, bool fp64, const BatchDev* bt,
+                             int cap, const void* psi, void* w, void* tmp,
                              double* epart, hipStream_t st, hipEvent_t* ev,
                              const BatchSync* sy) {
-  if (qa.n <= 0) return hipSuccess;
-  return fp64 ? quad_batch_t<double>(c, qa, psi, w, tmp, epart, st, ev, sy)
-              : quad_batch_t<float>(c, qa, psi, w, tmp, epart, st, ev, sy);
+  if (cap <= 0 || cap > QMAX) return hipErrorInvalidValue;
+  return fp64 ? quad_batch_t<double>(c, bt, cap, psi, w, tmp, epart, st, ev, sy)
+              : quad_batch_t<float>(c, bt, cap, psi, w, tmp, epart, st, ev, sy);
 }
 
 // per block: sum |C_m - conj C_{-m}|^2 and sum |C_m|^2 over its share

@@ -48,6 +48,22 @@ struct QuadArgs {
   uint64_t one_sided;
 };
 
+// One batch of the pair pipeline as the kernels read it from device memory.
+// Slot q: complex orbitals hold one pair (i[q], j[q]); real orbitals pack
+// two pair densities rho_ij + i rho_kl in one transform (k = l = -1: a
+// single pair; k = i: a star slot, whose two pairs share orbital i).  No
+// orbital appears in two slots.  Batches past the end of a schedule have
+// n = 0, and every kernel of such a batch returns at once.
+struct BatchDev {
+  int32_t n;          // slots
+  int32_t star;       // 1: every slot is a star slot (real orbitals)
+  int32_t npairs;     // pairs in the batch
+  int32_t pad;
+  uint64_t one_sided; // bit q: slot q holds one-sided pairs (no energy)
+  uint64_t skip[4];   // bit q: W_i, W_j, W_k, W_l of slot q not updated
+  int32_t i[PMAX], j[PMAX], k[PMAX], l[PMAX];
+};
+
 // Geometry and device tables of one cell, shared by all launchers.
 struct CellDev {
   int n;              // grid points per axis
@@ -87,16 +103,14 @@ struct BatchSync {
   hipEvent_t wait_c;
   hipEvent_t done_c;
 };
-hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
-                             const void* psi, void* w, void* tmp,
-                             double* epart, hipStream_t st,
-                             const BatchSync* sy = nullptr);
-// Same, with ev[0..3] recorded before pass A, between the passes and
+// bt: the batch in device memory; cap: its slot capacity (the launch
+// grids are sized for cap slots; the kernels read the batch's own count).
+// ev (may be null): ev[0..3] recorded before pass A, between the passes and
 // after pass C.
-hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64,
-                                   const PairArgs& pa, const void* psi,
-                                   void* w, void* tmp, double* epart,
-                                   hipStream_t st, hipEvent_t* ev);
+hipError_t launch_pair_batch(const CellDev& c, bool fp64, const BatchDev* bt,
+                             int cap, const void* psi, void* w, void* tmp,
+                             double* epart, hipStream_t st, hipEvent_t* ev,
+                             const BatchSync* sy = nullptr);
 // ---- real (Gamma-point) orbitals: real grids, packed complex transforms
 // psi_real (n_orb real grids) <- real parts of Omega^{-1/2} B[C]; two
 // orbitals per complex transform.  psi_real must hold ceil(n_orb/2) complex
@@ -112,10 +126,10 @@ hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64,
                                   const void* w_real, int n_orb, void* scratch,
                                   void* w_pw, hipStream_t st);
 // One batch of packed pair slots of real orbitals (no orbital twice).
-hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
-                             const void* psi_real, void* w_real, void* tmp,
-                             double* epart, hipStream_t st, hipEvent_t* ev,
-                             const BatchSync* sy = nullptr);
+hipError_t launch_quad_batch(const CellDev& c, bool fp64, const BatchDev* bt,
+                             int cap, const void* psi_real, void* w_real,
+                             void* tmp, double* epart, hipStream_t st,
+                             hipEvent_t* ev, const BatchSync* sy = nullptr);
 // Sum over orbitals of sum_m |C_m - conj(C_{-m})|^2 and sum_m |C_m|^2 into
 // part[2 * nblocks] (host reduces); returns the number of blocks used.
 hipError_t launch_real_check(const CellDev& c, const void* coeffs, int n_orb,
@@ -172,6 +186,37 @@ hipError_t launch_polar_elem(int mode, const void* in, int n, const double* s,
                              void* out, hipStream_t st);
 hipError_t launch_polar_norm(int mode, const void* B, int n, double* out,
                              hipStream_t st);
+
+// ---- screening decision and batch schedule on the device ----
+// Kept pairs of Eq. (6) from S (n x n, device): pairs (2 int32 each) column
+// by column, *total their count; s == nullptr lists every pair.  cnt: n
+// int32, off: n + 1 int64 scratch.
+hipError_t launch_kept_pairs(const double* s, int n, double thr, int32_t* cnt,
+                             int64_t* off, int32_t* pairs, int64_t* total,
+                             hipStream_t st);
+// Schedule of the pair pipeline into a batch table (device), from S and a
+// threshold or from an explicit device pair list.
+struct SchedDesc {
+  int n_orb;               // orbitals (occupied first)
+  int n_occ;               // n_occ < n_orb: pairs (i < n_occ <= j) are one-sided
+  int ppb;                 // pairs per batch
+  bool gamma;              // real orbitals: two pairs per slot, stars
+  bool force_fallback;     // build the round-robin schedule directly
+  int64_t max_batches;     // table entries (the host launches this many)
+  const double* s;         // S (device, s_n x s_n) or nullptr: every pair
+  int s_n;                 // orbitals with two-sided pairs (S's size)
+  double s_thr;
+  const int32_t* pair_i;   // explicit list (device) instead of S, or nullptr
+  const int32_t* pair_j;
+  int64_t n_pairs;
+  BatchDev* table;         // device, max_batches entries
+  int32_t* n_batches;      // device: batches used
+  int64_t* n_kept;         // device: pairs scheduled (may be null)
+  int32_t* bad;            // device: bit 0 set for a bad explicit list (may be null)
+  void* scratch;           // sched_scratch_bytes(n_orb)
+};
+int64_t sched_scratch_bytes(int n_orb);
+hipError_t launch_schedule(const SchedDesc& d, hipStream_t st);
 
 // SCDM point selection on the workspace orbital grids (complex or real,
 // FP32 or FP64): n_orb greedy picks of column-pivoted QR of Psi^H into

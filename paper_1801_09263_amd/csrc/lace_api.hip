@@ -92,8 +92,9 @@ struct lace_plan {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;   // fork/join events, no timing
   hipStream_t origin = nullptr;     // capture stream of the batched call
-  hipEvent_t s_ready = nullptr;     // screened exchange: S copied to the host
   GraphCache graph;
+  // LACE_SCHEDULE_FALLBACK=1: schedules take the round-robin form (tests)
+  bool force_fallback = false;
 };
 
 // ---------------------------------------------------------------- helpers
@@ -103,8 +104,18 @@ static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t info, psi, w, tmp, epart, s, part, mw, a, z, t, u, dens, scdm, pts,
-      total;
+      tab, sched, kcnt, koff, total;
+  int64_t max_batches;
   int pairs_per_batch;
+};
+
+// The status block at the start of every workspace: the Cholesky info word
+// of builds that pass none (offset 0, where lace_get_info reads it), the
+// batch count of the last schedule, the count of pairs it holds.
+struct Status {
+  int32_t info;
+  int32_t n_batches;
+  int64_t n_kept;
 };
 
 // bytes of one complex grid point in the plan precision
@@ -114,6 +125,22 @@ static size_t orb_bytes(const lace_plan* p) {
   return p->gamma ? grid_bytes(p) / 2 : grid_bytes(p);
 }
 
+// The most batches a schedule of any set of pairs of n_orb orbitals takes
+// with at most ppb pairs per batch: the count of the round-robin schedule,
+// which runs each round (a set of disjoint pairs, at most nv/2 of them)
+// and the diagonal round in batches of their own.  Real orbitals pack two
+// pairs of one kind per slot (one-sided pairs with the virtual orbitals are
+// a second kind) and a batch holds at most ppb / 2 two-pair slots.
+static int64_t batch_bound(int n_orb, int ppb, bool gamma, bool virt) {
+  const int64_t nv = n_orb + (n_orb & 1), pr = nv / 2;
+  auto cdiv = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+  if (!gamma) return (nv - 1) * cdiv(pr, ppb) + cdiv(n_orb, ppb);
+  if (ppb == 1) return (nv - 1) * pr + n_orb;
+  const int64_t sp = ppb / 2;
+  const int64_t slots_r = virt ? pr / 2 + 1 : cdiv(pr, 2);
+  return (nv - 1) * cdiv(slots_r, sp) + cdiv(cdiv(n_orb, 2), sp);
+}
+
 static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   const CellDev& c = p->cells[cell].dev;
   const bool fp64 = p->fp64;
@@ -121,8 +148,8 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.pairs_per_batch = c.ppb;
   const size_t gb = (size_t)c.ng * grid_bytes(p);
   size_t off = 0;
-  // the Cholesky info word of builds that pass no info pointer: first, so
-  // that lace_get_info finds it without the layout
+  // the status block: first, so that lace_get_info finds the info word
+  // without the layout
   L.info = off; off += 256;
   // pair buffer and energy partials sized for the largest batch, so that
   // one workspace serves every tuning of the cell
@@ -150,6 +177,13 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.dens = off; off += align_up(sizeof(double) * (size_t)c.ng);
   L.scdm = off; off += align_up((size_t)scdm_scratch_bytes(n_orb));
   L.pts = off; off += align_up(sizeof(int32_t) * (size_t)n_orb);
+  // batch table, sized for one pair per batch (any tuning) and one-sided
+  // pairs
+  L.max_batches = batch_bound(n_orb, 1, p->gamma, true);
+  L.tab = off; off += align_up(sizeof(BatchDev) * (size_t)L.max_batches);
+  L.sched = off; off += align_up((size_t)sched_scratch_bytes(n_orb));
+  L.kcnt = off; off += align_up(sizeof(int32_t) * (size_t)n_orb);
+  L.koff = off; off += align_up(sizeof(int64_t) * ((size_t)n_orb + 1));
   L.total = off;
   return L;
 }
@@ -209,350 +243,6 @@ static hipError_t prof_collect(Profile& pr) {
 // Signed frequency of FFT index k on an n-point axis.
 static int signed_freq(int k, int n) { return k < (n + 1) / 2 ? k : k - n; }
 
-// Round of an unordered pair in the circle-method round robin over n'
-// vertices (n' = n_orb rounded up to even): vertex n'-1 stays fixed and
-// round r pairs it with r and pairs (r + k, r - k) mod (n'-1); so pair
-// (i, j) with i < j < n'-1 sits in round (i + j) / 2 mod (n'-1), and every
-// round is a set of disjoint pairs.  Diagonal pairs form one extra round.
-static int pair_round(int i, int j, int nv) {
-  if (i == j) return nv - 1;
-  if (j == nv - 1) return i;
-  const int64_t m = nv - 1;                  // odd
-  return (int)(((int64_t)(i + j) * (nv / 2)) % m);  // (nv/2) = 1/2 mod m
-}
-
-// One batch of the pair pipeline: its pairs and, for plans of real
-// orbitals, the packed slots (the pairs then listed slot by slot).
-struct Batch {
-  PairArgs p;
-  QuadArgs q;
-};
-
-// Group pairs into batches of at most per_batch pairs in which no orbital
-// appears twice, so the accumulation into W has no write conflicts.  Pairs
-// are taken round by round (stable within a round) and placed first-fit
-// into a small window of open batches; a round is itself conflict-free, so
-// batches fill to per_batch except at round boundaries.
-static void build_schedule(const std::vector<std::pair<int, int>>& pairs,
-                           int n_orb, int per_batch,
-                           std::vector<Batch>& outb,
-                           std::vector<int32_t>* batch_of = nullptr,
-                           const std::vector<char>* one_sided = nullptr) {
-  std::vector<PairArgs> out;
-  const int nv = n_orb + (n_orb & 1);
-  std::vector<int> order(pairs.size());
-  std::vector<int> round(pairs.size());
-  for (size_t k = 0; k < pairs.size(); ++k) {
-    order[k] = (int)k;
-    round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
-  }
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return round[a] < round[b]; });
-  if (batch_of) batch_of->assign(pairs.size(), -1);
-  const int words = (n_orb + 63) / 64;
-  struct Open {
-    size_t idx;
-    std::vector<uint64_t> used;
-  };
-  std::vector<Open> open;
-  const size_t window = 8;
-  for (int k : order) {
-    const int i = pairs[k].first, j = pairs[k].second;
-    bool placed = false;
-    for (size_t o = 0; o < open.size(); ++o) {
-      Open& ob = open[o];
-      const bool ui = (ob.used[i / 64] >> (i % 64)) & 1ull;
-      const bool uj = (ob.used[j / 64] >> (j % 64)) & 1ull;
-      if (ui || uj) continue;
-      PairArgs& b = out[ob.idx];
-      if (one_sided && (*one_sided)[k]) b.one_sided |= 1ull << b.n;
-      b.i[b.n] = i; b.j[b.n] = j; ++b.n;
-      if (batch_of) (*batch_of)[k] = (int32_t)ob.idx;
-      ob.used[i / 64] |= 1ull << (i % 64);
-      ob.used[j / 64] |= 1ull << (j % 64);
-      if (b.n == per_batch) open.erase(open.begin() + o);
-      placed = true;
-      break;
-    }
-    if (placed) continue;
-    PairArgs b;
-    std::memset(&b, 0, sizeof(b));
-    b.n = 1; b.i[0] = i; b.j[0] = j;
-    if (one_sided && (*one_sided)[k]) b.one_sided = 1ull;
-    out.push_back(b);
-    if (batch_of) (*batch_of)[k] = (int32_t)(out.size() - 1);
-    if (per_batch > 1) {
-      Open ob;
-      ob.idx = out.size() - 1;
-      ob.used.assign(words, 0ull);
-      ob.used[i / 64] |= 1ull << (i % 64);
-      ob.used[j / 64] |= 1ull << (j % 64);
-      open.push_back(ob);
-      if (open.size() > window) open.erase(open.begin());
-    }
-  }
-  outb.resize(out.size());
-  for (size_t b = 0; b < out.size(); ++b) {
-    outb[b].p = out[b];
-    outb[b].q.n = 0;
-  }
-}
-
-// Plans of real orbitals pack two pair densities into one complex
-// transform (a slot); slots of one batch use disjoint orbitals.  A slot
-// whose two pairs share an orbital (a star slot) reads and updates three
-// orbital grids instead of four.  Stars come from trails: a walk along
-// pairs not yet used, cut into runs of two consecutive pairs, which share
-// the orbital between them.  Off-diagonal pairs are first walked two
-// round-robin rounds at a time (each round a set of disjoint pairs, so the
-// stars of one group overlap little and pack densely into batches); what
-// is left (one pair per trail of odd length) is walked once more as a
-// whole, and the rest is packed two by two, then the diagonal pairs; a
-// last odd pair of either kind gets a slot of its own.
-struct Slot {
-  int i, j, k, l;   // k = l = -1: a single pair; k = i: a star slot
-  int pk[2];        // the slot's pairs (indices into the pair list, or -1)
-  bool os;          // one-sided pairs (occupied x virtual)
-};
-
-static int slot_orbitals(const Slot& s, int o[4]) {
-  int n = 0;
-  for (int v : {s.i, s.j, s.k, s.l}) {
-    if (v < 0) continue;
-    bool seen = false;
-    for (int t = 0; t < n; ++t) seen = seen || o[t] == v;
-    if (!seen) o[n++] = v;
-  }
-  return n;
-}
-
-static Slot make_slot(const std::vector<std::pair<int, int>>& pairs, int a,
-                      int b) {
-  Slot s;
-  s.pk[0] = a;
-  s.pk[1] = b;
-  s.os = false;
-  int i = pairs[a].first, j = pairs[a].second;
-  if (b < 0) {
-    s.i = i; s.j = j; s.k = s.l = -1;
-    return s;
-  }
-  int k = pairs[b].first, l = pairs[b].second;
-  if (i != j) {   // a shared orbital goes first in both pairs
-    if (j == k || j == l) std::swap(i, j);
-    if (k != i && l == i) std::swap(k, l);
-  }
-  s.i = i; s.j = j; s.k = k; s.l = l;
-  return s;
-}
-
-// Trail decomposition of the off-diagonal pairs `edges`: consecutive pairs
-// of each walk become star slots, the last pair of an odd walk goes to
-// `left`.  Walks start at orbitals with an odd number of unused pairs.
-// Adjacency buffers of trail_slots, reused across its calls.
-struct TrailWork {
-  std::vector<int> off, rem, cur, adj;
-};
-
-static void trail_slots(const std::vector<std::pair<int, int>>& pairs,
-                        const std::vector<int>& edges, int n_orb,
-                        std::vector<char>& done, std::vector<Slot>& slots,
-                        std::vector<int>& left, TrailWork& tw) {
-  std::vector<int>& off = tw.off;
-  std::vector<int>& rem = tw.rem;
-  std::vector<int>& cur = tw.cur;
-  std::vector<int>& adj = tw.adj;
-  off.assign(n_orb + 1, 0);
-  rem.resize(n_orb);
-  for (int e : edges) {
-    ++off[pairs[e].first + 1];
-    ++off[pairs[e].second + 1];
-  }
-  for (int v = 0; v < n_orb; ++v) off[v + 1] += off[v];
-  adj.resize(off[n_orb]);
-  cur.assign(off.begin(), off.end() - 1);
-  for (int e : edges)
-    for (int v : {pairs[e].first, pairs[e].second}) adj[cur[v]++] = e;
-  for (int v = 0; v < n_orb; ++v) {
-    cur[v] = off[v];
-    rem[v] = off[v + 1] - off[v];
-  }
-  auto walk = [&](int v) {
-    int pend = -1;
-    for (;;) {
-      while (cur[v] < off[v + 1] && done[adj[cur[v]]]) ++cur[v];
-      if (cur[v] == off[v + 1]) break;
-      const int e = adj[cur[v]++];
-      done[e] = 1;
-      --rem[pairs[e].first];
-      --rem[pairs[e].second];
-      if (pend < 0) {
-        pend = e;
-      } else {
-        slots.push_back(make_slot(pairs, pend, e));
-        pend = -1;
-      }
-      v = pairs[e].first == v ? pairs[e].second : pairs[e].first;
-    }
-    if (pend >= 0) left.push_back(pend);
-  };
-  for (int e : edges)
-    for (int v : {pairs[e].first, pairs[e].second})
-      if (rem[v] & 1) walk(v);
-  for (int e : edges)
-    if (!done[e]) walk(pairs[e].first);
-}
-
-// Off-diagonal pairs of one kind (two-sided, or one-sided) into slots.
-static void star_slots(const std::vector<std::pair<int, int>>& pairs,
-                       std::vector<int> off, int n_orb, std::vector<char>& done,
-                       std::vector<Slot>& slots) {
-  const int nv = n_orb + (n_orb & 1);
-  std::vector<int> round(pairs.size(), 0), left, rest, group;
-  // stable counting sort of the pairs by round (rounds are < nv)
-  std::vector<int> start(nv + 1, 0), sorted(off.size());
-  for (int k : off) {
-    round[k] = pair_round(pairs[k].first, pairs[k].second, nv);
-    ++start[round[k] + 1];
-  }
-  for (int r = 0; r < nv; ++r) start[r + 1] += start[r];
-  for (int k : off) sorted[start[round[k]]++] = k;
-  off.swap(sorted);
-  TrailWork tw;
-  for (size_t a = 0; a < off.size();) {
-    const int g = round[off[a]] / 2;
-    group.clear();
-    while (a < off.size() && round[off[a]] / 2 == g) group.push_back(off[a++]);
-    trail_slots(pairs, group, n_orb, done, slots, left, tw);
-  }
-  for (int e : left) done[e] = 0;
-  trail_slots(pairs, left, n_orb, done, slots, rest, tw);
-  for (size_t t = 0; t < rest.size(); t += 2)
-    slots.push_back(make_slot(pairs, rest[t],
-                              t + 1 < rest.size() ? rest[t + 1] : -1));
-}
-
-static void make_slots(const std::vector<std::pair<int, int>>& pairs,
-                       int n_orb, bool pack, std::vector<Slot>& slots,
-                       const std::vector<char>* one_sided) {
-  slots.clear();
-  auto is_os = [&](int k) { return one_sided && (*one_sided)[k]; };
-  if (!pack) {
-    for (size_t k = 0; k < pairs.size(); ++k) {
-      slots.push_back(make_slot(pairs, (int)k, -1));
-      slots.back().os = is_os((int)k);
-    }
-    return;
-  }
-  std::vector<int> off, offo, diag;
-  for (size_t k = 0; k < pairs.size(); ++k) {
-    if (is_os((int)k)) offo.push_back((int)k);
-    else if (pairs[k].first == pairs[k].second) diag.push_back((int)k);
-    else off.push_back((int)k);
-  }
-  std::vector<char> done(pairs.size(), 0);
-  star_slots(pairs, off, n_orb, done, slots);
-  const size_t first_os = slots.size();
-  star_slots(pairs, offo, n_orb, done, slots);
-  for (size_t t = first_os; t < slots.size(); ++t) slots[t].os = true;
-  for (size_t t = 0; t < diag.size(); t += 2)
-    slots.push_back(make_slot(pairs, diag[t],
-                              t + 1 < diag.size() ? diag[t + 1] : -1));
-}
-
-// Slots into batches of at most per_batch pairs and (per_batch + 1) / 2
-// slots, first-fit over a window of open batches, no orbital twice in a
-// batch.
-static void build_slot_schedule(const std::vector<std::pair<int, int>>& pairs,
-                                int n_orb, int per_batch,
-                                std::vector<Batch>& out,
-                                std::vector<int32_t>* batch_of = nullptr,
-                                std::vector<int32_t>* slot_of = nullptr,
-                                const std::vector<char>* one_sided = nullptr,
-                                int n_occ = -1) {
-  out.clear();
-  std::vector<Slot> slots;
-  make_slots(pairs, n_orb, per_batch >= 2, slots, one_sided);
-  if (batch_of) batch_of->assign(pairs.size(), -1);
-  if (slot_of) slot_of->assign(pairs.size(), -1);
-  const int cap_slots = (per_batch + 1) / 2;
-  const int words = (n_orb + 63) / 64;
-  struct Open {
-    size_t idx;
-    std::vector<uint64_t> used;
-  };
-  std::vector<Open> open;
-  const size_t window = 8;
-  auto put = [&](size_t idx, const Slot& sl) {
-    Batch& b = out[idx];
-    const int q = b.q.n++;
-    b.q.i[q] = sl.i; b.q.j[q] = sl.j; b.q.k[q] = sl.k; b.q.l[q] = sl.l;
-    if (sl.os) {   // the occupied orbital of a one-sided pair keeps its W
-      b.q.one_sided |= 1ull << q;
-      const int pos[4] = {sl.i, sl.j, sl.k, sl.l};
-      for (int t = 0; t < 4; ++t)
-        if (pos[t] >= 0 && pos[t] < n_occ) b.q.skip[t] |= 1ull << q;
-    }
-    for (int t = 0; t < 2; ++t) {
-      const int k = sl.pk[t];
-      if (k < 0) continue;
-      b.p.i[b.p.n] = pairs[k].first;
-      b.p.j[b.p.n] = pairs[k].second;
-      if (sl.os) b.p.one_sided |= 1ull << b.p.n;
-      ++b.p.n;
-      if (batch_of) (*batch_of)[k] = (int32_t)idx;
-      if (slot_of) (*slot_of)[k] = q;
-    }
-  };
-  for (const Slot& sl : slots) {
-    int o[4];
-    const int no = slot_orbitals(sl, o);
-    const int np = sl.pk[1] >= 0 ? 2 : 1;
-    bool placed = false;
-    for (size_t w = 0; w < open.size() && !placed; ++w) {
-      Open& ob = open[w];
-      const Batch& b = out[ob.idx];
-      if (b.p.n + np > per_batch) continue;
-      bool clash = false;
-      for (int t = 0; t < no; ++t)
-        clash = clash || ((ob.used[o[t] / 64] >> (o[t] % 64)) & 1ull);
-      if (clash) continue;
-      put(ob.idx, sl);
-      for (int t = 0; t < no; ++t) ob.used[o[t] / 64] |= 1ull << (o[t] % 64);
-      if (out[ob.idx].p.n == per_batch || out[ob.idx].q.n == cap_slots)
-        open.erase(open.begin() + w);
-      placed = true;
-    }
-    if (placed) continue;
-    Batch nb;
-    std::memset(&nb, 0, sizeof(nb));
-    out.push_back(nb);
-    put(out.size() - 1, sl);
-    if (out.back().p.n < per_batch && out.back().q.n < cap_slots) {
-      Open ob;
-      ob.idx = out.size() - 1;
-      ob.used.assign(words, 0ull);
-      for (int t = 0; t < no; ++t) ob.used[o[t] / 64] |= 1ull << (o[t] % 64);
-      open.push_back(ob);
-      if (open.size() > window) open.erase(open.begin());
-    }
-  }
-}
-
-// one_sided (optional): per pair, occupied x virtual; n_occ: orbitals
-// below it are occupied.
-static void schedule_for(const lace_plan* p,
-                         const std::vector<std::pair<int, int>>& pairs,
-                         int n_orb, int per_batch, std::vector<Batch>& out,
-                         const std::vector<char>* one_sided = nullptr,
-                         int n_occ = -1) {
-  if (p->gamma)
-    build_slot_schedule(pairs, n_orb, per_batch, out, nullptr, nullptr,
-                        one_sided, n_occ);
-  else
-    build_schedule(pairs, n_orb, per_batch, out, nullptr, one_sided);
-}
-
 // ------------------------------------------------------------------ API
 // The entry points keep the C linkage of their declarations in lace.h.
 
@@ -608,6 +298,10 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
   lace_plan* p = new (std::nothrow) lace_plan;
   if (!p) return LACE_ENOMEM;
   p->prec = prec;
+  {
+    const char* fb = std::getenv("LACE_SCHEDULE_FALLBACK");
+    p->force_fallback = fb && fb[0] == '1';
+  }
   p->fp64 = prec == LACE_FP64 || prec == LACE_FP64_GAMMA;
   p->gamma = gamma;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return LACE_EHIP; }
@@ -733,7 +427,6 @@ int lace_plan_destroy(lace_plan* p) {
   if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
   if (p->graph.graph) (void)hipGraphDestroy(p->graph.graph);
   for (auto ev : p->events) (void)hipEventDestroy(ev);
-  if (p->s_ready) (void)hipEventDestroy(p->s_ready);
   for (auto st : p->streams) (void)hipStreamDestroy(st);
   if (p->origin) (void)hipStreamDestroy(p->origin);
   delete p;
@@ -756,6 +449,10 @@ static int check_common(const lace_plan* p, int cell, int n_orb) {
   return LACE_OK;
 }
 
+// The device schedule keeps one bit per orbital pair in 64-bit words of at
+// most 4096 orbitals.
+static constexpr int kMaxExchangeOrbitals = 4096;
+
 int lace_screen(lace_plan* p, int cell, const void* psi_g, int n_orb,
                 double* s_out, void* ws, size_t ws_bytes, lace_stream_t stream) {
   int rc = check_common(p, cell, n_orb);
@@ -768,39 +465,6 @@ int lace_screen(lace_plan* p, int cell, const void* psi_g, int n_orb,
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
   if (e == hipSuccess) e = enqueue_screen(p, c, n_orb, L, ws, s_out, st);
   return hip_status(e);
-}
-
-// Host copy of an explicit pair list after validation; false on a bad list.
-static bool copy_pairs(const int32_t* pair_i, const int32_t* pair_j,
-                       int64_t n_pairs, int n_orb,
-                       std::vector<std::pair<int, int>>& pairs) {
-  std::vector<uint8_t> seen((size_t)n_orb * n_orb, 0);
-  pairs.clear();
-  pairs.reserve(n_pairs);
-  for (int64_t k = 0; k < n_pairs; ++k) {
-    const int i = pair_i[k], j = pair_j[k];
-    if (i < 0 || j < 0 || i > j || j >= n_orb) return false;
-    if (seen[(size_t)i * n_orb + j]) return false;
-    seen[(size_t)i * n_orb + j] = 1;
-    pairs.emplace_back(i, j);
-  }
-  return true;
-}
-
-static void all_pairs(int n_orb, std::vector<std::pair<int, int>>& pairs) {
-  pairs.clear();
-  pairs.reserve((size_t)n_orb * (n_orb + 1) / 2);
-  for (int j = 0; j < n_orb; ++j)
-    for (int i = 0; i <= j; ++i) pairs.emplace_back(i, j);
-}
-
-// Kept pairs from a host copy of S: S_ij >= s_thr (upper triangle, Eq. (6)).
-static void kept_from_s(const std::vector<double>& hs, int n_orb, double s_thr,
-                        std::vector<std::pair<int, int>>& pairs) {
-  pairs.clear();
-  for (int j = 0; j < n_orb; ++j)
-    for (int i = 0; i <= j; ++i)
-      if (hs[(size_t)i * n_orb + j] >= s_thr) pairs.emplace_back(i, j);
 }
 
 // Grid orbitals into the workspace (real grids for Gamma plans, packed two
@@ -828,16 +492,16 @@ static hipError_t enqueue_screen(const lace_plan* p, const CellDev& c, int n_orb
 }
 
 // Algorithmic bytes of one batch per pass (see lace_profile_read).
-static void batch_bytes(const lace_plan* p, const CellDev& c, const Batch& bt,
+static void batch_bytes(const lace_plan* p, const CellDev& c, const BatchDev& bt,
                         double out[3]) {
   const double U = double(c.ng) * grid_bytes(p);
   const double G = double(c.ng) * orb_bytes(p);
   // orbs: orbital grids read by pass A; orbs_c: orbital grids read by pass
   // C plus twice the W grids it updates
-  double orbs = 0.0, orbs_c = 0.0, slots = 0.0;
-  if (p->gamma) {
-    for (int q = 0; q < bt.q.n; ++q) {
-      const int pos[4] = {bt.q.i[q], bt.q.j[q], bt.q.k[q], bt.q.l[q]};
+  double orbs = 0.0, orbs_c = 0.0;
+  for (int q = 0; q < bt.n; ++q) {
+    if (p->gamma) {
+      const int pos[4] = {bt.i[q], bt.j[q], bt.k[q], bt.l[q]};
       const int mate[4] = {1, 0, 3, 2};
       int all[4], upd[4], rd[4], na = 0, nu = 0, nr = 0;
       auto add = [](int* set, int& n, int v) {
@@ -847,58 +511,66 @@ static void batch_bytes(const lace_plan* p, const CellDev& c, const Batch& bt,
       for (int t = 0; t < 4; ++t) {
         if (pos[t] < 0) continue;
         add(all, na, pos[t]);
-        if (!((bt.q.skip[t] >> q) & 1ull)) {
+        if (!((bt.skip[t] >> q) & 1ull)) {
           add(upd, nu, pos[t]);
           add(rd, nr, pos[mate[t]]);
         }
       }
       orbs += na;
       orbs_c += nr + 2 * nu;
-    }
-    slots = bt.q.n;
-  } else {
-    for (int k = 0; k < bt.p.n; ++k) {
-      const bool diag = bt.p.i[k] == bt.p.j[k];
-      const bool os = (bt.p.one_sided >> k) & 1ull;
+    } else {
+      const bool diag = bt.i[q] == bt.j[q];
+      const bool os = (bt.one_sided >> q) & 1ull;
       orbs += diag ? 1.0 : 2.0;
       orbs_c += (diag || os) ? 3.0 : 6.0;
     }
-    slots = bt.p.n;
   }
-  out[0] = orbs * G + slots * U;
-  out[1] = 2.0 * slots * U;
-  out[2] = slots * U + orbs_c * G;
+  out[0] = orbs * G + bt.n * U;
+  out[1] = 2.0 * bt.n * U;
+  out[2] = bt.n * U + orbs_c * G;
 }
 
 // One batch of the pair pipeline (pairs, or packed slots for Gamma plans).
 // `lane` picks the pair buffer and the energy partials (0 or 1).
+// Slot capacity of a batch with at most ppb pairs.
+static int slot_cap(const lace_plan* p, int ppb) {
+  return p->gamma ? (ppb + 1) / 2 : ppb;
+}
+
+// Batch b of the workspace's batch table through the pair pipeline.
+// `lane` picks the pair buffer and the energy partials (0 or 1).
 static hipError_t enqueue_batch(const lace_plan* p, const CellDev& c,
-                                const Batch& bt, const Layout& L, void* ws,
+                                int64_t b, int ppb, const Layout& L, void* ws,
                                 int lane, hipStream_t st, hipEvent_t* ev,
                                 const BatchSync* sy = nullptr) {
   void* tmp = at(ws, L.tmp + (size_t)lane * PMAX * c.ng * grid_bytes(p));
   double* epart = reinterpret_cast<double*>(at(ws, L.epart)) +
                   (size_t)lane * PMAX * energy_tiles(c.n, p->fp64);
+  const BatchDev* bt = reinterpret_cast<const BatchDev*>(at(ws, L.tab)) + b;
+  const int cap = slot_cap(p, ppb);
   if (p->gamma)
-    return launch_quad_batch(c, p->fp64, bt.q, at(ws, L.psi), at(ws, L.w),
+    return launch_quad_batch(c, p->fp64, bt, cap, at(ws, L.psi), at(ws, L.w),
                              tmp, epart, st, ev, sy);
-  const PairArgs& b = bt.p;
-  if (ev)
-    return launch_pair_batch_timed(c, p->fp64, b, at(ws, L.psi), at(ws, L.w),
-                                   tmp, epart, st, ev);
-  return launch_pair_batch(c, p->fp64, b, at(ws, L.psi), at(ws, L.w), tmp,
-                           epart, st, sy);
+  return launch_pair_batch(c, p->fp64, bt, cap, at(ws, L.psi), at(ws, L.w),
+                           tmp, epart, st, ev, sy);
 }
 
 static hipError_t ensure_streams(lace_plan* p, int k);
 static hipError_t link(lace_plan* p, hipStream_t from, hipStream_t to, int k);
 
-// Pair pipeline over a schedule, energy reduction, W back to plane waves.
-// Requires the grid orbitals in the workspace.
-// overlap: run consecutive batches on two internal streams (batch b on
-// lane b % 2): a batch's passes A and B overlap the previous batch's passes,
-// and its pass C waits for the previous pass C (they may share W grids), so
-// W is summed in batch order either way.  Profiled calls run on one stream.
+// Which pairs to run: kept by S >= s_thr (s: device S, or nullptr for every
+// pair), or an explicit device list.  n_occ < n_orb: orbitals from n_occ on
+// are virtual, with every occupied x virtual pair one-sided.
+struct PairSource {
+  const double* s = nullptr;
+  double s_thr = 0.0;
+  int s_n = 0;                 // orbitals S covers (two-sided pairs)
+  const int32_t* pair_i = nullptr;
+  const int32_t* pair_j = nullptr;
+  int64_t n_pairs = 0;
+  int n_occ = 0;
+};
+
 // W and the energy partials start at zero.
 static hipError_t enqueue_exchange_zero(const lace_plan* p, const CellDev& c,
                                         int n_orb, const Layout& L, void* ws,
@@ -910,20 +582,88 @@ static hipError_t enqueue_exchange_zero(const lace_plan* p, const CellDev& c,
   return e;
 }
 
-// zeroed: the caller has already enqueued enqueue_exchange_zero on st.
+static Status* status_of(void* ws, const Layout& L) {
+  return reinterpret_cast<Status*>(at(ws, L.info));
+}
+
+// The batch schedule of `src` into the workspace's table, on the device.
+static hipError_t enqueue_schedule(const lace_plan* p, const CellDev& c,
+                                   int n_orb, int ppb, const PairSource& src,
+                                   const Layout& L, void* ws, int64_t* n_kept,
+                                   hipStream_t st) {
+  Status* stw = status_of(ws, L);
+  SchedDesc d{};
+  d.n_orb = n_orb;
+  d.n_occ = src.n_occ;
+  d.ppb = ppb;
+  d.gamma = p->gamma;
+  d.force_fallback = p->force_fallback;
+  d.max_batches = batch_bound(n_orb, ppb, p->gamma, src.n_occ < n_orb);
+  d.s = src.s;
+  d.s_n = src.s_n;
+  d.s_thr = src.s_thr;
+  d.pair_i = src.pair_i;
+  d.pair_j = src.pair_j;
+  d.n_pairs = src.n_pairs;
+  d.table = reinterpret_cast<BatchDev*>(at(ws, L.tab));
+  d.n_batches = &stw->n_batches;
+  d.n_kept = n_kept ? n_kept : &stw->n_kept;
+  d.scratch = at(ws, L.sched);
+  (void)c;
+  return launch_schedule(d, st);
+}
+
+// Schedule, pair pipeline, energy reduction, W back to plane waves.
+// Requires the grid orbitals in the workspace.  Without profiling the host
+// launches the bound of the schedule's batch count (batch_bound) and the
+// kernels of batches past the schedule's end return at once, so nothing
+// waits on the host.  Consecutive batches alternate between two internal
+// streams when `overlap` (batch b on lane b % 2): a batch's passes A and B
+// overlap the previous batch's passes, and its pass C waits for the
+// previous pass C (they may share W grids), so W is summed in batch order
+// either way.  Profiled calls read the schedule back (they synchronize the
+// stream) and run the batches it holds one launch at a time on `st`.
 static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
-                                   const std::vector<Batch>& sched,
-                                   const Layout& L, void* ws, void* w_g,
-                                   double* e_x, hipStream_t st, bool profile,
-                                   bool overlap = false, bool zeroed = false) {
+                                   const PairSource& src, const Layout& L,
+                                   void* ws, void* w_g, double* e_x,
+                                   int64_t* n_kept, hipStream_t st,
+                                   bool profile, bool overlap = false) {
   const bool fp64 = p->fp64;
   void* w = at(ws, L.w);
   const int64_t ntiles = energy_tiles(c.n, fp64);
   double* epart = reinterpret_cast<double*>(at(ws, L.epart));
-  hipError_t e = zeroed ? hipSuccess : enqueue_exchange_zero(p, c, n_orb, L, ws, st);
+  const int ppb = c.ppb;
+  hipError_t e = enqueue_exchange_zero(p, c, n_orb, L, ws, st);
+  if (e == hipSuccess) e = enqueue_schedule(p, c, n_orb, ppb, src, L, ws, n_kept, st);
   Profile& pr = p->prof;
   const bool timed = profile && pr.on;
-  const bool two = overlap && !timed && sched.size() > 1;
+  int64_t nb = batch_bound(n_orb, ppb, p->gamma, src.n_occ < n_orb);
+  std::vector<BatchDev> host_tab;
+  if (e == hipSuccess && timed) {
+    // read the schedule back: the profile records each batch's bytes and
+    // launches only the batches the schedule holds
+    Status h{};
+    e = hipMemcpyAsync(&h, status_of(ws, L), sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) {
+      nb = h.n_batches;
+      host_tab.resize((size_t)nb);
+      if (nb > 0)
+        e = hipMemcpyAsync(host_tab.data(), at(ws, L.tab), sizeof(BatchDev) * nb,
+                           hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e == hipSuccess && pr.used + 4 * (size_t)nb > 65536) e = prof_collect(pr);
+  }
+  // Under stream capture the batches stay on the caller's stream: a capture
+  // of the two-lane form (events recorded and waited for by turns on two
+  // internal streams) ended in a host fault in the runtime's capture end,
+  // whose cause is not known; the library's own graph (the batched call)
+  // runs every job on one stream as well.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (e == hipSuccess && overlap && hipStreamIsCapturing(st, &cap) != hipSuccess)
+    cap = hipStreamCaptureStatusNone;
+  const bool two = overlap && !timed && nb > 1 && cap == hipStreamCaptureStatusNone;
   hipStream_t lane[2] = {st, st};
   hipEvent_t cdone[2] = {nullptr, nullptr};
   if (e == hipSuccess && two) {
@@ -937,12 +677,7 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
       if (e == hipSuccess) e = link(p, st, lane[1], 1);
     }
   }
-  if (e == hipSuccess && timed && pr.used + 4 * sched.size() > 65536) {
-    // bound the number of outstanding events: fold what is recorded
-    e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = prof_collect(pr);
-  }
-  for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b) {
+  for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
     if (timed) {
       const size_t first = pr.used;
       hipEvent_t ev[4];
@@ -950,16 +685,16 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
       if (!ev[0] || !ev[1] || !ev[2] || !ev[3]) return hipErrorOutOfMemory;
       Profile::Rec r;
       r.ev = first;
-      r.pairs = sched[b].p.n;
-      batch_bytes(p, c, sched[b], r.bytes);
+      r.pairs = host_tab[(size_t)b].npairs;
+      batch_bytes(p, c, host_tab[(size_t)b], r.bytes);
       pr.recs.push_back(r);
-      e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), st, ev);
+      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), st, ev);
     } else if (two) {
       BatchSync sy{b > 0 ? cdone[(b - 1) % 2] : nullptr, cdone[b % 2]};
-      e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), lane[b % 2],
-                        nullptr, &sy);
+      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), lane[b % 2], nullptr,
+                        &sy);
     } else {
-      e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), st, nullptr);
+      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), st, nullptr);
     }
   }
   if (e == hipSuccess && two) {
@@ -1007,53 +742,43 @@ static hipError_t enqueue_build_ace(const CellPlan& cp, int n_orb, int sym,
 int lace_apply_exchange(lace_plan* p, int cell, const void* psi_g, int n_orb,
                         double s_thr, const int32_t* pair_i,
                         const int32_t* pair_j, int64_t n_pairs, void* w_g,
-                        double* e_x, int64_t* n_kept, void* ws, size_t ws_bytes,
-                        lace_stream_t stream) {
+                        double* e_x, int64_t* n_kept, int32_t* kept, void* ws,
+                        size_t ws_bytes, lace_stream_t stream) {
   int rc = check_common(p, cell, n_orb);
   if (rc) return rc;
+  if (n_orb > kMaxExchangeOrbitals) return LACE_EINVAL;
   if (!psi_g || !w_g || !ws) return LACE_EINVAL;
   if (!(s_thr >= 0.0 && s_thr < 1.0)) return LACE_EINVAL;
   if ((pair_i == nullptr) != (pair_j == nullptr)) return LACE_EINVAL;
-  if (pair_i && n_pairs < 0) return LACE_EINVAL;
+  if (pair_i && (n_pairs < 0 || n_pairs > (int64_t)n_orb * (n_orb + 1) / 2))
+    return LACE_EINVAL;
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
-  std::vector<std::pair<int, int>> pairs;
-  if (pair_i && !copy_pairs(pair_i, pair_j, n_pairs, n_orb, pairs))
-    return LACE_EINVAL;
   const CellDev& c = p->cells[cell].dev;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
-  if (e != hipSuccess) return LACE_EHIP;
-  bool zeroed = false;
-  if (!pair_i) {
-    if (s_thr > 0.0) {
-      double* s = reinterpret_cast<double*>(at(ws, L.s));
-      e = enqueue_screen(p, c, n_orb, L, ws, s, st);
-      if (e != hipSuccess) return LACE_EHIP;
-      std::vector<double> hs((size_t)n_orb * n_orb);
-      e = hipMemcpyAsync(hs.data(), s, sizeof(double) * hs.size(),
-                         hipMemcpyDeviceToHost, st);
-      if (e == hipSuccess && !p->s_ready)
-        e = hipEventCreateWithFlags(&p->s_ready, hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventRecord(p->s_ready, st);
-      // the device clears W while the host builds the pair list and the
-      // schedule
-      if (e == hipSuccess) e = enqueue_exchange_zero(p, c, n_orb, L, ws, st);
-      if (e == hipSuccess) e = hipEventSynchronize(p->s_ready);
-      if (e != hipSuccess) return LACE_EHIP;
-      zeroed = true;
-      kept_from_s(hs, n_orb, s_thr, pairs);
-    } else {
-      all_pairs(n_orb, pairs);
-    }
+  PairSource src;
+  src.n_occ = n_orb;
+  src.s_n = n_orb;
+  if (pair_i) {
+    src.pair_i = pair_i;
+    src.pair_j = pair_j;
+    src.n_pairs = n_pairs;
+  } else if (s_thr > 0.0) {
+    double* s = reinterpret_cast<double*>(at(ws, L.s));
+    if (e == hipSuccess) e = enqueue_screen(p, c, n_orb, L, ws, s, st);
+    src.s = s;
+    src.s_thr = s_thr;
   }
-  std::vector<Batch> sched;
-  schedule_for(p, pairs, n_orb, c.ppb, sched);
-  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true, true,
-                       zeroed);
-  if (e != hipSuccess) return LACE_EHIP;
-  if (n_kept) *n_kept = (int64_t)pairs.size();
-  return LACE_OK;
+  if (e == hipSuccess && kept && !pair_i)
+    e = launch_kept_pairs(src.s, n_orb, s_thr,
+                          reinterpret_cast<int32_t*>(at(ws, L.kcnt)),
+                          reinterpret_cast<int64_t*>(at(ws, L.koff)), kept,
+                          nullptr, st);
+  if (e == hipSuccess)
+    e = enqueue_exchange(p, c, n_orb, src, L, ws, w_g, e_x, n_kept, st, true,
+                         true);
+  return hip_status(e);
 }
 
 // Newton-Schulz steps of the polar factor; quadratic near convergence and
@@ -1152,6 +877,7 @@ int lace_apply_exchange_virtual(lace_plan* p, int cell, const void* psi_g,
                                 size_t ws_bytes, lace_stream_t stream) {
   if (n_occ < 1 || n_virt < 0) return LACE_EINVAL;
   const int n_orb = n_occ + n_virt;
+  if (n_orb > kMaxExchangeOrbitals) return LACE_EINVAL;
   int rc = check_common(p, cell, n_orb);
   if (rc) return rc;
   if (!psi_g || !w_g || !ws) return LACE_EINVAL;
@@ -1161,35 +887,21 @@ int lace_apply_exchange_virtual(lace_plan* p, int cell, const void* psi_g,
   const CellDev& c = p->cells[cell].dev;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
-  if (e != hipSuccess) return LACE_EHIP;
-  // occupied pairs, screened among the occupied orbitals
-  std::vector<std::pair<int, int>> pairs;
+  // occupied pairs screened among the occupied orbitals; every occupied x
+  // virtual pair one-sided
+  PairSource src;
+  src.n_occ = n_occ;
+  src.s_n = n_occ;
   if (s_thr > 0.0) {
     double* s = reinterpret_cast<double*>(at(ws, L.s));
-    e = enqueue_screen(p, c, n_occ, L, ws, s, st);
-    if (e != hipSuccess) return LACE_EHIP;
-    std::vector<double> hs((size_t)n_occ * n_occ);
-    e = hipMemcpyAsync(hs.data(), s, sizeof(double) * hs.size(),
-                       hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return LACE_EHIP;
-    kept_from_s(hs, n_occ, s_thr, pairs);
-  } else {
-    all_pairs(n_occ, pairs);
+    if (e == hipSuccess) e = enqueue_screen(p, c, n_occ, L, ws, s, st);
+    src.s = s;
+    src.s_thr = s_thr;
   }
-  // every occupied x virtual pair, one-sided
-  std::vector<char> os(pairs.size(), 0);
-  for (int v = n_occ; v < n_orb; ++v)
-    for (int i = 0; i < n_occ; ++i) {
-      pairs.emplace_back(i, v);
-      os.push_back(1);
-    }
-  std::vector<Batch> sched;
-  schedule_for(p, pairs, n_orb, c.ppb, sched, &os, n_occ);
-  e = enqueue_exchange(p, c, n_orb, sched, L, ws, w_g, e_x, st, true, true);
-  if (e != hipSuccess) return LACE_EHIP;
-  if (n_kept) *n_kept = (int64_t)pairs.size();
-  return LACE_OK;
+  if (e == hipSuccess)
+    e = enqueue_exchange(p, c, n_orb, src, L, ws, w_g, e_x, n_kept, st, true,
+                         true);
+  return hip_status(e);
 }
 
 int lace_build_ace(lace_plan* p, int cell, const void* psi_g, const void* w_g,
@@ -1240,49 +952,374 @@ int lace_fft3d(lace_plan* p, int cell, int direction, void* grids, int count,
                                  static_cast<hipStream_t>(stream)));
 }
 
-int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
-                        int64_t n_pairs, int n_orb, int per_batch,
-                        int32_t* batch_of, int64_t* n_batches) {
+// Host form of the device schedule (screen_kernels.hip), step for step, so
+// that the host-only entry points return the schedule the library runs.
+namespace {
+
+struct HSlot { int i, j, k, l, np; uint32_t flags; };
+
+struct HostSched {
+  int n, n_occ, ppb, cap, words;
+  bool gamma, force_fallback;
+  int64_t max_batches;
+  std::vector<uint64_t> kb, db;
+  bool kbit(int a, int b) const {
+    return (kb[(size_t)a * words + (b >> 6)] >> (b & 63)) & 1ull;
+  }
+  bool dbit(int a) const { return (db[a >> 6] >> (a & 63)) & 1ull; }
+};
+
+int cyc_host(int t, int r, int nv) {
+  const int m = nv - 1;
+  if (t == 0) return nv - 1;
+  return (t & 1) ? ((r - t + 1) % m + m) % m : (r + t) % m;
+}
+
+void put_host(BatchDev& b, int q, const HSlot& s) {
+  b.i[q] = s.i; b.j[q] = s.j; b.k[q] = s.k; b.l[q] = s.l;
+  if (s.flags & 1u) b.one_sided |= 1ull << q;
+  for (int t = 0; t < 4; ++t)
+    if ((s.flags >> (1 + t)) & 1u) b.skip[t] |= 1ull << q;
+  if (s.k != s.i) b.star = 0;
+  b.n = q + 1;
+  b.npairs += s.np;
+}
+
+void clear_host(BatchDev& b) {
+  std::memset(&b, 0, sizeof(b));
+  b.star = 1;
+}
+
+void slot_list(const HostSched& h, std::vector<HSlot>& slots) {
+  const int n = h.n, nv = n + (n & 1), m = nv - 1;
+  auto kept = [&](int a, int b) { return a < n && b < n && h.kbit(a, b); };
+  slots.clear();
+  if (!h.gamma || h.ppb < 2) {   // single-pair slots
+    for (int r = 0; r < nv; ++r) {
+      auto add = [&](int a, int b) {
+        if (a > b) std::swap(a, b);
+        if (b >= n) return;
+        const bool os = a < h.n_occ && b >= h.n_occ;
+        if (os || (b < h.n_occ && h.kbit(a, b)))
+          slots.push_back({a, b, -1, -1, 1, os ? 3u : 0u});
+      };
+      if (r == nv - 1) {
+        for (int a = 0; a < n; ++a)
+          if (h.dbit(a)) slots.push_back({a, a, -1, -1, 1, 0u});
+      } else {
+        add(r, nv - 1);
+        for (int k = 1; k <= (m - 1) / 2; ++k) add((r + k) % m, ((r - k) % m + m) % m);
+      }
+    }
+    return;
+  }
+  const int ng = nv / 2;
+  std::vector<std::pair<int, int>> left;
+  for (int g = 0; g < ng; ++g) {
+    if (g == ng - 1) {
+      const int r = nv - 2;
+      if (kept(r, nv - 1)) left.emplace_back(std::min(r, nv - 1), std::max(r, nv - 1));
+      for (int k = 1; k <= (m - 1) / 2; ++k) {
+        const int a = (r + k) % m, b = ((r - k) % m + m) % m;
+        if (kept(a, b)) left.emplace_back(std::min(a, b), std::max(a, b));
+      }
+      continue;
+    }
+    const int r = 2 * g;
+    auto ek = [&](int t) { return kept(cyc_host(t, r, nv), cyc_host((t + 1) % nv, r, nv)); };
+    auto star = [&](int ta) {
+      const int a = cyc_host(ta % nv, r, nv), c = cyc_host((ta + 1) % nv, r, nv),
+                b = cyc_host((ta + 2) % nv, r, nv);
+      slots.push_back({c, a, c, b, 2, 0u});
+    };
+    int t0 = -1;
+    for (int t = 0; t < nv && t0 < 0; ++t)
+      if (!ek(t)) t0 = t;
+    if (t0 < 0) {
+      for (int t = 0; t < nv; t += 2) star(t);
+    } else {
+      int pend = -1;
+      for (int step = 1; step <= nv; ++step) {
+        const int t = (t0 + step) % nv;
+        if (ek(t)) {
+          if (pend < 0) pend = t;
+          else { star(pend); pend = -1; }
+        } else if (pend >= 0) {
+          const int pa = cyc_host(pend, r, nv), pb = cyc_host((pend + 1) % nv, r, nv);
+          left.emplace_back(std::min(pa, pb), std::max(pa, pb));
+          pend = -1;
+        }
+      }
+    }
+  }
+  // left-overs: stars at the smaller orbital, interleaved by rank
+  std::vector<std::vector<HSlot>> per(n);
+  std::vector<int> pend1(n, -1), pend2(n, -1);
+  for (int v = 0; v < n; ++v) {
+    int have = -1;
+    for (size_t e = 0; e < left.size(); ++e) {
+      if (left[e].first != v) continue;
+      if (have < 0) { have = (int)e; continue; }
+      per[v].push_back({v, left[have].second, v, left[e].second, 2, 0u});
+      have = -1;
+    }
+    pend1[v] = have;
+  }
+  for (size_t rho = 0;; ++rho) {
+    bool got = false;
+    for (int v = 0; v < n; ++v)
+      if (rho < per[v].size()) { slots.push_back(per[v][rho]); got = true; }
+    if (!got) break;
+  }
+  // at the larger orbital, then the rest as it comes
+  for (int v = 0; v < n; ++v) {
+    const int e = pend1[v];
+    if (e < 0) continue;
+    const int b = left[e].second;
+    const int hh = pend2[b];
+    if (hh < 0) { pend2[b] = e; continue; }
+    slots.push_back({b, left[hh].first, b, left[e].first, 2, 0u});
+    pend2[b] = -1;
+  }
+  int held = -1;
+  for (int v = 0; v < n; ++v) {
+    const int e = pend2[v];
+    if (e < 0) continue;
+    if (held < 0) { held = e; continue; }
+    const auto pp = left[held], q = left[e];
+    if (pp.first == q.first || pp.first == q.second || pp.second == q.first ||
+        pp.second == q.second) {
+      const int c = (pp.first == q.first || pp.first == q.second) ? pp.first : pp.second;
+      const int pj = pp.first == c ? pp.second : pp.first;
+      const int ql = q.first == c ? q.second : q.first;
+      slots.push_back({c, pj, c, ql, 2, 0u});
+    } else {
+      slots.push_back({pp.first, pp.second, q.first, q.second, 2, 0u});
+    }
+    held = -1;
+  }
+  if (held >= 0) slots.push_back({left[held].first, left[held].second, -1, -1, 1, 0u});
+  if (h.n_occ < n) {
+    const int P = h.n_occ / 2, nvirt = n - h.n_occ;
+    for (int k = 0; k < P; ++k)
+      for (int u = 0; u < nvirt; ++u) {
+        const int v = h.n_occ + u, t = 2 * ((k + u) % P);
+        slots.push_back({v, t, v, t + 1, 2, 1u | 4u | 16u});
+      }
+    if (h.n_occ & 1)
+      for (int u = 0; u < nvirt; ++u)
+        slots.push_back({h.n_occ - 1, h.n_occ + u, -1, -1, 1, 1u | 2u});
+  }
+  int hd = -1;
+  for (int d = 0; d < n; ++d) {
+    if (!h.dbit(d)) continue;
+    if (hd < 0) { hd = d; continue; }
+    slots.push_back({hd, hd, d, d, 2, 0u});
+    hd = -1;
+  }
+  if (hd >= 0) slots.push_back({hd, hd, -1, -1, 1, 0u});
+}
+
+void fallback_host(const HostSched& h, std::vector<BatchDev>& tab, int64_t& nb) {
+  const int n = h.n, nv = n + (n & 1), m = nv - 1;
+  const bool virt = h.n_occ < n;
+  const int sp = h.gamma ? (h.ppb >= 2 ? h.ppb / 2 : 1) : h.ppb;
+  nb = 0;
+  int cur = -1, cur_slots = 0, cur_pairs = 0;
+  auto emit = [&](const HSlot& s) {
+    if (cur < 0 || cur_slots == sp || cur_pairs + s.np > h.ppb) {
+      cur = (int)nb++;
+      clear_host(tab[cur]);
+      cur_slots = cur_pairs = 0;
+    }
+    put_host(tab[cur], cur_slots++, s);
+    cur_pairs += s.np;
+  };
+  for (int r = 0; r < nv; ++r) {
+    HSlot held[2] = {};
+    int nh[2] = {0, 0};
+    auto take = [&](int x, int y, bool os) {
+      HSlot s{x, y, -1, -1, 1, 0u};
+      if (os) s.flags = 1u | (x < h.n_occ ? 2u : 0u);
+      if (!h.gamma || h.ppb == 1) { emit(s); return; }
+      const int kd = os ? 1 : 0;
+      if (nh[kd]) {
+        HSlot t = held[kd];
+        t.k = x; t.l = y; t.np = 2;
+        if (os && x < h.n_occ) t.flags |= 8u;
+        emit(t);
+        nh[kd] = 0;
+      } else {
+        held[kd] = s;
+        nh[kd] = 1;
+      }
+    };
+    if (r == nv - 1) {
+      for (int d = 0; d < n; ++d)
+        if (h.dbit(d)) take(d, d, false);
+    } else {
+      auto pr = [&](int x, int y) {
+        if (x > y) std::swap(x, y);
+        if (y >= n) return;
+        const bool os = virt && x < h.n_occ && y >= h.n_occ;
+        if (os) take(x, y, true);
+        else if (y < h.n_occ && h.kbit(x, y)) take(x, y, false);
+      };
+      pr(r, nv - 1);
+      for (int k = 1; k <= (m - 1) / 2; ++k) pr((r + k) % m, ((r - k) % m + m) % m);
+    }
+    for (int kd = 0; kd < 2; ++kd)
+      if (nh[kd]) emit(held[kd]);
+    cur = -1;
+  }
+  for (int64_t b = nb; b < h.max_batches; ++b) clear_host(tab[(size_t)b]);
+}
+
+// First-fit over a window of 8 open batches, as on the device.
+void host_schedule(const HostSched& h, std::vector<BatchDev>& tab, int64_t& nb) {
+  std::vector<HSlot> slots;
+  slot_list(h, slots);
+  tab.assign((size_t)h.max_batches, BatchDev{});
+  for (auto& b : tab) clear_host(b);
+  struct Win { int id, slots, pairs; std::vector<uint64_t> mask; };
+  std::vector<Win> win;
+  nb = 0;
+  bool over = h.force_fallback;
+  for (size_t q = 0; q < slots.size() && !over; ++q) {
+    const HSlot& s = slots[q];
+    const int orb[4] = {s.i, s.j, s.k, s.l};
+    int pick = -1;
+    for (size_t x = 0; x < win.size() && pick < 0; ++x) {
+      const Win& w = win[x];
+      bool ok = w.pairs + s.np <= h.ppb && w.slots + 1 <= h.cap;
+      for (int t = 0; t < 4 && ok; ++t)
+        if (orb[t] >= 0 && ((w.mask[orb[t] >> 6] >> (orb[t] & 63)) & 1ull)) ok = false;
+      if (ok) pick = (int)x;
+    }
+    if (pick < 0) {
+      if (nb >= h.max_batches) { over = true; break; }
+      if (win.size() == 8) win.erase(win.begin());
+      win.push_back({(int)nb++, 0, 0, std::vector<uint64_t>(h.words, 0ull)});
+      pick = (int)win.size() - 1;
+    }
+    Win& w = win[pick];
+    put_host(tab[(size_t)w.id], w.slots, s);
+    w.slots += 1;
+    w.pairs += s.np;
+    for (int t = 0; t < 4; ++t)
+      if (orb[t] >= 0) w.mask[orb[t] >> 6] |= 1ull << (orb[t] & 63);
+    if (w.pairs >= h.ppb || w.slots >= h.cap) win.erase(win.begin() + pick);
+  }
+  if (over) fallback_host(h, tab, nb);
+}
+
+// Host schedule of an explicit pair list; batch and slot of every pair.
+int schedule_list(const int32_t* pair_i, const int32_t* pair_j, int64_t n_pairs,
+                  int n_orb, int per_batch, bool gamma, int32_t* batch_of,
+                  int32_t* slot_of, int64_t* n_batches) {
   if (!pair_i || !pair_j || !batch_of || !n_batches || n_pairs < 0 ||
-      n_orb < 1 || per_batch < 1 || per_batch > PMAX)
+      n_orb < 1 || n_orb > 4096 || per_batch < 1 || per_batch > PMAX)
     return LACE_EINVAL;
-  std::vector<std::pair<int, int>> pairs;
-  pairs.reserve(n_pairs);
+  HostSched h;
+  h.n = n_orb; h.n_occ = n_orb; h.ppb = per_batch;
+  h.cap = gamma ? (per_batch + 1) / 2 : per_batch;
+  h.words = (n_orb + 63) / 64;
+  h.gamma = gamma;
+  h.force_fallback = false;
+  h.max_batches = batch_bound(n_orb, per_batch, gamma, false);
+  h.kb.assign((size_t)n_orb * h.words, 0ull);
+  h.db.assign((size_t)h.words, 0ull);
   for (int64_t k = 0; k < n_pairs; ++k) {
     const int i = pair_i[k], j = pair_j[k];
     if (i < 0 || j < i || j >= n_orb) return LACE_EINVAL;
-    pairs.emplace_back(i, j);
+    uint64_t* w = i == j ? &h.db[i >> 6] : &h.kb[(size_t)j * h.words + (i >> 6)];
+    if ((*w >> (i & 63)) & 1ull) return LACE_EINVAL;   // repeated pair
+    *w |= 1ull << (i & 63);
+    if (i != j) h.kb[(size_t)i * h.words + (j >> 6)] |= 1ull << (j & 63);
   }
-  std::vector<Batch> sched;
-  std::vector<int32_t> bo;
-  build_schedule(pairs, n_orb, per_batch, sched, &bo);
-  for (int64_t k = 0; k < n_pairs; ++k) batch_of[k] = bo[k];
-  *n_batches = (int64_t)sched.size();
+  std::vector<BatchDev> tab;
+  int64_t nb = 0;
+  host_schedule(h, tab, nb);
+  std::vector<int64_t> where((size_t)n_orb * n_orb, -1);
+  for (int64_t b = 0; b < nb; ++b)
+    for (int q = 0; q < tab[(size_t)b].n; ++q) {
+      const BatchDev& d = tab[(size_t)b];
+      const int64_t code = b * 64 + q;
+      where[(size_t)std::min(d.i[q], d.j[q]) * n_orb + std::max(d.i[q], d.j[q])] = code;
+      if (d.k[q] >= 0)
+        where[(size_t)std::min(d.k[q], d.l[q]) * n_orb + std::max(d.k[q], d.l[q])] = code;
+    }
+  for (int64_t k = 0; k < n_pairs; ++k) {
+    const int64_t code = where[(size_t)pair_i[k] * n_orb + pair_j[k]];
+    if (code < 0) return LACE_EINVAL;
+    batch_of[k] = (int32_t)(code / 64);
+    if (slot_of) slot_of[k] = (int32_t)(code % 64);
+  }
+  *n_batches = nb;
   return LACE_OK;
+}
+
+}  // namespace
+
+int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
+                        int64_t n_pairs, int n_orb, int per_batch,
+                        int32_t* batch_of, int64_t* n_batches) {
+  return schedule_list(pair_i, pair_j, n_pairs, n_orb, per_batch, false,
+                       batch_of, nullptr, n_batches);
 }
 
 int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int32_t* slot_of,
                         int64_t* n_batches) {
-  if (!pair_i || !pair_j || !batch_of || !slot_of || !n_batches ||
-      n_pairs < 0 || n_orb < 1 || per_batch < 1 || per_batch > PMAX)
+  if (!slot_of) return LACE_EINVAL;
+  return schedule_list(pair_i, pair_j, n_pairs, n_orb, per_batch, true,
+                       batch_of, slot_of, n_batches);
+}
+
+int lace_read_schedule(const lace_plan* p, int cell, int n_orb, const void* ws,
+                       lace_stream_t stream, const int32_t* pair_i,
+                       const int32_t* pair_j, int64_t n_pairs,
+                       int32_t* batch_of, int32_t* slot_of,
+                       int64_t* n_batches) {
+  if (!p || cell < 0 || cell >= (int)p->cells.size() || n_orb < 1 || !ws ||
+      !n_batches || n_pairs < 0 || (n_pairs > 0 && (!pair_i || !pair_j || !batch_of || !slot_of)))
     return LACE_EINVAL;
-  std::vector<std::pair<int, int>> pairs;
-  pairs.reserve(n_pairs);
+  const Layout L = layout_for(p, cell, n_orb, 0);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Status h{};
+  void* w = const_cast<void*>(ws);
+  hipError_t e = hipMemcpyAsync(&h, status_of(w, L), sizeof(h),
+                                hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return LACE_EHIP;
+  if (h.n_batches < 0 || h.n_batches > L.max_batches) return LACE_EINVAL;
+  std::vector<BatchDev> tab((size_t)h.n_batches);
+  if (h.n_batches > 0) {
+    e = hipMemcpyAsync(tab.data(), at(w, L.tab), sizeof(BatchDev) * tab.size(),
+                       hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return LACE_EHIP;
+  }
+  std::vector<int64_t> where((size_t)n_orb * n_orb, -1);
+  for (size_t b = 0; b < tab.size(); ++b)
+    for (int q = 0; q < tab[b].n && q < PMAX; ++q) {
+      const BatchDev& d = tab[b];
+      const int64_t code = (int64_t)b * 64 + q;
+      for (int t = 0; t < 2; ++t) {
+        const int a = t ? d.k[q] : d.i[q], c = t ? d.l[q] : d.j[q];
+        if (a < 0 || c < 0 || a >= n_orb || c >= n_orb) continue;
+        where[(size_t)std::min(a, c) * n_orb + std::max(a, c)] = code;
+      }
+    }
   for (int64_t k = 0; k < n_pairs; ++k) {
     const int i = pair_i[k], j = pair_j[k];
     if (i < 0 || j < i || j >= n_orb) return LACE_EINVAL;
-    pairs.emplace_back(i, j);
+    const int64_t code = where[(size_t)i * n_orb + j];
+    batch_of[k] = code < 0 ? -1 : (int32_t)(code / 64);
+    slot_of[k] = code < 0 ? -1 : (int32_t)(code % 64);
   }
-  std::vector<Batch> sched;
-  std::vector<int32_t> bo, so;
-  build_slot_schedule(pairs, n_orb, per_batch, sched, &bo, &so);
-  for (int64_t k = 0; k < n_pairs; ++k) {
-    batch_of[k] = bo[k];
-    slot_of[k] = so[k];
-  }
-  *n_batches = (int64_t)sched.size();
+  *n_batches = h.n_batches;
   return LACE_OK;
 }
 
@@ -1309,6 +1346,7 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
                   int* cand_ppb, int* cand_plane, double* cand_us, int* n_cand) {
   int rc = check_common(p, cell, n_orb);
   if (rc) return rc;
+  if (n_orb > kMaxExchangeOrbitals) return LACE_EINVAL;
   if (!psi_g || !ws) return LACE_EINVAL;
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
@@ -1320,8 +1358,9 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   // every candidate schedules all pairs its own way and is timed on its
   // first batches holding at least 4 * PMAX pairs: steady-state batches of
   // that candidate's own schedule
-  std::vector<std::pair<int, int>> pairs;
-  all_pairs(n_orb, pairs);
+  PairSource all;
+  all.n_occ = n_orb;
+  all.s_n = n_orb;
   struct Cand { int ppb, plane; double us; };
   std::vector<Cand> cands;
   const int ppbs[4] = {8, 16, 32, 64};
@@ -1336,25 +1375,32 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   for (auto& cd : cands) {
     c.ppb = cd.ppb;
     c.use_plane = cd.plane;
-    std::vector<Batch> sched;
-    schedule_for(p, pairs, n_orb, cd.ppb, sched);
+    if (e == hipSuccess) e = enqueue_schedule(p, c, n_orb, cd.ppb, all, L, ws, nullptr, st);
+    Status h{};
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&h, status_of(ws, L), sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    std::vector<BatchDev> tab((size_t)std::max(h.n_batches, 0));
+    if (e == hipSuccess && !tab.empty())
+      e = hipMemcpyAsync(tab.data(), at(ws, L.tab), sizeof(BatchDev) * tab.size(),
+                         hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     int64_t timed_pairs = 0;
     size_t nb = 0;
-    while (nb < sched.size() && timed_pairs < 4 * PMAX)
-      timed_pairs += sched[nb++].p.n;
-    sched.resize(nb);
+    while (nb < tab.size() && timed_pairs < 4 * PMAX) timed_pairs += tab[nb++].npairs;
     double best = 1e30;
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       e = hipEventRecord(t0, st);
-      for (size_t b = 0; e == hipSuccess && b < sched.size(); ++b)
-        e = enqueue_batch(p, c, sched[b], L, ws, (int)(b % 2), st, nullptr);
+      for (size_t b = 0; e == hipSuccess && b < nb; ++b)
+        e = enqueue_batch(p, c, (int64_t)b, cd.ppb, L, ws, (int)(b % 2), st,
+                          nullptr);
       if (e == hipSuccess) e = hipEventRecord(t1, st);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (rep > 0 && ms < best) best = ms;   // first repetition warms up
     }
-    cd.us = 1e3 * best / double(timed_pairs);
+    cd.us = timed_pairs > 0 ? 1e3 * best / double(timed_pairs) : 1e30;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
@@ -1420,6 +1466,7 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     const lace_job& j = jobs[k];
     int rc = check_common(p, j.cell, j.n_orb);
     if (rc) return rc;
+    if (j.n_orb > kMaxExchangeOrbitals) return LACE_EINVAL;
     if (!j.psi_g || !j.w_g || !j.ws) return LACE_EINVAL;
     if (!(j.s_thr >= 0.0 && j.s_thr < 1.0)) return LACE_EINVAL;
     if (j.xi_g && j.sym != LACE_SYM_AVG && j.sym != LACE_SYM_UPPER &&
@@ -1452,54 +1499,28 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     on[k] = best;
     load[best] += cost(k);
   }
-  // phase 1: grid orbitals and screening, eagerly
-  for (int q = 0; q < ns && e == hipSuccess; ++q) e = link(p, st, p->streams[q], q);
-  bool any_screen = false;
-  for (int k = 0; k < n_jobs && e == hipSuccess; ++k) {
-    const lace_job& j = jobs[k];
-    const CellDev& c = p->cells[j.cell].dev;
-    hipStream_t js = p->streams[on[k]];
-    e = enqueue_orbitals(p, c, j.psi_g, j.n_orb, lay[k], j.ws, js);
-    if (e == hipSuccess && j.s_thr > 0.0) {
-      any_screen = true;
-      e = enqueue_screen(p, c, j.n_orb, lay[k], j.ws,
-                         reinterpret_cast<double*>(at(j.ws, lay[k].s)), js);
-    }
-  }
-  if (e != hipSuccess) return LACE_EHIP;
-  std::vector<std::vector<Batch>> scheds(n_jobs);
-  {
-    std::vector<std::vector<double>> hs(n_jobs);
-    for (int k = 0; k < n_jobs && e == hipSuccess; ++k) {
-      if (jobs[k].s_thr > 0.0) {
-        hs[k].resize((size_t)jobs[k].n_orb * jobs[k].n_orb);
-        e = hipMemcpyAsync(hs[k].data(), at(jobs[k].ws, lay[k].s),
-                           sizeof(double) * hs[k].size(), hipMemcpyDeviceToHost,
-                           p->streams[on[k]]);
-      }
-    }
-    if (any_screen)
-      for (int q = 0; q < ns && e == hipSuccess; ++q)
-        e = hipStreamSynchronize(p->streams[q]);
-    if (e != hipSuccess) return LACE_EHIP;
-    for (int k = 0; k < n_jobs; ++k) {
-      std::vector<std::pair<int, int>> pairs;
-      if (jobs[k].s_thr > 0.0) kept_from_s(hs[k], jobs[k].n_orb, jobs[k].s_thr, pairs);
-      else all_pairs(jobs[k].n_orb, pairs);
-      jobs[k].n_kept = (int64_t)pairs.size();
-      schedule_for(p, pairs, jobs[k].n_orb, p->cells[jobs[k].cell].dev.ppb,
-                   scheds[k]);
-    }
-  }
-  // phase 2: pair pipelines, back-transforms, ACE builds
-  auto enqueue_phase2 = [&]() -> hipError_t {
+  // every job's device work on its stream: grid orbitals, screening,
+  // schedule, pair pipeline, W to plane waves, ACE build
+  auto enqueue_all = [&]() -> hipError_t {
     hipError_t r = hipSuccess;
     for (int k = 0; k < n_jobs && r == hipSuccess; ++k) {
       const lace_job& j = jobs[k];
       const CellPlan& cp = p->cells[j.cell];
+      const CellDev& c = cp.dev;
       hipStream_t js = p->streams[on[k]];
-      r = enqueue_exchange(p, cp.dev, j.n_orb, scheds[k], lay[k], j.ws, j.w_g,
-                           j.e_x, js, false);
+      r = enqueue_orbitals(p, c, j.psi_g, j.n_orb, lay[k], j.ws, js);
+      PairSource src;
+      src.n_occ = j.n_orb;
+      src.s_n = j.n_orb;
+      if (r == hipSuccess && j.s_thr > 0.0) {
+        double* sm = reinterpret_cast<double*>(at(j.ws, lay[k].s));
+        r = enqueue_screen(p, c, j.n_orb, lay[k], j.ws, sm, js);
+        src.s = sm;
+        src.s_thr = j.s_thr;
+      }
+      if (r == hipSuccess)
+        r = enqueue_exchange(p, c, j.n_orb, src, lay[k], j.ws, j.w_g, j.e_x,
+                             j.n_kept, js, false);
       if (r == hipSuccess && j.xi_g)
         r = enqueue_build_ace(cp, j.n_orb, j.sym, lay[k], j.ws, j.psi_g, j.w_g,
                               j.xi_g, j.m_out, j.ex_tr, j.info, js);
@@ -1507,48 +1528,40 @@ int lace_apply_exchange_batched(lace_plan* p, lace_job* jobs, int n_jobs,
     return r;
   };
   if (!(flags & LACE_BATCH_GRAPH)) {
-    e = enqueue_phase2();
+    for (int q = 0; q < ns && e == hipSuccess; ++q) e = link(p, st, p->streams[q], q);
+    if (e == hipSuccess) e = enqueue_all();
     for (int q = 0; q < ns && e == hipSuccess; ++q)
       e = link(p, p->streams[q], st, q);
     return hip_status(e);
   }
-  // graph: key on everything the captured work depends on
+  // graph: key on everything the captured work depends on (the pair lists
+  // are built inside it, so a replay follows the current orbitals)
   std::vector<uint64_t> key;
   hash_mix(key, (uint64_t)n_jobs);
   for (int k = 0; k < n_jobs; ++k) {
     const lace_job& j = jobs[k];
     const CellDev& c = p->cells[j.cell].dev;
+    uint64_t thr_bits = 0;
+    std::memcpy(&thr_bits, &j.s_thr, sizeof(thr_bits));
     for (uint64_t v : {(uint64_t)j.cell, (uint64_t)(uintptr_t)j.psi_g,
-                       (uint64_t)j.n_orb, (uint64_t)(uintptr_t)j.w_g,
-                       (uint64_t)(uintptr_t)j.e_x, (uint64_t)j.sym,
-                       (uint64_t)(uintptr_t)j.xi_g, (uint64_t)(uintptr_t)j.m_out,
-                       (uint64_t)(uintptr_t)j.ex_tr, (uint64_t)(uintptr_t)j.info,
-                       (uint64_t)(uintptr_t)j.ws,
-                       (uint64_t)on[k], (uint64_t)c.ppb, (uint64_t)c.use_plane,
-                       (uint64_t)scheds[k].size()})
+                       (uint64_t)j.n_orb, thr_bits, (uint64_t)(uintptr_t)j.w_g,
+                       (uint64_t)(uintptr_t)j.e_x, (uint64_t)(uintptr_t)j.n_kept,
+                       (uint64_t)j.sym, (uint64_t)(uintptr_t)j.xi_g,
+                       (uint64_t)(uintptr_t)j.m_out, (uint64_t)(uintptr_t)j.ex_tr,
+                       (uint64_t)(uintptr_t)j.info, (uint64_t)(uintptr_t)j.ws,
+                       (uint64_t)on[k], (uint64_t)c.ppb, (uint64_t)c.use_plane})
       hash_mix(key, v);
-    uint64_t h = 1469598103934665603ull;
-    for (const auto& bt : scheds[k]) {
-      for (int q = 0; q < bt.p.n; ++q)
-        h = (h ^ (uint64_t)(bt.p.i[q] * 65536 + bt.p.j[q] + 1)) *
-            1099511628211ull;
-      for (int q = 0; q < bt.q.n; ++q)
-        for (int v : {bt.q.i[q], bt.q.j[q], bt.q.k[q], bt.q.l[q]})
-          h = (h ^ (uint64_t)(v + 2)) * 1099511628211ull;
-      h = (h ^ 0x9e3779b97f4a7c15ull) * 1099511628211ull;   // batch boundary
-    }
-    hash_mix(key, h);
   }
-  // the origin stream waits for phase 1 on every internal stream
-  for (int q = 0; q < ns && e == hipSuccess; ++q) e = link(p, p->streams[q], p->origin, q);
+  // the origin stream waits for the caller's stream
+  e = link(p, st, p->origin, ns);
   if (e != hipSuccess) return LACE_EHIP;
   if (!p->graph.exec || p->graph.key != key) {
     if (p->graph.exec) { (void)hipGraphExecDestroy(p->graph.exec); p->graph.exec = nullptr; }
     if (p->graph.graph) { (void)hipGraphDestroy(p->graph.graph); p->graph.graph = nullptr; }
     e = hipStreamBeginCapture(p->origin, hipStreamCaptureModeThreadLocal);
     for (int q = 0; q < ns && e == hipSuccess; ++q)
-      e = link(p, p->origin, p->streams[q], ns);
-    hipError_t r = (e == hipSuccess) ? enqueue_phase2() : e;
+      e = link(p, p->origin, p->streams[q], q);
+    hipError_t r = (e == hipSuccess) ? enqueue_all() : e;
     for (int q = 0; q < ns && r == hipSuccess; ++q)
       r = link(p, p->streams[q], p->origin, q);
     hipGraph_t g = nullptr;

@@ -42,7 +42,7 @@ SYMBOLS = (
     "lace_schedule_slots", "lace_apply_exchange_virtual", "lace_align",
     "lace_scdm",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
-    "lace_autotune", "lace_check_real",
+    "lace_autotune", "lace_check_real", "lace_read_schedule",
 )
 LACE_BATCH_GRAPH = 1
 
@@ -68,7 +68,7 @@ class LaceJob(ctypes.Structure):
     _fields_ = [("cell", ctypes.c_int32), ("psi_g", ctypes.c_void_p),
                 ("n_orb", ctypes.c_int32), ("s_thr", ctypes.c_double),
                 ("w_g", ctypes.c_void_p), ("e_x", ctypes.c_void_p),
-                ("n_kept", ctypes.c_int64), ("sym", ctypes.c_int32),
+                ("n_kept", ctypes.c_void_p), ("sym", ctypes.c_int32),
                 ("xi_g", ctypes.c_void_p), ("m_out", ctypes.c_void_p),
                 ("ex_tr", ctypes.c_void_p), ("info", ctypes.c_void_p),
                 ("ws", ctypes.c_void_p),
@@ -96,13 +96,10 @@ def load(path: str = LIB_PATH):
     lib.lace_workspace_size.argtypes = [vp, i32, i32, i32,
                                         ctypes.POINTER(sz)]
     lib.lace_screen.argtypes = [vp, i32, vp, i32, vp, vp, sz, vp]
-    lib.lace_apply_exchange.argtypes = [vp, i32, vp, i32, dbl, p_i32, p_i32,
-                                        i64, vp, vp,
-                                        ctypes.POINTER(ctypes.c_int64), vp, sz,
-                                        vp]
+    lib.lace_apply_exchange.argtypes = [vp, i32, vp, i32, dbl, vp, vp, i64,
+                                        vp, vp, vp, vp, vp, sz, vp]
     lib.lace_apply_exchange_virtual.argtypes = [
-        vp, i32, vp, i32, i32, dbl, vp, vp, ctypes.POINTER(ctypes.c_int64), vp,
-        sz, vp]
+        vp, i32, vp, i32, i32, dbl, vp, vp, vp, vp, sz, vp]
     lib.lace_align.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, sz, vp]
     lib.lace_scdm.argtypes = [vp, i32, vp, i32, vp, vp, vp, vp, sz, vp]
     lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
@@ -121,6 +118,8 @@ def load(path: str = LIB_PATH):
                                         p_i64]
     lib.lace_schedule_slots.argtypes = [p_i32, p_i32, i64, i32, i32, p_i32,
                                         p_i32, p_i64]
+    lib.lace_read_schedule.argtypes = [vp, i32, i32, vp, vp, p_i32, p_i32, i64,
+                                       p_i32, p_i32, p_i64]
     lib.lace_apply_exchange_batched.argtypes = [vp, ctypes.POINTER(LaceJob),
                                                 i32, i32, vp]
     lib.lace_set_tuning.argtypes = [vp, i32, i32, i32]
@@ -175,11 +174,61 @@ def _need(t, count, what):
         raise ValueError(f"{what} holds {t.numel()} elements, needs {count}")
 
 
-def _stream(stream):
+def _stream_obj(stream):
     if stream is None:
         import torch
         stream = torch.cuda.current_stream()
-    return ctypes.c_void_p(stream.cuda_stream)
+    return stream
+
+
+def _stream(stream):
+    return ctypes.c_void_p(_stream_obj(stream).cuda_stream)
+
+
+def _count(t, stream):
+    """A one-element int64 device tensor for a count the library writes:
+    the caller's, or a new one kept alive for the stream."""
+    import torch
+    if t is not None:
+        return t, False
+    st = _stream_obj(stream)
+    with torch.cuda.stream(st):
+        t = torch.zeros(1, dtype=torch.int64, device="cuda")
+    return t, True
+
+
+def _read_count(t, own, stream):
+    """The count as an int when the binding made the tensor (synchronizes
+    the stream), else the caller's tensor."""
+    if not own:
+        return t
+    _stream_obj(stream).synchronize()
+    return int(t.item())
+
+
+def pair_tensors(pairs, n_orb, device="cuda", stream=None):
+    """An explicit pair list as two device int32 tensors (i, j) and its
+    length, checked on the host first: 0 <= i <= j < n_orb and no repeats.
+    An empty list still gets (one-element) tensors, so that the library sees
+    a list and not a request to screen."""
+    import torch
+    if isinstance(pairs, tuple) and len(pairs) == 2 and hasattr(pairs[0], "is_cuda"):
+        return pairs[0], pairs[1], pairs[0].numel()
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    if pr.size:
+        i, j = pr[:, 0], pr[:, 1]
+        if (i < 0).any() or (j < i).any() or (j >= n_orb).any():
+            raise ValueError("pairs must satisfy 0 <= i <= j < n_orb")
+        if np.unique(i * n_orb + j).size != pr.shape[0]:
+            raise ValueError("repeated pair")
+    st = _stream_obj(stream)
+    count = pr.shape[0]
+    if count == 0:
+        pr = np.zeros((1, 2), np.int64)
+    with torch.cuda.stream(st):
+        pi = torch.tensor(pr[:, 0].astype(np.int32), device=device)
+        pj = torch.tensor(pr[:, 1].astype(np.int32), device=device)
+    return pi, pj, count
 
 
 class Plan:
@@ -244,22 +293,23 @@ def lace_screen(plan, cell, psi_g, n_orb, s_out, ws, stream=None):
 
 
 def lace_apply_exchange_virtual(plan, cell, psi_g, n_occ, n_virt, s_thr, w_g,
-                                e_x, ws, stream=None) -> int:
+                                e_x, ws, stream=None, n_kept=None):
     """W for n_occ occupied and n_virt virtual orbitals (occupied first).
-    Returns the number of pair transforms run."""
+    Returns the number of pair transforms run (an int, after synchronizing
+    the stream), or the caller's n_kept tensor, which receives it."""
     import torch
     n = (int(n_occ) + int(n_virt)) * _n_pw(plan, cell)
     _need(psi_g, n, "psi_g")
     _need(w_g, n, "w_g")
     _need(e_x, 1, "e_x")
-    kept = ctypes.c_int64(0)
+    nk, own = _count(n_kept, stream)
     _check(load().lace_apply_exchange_virtual(
         plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), int(n_occ),
         int(n_virt), float(s_thr), _ptr(w_g, torch.complex128, "w_g"),
-        _ptr(e_x, torch.float64, "e_x"), ctypes.byref(kept),
+        _ptr(e_x, torch.float64, "e_x"), _ptr(nk, torch.int64, "n_kept"),
         _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)),
         "lace_apply_exchange_virtual")
-    return kept.value
+    return _read_count(nk, own, stream)
 
 
 def lace_align(plan, cell, psi_new, psi_old, n_orb, psi_out, resid, ws,
@@ -297,31 +347,59 @@ def lace_scdm(plan, cell, psi_g, n_orb, phi_g, points, resid, ws,
 
 
 def lace_apply_exchange(plan, cell, psi_g, n_orb, s_thr, pairs, w_g, e_x, ws,
-                        stream=None) -> int:
-    """``pairs``: None (screen with s_thr) or an (n, 2) int array of
-    unordered pairs i <= j.  Returns the number of pairs run."""
+                        stream=None, n_kept=None, kept=None):
+    """``pairs``: None (screen with s_thr), an (n, 2) int array of
+    unordered pairs i <= j (checked here, then copied to the device), or a
+    tuple of two device int32 tensors.  ``kept``: optional int32 device
+    tensor of n_orb (n_orb + 1) elements that receives the kept pairs when
+    the call screens.  Returns the number of pairs run (an int, after
+    synchronizing the stream), or the caller's n_kept tensor, which
+    receives it."""
     import torch
     _need(psi_g, n_orb * _n_pw(plan, cell), "psi_g")
     _need(w_g, n_orb * _n_pw(plan, cell), "w_g")
     _need(e_x, 1, "e_x")
+    _need(kept, n_orb * (n_orb + 1), "kept")
+    st = _stream_obj(stream)
     if pairs is None:
         pi = pj = None
         npairs = 0
     else:
-        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
-        pi_arr = np.ascontiguousarray(pr[:, 0])
-        pj_arr = np.ascontiguousarray(pr[:, 1])
-        pi = pi_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        pj = pj_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-        npairs = pr.shape[0]
-    kept = ctypes.c_int64(0)
+        pi, pj, npairs = pair_tensors(pairs, n_orb, stream=st)
+        if pj.numel() < npairs:
+            raise ValueError("pair_i and pair_j differ in length")
+        pi.record_stream(st)
+        pj.record_stream(st)
+    nk, own = _count(n_kept, st)
     _check(load().lace_apply_exchange(
         plan.handle, cell, _ptr(psi_g, torch.complex128, "psi_g"), n_orb,
-        float(s_thr), pi, pj, npairs, _ptr(w_g, torch.complex128, "w_g"),
-        _ptr(e_x, torch.float64, "e_x"), ctypes.byref(kept),
-        _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream)),
+        float(s_thr), _ptr(pi, torch.int32, "pair_i"),
+        _ptr(pj, torch.int32, "pair_j"), npairs,
+        _ptr(w_g, torch.complex128, "w_g"), _ptr(e_x, torch.float64, "e_x"),
+        _ptr(nk, torch.int64, "n_kept"), _ptr(kept, torch.int32, "kept"),
+        _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(st)),
         "lace_apply_exchange")
-    return kept.value
+    return _read_count(nk, own, st)
+
+
+def lace_read_schedule(plan, cell, n_orb, ws, pairs, stream=None):
+    """The batch and slot of each of ``pairs`` in the schedule the last
+    exchange call on ``ws`` built on the device (synchronizes the stream).
+    Returns (batch_of, slot_of, n_batches)."""
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    pi = np.ascontiguousarray(pr[:, 0])
+    pj = np.ascontiguousarray(pr[:, 1])
+    bo = np.empty(pr.shape[0], dtype=np.int32)
+    so = np.empty(pr.shape[0], dtype=np.int32)
+    nb = ctypes.c_int64(0)
+    P = ctypes.POINTER(ctypes.c_int32)
+    _check(load().lace_read_schedule(plan.handle, cell, int(n_orb),
+                                     _ptr(ws, None, "ws"), _stream(stream),
+                                     pi.ctypes.data_as(P), pj.ctypes.data_as(P),
+                                     pr.shape[0], bo.ctypes.data_as(P),
+                                     so.ctypes.data_as(P), ctypes.byref(nb)),
+           "lace_read_schedule")
+    return bo, so, nb.value
 
 
 def lace_build_ace(plan, cell, psi_g, w_g, n_orb, sym, xi_g, m_out, ex_tr, ws,
@@ -456,16 +534,21 @@ def _vp(t):
 
 def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
     """``jobs``: list of dicts with cell, psi_g, n_orb, s_thr, w_g and
-    optional e_x, sym, xi_g, m_out, ex_tr, plus ws (torch tensors).
-    Returns the kept pair count of each job."""
+    optional e_x, n_kept (int64 device tensor), sym, xi_g, m_out, ex_tr,
+    info, plus ws (torch tensors).  Returns the kept pair count of each job:
+    ints (after synchronizing the stream) when no job brings an n_kept
+    tensor, else the n_kept tensors (None for a job without one)."""
     import torch
     arr = (LaceJob * len(jobs))()
+    st = _stream_obj(stream)
+    any_count = any(j.get("n_kept") is not None for j in jobs)
+    counts = []
     for k, j in enumerate(jobs):
         n_orb, n_pw = int(j["n_orb"]), _n_pw(plan, j.get("cell", 0))
         for name in ("psi_g", "w_g", "xi_g"):
             _need(j.get(name), n_orb * n_pw, name)
         _need(j.get("m_out"), n_orb * n_orb, "m_out")
-        for name in ("e_x", "ex_tr", "info"):
+        for name in ("e_x", "ex_tr", "info", "n_kept"):
             _need(j.get(name), 1, name)
         for name in ("psi_g", "w_g", "xi_g", "m_out"):
             t = j.get(name)
@@ -484,6 +567,14 @@ def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
         arr[k].s_thr = float(j.get("s_thr", 0.0))
         arr[k].w_g = _vp(j["w_g"])
         arr[k].e_x = _vp(j.get("e_x"))
+        if any_count:
+            nk = j.get("n_kept")
+        else:
+            nk, _ = _count(None, st)
+        if nk is not None:
+            _ptr(nk, torch.int64, "n_kept")
+        counts.append(nk)
+        arr[k].n_kept = _vp(nk)
         arr[k].sym = SYM_MODES.get(j.get("sym", "avg"), 0) \
             if isinstance(j.get("sym", "avg"), str) else int(j["sym"])
         arr[k].xi_g = _vp(j.get("xi_g"))
@@ -494,8 +585,11 @@ def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
         arr[k].ws_bytes = j["ws"].numel() * j["ws"].element_size()
     _check(load().lace_apply_exchange_batched(
         plan.handle, arr, len(jobs), LACE_BATCH_GRAPH if graph else 0,
-        _stream(stream)), "lace_apply_exchange_batched")
-    return [arr[k].n_kept for k in range(len(jobs))]
+        _stream(st)), "lace_apply_exchange_batched")
+    if any_count:
+        return counts
+    st.synchronize()
+    return [int(t.item()) for t in counts]
 
 
 def lace_set_tuning(plan, cell, pairs_per_batch, use_plane):

@@ -104,8 +104,11 @@ class Server:
             ex = torch.zeros(len(job.variants), dtype=torch.float64,
                              device=self.device)
             ex_tr = torch.empty(1, dtype=torch.float64, device=self.device)
-            # Cholesky info word of each outer step's ACE build
+            # Cholesky info word of each outer step's ACE build, and the
+            # pairs each step runs
             info = torch.zeros(len(job.variants), dtype=torch.int32,
+                               device=self.device)
+            kept = torch.zeros(len(job.variants), dtype=torch.int64,
                                device=self.device)
             ws = torch.empty(lace.lace_workspace_size(plan, cell, n, n),
                              dtype=torch.uint8, device=self.device)
@@ -119,22 +122,22 @@ class Server:
                     lace.lace_align(plan, cell, psi, prev, n, nxt, None, ws, st)
                     psi = nxt
                     cur, nxt = nxt, cur
-                kept = lace.lace_apply_exchange(
+                lace.lace_apply_exchange(
                     plan, cell, psi, n, c.cell.get("s_thr", 0.0), None, w,
-                    ex[step:step + 1], ws, st)
+                    ex[step:step + 1], ws, st, n_kept=kept[step:step + 1])
                 lace.lace_build_ace(plan, cell, psi, w, n, "avg", xi, m,
                                     ex_tr, ws, st, info=info[step:step + 1])
                 for _ in range(self.inner):
                     lace.lace_apply_ace(plan, cell, xi, n, psi, n, y, ws, st)
-                job.kept.append(kept)
                 prev = psi
             st.synchronize()
         job.done = time.perf_counter() - t0
         job.e_x = ex.cpu().tolist()
         job.info = info.cpu().tolist()
+        job.kept = kept.cpu().tolist()
         if self.keep_xi:
             job.xi_host = xi.cpu().numpy()
-        del w, xi, y, m, ex, ex_tr, ws, info
+        del w, xi, y, m, ex, ex_tr, ws, info, kept
         if any(job.info):
             raise lace.LaceError(lace.LACE_ENOTPD,
                                  f"job {job.jid}: ACE build (info {job.info})")

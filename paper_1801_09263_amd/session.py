@@ -34,7 +34,9 @@ class CellSession:
                              device=device)
         self.e_x = torch.zeros(1, dtype=torch.float64, device=device)
         self.ex_tr = torch.zeros(1, dtype=torch.float64, device=device)
-        self.n_kept = 0
+        # pairs run by the last exchange call, written on the device
+        self.n_kept_t = torch.zeros(1, dtype=torch.int64, device=device)
+        self.kept = None
 
     def set_orbitals(self, coeffs):
         c = torch.as_tensor(np.ascontiguousarray(coeffs), dtype=torch.complex128)
@@ -46,20 +48,39 @@ class CellSession:
                          stream)
         return self.s
 
-    def apply_exchange(self, s_thr=0.0, pairs=None, stream=None, n_occ=None):
+    @property
+    def n_kept(self) -> int:
+        """Pairs run by the last exchange call (synchronizes the device)."""
+        torch.cuda.synchronize()
+        return int(self.n_kept_t.item())
+
+    def apply_exchange(self, s_thr=0.0, pairs=None, stream=None, n_occ=None,
+                       want_kept=False):
         """W = K psi.  With n_occ < n_orb the first n_occ orbitals are the
-        occupied ones and the rest virtual (pairs must then be None)."""
+        occupied ones and the rest virtual (pairs must then be None).
+        want_kept: the screened call also writes the kept pair list to
+        self.kept (int32, (n, 2) after n_kept rows)."""
         if n_occ is not None and n_occ < self.n_orb:
             if pairs is not None:
                 raise ValueError("explicit pairs with virtual orbitals")
-            self.n_kept = lace.lace_apply_exchange_virtual(
+            lace.lace_apply_exchange_virtual(
                 self.plan, 0, self.psi, n_occ, self.n_orb - n_occ, s_thr,
-                self.w, self.e_x, self.ws, stream)
+                self.w, self.e_x, self.ws, stream, n_kept=self.n_kept_t)
         else:
-            self.n_kept = lace.lace_apply_exchange(
+            if want_kept and self.kept is None:
+                self.kept = torch.zeros(self.n_orb * (self.n_orb + 1),
+                                        dtype=torch.int32, device=self.device)
+            lace.lace_apply_exchange(
                 self.plan, 0, self.psi, self.n_orb, s_thr, pairs, self.w,
-                self.e_x, self.ws, stream)
+                self.e_x, self.ws, stream, n_kept=self.n_kept_t,
+                kept=self.kept if want_kept else None)
         return self.w
+
+    def kept_pairs(self):
+        """The kept pairs of the last screened call with want_kept, as an
+        (n_kept, 2) numpy array (synchronizes the device)."""
+        n = self.n_kept
+        return self.kept[: 2 * n].cpu().numpy().reshape(n, 2)
 
     def build_ace(self, sym="avg", stream=None):
         lace.lace_build_ace(self.plan, 0, self.psi, self.w, self.n_orb, sym,

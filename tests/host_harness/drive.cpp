@@ -4,6 +4,7 @@
 // the thread or the address and undefined-behaviour sanitizers.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <thread>
 #include <vector>
 
@@ -65,18 +66,29 @@ static void worker(int t, int reps) {
       double* e = static_cast<double*>(dev(64));
       int32_t* info = static_cast<int32_t*>(dev(64));
       int32_t* pts = static_cast<int32_t*>(dev(4 * (size_t)n));
-      int64_t kept = 0;
+      int64_t* kept = static_cast<int64_t*>(dev(64));
+      int32_t* klist = static_cast<int32_t*>(dev(4 * (size_t)n * (n + 1)));
       CHECK(lace_screen(plan, c, psi, n, s, ws, wsb, nullptr));
       for (double thr : {0.0, 0.05, 0.4})
         CHECK(lace_apply_exchange(plan, c, psi, n, thr, nullptr, nullptr, 0, w,
-                                  e, &kept, ws, wsb, nullptr));
+                                  e, kept, thr > 0.1 ? klist : nullptr, ws, wsb,
+                                  nullptr));
       std::vector<int32_t> pi, pj;
       for (int j = 0; j < n; ++j)
         for (int i = 0; i <= j; i += 3) { pi.push_back(i); pj.push_back(j); }
-      CHECK(lace_apply_exchange(plan, c, psi, n, 0.0, pi.data(), pj.data(),
-                                (int64_t)pi.size(), w, e, &kept, ws, wsb, nullptr));
+      int32_t* dpi = static_cast<int32_t*>(dev(4 * pi.size()));
+      int32_t* dpj = static_cast<int32_t*>(dev(4 * pj.size()));
+      std::memcpy(dpi, pi.data(), 4 * pi.size());
+      std::memcpy(dpj, pj.data(), 4 * pj.size());
+      CHECK(lace_apply_exchange(plan, c, psi, n, 0.0, dpi, dpj,
+                                (int64_t)pi.size(), w, e, kept, nullptr, ws, wsb,
+                                nullptr));
+      int32_t bo[8], so[8];
+      int64_t nbr = 0;
+      CHECK(lace_read_schedule(plan, c, n, ws, nullptr, pi.data(), pj.data(), 8,
+                               bo, so, &nbr));
       CHECK(lace_apply_exchange_virtual(plan, c, psi, n - 5, 5, 0.1, w, e,
-                                        &kept, ws, wsb, nullptr));
+                                        nullptr, ws, wsb, nullptr));
       for (int sym = 0; sym < 3; ++sym)
         CHECK(lace_build_ace(plan, c, psi, w, n, (lace_sym)sym, xi, m, e + 1,
                              sym == 1 ? info : nullptr, ws, wsb, nullptr));
@@ -93,7 +105,7 @@ static void worker(int t, int reps) {
       CHECK(lace_autotune(plan, c, psi, n, ws, wsb, nullptr, ppb, pl, us, &nc));
       CHECK(lace_profile_enable(plan, 1));
       CHECK(lace_apply_exchange(plan, c, psi, n, 0.05, nullptr, nullptr, 0, w,
-                                e, &kept, ws, wsb, nullptr));
+                                e, kept, nullptr, ws, wsb, nullptr));
       double ms[3], bytes[3];
       int64_t la[3], pr[3];
       CHECK(lace_profile_read(plan, ms, la, pr, bytes));
@@ -113,6 +125,7 @@ static void worker(int t, int reps) {
       jobs[k].s_thr = k < 2 ? 0.0 : 0.05;
       jobs[k].w_g = dev(16 * npw * n);
       jobs[k].e_x = static_cast<double*>(dev(8));
+      jobs[k].n_kept = static_cast<int64_t*>(dev(8));
       jobs[k].sym = k % 3;
       jobs[k].xi_g = dev(16 * npw * n);
       jobs[k].m_out = dev(16 * (size_t)n * n);

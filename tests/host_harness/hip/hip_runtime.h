@@ -29,6 +29,11 @@ enum hipMemcpyKind {
   hipMemcpyDeviceToHost = 2,
   hipMemcpyDeviceToDevice = 3,
 };
+enum hipStreamCaptureStatus {
+  hipStreamCaptureStatusNone = 0,
+  hipStreamCaptureStatusActive = 1,
+  hipStreamCaptureStatusInvalidated = 2,
+};
 enum hipStreamCaptureMode {
   hipStreamCaptureModeGlobal = 0,
   hipStreamCaptureModeThreadLocal = 1,
@@ -55,6 +60,8 @@ inline hipError_t hipMalloc(T** p, size_t bytes) {
   return e;
 }
 hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned flags);
+hipError_t hipHostFree(void* p);
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind k);
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes,
                           hipMemcpyKind k, hipStream_t st);
@@ -70,6 +77,7 @@ hipError_t hipStreamDestroy(hipStream_t st);
 hipError_t hipStreamSynchronize(hipStream_t st);
 hipError_t hipStreamWaitEvent(hipStream_t st, hipEvent_t e, unsigned flags);
 hipError_t hipStreamBeginCapture(hipStream_t st, hipStreamCaptureMode mode);
+hipError_t hipStreamIsCapturing(hipStream_t st, hipStreamCaptureStatus* s);
 hipError_t hipStreamEndCapture(hipStream_t st, hipGraph_t* g);
 hipError_t hipGraphInstantiate(hipGraphExec_t* ex, hipGraph_t g,
                                hipGraphNode_t* err_node, char* log,

@@ -49,33 +49,30 @@ hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
   touch(w_pw, c.n_pw * n_orb * 16);
   return hipSuccess;
 }
-static hipError_t pairs(const CellDev& c, bool fp64, const PairArgs& pa,
-                        const void* psi, void* w, void* tmp, double* epart) {
-  if (pa.n < 1 || pa.n > PMAX) return hipErrorInvalidValue;
-  const int64_t g = c.ng * gb(fp64);
-  for (int q = 0; q < pa.n; ++q) {
-    const char* pp = static_cast<const char*>(psi);
-    char* ww = static_cast<char*>(w);
-    for (int o : {pa.i[q], pa.j[q]}) {
-      sink = peek(pp + o * g, g);
-      touch(ww + o * g, g);
+static hipError_t batch(const CellDev& c, bool fp64, bool real,
+                        const BatchDev* bt, int cap, const void* psi, void* w,
+                        void* tmp, double* epart, hipEvent_t* ev) {
+  if (cap < 1 || cap > (real ? QMAX : PMAX) || bt->n < 0 || bt->n > cap)
+    return hipErrorInvalidValue;
+  if (ev)
+    for (int k = 0; k < 4; ++k)
+      if (!ev[k]) return hipErrorInvalidValue;
+  const int64_t g = c.ng * gb(fp64) / (real ? 2 : 1);
+  for (int q = 0; q < bt->n; ++q)
+    for (int o : {bt->i[q], bt->j[q], bt->k[q], bt->l[q]}) {
+      if (o < 0) continue;
+      sink = peek(static_cast<const char*>(psi) + o * g, g);
+      touch(static_cast<char*>(w) + o * g, g);
     }
-  }
-  touch(tmp, pa.n * g);
-  touch(epart, pa.n * energy_tiles(c.n, fp64) * (int64_t)sizeof(double));
+  touch(tmp, cap * c.ng * gb(fp64));
+  touch(epart, cap * energy_tiles(c.n, fp64) * (int64_t)sizeof(double));
   return hipSuccess;
 }
-hipError_t launch_pair_batch(const CellDev& c, bool fp64, const PairArgs& pa,
-                             const void* psi, void* w, void* tmp, double* epart,
-                             hipStream_t, const BatchSync*) {
-  return pairs(c, fp64, pa, psi, w, tmp, epart);
-}
-hipError_t launch_pair_batch_timed(const CellDev& c, bool fp64, const PairArgs& pa,
-                                   const void* psi, void* w, void* tmp,
-                                   double* epart, hipStream_t, hipEvent_t* ev) {
-  for (int k = 0; k < 4; ++k)
-    if (!ev[k]) return hipErrorInvalidValue;
-  return pairs(c, fp64, pa, psi, w, tmp, epart);
+hipError_t launch_pair_batch(const CellDev& c, bool fp64, const BatchDev* bt,
+                             int cap, const void* psi, void* w, void* tmp,
+                             double* epart, hipStream_t, hipEvent_t* ev,
+                             const BatchSync*) {
+  return batch(c, fp64, false, bt, cap, psi, w, tmp, epart, ev);
 }
 hipError_t launch_orbitals_to_grid_real(const CellDev& c, bool fp64,
                                         const void* coeffs, int n_orb,
@@ -92,24 +89,11 @@ hipError_t launch_grid_to_pw_real(const CellDev& c, bool fp64, const void* w_rea
   touch(w_pw, c.n_pw * n_orb * 16);
   return hipSuccess;
 }
-hipError_t launch_quad_batch(const CellDev& c, bool fp64, const QuadArgs& qa,
-                             const void* psi_real, void* w_real, void* tmp,
-                             double* epart, hipStream_t, hipEvent_t* ev,
-                             const BatchSync*) {
-  if (qa.n < 1 || qa.n > QMAX) return hipErrorInvalidValue;
-  if (ev)
-    for (int k = 0; k < 4; ++k)
-      if (!ev[k]) return hipErrorInvalidValue;
-  const int64_t g = c.ng * gb(fp64) / 2;
-  for (int q = 0; q < qa.n; ++q)
-    for (int o : {qa.i[q], qa.j[q], qa.k[q], qa.l[q]}) {
-      if (o < 0) continue;
-      sink = peek(static_cast<const char*>(psi_real) + o * g, g);
-      touch(static_cast<char*>(w_real) + o * g, g);
-    }
-  touch(tmp, qa.n * 2 * g);
-  touch(epart, qa.n * energy_tiles(c.n, fp64) * (int64_t)sizeof(double));
-  return hipSuccess;
+hipError_t launch_quad_batch(const CellDev& c, bool fp64, const BatchDev* bt,
+                             int cap, const void* psi_real, void* w_real,
+                             void* tmp, double* epart, hipStream_t,
+                             hipEvent_t* ev, const BatchSync*) {
+  return batch(c, fp64, true, bt, cap, psi_real, w_real, tmp, epart, ev);
 }
 hipError_t launch_real_check(const CellDev& c, const void* coeffs, int n_orb,
                              double* part, int* nblocks, hipStream_t) {
@@ -207,6 +191,40 @@ hipError_t launch_polar_norm(int, const void* B, int n, double* out, hipStream_t
   *out = 1.0;
   return hipSuccess;
 }
+int64_t sched_scratch_bytes(int n_orb) { return 4096 + 64 * (int64_t)n_orb * n_orb; }
+// A schedule of the diagonal pairs, one per batch, written where the device
+// scheduler writes its table; the scratch is touched whole.
+hipError_t launch_schedule(const SchedDesc& d, hipStream_t) {
+  if (d.n_orb < 1 || d.ppb < 1 || d.ppb > PMAX || d.max_batches < 1) return hipErrorInvalidValue;
+  if (!d.pair_i && d.s && d.s_n < 1) return hipErrorInvalidValue;
+  if (d.s) sink = peek(d.s, 8 * (int64_t)d.s_n * d.s_n);
+  if (d.pair_i) {
+    sink = peek(d.pair_i, 4 * d.n_pairs);
+    sink = peek(d.pair_j, 4 * d.n_pairs);
+  }
+  touch(d.scratch, sched_scratch_bytes(d.n_orb));
+  const int64_t nb = d.max_batches < d.n_orb ? d.max_batches : d.n_orb;
+  for (int64_t b = 0; b < d.max_batches; ++b) {
+    BatchDev& t = d.table[b];
+    std::memset(&t, 0, sizeof(t));
+    if (b < nb) { t.n = 1; t.npairs = 1; t.i[0] = t.j[0] = (int)b; t.k[0] = t.l[0] = -1; }
+  }
+  *d.n_batches = (int32_t)nb;
+  if (d.n_kept) *d.n_kept = nb;
+  if (d.bad) *d.bad = 0;
+  return hipSuccess;
+}
+hipError_t launch_kept_pairs(const double* s, int n, double, int32_t* cnt,
+                             int64_t* off, int32_t* pairs, int64_t* total,
+                             hipStream_t) {
+  if (s) sink = peek(s, 8 * (int64_t)n * n);
+  touch(cnt, 4 * (int64_t)n);
+  touch(off, 8 * ((int64_t)n + 1));
+  touch(pairs, 4 * (int64_t)n * (n + 1));
+  if (total) *total = (int64_t)n * (n + 1) / 2;
+  return hipSuccess;
+}
+
 hipError_t launch_scdm(bool fp64, bool real, const void* psi, int n_orb,
                        int64_t ng, double* d, void* scratch, int32_t* points,
                        void* Y, hipStream_t) {

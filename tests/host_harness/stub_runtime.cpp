@@ -18,6 +18,8 @@ hipError_t hipMallocBytes(void** p, size_t bytes) {
   return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned) { return hipMallocBytes(p, bytes); }
+hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind) {
   std::memcpy(dst, src, bytes);
   return hipSuccess;
@@ -48,6 +50,10 @@ hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned) {
   return e ? hipSuccess : hipErrorInvalidValue;
 }
 hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+hipError_t hipStreamIsCapturing(hipStream_t, hipStreamCaptureStatus* s) {
+  *s = hipStreamCaptureStatusNone;
+  return hipSuccess;
+}
 hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
   *g = new ihipGraph();
   return hipSuccess;

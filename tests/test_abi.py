@@ -67,7 +67,8 @@ def test_null_arguments_rejected(lib):
     nb = ctypes.c_size_t()
     assert lib.lace_workspace_size(None, 0, 8, 0, ctypes.byref(nb)) == lace.LACE_EINVAL
     assert lib.lace_apply_exchange(None, 0, None, 8, 0.0, None, None, 0, None,
-                                   None, None, None, 0, None) == lace.LACE_EINVAL
+                                   None, None, None, None, 0,
+                                   None) == lace.LACE_EINVAL
     assert lib.lace_build_ace(None, 0, None, None, 8, 0, None, None, None,
                               None, None, 0, None) == lace.LACE_EINVAL
     assert lib.lace_apply_ace(None, 0, None, 8, None, 1, None, None, 0,
@@ -225,3 +226,31 @@ def test_binding_rejects_undersized_buffers():
     for call in calls:
         with pytest.raises(ValueError):
             call()
+
+
+def _golden_kept():
+    """The oracle's kept set of the localized 120^3 workload (Eq. (6)),
+    from tests/golden/lace120_screening.txt."""
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "lace120_screening.txt")
+    lines = open(path).read().split("\n")
+    at = lines.index("mask")
+    n = int(next(l for l in lines if l.startswith("n_orb")).split()[1])
+    pairs = []
+    for j in range(n):
+        word = int(lines[at + 1 + j], 16)
+        pairs += [(i, j) for i in range(j + 1) if (word >> i) & 1]
+    return n, pairs
+
+
+def test_slot_schedule_of_the_localized_kept_set():
+    """The real-orbital schedule of the oracle's kept set of the localized
+    120^3 workload (23,598 pairs): every pair once, nearly all off-diagonal
+    pairs in star slots, and batches of 64 pairs nearly full (the lower
+    bound is 23,598 / 64 = 369 batches)."""
+    n, pairs = _golden_kept()
+    assert len(pairs) == 23598
+    nb, n_slots, n_star = _check_slots(pairs, n, 64)
+    n_off = sum(1 for i, j in pairs if i != j)
+    assert 2 * n_star >= 0.98 * n_off
+    assert nb <= 375

@@ -121,6 +121,24 @@ def test_graph_replays_match_eager():
     stream.synchronize()
     ref2 = single_results(cells2[1:2], FP32)[0]
     assert torch.equal(mc.jobs[1]["w_g"], ref2["w"])
+    # new orbitals in the screened job: the replay screens them on the
+    # device (new pair list, new schedule) and matches the eager call
+    cell3 = cells[3][0]
+    c3 = synth.gaussian_orbitals(cell3["miller"], cell3["L"],
+                                 cells[3][1].shape[0],
+                                 cells[3][1].shape[0] // 2, synth.rng_for(82))
+    cells2[3] = (cell3, c3)
+    mc.set_orbitals(3, c3)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        mc.run(graph=True, stream=stream)
+    stream.synchronize()
+    ref3 = single_results(cells2[3:4], FP32)[0]
+    say(f"  screened job: kept {mc.n_kept[3]} (was {ref[3]['kept']}), "
+        f"eager {ref3['kept']}")
+    assert mc.n_kept[3] == ref3["kept"]
+    assert torch.equal(mc.jobs[3]["w_g"], ref3["w"])
+    assert torch.equal(mc.jobs[3]["xi_g"], ref3["xi"])
     mc.close()
 
 

@@ -281,13 +281,26 @@ def test_cholesky_failure_sets_info(c0):
     s.close()
 
 
-def test_explicit_pairs_rejected_when_invalid(c0):
+def test_explicit_pairs_checked(c0):
+    """Host pair lists are checked by the binding (i > j, out of range,
+    repeats).  Device lists reach the library unchecked: the device drops
+    the bad entries and runs a repeat once, which n_kept shows, and W is the
+    oracle's for the pairs that remain."""
     inp, _ = c0
     s = CellSession(inp, 8, FP64)
+    s.set_orbitals(inp["coeffs"])
     for bad in ([[1, 0]], [[0, 8]], [[0, 1], [0, 1]], [[-1, 2]]):
-        with pytest.raises(lace.LaceError) as ei:
+        with pytest.raises(ValueError):
             s.apply_exchange(0.0, pairs=np.array(bad))
-        assert ei.value.code == lace.LACE_EINVAL
+    pi = torch.tensor([0, 1, 0, 0, 3, -1], dtype=torch.int32, device="cuda")
+    pj = torch.tensor([1, 0, 1, 8, 3, 2], dtype=torch.int32, device="cuda")
+    s.apply_exchange(0.0, pairs=(pi, pj))
+    torch.cuda.synchronize()
+    assert s.n_kept == 2
+    psi = O.orbitals_on_grid(inp["coeffs"], inp["miller"], inp["L"], inp["n"])
+    w_pw = O.grid_to_pw(O.apply_exchange(psi, O.coulomb_kernel(inp["L"], inp["n"]),
+                                         [(0, 1), (3, 3)]), inp["miller"], inp["L"])
+    assert rel(s.w.cpu().numpy(), w_pw) <= TOL[FP64]["w"]
     with pytest.raises(lace.LaceError):
         s.apply_exchange(1.5)
     s.close()
