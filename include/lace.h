@@ -250,6 +250,23 @@ int lace_apply_ace(lace_plan* plan, int cell, const void* xi_g, int n_orb,
                    const void* x_g, int n_vec, void* y_g, void* ws,
                    size_t ws_bytes, lace_stream_t stream);
 
+/* lace_apply_ace without a workspace, for callers that cannot allocate
+ * device memory or pass one: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Arguments, layouts and the
+ * result are those of lace_apply_ace (the same kernels, bit for bit).
+ * The intermediate xi^H x and its split-K partials live in one fixed
+ * 96 MiB array per GPU that the library holds until the process ends;
+ * the call allocates nothing.  A problem whose n_orb x n_vec product and
+ * partials need more than that returns LACE_ENOMEM before any work is
+ * enqueued (n_orb = n_vec = 1024 fits at any n_pw).  Every call on a GPU
+ * shares that GPU's array: calls that overlap in time on one GPU
+ * (different streams, or different host threads) race, and the caller
+ * must order them.
+ * The plan must have been created on the current device.  Asynchronous. */
+int lace_apply_ace_noalloc(lace_plan* plan, int cell, const void* xi_g,
+                           int n_orb, const void* x_g, int n_vec, void* y_g,
+                           lace_stream_t stream);
+
 /* One job of lace_apply_exchange_batched: the exchange (and optionally the
  * ACE build) of one set of orbitals on one cell of the plan.  Fields are as
  * in lace_apply_exchange / lace_build_ace; each job brings its own

@@ -33,6 +33,41 @@ hipError_t lace::resolve_kernel(const void* kernel, std::atomic<uint64_t>& done)
   return e;
 }
 
+// Scratch of lace_apply_ace_noalloc: one fixed array per GPU, for callers
+// that cannot allocate.  In host code the array's name is not a device
+// address; its address on each device is looked up once, with that device
+// current, when the first plan is created there, and kept here.
+static constexpr size_t kNoAllocScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+// Looks up the scratch array's address on device d (the current device).
+static void noalloc_scratch_init(int d) {
+  if (d < 0 || d >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_done[d]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_ptr[d] = e == hipSuccess ? ptr : nullptr;
+  g_scratch_err[d] = e;
+  g_scratch_done[d] = true;
+}
+
+// The device address of device d's scratch array, or nullptr when the
+// lookup failed or has not run.
+static void* noalloc_scratch(int d) {
+  if (d < 0 || d >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  return g_scratch_done[d] && g_scratch_err[d] == hipSuccess ? g_scratch_ptr[d] : nullptr;
+}
+
 namespace {
 
 struct CellPlan {
@@ -305,6 +340,7 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
   p->fp64 = prec == LACE_FP64 || prec == LACE_FP64_GAMMA;
   p->gamma = gamma;
   if (hipGetDevice(&p->device) != hipSuccess) { delete p; return LACE_EHIP; }
+  noalloc_scratch_init(p->device);
   p->cells.resize(n_cells);
   const bool fp64 = p->fp64;
   for (int ci = 0; ci < n_cells; ++ci) {
@@ -938,6 +974,30 @@ int lace_apply_ace(lace_plan* p, int cell, const void* xi_g, int n_orb,
   if (e == hipSuccess)
     e = launch_gemm_tall(xi_g, c.n_pw, c.n_pw, n_orb, at(ws, L.t), n_vec, y_g,
                          c.n_pw, st);
+  return hip_status(e);
+}
+
+int lace_apply_ace_noalloc(lace_plan* p, int cell, const void* xi_g, int n_orb,
+                           const void* x_g, int n_vec, void* y_g,
+                           lace_stream_t stream) {
+  int rc = check_common(p, cell, n_orb);
+  if (rc) return rc;
+  if (!xi_g || !x_g || !y_g || n_vec < 1) return LACE_EINVAL;
+  if (x_g == y_g) return LACE_EINVAL;
+  const CellDev& c = p->cells[cell].dev;
+  // T = -(xi^H x) and the split-K partials of the same product, in the
+  // device's scratch array
+  const size_t t_bytes = align_up(16 * (size_t)n_orb * (size_t)n_vec);
+  const int64_t part_bytes = gemm_ip_part_bytes(n_orb, n_vec, c.n_pw, true);
+  if (t_bytes + (size_t)part_bytes > kNoAllocScratchBytes) return LACE_ENOMEM;
+  char* base = static_cast<char*>(noalloc_scratch(p->device));
+  if (!base) return LACE_EHIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_gemm_ip_c128(xi_g, c.n_pw, n_orb, x_g, c.n_pw, n_vec,
+                                     c.n_pw, -1.0, base, base + t_bytes,
+                                     part_bytes, st);
+  if (e == hipSuccess)
+    e = launch_gemm_tall(xi_g, c.n_pw, c.n_pw, n_orb, base, n_vec, y_g, c.n_pw, st);
   return hip_status(e);
 }
 

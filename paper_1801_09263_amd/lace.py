@@ -43,6 +43,7 @@ SYMBOLS = (
     "lace_scdm",
     "lace_apply_exchange_batched", "lace_set_tuning", "lace_get_tuning",
     "lace_autotune", "lace_check_real", "lace_read_schedule",
+    "lace_apply_ace_noalloc",
 )
 LACE_BATCH_GRAPH = 1
 
@@ -105,6 +106,7 @@ def load(path: str = LIB_PATH):
     lib.lace_build_ace.argtypes = [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp,
                                    vp, sz, vp]
     lib.lace_apply_ace.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp, sz, vp]
+    lib.lace_apply_ace_noalloc.argtypes = [vp, i32, vp, i32, vp, i32, vp, vp]
     lib.lace_fft3d.argtypes = [vp, i32, i32, vp, i32, vp]
     lib.lace_get_info.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
     lib.lace_profile_enable.argtypes = [vp, i32]
@@ -436,6 +438,22 @@ def lace_apply_ace(plan, cell, xi_g, n_orb, x_g, n_vec, y_g, ws, stream=None):
         _ptr(x_g, torch.complex128, "x_g"), n_vec,
         _ptr(y_g, torch.complex128, "y_g"), _ptr(ws, None, "ws"),
         ws.numel() * ws.element_size(), _stream(stream)), "lace_apply_ace")
+
+
+def lace_apply_ace_noalloc(plan, cell, xi_g, n_orb, x_g, n_vec, y_g,
+                           stream=None):
+    """lace_apply_ace with the library's fixed per-GPU scratch instead of a
+    workspace: no device memory is allocated by the call."""
+    import torch
+    n_pw = _n_pw(plan, cell)
+    _need(xi_g, n_orb * n_pw, "xi_g")
+    _need(x_g, n_vec * n_pw, "x_g")
+    _need(y_g, n_vec * n_pw, "y_g")
+    _check(load().lace_apply_ace_noalloc(
+        plan.handle, cell, _ptr(xi_g, torch.complex128, "xi_g"), n_orb,
+        _ptr(x_g, torch.complex128, "x_g"), n_vec,
+        _ptr(y_g, torch.complex128, "y_g"), _stream(stream)),
+        "lace_apply_ace_noalloc")
 
 
 def lace_fft3d(plan, cell, direction, grids, count, stream=None):

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -29,6 +30,10 @@ static std::vector<int32_t> sphere(int mmax) {
         }
   return m;
 }
+
+// lace_apply_ace_noalloc shares one scratch array per GPU: its callers
+// order their calls, as its contract asks.
+static std::mutex noalloc_order;
 
 static void worker(int t, int reps) {
   const lace_precision precs[4] = {LACE_FP32_GAMMA, LACE_FP32, LACE_FP64,
@@ -95,6 +100,10 @@ static void worker(int t, int reps) {
       int32_t hinfo = -1;
       CHECK(lace_get_info(ws, nullptr, &hinfo));
       CHECK(lace_apply_ace(plan, c, xi, n, psi, n, y, ws, wsb, nullptr));
+      {
+        std::lock_guard<std::mutex> order(noalloc_order);
+        CHECK(lace_apply_ace_noalloc(plan, c, xi, n, psi, n, y, nullptr));
+      }
       CHECK(lace_align(plan, c, psi, psi2, n, y, e + 2, ws, wsb, nullptr));
       CHECK(lace_scdm(plan, c, psi, n, y, pts, e + 3, ws, wsb, nullptr));
       double dev_real = 0;

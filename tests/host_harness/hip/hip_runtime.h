@@ -86,3 +86,8 @@ hipError_t hipGraphLaunch(hipGraphExec_t ex, hipStream_t st);
 hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipGraphExecDestroy(hipGraphExec_t ex);
 hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void* f);
+// device variables are host variables here; a symbol's address is its own
+#define __device__
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(X) (&(X))
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);

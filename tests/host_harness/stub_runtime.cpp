@@ -68,6 +68,10 @@ hipError_t hipGraphLaunch(hipGraphExec_t ex, hipStream_t) {
 }
 hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t ex) { delete ex; return hipSuccess; }
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void* f) {
   if (!f) return hipErrorInvalidValue;
   a->maxThreadsPerBlock = 1024;
