@@ -355,7 +355,9 @@ int lace_get_info(const void* ws, lace_stream_t stream, int32_t* info_host);
  * twice; batch_of[k] (host, n_pairs int32) receives the batch of pair k and
  * *n_batches the number of batches.  Pairs are taken round by round of a
  * round-robin tournament over the orbitals (every round a set of disjoint
- * pairs) and placed first-fit into a window of eight open batches. */
+ * pairs); the list is cut into sections of whole rounds, each section is
+ * placed first-fit into a window of eight open batches, and the pairs of
+ * the batches that did not fill are placed first-fit once more. */
 int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int64_t* n_batches);
@@ -371,8 +373,10 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
  * instead of four (the pair products are those inside the integrals of
  * Eqs. (2) and (8)).  Stars come from the cycle that two consecutive rounds
  * of the round robin form, then from left-over pairs meeting at an orbital.
- * No orbital appears in two slots of one batch; a batch holds at most
- * per_batch pairs and (per_batch + 1) / 2 slots. */
+ * The slots are packed like the pairs of lace_schedule_pairs (sections of
+ * whole cycles, then the unfilled batches once more).  No orbital appears
+ * in two slots of one batch; a batch holds at most per_batch pairs and
+ * (per_batch + 1) / 2 slots. */
 int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int32_t* slot_of,

@@ -217,6 +217,10 @@ struct SchedDesc {
 };
 int64_t sched_scratch_bytes(int n_orb);
 hipError_t launch_schedule(const SchedDesc& d, hipStream_t st);
+// First-fit sections of the schedule for n_orb orbitals, and the bound on
+// its slots (the host form of the schedule uses the same).
+int sched_sections(int n_orb);
+int64_t sched_slot_bound(int n_orb);
 
 // SCDM point selection on the workspace orbital grids (complex or real,
 // FP32 or FP64): n_orb greedy picks of column-pivoted QR of Psi^H into

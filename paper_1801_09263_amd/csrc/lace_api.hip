@@ -1050,12 +1050,17 @@ void clear_host(BatchDev& b) {
   b.star = 1;
 }
 
-void slot_list(const HostSched& h, std::vector<HSlot>& slots) {
+// The ordered slot list; goff[g] is where group (round) g's slots start
+// and G the number of slots in group order.
+void slot_list(const HostSched& h, std::vector<HSlot>& slots,
+               std::vector<int64_t>& goff, int64_t& G) {
   const int n = h.n, nv = n + (n & 1), m = nv - 1;
   auto kept = [&](int a, int b) { return a < n && b < n && h.kbit(a, b); };
   slots.clear();
+  goff.clear();
   if (!h.gamma || h.ppb < 2) {   // single-pair slots
     for (int r = 0; r < nv; ++r) {
+      goff.push_back((int64_t)slots.size());
       auto add = [&](int a, int b) {
         if (a > b) std::swap(a, b);
         if (b >= n) return;
@@ -1071,11 +1076,13 @@ void slot_list(const HostSched& h, std::vector<HSlot>& slots) {
         for (int k = 1; k <= (m - 1) / 2; ++k) add((r + k) % m, ((r - k) % m + m) % m);
       }
     }
+    G = (int64_t)slots.size();
     return;
   }
   const int ng = nv / 2;
   std::vector<std::pair<int, int>> left;
   for (int g = 0; g < ng; ++g) {
+    goff.push_back((int64_t)slots.size());
     if (g == ng - 1) {
       const int r = nv - 2;
       if (kept(r, nv - 1)) left.emplace_back(std::min(r, nv - 1), std::max(r, nv - 1));
@@ -1112,53 +1119,47 @@ void slot_list(const HostSched& h, std::vector<HSlot>& slots) {
       }
     }
   }
-  // left-overs: stars at the smaller orbital, interleaved by rank
-  std::vector<std::vector<HSlot>> per(n);
-  std::vector<int> pend1(n, -1), pend2(n, -1);
-  for (int v = 0; v < n; ++v) {
-    int have = -1;
-    for (size_t e = 0; e < left.size(); ++e) {
-      if (left[e].first != v) continue;
-      if (have < 0) { have = (int)e; continue; }
-      per[v].push_back({v, left[have].second, v, left[e].second, 2, 0u});
-      have = -1;
+  G = (int64_t)slots.size();
+  // stars of edge rows: each vertex pairs its edges in row order; the stars
+  // leave interleaved by rank; pend[v] is the other orbital of v's unpaired
+  // edge (the last), or -1
+  auto emit_stars = [&](const std::vector<std::vector<int>>& rows, std::vector<int>& pend) {
+    size_t most = 0;
+    for (int v = 0; v < n; ++v) {
+      most = std::max(most, rows[v].size() / 2);
+      pend[v] = (rows[v].size() & 1) ? rows[v].back() : -1;
     }
-    pend1[v] = have;
-  }
-  for (size_t rho = 0;; ++rho) {
-    bool got = false;
-    for (int v = 0; v < n; ++v)
-      if (rho < per[v].size()) { slots.push_back(per[v][rho]); got = true; }
-    if (!got) break;
-  }
-  // at the larger orbital, then the rest as it comes
+    for (size_t rho = 0; rho < most; ++rho)
+      for (int v = 0; v < n; ++v)
+        if (rho < rows[v].size() / 2)
+          slots.push_back({v, rows[v][2 * rho], v, rows[v][2 * rho + 1], 2, 0u});
+  };
+  // left-overs, round 1: at the smaller orbital, in group order
+  std::vector<std::vector<int>> rows(n);
+  for (const auto& e : left) rows[e.first].push_back(e.second);
+  std::vector<int> pend(n, -1);
+  emit_stars(rows, pend);
+  // round 2: the unpaired edges at their larger orbital
+  std::vector<std::vector<int>> rows2(n);
+  for (int v = 0; v < n; ++v)
+    if (pend[v] >= 0) rows2[pend[v]].push_back(v);   // v ascending
+  emit_stars(rows2, pend);
+  // what is left, edge (pend[b], b) at each b, is paired as it comes
+  int hx = -1, hy = -1;
   for (int v = 0; v < n; ++v) {
-    const int e = pend1[v];
-    if (e < 0) continue;
-    const int b = left[e].second;
-    const int hh = pend2[b];
-    if (hh < 0) { pend2[b] = e; continue; }
-    slots.push_back({b, left[hh].first, b, left[e].first, 2, 0u});
-    pend2[b] = -1;
-  }
-  int held = -1;
-  for (int v = 0; v < n; ++v) {
-    const int e = pend2[v];
-    if (e < 0) continue;
-    if (held < 0) { held = e; continue; }
-    const auto pp = left[held], q = left[e];
-    if (pp.first == q.first || pp.first == q.second || pp.second == q.first ||
-        pp.second == q.second) {
-      const int c = (pp.first == q.first || pp.first == q.second) ? pp.first : pp.second;
-      const int pj = pp.first == c ? pp.second : pp.first;
-      const int ql = q.first == c ? q.second : q.first;
+    const int x = pend[v];
+    if (x < 0) continue;
+    if (hx < 0) { hx = x; hy = v; continue; }
+    if (hx == x || hx == v || hy == x || hy == v) {
+      const int c = (hx == x || hx == v) ? hx : hy;
+      const int pj = hx == c ? hy : hx, ql = x == c ? v : x;
       slots.push_back({c, pj, c, ql, 2, 0u});
     } else {
-      slots.push_back({pp.first, pp.second, q.first, q.second, 2, 0u});
+      slots.push_back({hx, hy, x, v, 2, 0u});
     }
-    held = -1;
+    hx = -1;
   }
-  if (held >= 0) slots.push_back({left[held].first, left[held].second, -1, -1, 1, 0u});
+  if (hx >= 0) slots.push_back({hx, hy, -1, -1, 1, 0u});
   if (h.n_occ < n) {
     const int P = h.n_occ / 2, nvirt = n - h.n_occ;
     for (int k = 0; k < P; ++k)
@@ -1235,42 +1236,104 @@ void fallback_host(const HostSched& h, std::vector<BatchDev>& tab, int64_t& nb) 
   for (int64_t b = nb; b < h.max_batches; ++b) clear_host(tab[(size_t)b]);
 }
 
-// First-fit over a window of 8 open batches, as on the device.
-void host_schedule(const HostSched& h, std::vector<BatchDev>& tab, int64_t& nb) {
-  std::vector<HSlot> slots;
-  slot_list(h, slots);
-  tab.assign((size_t)h.max_batches, BatchDev{});
-  for (auto& b : tab) clear_host(b);
-  struct Win { int id, slots, pairs; std::vector<uint64_t> mask; };
+// First-fit over a window of 8 open batches, as on the device: the slots
+// in the order ord; emit(list, full) gets each batch as it leaves the
+// window (full; the oldest when a new one is needed; the rest at the end,
+// oldest first).  Returns true when more than max_open batches would be
+// opened.
+template <class Emit>
+bool ff_host(const HostSched& h, const std::vector<HSlot>& slots,
+             const std::vector<int>& ord, int64_t max_open, Emit emit) {
+  struct Win { std::vector<int> list; int pairs; std::vector<uint64_t> mask; };
   std::vector<Win> win;
-  nb = 0;
-  bool over = h.force_fallback;
-  for (size_t q = 0; q < slots.size() && !over; ++q) {
-    const HSlot& s = slots[q];
+  int64_t opened = 0;
+  for (int q : ord) {
+    const HSlot& s = slots[(size_t)q];
     const int orb[4] = {s.i, s.j, s.k, s.l};
     int pick = -1;
     for (size_t x = 0; x < win.size() && pick < 0; ++x) {
       const Win& w = win[x];
-      bool ok = w.pairs + s.np <= h.ppb && w.slots + 1 <= h.cap;
+      bool ok = w.pairs + s.np <= h.ppb && (int)w.list.size() + 1 <= h.cap;
       for (int t = 0; t < 4 && ok; ++t)
         if (orb[t] >= 0 && ((w.mask[orb[t] >> 6] >> (orb[t] & 63)) & 1ull)) ok = false;
       if (ok) pick = (int)x;
     }
     if (pick < 0) {
-      if (nb >= h.max_batches) { over = true; break; }
-      if (win.size() == 8) win.erase(win.begin());
-      win.push_back({(int)nb++, 0, 0, std::vector<uint64_t>(h.words, 0ull)});
+      if (opened >= max_open) return true;
+      if (win.size() == 8) {
+        emit(win[0].list, false);
+        win.erase(win.begin());
+      }
+      win.push_back({{}, 0, std::vector<uint64_t>(h.words, 0ull)});
+      ++opened;
       pick = (int)win.size() - 1;
     }
-    Win& w = win[pick];
-    put_host(tab[(size_t)w.id], w.slots, s);
-    w.slots += 1;
+    Win& w = win[(size_t)pick];
+    w.list.push_back(q);
     w.pairs += s.np;
     for (int t = 0; t < 4; ++t)
       if (orb[t] >= 0) w.mask[orb[t] >> 6] |= 1ull << (orb[t] & 63);
-    if (w.pairs >= h.ppb || w.slots >= h.cap) win.erase(win.begin() + pick);
+    if (w.pairs >= h.ppb || (int)w.list.size() >= h.cap) {
+      emit(w.list, true);
+      win.erase(win.begin() + pick);
+    }
   }
-  if (over) fallback_host(h, tab, nb);
+  for (const Win& w : win) emit(w.list, false);
+  return false;
+}
+
+// The slot list cut into sched_sections(n) sections, each packed on its
+// own; their full batches in section order, then first-fit of all other
+// slots (section order) into further batches; as on the device.
+void host_schedule(const HostSched& h, std::vector<BatchDev>& tab, int64_t& nb) {
+  std::vector<HSlot> slots;
+  std::vector<int64_t> goff;
+  int64_t G = 0;
+  slot_list(h, slots, goff, G);
+  tab.assign((size_t)h.max_batches, BatchDev{});
+  for (auto& b : tab) clear_host(b);
+  nb = 0;
+  bool over = h.force_fallback;
+  std::vector<std::vector<int>> batches;
+  if (!over) {
+    const int S = sched_sections(h.n);
+    const int64_t N = (int64_t)slots.size(), per = (N + S - 1) / S;
+    // section k starts at k * per, moved up to the next group boundary
+    // while among the group-ordered slots
+    auto start = [&](int k) -> int64_t {
+      if (k >= S) return N;
+      const int64_t t = std::min(N, (int64_t)k * per);
+      if (t >= G) return t;
+      for (int64_t o : goff)
+        if (o >= t) return o;
+      return G;
+    };
+    std::vector<int> rest;
+    for (int k = 0; k < S; ++k) {
+      const int64_t lo = start(k), hi = start(k + 1);
+      std::vector<int> ord;
+      for (int64_t q = lo; q < hi; ++q) ord.push_back((int)q);
+      ff_host(h, slots, ord, INT64_MAX, [&](const std::vector<int>& l, bool full) {
+        if (full) batches.push_back(l);
+        else rest.insert(rest.end(), l.begin(), l.end());
+      });
+    }
+    const int64_t F = (int64_t)batches.size();
+    if (F > h.max_batches) {
+      over = true;
+    } else {
+      over = ff_host(h, slots, rest, h.max_batches - F,
+                     [&](const std::vector<int>& l, bool) { batches.push_back(l); });
+    }
+  }
+  if (over) {
+    fallback_host(h, tab, nb);
+    return;
+  }
+  nb = (int64_t)batches.size();
+  for (int64_t b = 0; b < nb; ++b)
+    for (size_t q = 0; q < batches[(size_t)b].size(); ++q)
+      put_host(tab[(size_t)b], (int)q, slots[(size_t)batches[(size_t)b][q]]);
 }
 
 // Host schedule of an explicit pair list; batch and slot of every pair.

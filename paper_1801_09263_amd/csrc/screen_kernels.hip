@@ -139,8 +139,7 @@ hipError_t launch_kept_pairs(const double* s, int n, double thr, int32_t* cnt,
 // (r + k, r - k) mod (nv - 1); each round is a set of disjoint pairs, and
 // the diagonal pairs form one more round.
 //
-// Complex orbitals: the kept pairs, round by round, are placed first-fit
-// into a window of open batches (no orbital twice in a batch).
+// Complex orbitals: the kept pairs, round by round, form the slot list.
 //
 // Real orbitals: two pair densities share one transform (a slot); two pairs
 // that share an orbital make a star slot (three orbital grids instead of
@@ -149,16 +148,23 @@ hipError_t launch_kept_pairs(const double* s, int n, double thr, int32_t* cnt,
 // r + 1 (mod nv - 1), edges alternating between the two rounds.  The kept
 // edges of the cycle form runs; consecutive edges of a run become star
 // slots, and a run of odd length leaves its last edge over.  Left-over
-// edges are paired at their smaller orbital, then at their larger one
-// (stars again), and what is left is paired as it comes.  One-sided pairs
-// (occupied x virtual) form stars around their virtual orbital; diagonal
-// pairs go two by two.  The slots are then placed first-fit like the pairs.
+// edges are paired at their smaller orbital (in group order), then the
+// unpaired ones at their larger orbital (stars again), both interleaved by
+// rank, and what is left is paired as it comes.  One-sided pairs (occupied
+// x virtual) form stars around their virtual orbital; diagonal pairs go
+// two by two.
+//
+// Packing: the slot list is cut into sections (boundaries moved to whole
+// groups or rounds), each section is placed first-fit into a window of
+// open batches on its own wave (no orbital twice in a batch), and the
+// slots of the batches that did not fill are placed first-fit once more
+// after the full ones.
 //
 // The host launches max_batches batches, the count of the round-robin
 // schedule (every round, and the diagonal round, in batches of their own),
-// which bounds any set of pairs; if first-fit would need more, the table is
-// rebuilt as that round-robin schedule.  Entries past the last batch have
-// n = 0.
+// which bounds any set of pairs; if the packing would need more, the table
+// is rebuilt as that round-robin schedule.  Entries past the last batch
+// have n = 0.
 
 namespace {
 
@@ -365,11 +371,10 @@ __global__ __launch_bounds__(64) void k_sched_rounds(const uint64_t* __restrict_
   if (lane == 0) rcnt[r] = c;
 }
 
-constexpr int PK_NT = 256;      // packing workgroup
-constexpr int PK_WIN = 8;       // open batches considered
-constexpr int PK_LCH = 1024;    // left-over edges staged in LDS at a time
+constexpr int PK_NT = 256;      // list and merge workgroups
+constexpr int PK_WIN = 8;       // open batches considered by first-fit
 
-// Exclusive prefix of one value per thread over the packing workgroup;
+// Exclusive prefix of one value per thread over a PK_NT workgroup;
 // *total gets the sum.  `wtot` holds PK_NT / 64 values.
 __device__ inline int64_t block_scan(int64_t v, int64_t* wtot, int64_t* total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -408,20 +413,438 @@ __device__ void block_prefix(const int32_t* cnt, int count, int stride,
 }
 
 struct PackArgs {
-  int n_orb, n_occ, words, ppb, cap, gamma, force_fallback;
+  int n_orb, n_occ, words, ppb, cap, gamma, force_fallback, sections;
   int64_t max_batches;
+  int64_t per_bound;      // slots a section's index regions hold
 };
 
 struct PackScratch {
   const SlotRec* gstar;   // real: per-group stars; complex: per-round pairs
-  const int2* gleft;
+  const int2* gleft;      // real: per-group left-over edges
   const int32_t* gcnt;
   const uint64_t* kb;
   const uint64_t* db;
   SlotRec* slots;         // the ordered slot list
-  int64_t* off;           // per-group offsets (stars, left-overs)
-  int2* left;             // left-over edges in group order
+  int64_t* off;           // per-group offsets
+  uint64_t* lb;           // n x ceil(groups / 64): left-over edges by group
+  int16_t* ytab;          // n x groups: their larger orbital
+  uint64_t* rb;           // n x words: unpaired edges at their larger orbital
+  int64_t* count;         // [0] slots, [1] pairs, [2] slots in group (or
+                          // round) order, [3] groups (rounds)
+  int32_t* idx;           // 2 x sections x per_bound slot indices: the full
+                          // batches of each section, then the refill batches
+  int32_t* fcnt;          // sections x per_bound: slots of each full batch
+  int32_t* pidx;          // sections x per_bound: slots of the other batches
+  int32_t* scnt;          // sections x 4: full batches, their slots, others
+  int32_t* rlist;         // sections x per_bound: the refill order
+  int32_t* dir;           // per batch: first index in idx, slot count
+  int32_t* flags;         // [0]: fallback used, [1]: batches
 };
+
+// Lowest set bit at or above position p of a bit row that has one.
+__device__ inline int next_bit(const uint64_t* row, int p) {
+  int w = p >> 6;
+  uint64_t m = row[w] & (~0ull << (p & 63));
+  while (!m) m = row[++w];
+  return 64 * w + __builtin_ctzll(m);
+}
+
+// Stars of bit rows: row v lists v's edges, bit b standing for the edge to
+// orbital other(v, b); each vertex pairs its edges in ascending bit order,
+// and the stars leave interleaved, every vertex's first star, then every
+// vertex's second one, ... (consecutive slots then rarely share their
+// centre).  pend[v] gets the other orbital of v's unpaired edge (the last
+// bit), or -1.  Returns the number of stars written to out.  Called by the
+// whole PK_NT workgroup.
+template <class Other>
+__device__ int64_t emit_stars(const uint64_t* rows, int n, int words, Other other,
+                              SlotRec* out, int16_t* vcnt, int16_t* cur,
+                              int16_t* pend, int* red) {
+  const int tid = threadIdx.x;
+  for (int v = tid; v < n; v += PK_NT) {
+    int c = 0, last = -1;
+    for (int w = 0; w < words; ++w) {
+      const uint64_t m = rows[(int64_t)v * words + w];
+      c += __popcll(m);
+      if (m) last = 64 * w + 63 - __clzll(m);
+    }
+    vcnt[v] = (int16_t)(c >> 1);
+    pend[v] = (int16_t)((c & 1) ? other(v, last) : -1);
+    cur[v] = 0;
+  }
+  __syncthreads();
+  int64_t base = 0;
+  for (int rho = 0;; ++rho) {
+    int64_t got = 0;
+    for (int v0 = 0; v0 < n; v0 += PK_NT) {
+      const int v = v0 + tid;
+      const int flag = v < n && vcnt[v] > rho;
+      int ex;
+      const int t = block_exclusive(flag, &ex, red);
+      if (flag) {
+        const uint64_t* row = rows + (int64_t)v * words;
+        const int b1 = next_bit(row, cur[v]);
+        const int b2 = next_bit(row, b1 + 1);
+        cur[v] = (int16_t)(b2 + 1);
+        out[base + got + ex] = SlotRec{v, other(v, b1), v, other(v, b2), 2, 0u};
+      }
+      got += t;
+    }
+    if (got == 0) break;
+    base += got;
+  }
+  __syncthreads();
+  return base;
+}
+
+// The ordered slot list, its length and pair count.  One workgroup.
+__global__ __launch_bounds__(PK_NT) void k_sched_list(PackArgs a, PackScratch sc) {
+  __shared__ int64_t wtot[PK_NT / 64];
+  __shared__ int64_t tot[4];
+  __shared__ int red[PK_NT / 64];
+  __shared__ int16_t vcnt[4096], cur[4096], pend[4096];
+  const int n = a.n_orb, nv = n + (n & 1), tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  int64_t nslots = 0;
+  if (a.gamma) {
+    const int ng = nv / 2;
+    block_prefix(sc.gcnt, ng, 2, sc.off, &tot[0], wtot);   // stars per group
+    // left-over edges by group: a vertex has at most one per group (two
+    // in one group would be adjacent kept edges of one run), so row x of lb
+    // has bit g for the left-over (x, y), x < y, of group g, and
+    // ytab[x][g] = y; rb rows are orbital bits
+    const int gw = (ng + 63) / 64;
+    for (int64_t t = tid; t < (int64_t)n * gw; t += PK_NT) sc.lb[t] = 0ull;
+    for (int64_t t = tid; t < (int64_t)n * a.words; t += PK_NT) sc.rb[t] = 0ull;
+    __syncthreads();
+    for (int g = wave; g < ng; g += PK_NT / 64) {
+      const int64_t o = sc.off[g];
+      const int c = sc.gcnt[2 * g], cl = sc.gcnt[2 * g + 1];
+      for (int t = lane; t < c; t += 64)
+        sc.slots[o + t] = sc.gstar[(int64_t)g * (nv / 2) + t];
+      for (int t = lane; t < cl; t += 64) {
+        const int2 e = sc.gleft[(int64_t)g * nv + t];
+        sc.ytab[(int64_t)e.x * ng + g] = (int16_t)e.y;
+        atomicOr(reinterpret_cast<unsigned long long*>(&sc.lb[(int64_t)e.x * gw + (g >> 6)]),
+                 1ull << (g & 63));
+      }
+    }
+    __syncthreads();
+    nslots = tot[0];
+    // left-overs, round 1: stars at the smaller orbital, in group order
+    const int16_t* ytab = sc.ytab;
+    nslots += emit_stars(sc.lb, n, gw,
+                         [ytab, ng](int v, int g) { return (int)ytab[(int64_t)v * ng + g]; },
+                         sc.slots + nslots, vcnt, cur, pend, red);
+    // round 2: the unpaired edges, stars at their larger orbital
+    for (int v = tid; v < n; v += PK_NT) {
+      const int y = pend[v];
+      if (y >= 0)
+        atomicOr(reinterpret_cast<unsigned long long*>(
+                     &sc.rb[(int64_t)y * a.words + (v >> 6)]),
+                 1ull << (v & 63));
+    }
+    __syncthreads();
+    nslots += emit_stars(sc.rb, n, a.words, [](int, int x) { return x; },
+                         sc.slots + nslots, vcnt, cur, pend, red);
+    // what is left (edge (pend[b], b) at each b) is paired as it comes
+    if (tid == 0) {
+      int64_t w = nslots;
+      int hx = -1, hy = -1;
+      for (int v = 0; v < n; ++v) {
+        const int x = pend[v];
+        if (x < 0) continue;
+        if (hx < 0) { hx = x; hy = v; continue; }
+        // edges (hx, hy) and (x, v)
+        if (hx == x || hx == v || hy == x || hy == v) {
+          const int c = (hx == x || hx == v) ? hx : hy;
+          const int pj = hx == c ? hy : hx, ql = x == c ? v : x;
+          sc.slots[w++] = SlotRec{c, pj, c, ql, 2, 0u};
+        } else {
+          sc.slots[w++] = SlotRec{hx, hy, x, v, 2, 0u};
+        }
+        hx = -1;
+      }
+      if (hx >= 0) sc.slots[w++] = SlotRec{hx, hy, -1, -1, 1, 0u};
+      tot[3] = w;
+    }
+    __syncthreads();
+    int64_t w = tot[3];
+    // one-sided pairs: stars around each virtual orbital u with the
+    // occupied pair (2t, 2t + 1), t = (k + u) mod P in round k, so that
+    // the stars of one round share no orbital
+    if (a.n_occ < n) {
+      const int P = a.n_occ / 2, nvirt = n - a.n_occ;
+      const int64_t cnt = (int64_t)P * nvirt;
+      for (int64_t q = tid; q < cnt; q += PK_NT) {
+        const int k = (int)(q / nvirt), u = (int)(q % nvirt);
+        const int v = a.n_occ + u, t = 2 * ((k + u) % P);
+        sc.slots[w + q] = SlotRec{v, t, v, t + 1, 2, 1u | 4u | 16u};
+      }
+      w += cnt;
+      if (a.n_occ & 1) {
+        for (int u = tid; u < nvirt; u += PK_NT)
+          sc.slots[w + u] = SlotRec{a.n_occ - 1, a.n_occ + u, -1, -1, 1, 1u | 2u};
+        w += nvirt;
+      }
+    }
+    // diagonal pairs, two by two
+    if (tid == 0) {
+      int hd = -1;
+      for (int wd = 0; wd < a.words; ++wd) {
+        uint64_t bits = sc.db[wd];
+        while (bits) {
+          const int d = 64 * wd + __builtin_ctzll(bits);
+          bits &= bits - 1ull;
+          if (hd < 0) { hd = d; continue; }
+          sc.slots[w++] = SlotRec{hd, hd, d, d, 2, 0u};
+          hd = -1;
+        }
+      }
+      if (hd >= 0) sc.slots[w++] = SlotRec{hd, hd, -1, -1, 1, 0u};
+      tot[2] = w;
+    }
+    __syncthreads();
+    nslots = tot[2];
+  } else {
+    block_prefix(sc.gcnt, nv, 1, sc.off, &tot[0], wtot);
+    for (int r = wave; r < nv; r += PK_NT / 64) {
+      const int64_t o = sc.off[r];
+      const int c = sc.gcnt[r];
+      for (int t = lane; t < c; t += 64)
+        sc.slots[o + t] = sc.gstar[(int64_t)r * nv + t];
+    }
+    nslots = tot[0];
+    __syncthreads();
+  }
+  int64_t np = 0;
+  for (int64_t q = tid; q < nslots; q += PK_NT) np += sc.slots[q].np;
+  int64_t total = 0;
+  block_scan(np, wtot, &total);
+  if (tid == 0) {
+    sc.count[0] = nslots;
+    sc.count[1] = total;
+    sc.count[2] = tot[0];
+    sc.count[3] = a.gamma ? nv / 2 : nv;
+  }
+}
+
+// First-fit of count slots (slot t of the order: slots[ord(t)]) into a
+// window of PK_WIN open batches, no orbital twice in a batch, by one wave.
+// The wave's state is uniform.  The open batches sit at window positions
+// 0 .. nopen - 1, oldest first, so the first fit is the lowest candidate
+// bit.  inwin[o] has bit x set when orbital o is in the batch at position x
+// (entry 4096 stands for "no orbital" and stays 0; 4097 takes the writes
+// for it).  The slot and pair counts of the positions are the bytes of two
+// 64-bit words; fit1 / fit2 are the positions that can take a one- / two-
+// pair slot.  Each open batch lists its slots' indices in one of PK_WIN
+// LDS rows (phys: the row of each position, 4 bits each).  A batch leaves
+// the window when it is full, when it is the oldest and a new one is
+// needed, or at the end, oldest first; it is then handed to
+// emit(row, slots, full), and the positions above it move down one.  The
+// masks of the next slot are read before the current one is placed, then
+// corrected for it.  Returns 1 when more than max_open batches would be
+// opened (the rest is then not placed).
+template <class Ord, class Emit>
+__device__ int window_ff(const PackArgs& a, int64_t count, Ord ord,
+                         const SlotRec* __restrict__ slots, int64_t max_open,
+                         Emit emit, uint32_t* inwin, int32_t* bidx) {
+  constexpr uint32_t NONE_R = 4096u, NONE_W = 4097u;
+  const int lane = threadIdx.x & 63, n = a.n_orb;
+  for (int o = lane; o < 4098; o += 64) inwin[o] = 0u;
+  uint64_t cnt_s = 0, cnt_p = 0;
+  uint32_t fit1 = 0, fit2 = 0, phys = 0, freep = (1u << PK_WIN) - 1u;
+  int nopen = 0, over = 0;
+  int64_t nb = 0;
+  // 64 slots a lane, packed: orbitals as 16 bits (-1 as NONE_R), then
+  // pairs | (shares an orbital with the next slot) << 17, and the index
+  auto load = [&](int64_t base, uint32_t& ij, uint32_t& kl, uint32_t& ex, int32_t& ix) {
+    ij = NONE_R | (NONE_R << 16);
+    kl = ij;
+    ex = 0;
+    ix = -1;
+    if (base + lane < count) {
+      ix = ord(base + lane);
+      const SlotRec r = slots[ix];
+      ij = (uint32_t)r.i | ((uint32_t)r.j << 16);
+      kl = (r.k < 0 ? NONE_R : (uint32_t)r.k) | ((r.l < 0 ? NONE_R : (uint32_t)r.l) << 16);
+      ex = (uint32_t)r.np;
+    }
+  };
+  auto share = [&](uint32_t& ex, uint32_t ij, uint32_t kl, uint32_t nij, uint32_t nkl) {
+    const uint32_t o[4] = {ij & 0xFFFFu, ij >> 16, kl & 0xFFFFu, kl >> 16};
+    const uint32_t m[4] = {nij & 0xFFFFu, nij >> 16, nkl & 0xFFFFu, nkl >> 16};
+    bool hit = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) hit |= o[u] != NONE_R && o[u] == m[v];
+    if (hit) ex |= 1u << 17;
+  };
+  auto masks = [&](uint32_t ij, uint32_t kl) -> uint32_t {
+    return inwin[ij & 0xFFFFu] | inwin[ij >> 16] | inwin[kl & 0xFFFFu] | inwin[kl >> 16];
+  };
+  uint32_t aij, akl, aex, bij, bkl, bex;   // slots c0 .. c0 + 63, and the next 64
+  int32_t aix, bix;
+  auto mark = [&]() {   // the share bits of chunk a
+    uint32_t nij = __shfl_down(aij, 1, 64), nkl = __shfl_down(akl, 1, 64);
+    const uint32_t fij = __builtin_amdgcn_readlane(bij, 0);
+    const uint32_t fkl = __builtin_amdgcn_readlane(bkl, 0);
+    if (lane == 63) { nij = fij; nkl = fkl; }
+    share(aex, aij, akl, nij, nkl);
+  };
+  auto drop = [&](int x, uint32_t& pre, bool full) {   // position x leaves
+    const int ph = (int)((phys >> (4 * x)) & 15u);
+    emit(bidx + ph * 64, (int)((cnt_s >> (8 * x)) & 0xFFu), full);
+    const uint64_t lowb = (1ull << (8 * x)) - 1ull;
+    cnt_s = (cnt_s & lowb) | ((cnt_s >> 8) & ~lowb);
+    cnt_p = (cnt_p & lowb) | ((cnt_p >> 8) & ~lowb);
+    const uint32_t lown = (1u << (4 * x)) - 1u;
+    phys = (phys & lown) | ((phys >> 4) & ~lown);
+    freep |= 1u << ph;
+    const uint32_t low = (1u << x) - 1u;
+    fit1 = (fit1 & low) | ((fit1 >> 1) & ~low);
+    fit2 = (fit2 & low) | ((fit2 >> 1) & ~low);
+    pre = (pre & low) | ((pre >> 1) & ~low);
+    for (int o = lane; o < n; o += 64) {
+      const uint32_t v = inwin[o];
+      inwin[o] = (v & low) | ((v >> 1) & ~low);
+    }
+    --nopen;
+  };
+  load(0, aij, akl, aex, aix);
+  load(64, bij, bkl, bex, bix);
+  mark();
+  int64_t c0 = 0;
+  uint32_t sij = __builtin_amdgcn_readlane(aij, 0);
+  uint32_t skl = __builtin_amdgcn_readlane(akl, 0);
+  uint32_t sex = __builtin_amdgcn_readlane(aex, 0);
+  int32_t six = __builtin_amdgcn_readlane(aix, 0);
+  uint32_t conf = count > 0 ? masks(sij, skl) : 0u;
+  for (int64_t q = 0; q < count; ++q) {
+    // the next slot and its masks, read before this one is placed
+    uint32_t nij = 0, nkl = 0, nex = 0, pre = 0;
+    int32_t nix = -1;
+    if (q + 1 < count) {
+      const int r = (int)(q + 1 - c0);
+      if (r < 64) {
+        nij = __builtin_amdgcn_readlane(aij, r);
+        nkl = __builtin_amdgcn_readlane(akl, r);
+        nex = __builtin_amdgcn_readlane(aex, r);
+        nix = __builtin_amdgcn_readlane(aix, r);
+      } else {
+        nij = __builtin_amdgcn_readlane(bij, 0);
+        nkl = __builtin_amdgcn_readlane(bkl, 0);
+        nex = __builtin_amdgcn_readlane(bex, 0);
+        nix = __builtin_amdgcn_readlane(bix, 0);
+      }
+      pre = masks(nij, nkl);
+    }
+    const int np = (int)(sex & 0xFFu);
+    const uint32_t cand = (np == 1 ? fit1 : fit2) & ~conf;
+    int x;
+    if (cand) {
+      x = __builtin_ctz(cand);
+    } else {
+      if (nb >= max_open) { over = 1; break; }
+      if (nopen == PK_WIN) drop(0, pre, false);   // the oldest leaves
+      x = nopen++;
+      const int ph = __builtin_ctz(freep);
+      freep &= ~(1u << ph);
+      phys |= (uint32_t)ph << (4 * x);
+      ++nb;
+      fit1 |= 1u << x;
+      if (a.ppb >= 2) fit2 |= 1u << x;
+    }
+    const uint32_t bit = 1u << x;
+    const int qs = (int)((cnt_s >> (8 * x)) & 0xFFu);
+    const int ph = (int)((phys >> (4 * x)) & 15u);
+    const uint32_t oi = sij & 0xFFFFu, oj = sij >> 16, ok = skl & 0xFFFFu, ol = skl >> 16;
+    if (lane == 0) {
+      bidx[ph * 64 + qs] = six;
+      atomicOr(&inwin[oi], bit);
+      atomicOr(&inwin[oj], bit);
+      atomicOr(&inwin[ok == NONE_R ? NONE_W : ok], bit);
+      atomicOr(&inwin[ol == NONE_R ? NONE_W : ol], bit);
+    }
+    cnt_s += 1ull << (8 * x);
+    cnt_p += (uint64_t)np << (8 * x);
+    const int fs = qs + 1, fp = (int)((cnt_p >> (8 * x)) & 0xFFu);
+    if (fs >= a.cap || fp + 1 > a.ppb) fit1 &= ~bit;
+    if (fs >= a.cap || fp + 2 > a.ppb) fit2 &= ~bit;
+    // the next slot shares an orbital with this one: not at position x
+    if ((sex >> 17) & 1u) pre |= bit;
+    if (fp >= a.ppb || fs >= a.cap) drop(x, pre, true);   // full
+    sij = nij; skl = nkl; sex = nex; six = nix; conf = pre;
+    if (q + 1 - c0 == 64) {
+      c0 += 64;
+      aij = bij; akl = bkl; aex = bex; aix = bix;
+      load(c0 + 64, bij, bkl, bex, bix);
+      mark();
+      sex = __builtin_amdgcn_readlane(aex, 0);   // now with its share bit
+    }
+  }
+  if (!over) {
+    uint32_t unused = 0;
+    while (nopen) drop(0, unused, false);
+  }
+  return over;
+}
+
+// Start of section k of the slot list: k * per moved up to the next group
+// (round) boundary while it falls among the group-ordered slots, so that a
+// section takes whole cycles; section `sections` ends the list.
+__device__ inline int64_t section_start(const PackScratch& sc, int sections,
+                                        int64_t per, int k) {
+  const int64_t ns = sc.count[0], G = sc.count[2];
+  const int ng = (int)sc.count[3];
+  if (k >= sections) return ns;
+  const int64_t t = min(ns, (int64_t)k * per);
+  if (t >= G) return t;
+  int lo = 0, hi = ng;   // first group g with off[g] >= t (off[ng] = G)
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sc.off[mid] >= t) hi = mid; else lo = mid + 1;
+  }
+  return lo < ng ? sc.off[lo] : G;
+}
+
+// First-fit of each section of the slot list on its own (one wave per
+// section): the full batches' slot indices go to idx (section region) and
+// their slot counts to fcnt, the other batches' indices to pidx.
+__global__ __launch_bounds__(64) void k_sched_sections(PackArgs a, PackScratch sc) {
+  __shared__ uint32_t inwin[4098];
+  __shared__ int32_t bidx[PK_WIN * 64];
+  const int k = blockIdx.x, lane = threadIdx.x;
+  if (k >= a.sections || a.force_fallback) return;
+  const int64_t ns = sc.count[0];
+  const int64_t per = (ns + a.sections - 1) / a.sections;
+  const int64_t lo = section_start(sc, a.sections, per, k);
+  const int64_t hi = section_start(sc, a.sections, per, k + 1);
+  int32_t* fidx = sc.idx + (int64_t)k * a.per_bound;
+  int32_t* fcnt = sc.fcnt + (int64_t)k * a.per_bound;
+  int32_t* pidx = sc.pidx + (int64_t)k * a.per_bound;
+  int nfb = 0;
+  int64_t nfi = 0, npi = 0;
+  auto emit = [&](const int32_t* row, int cnt, bool full) {
+    int32_t* dst = full ? fidx + nfi : pidx + npi;
+    for (int q = lane; q < cnt; q += 64) dst[q] = row[q];
+    if (full) {
+      if (lane == 0) fcnt[nfb] = cnt;
+      ++nfb;
+      nfi += cnt;
+    } else {
+      npi += cnt;
+    }
+  };
+  window_ff(a, hi - lo, [&](int64_t t) { return (int32_t)(lo + t); }, sc.slots,
+            INT64_MAX, emit, inwin, bidx);
+  if (lane == 0) {
+    sc.scnt[4 * k] = nfb;
+    sc.scnt[4 * k + 1] = (int32_t)nfi;
+    sc.scnt[4 * k + 2] = (int32_t)npi;
+  }
+}
 
 __device__ inline void put_slot(BatchDev* b, int q, const SlotRec& s) {
   b->i[q] = s.i; b->j[q] = s.j; b->k[q] = s.k; b->l[q] = s.l;
@@ -502,463 +925,251 @@ __device__ void fallback_schedule(const PackArgs& a, const uint64_t* kb,
   *n_batches = (int32_t)nb;
 }
 
-// Slot list, then first-fit packing into the batch table.  One workgroup.
-__global__ __launch_bounds__(PK_NT) void k_sched_pack(PackArgs a, PackScratch sc,
-                                                      BatchDev* __restrict__ tab,
-                                                      int32_t* __restrict__ n_batches,
-                                                      int64_t* __restrict__ n_pairs) {
-  __shared__ int64_t wtot[PK_NT / 64];
-  __shared__ int64_t tot[4];
-  __shared__ int red[PK_NT / 64];
+// The sections' full batches in section order, then first-fit of all
+// their other slots (section order) on one wave; the batch directory; the
+// round-robin fallback when the batches would not fit the table.  One
+// workgroup.
+__global__ __launch_bounds__(PK_NT) void k_sched_merge(PackArgs a, PackScratch sc,
+                                                       BatchDev* __restrict__ tab,
+                                                       int32_t* __restrict__ n_batches,
+                                                       int64_t* __restrict__ n_pairs) {
+  __shared__ uint32_t inwin[4098];
+  __shared__ int32_t bidx[PK_WIN * 64];
+  __shared__ int32_t sfb[32], sfi[32], spi[32];
   __shared__ int32_t st_nb, st_over;
-  // the slot-list phase and the first-fit phase share this space
-  __shared__ __attribute__((aligned(16))) char pool[8192 * 6];
-  int16_t* vcnt = reinterpret_cast<int16_t*>(pool);           // stars of each vertex
-  int32_t* voff = reinterpret_cast<int32_t*>(pool + 8192);    // their staging offsets
-  int16_t* p1 = reinterpret_cast<int16_t*>(pool + 8192 * 3);  // unpaired edge at v
-  int16_t* p2 = reinterpret_cast<int16_t*>(pool + 8192 * 4);  // edge held at v
-  int2* lbuf = reinterpret_cast<int2*>(pool + 8192 * 5);      // PK_LCH edges
-  uint32_t* inwin = reinterpret_cast<uint32_t*>(pool);        // 4098 words
-  int32_t* bst = reinterpret_cast<int32_t*>(pool + 16448);    // PK_WIN x 4 x 64 orbitals
-  int32_t* bid = reinterpret_cast<int32_t*>(pool + 24640);    // PK_WIN batch ids
-  uint64_t* bbits = reinterpret_cast<uint64_t*>(pool + 24704);  // PK_WIN x 5 header words
-  const int n = a.n_orb, nv = n + (n & 1), tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  int64_t nslots = 0;
-  // ---------------------------------------------------------- slot list
-  if (a.gamma) {
-    const int ng = nv / 2;
-    block_prefix(sc.gcnt, ng, 2, sc.off, &tot[0], wtot);            // stars
-    block_prefix(sc.gcnt + 1, ng, 2, sc.off + ng, &tot[1], wtot);   // left
-    const int64_t nstar = tot[0], nleft = tot[1];
-    for (int g = wave; g < ng; g += PK_NT / 64) {
-      const int64_t o = sc.off[g], ol = sc.off[ng + g];
-      const int c = sc.gcnt[2 * g], cl = sc.gcnt[2 * g + 1];
-      for (int t = lane; t < c; t += 64)
-        sc.slots[o + t] = sc.gstar[(int64_t)g * (nv / 2) + t];
-      for (int t = lane; t < cl; t += 64)
-        sc.left[ol + t] = sc.gleft[(int64_t)g * nv + t];
-    }
-    for (int v = tid; v < n; v += PK_NT) { vcnt[v] = 0; p1[v] = -1; p2[v] = -1; }
-    __syncthreads();
-    nslots = nstar;
-    // left-overs, round 1: pairs at the smaller orbital, in edge order.
-    // Vertex v belongs to thread v mod PK_NT, which alone reads and writes
-    // its entries.  Pass 0 counts each vertex's stars; pass 1 writes them to
-    // a staging area (the group-star region, no longer needed) at prefix
-    // offsets.  After either pass p1[v] is the edge left unpaired at v.
-    SlotRec* stage = const_cast<SlotRec*>(sc.gstar);
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int64_t c0 = 0; c0 < nleft; c0 += PK_LCH) {
-        const int cn = (int)min<int64_t>(PK_LCH, nleft - c0);
-        __syncthreads();
-        const int cn8 = (cn + 7) & ~7;   // padded with x = -1
-        for (int t = tid; t < cn8; t += PK_NT)
-          lbuf[t] = t < cn ? sc.left[c0 + t] : make_int2(-1, -1);
-        __syncthreads();
-        for (int t0 = 0; t0 < cn8; t0 += 8) {
-          int2 e8[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) e8[u] = lbuf[t0 + u];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int2 ed = e8[u];
-            if (ed.x < 0 || (ed.x & (PK_NT - 1)) != tid) continue;
-            const int v = ed.x, h = p1[v];
-            if (h < 0) { p1[v] = (int16_t)ed.y; continue; }
-            if (pass) stage[voff[v] + vcnt[v]] = SlotRec{v, h, v, ed.y, 2, 0u};
-            vcnt[v] = (int16_t)(vcnt[v] + 1);
-            p1[v] = -1;
-          }
-        }
-      }
-      __syncthreads();
-      if (!pass) {
-        // offsets of the vertices' stars: contiguous runs per thread
-        const int per = (n + PK_NT - 1) / PK_NT;
-        const int lo = tid * per, hi = min(lo + per, n);
-        int64_t t = 0;
-        for (int v = lo; v < hi; ++v) t += vcnt[v];
-        int64_t unused;
-        int64_t run = block_scan(t, wtot, &unused);
-        for (int v = lo; v < hi; ++v) {
-          voff[v] = (int32_t)run;
-          run += vcnt[v];
-          vcnt[v] = 0;
-          p1[v] = -1;
-        }
-        __syncthreads();
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int S = a.sections;
+  if (tid == 0) {
+    int32_t fb = 0, fi = 0, pi = 0;
+    for (int k = 0; k < S; ++k) {
+      sfb[k] = fb; sfi[k] = fi; spi[k] = pi;
+      if (!a.force_fallback) {
+        fb += sc.scnt[4 * k]; fi += sc.scnt[4 * k + 1]; pi += sc.scnt[4 * k + 2];
       }
     }
-    // the stars leave the staging area interleaved: every vertex's first
-    // star, then every vertex's second one, ...  (consecutive slots then
-    // rarely share their centre, which keeps first-fit from opening a new
-    // batch for each of them)
-    {
-      int64_t base = 0;
-      for (int rho = 0;; ++rho) {
-        int64_t got = 0;
-        for (int v0 = 0; v0 < n; v0 += PK_NT) {
-          const int v = v0 + tid;
-          const int flag = v < n && vcnt[v] > rho;
-          int ex;
-          const int t = block_exclusive(flag, &ex, red);
-          if (flag) sc.slots[nslots + base + got + ex] = stage[voff[v] + rho];
-          got += t;
-        }
-        if (got == 0) break;
-        base += got;
-      }
-      nslots += base;
-    }
-    __syncthreads();
-    // round 2: the unpaired edges at their larger orbital; then the rest
-    // as it comes
-    if (tid == 0) {
-      int64_t w = nslots;
-      for (int v = 0; v < n; ++v) {
-        const int y = p1[v];
-        if (y < 0) continue;
-        const int h = p2[y];
-        if (h < 0) { p2[y] = (int16_t)v; continue; }
-        sc.slots[w++] = SlotRec{y, h, y, v, 2, 0u};
-        p2[y] = -1;
-      }
-      int hx = -1, hy = -1;
-      for (int v = 0; v < n; ++v) {
-        const int x = p2[v];
-        if (x < 0) continue;
-        if (hx < 0) { hx = x; hy = v; continue; }
-        // edges (hx, hy) and (x, v)
-        if (hx == x || hx == v || hy == x || hy == v) {
-          const int c = (hx == x || hx == v) ? hx : hy;
-          const int pj = hx == c ? hy : hx, ql = x == c ? v : x;
-          sc.slots[w++] = SlotRec{c, pj, c, ql, 2, 0u};
-        } else {
-          sc.slots[w++] = SlotRec{hx, hy, x, v, 2, 0u};
-        }
-        hx = -1;
-      }
-      if (hx >= 0) sc.slots[w++] = SlotRec{hx, hy, -1, -1, 1, 0u};
-      tot[3] = w;
-    }
-    __syncthreads();
-    int64_t w = tot[3];
-    // one-sided pairs: stars around each virtual orbital u with the
-    // occupied pair (2t, 2t + 1), t = (k + u) mod P in round k, so that
-    // the stars of one round share no orbital
-    if (a.n_occ < n) {
-      const int P = a.n_occ / 2, nvirt = n - a.n_occ;
-      const int64_t cnt = (int64_t)P * nvirt;
-      for (int64_t q = tid; q < cnt; q += PK_NT) {
-        const int k = (int)(q / nvirt), u = (int)(q % nvirt);
-        const int v = a.n_occ + u, t = 2 * ((k + u) % P);
-        sc.slots[w + q] = SlotRec{v, t, v, t + 1, 2, 1u | 4u | 16u};
-      }
-      w += cnt;
-      if (a.n_occ & 1) {
-        for (int u = tid; u < nvirt; u += PK_NT)
-          sc.slots[w + u] = SlotRec{a.n_occ - 1, a.n_occ + u, -1, -1, 1, 1u | 2u};
-        w += nvirt;
-      }
-    }
-    // diagonal pairs, two by two
-    if (tid == 0) {
-      int hd = -1;
-      for (int wd = 0; wd < a.words; ++wd) {
-        uint64_t bits = sc.db[wd];
-        while (bits) {
-          const int d = 64 * wd + __builtin_ctzll(bits);
-          bits &= bits - 1ull;
-          if (hd < 0) { hd = d; continue; }
-          sc.slots[w++] = SlotRec{hd, hd, d, d, 2, 0u};
-          hd = -1;
-        }
-      }
-      if (hd >= 0) sc.slots[w++] = SlotRec{hd, hd, -1, -1, 1, 0u};
-      tot[2] = w;
-    }
-    __syncthreads();
-    nslots = tot[2];
-  } else {
-    block_prefix(sc.gcnt, nv, 1, sc.off, &tot[0], wtot);
-    for (int r = wave; r < nv; r += PK_NT / 64) {
-      const int64_t o = sc.off[r];
-      const int c = sc.gcnt[r];
-      for (int t = lane; t < c; t += 64)
-        sc.slots[o + t] = sc.gstar[(int64_t)r * nv + t];
-    }
-    nslots = tot[0];
+    sfb[S] = fb; sfi[S] = fi; spi[S] = pi;
   }
-  // clear the table and the window masks
-  for (int64_t b = tid; b < a.max_batches; b += PK_NT) clear_batch(tab + b);
   __syncthreads();
-  for (int o = tid; o < 4098; o += PK_NT) inwin[o] = 0u;
+  const int32_t F = sfb[S];
+  const int64_t pb = a.per_bound;
+  // directory of the full batches: wave w takes sections w, w + 4, ...
+  for (int k = wave; k < S; k += PK_NT / 64) {
+    const int nfb = sfb[k + 1] - sfb[k];
+    int32_t run = 0;
+    for (int c0 = 0; c0 < nfb; c0 += 64) {
+      const int t = c0 + lane;
+      const int32_t v = t < nfb ? sc.fcnt[k * pb + t] : 0;
+      int32_t x = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      if (t < nfb) {
+        sc.dir[2 * (sfb[k] + t)] = (int32_t)(k * pb) + run + x - v;
+        sc.dir[2 * (sfb[k] + t) + 1] = v;
+      }
+      run += __shfl(x, 63, 64);
+    }
+  }
+  // the refill order
+  for (int k = 0; k < S; ++k) {
+    const int np = spi[k + 1] - spi[k];
+    for (int t = tid; t < np; t += PK_NT) sc.rlist[spi[k] + t] = sc.pidx[k * pb + t];
+  }
   __syncthreads();
-  // ------------------------------------------------------ first-fit
-  // One wave; its state is uniform.  The open batches sit at window
-  // positions 0 .. nopen - 1, oldest first, so the first fit is the lowest
-  // candidate bit.  inwin[o] has bit x set when orbital o is in the batch at
-  // position x (entry 4096 stands for "no orbital" and stays 0; 4097 takes
-  // the writes for it).  The slot and pair counts of the positions are the
-  // bytes of two 64-bit words; fit1 / fit2 are the positions that can take
-  // a one- / two-pair slot.  Each open batch builds its slot lists, id and
-  // header bits in one of PK_WIN staging buffers in LDS (phys, 4 bits per
-  // position); a batch that leaves the window (full, or the oldest when a
-  // new one is needed) is written to the table whole, and the positions
-  // above it move down one.  The masks of the next slot are read before
-  // the current one is placed, then corrected for it.
   if (wave == 0) {
-    constexpr uint32_t NONE_R = 4096u, NONE_W = 4097u;
-    uint64_t cnt_s = 0, cnt_p = 0;
-    uint32_t fit1 = 0, fit2 = 0, nstar = 0, phys = 0, freep = (1u << PK_WIN) - 1u;
-    int nopen = 0, nb = 0, over = a.force_fallback;
-    // 64 slot records a lane, packed: orbitals as 16 bits (-1 as NONE_R),
-    // then pairs | flags << 8 | (not a star) << 16 | (shares an orbital
-    // with the next slot) << 17
-    auto load = [&](int64_t base, uint32_t& ij, uint32_t& kl, uint32_t& ex) {
-      ij = NONE_R | (NONE_R << 16);
-      kl = ij;
-      ex = 0;
-      if (base + lane < nslots) {
-        const SlotRec r = sc.slots[base + lane];
-        ij = (uint32_t)r.i | ((uint32_t)r.j << 16);
-        kl = (r.k < 0 ? NONE_R : (uint32_t)r.k) | ((r.l < 0 ? NONE_R : (uint32_t)r.l) << 16);
-        ex = (uint32_t)r.np | (r.flags << 8) | (r.k != r.i ? 1u << 16 : 0u);
-      }
-    };
-    auto share = [&](uint32_t& ex, uint32_t ij, uint32_t kl, uint32_t nij, uint32_t nkl) {
-      const uint32_t o[4] = {ij & 0xFFFFu, ij >> 16, kl & 0xFFFFu, kl >> 16};
-      const uint32_t m[4] = {nij & 0xFFFFu, nij >> 16, nkl & 0xFFFFu, nkl >> 16};
-      bool hit = false;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) hit |= o[u] != NONE_R && o[u] == m[v];
-      if (hit) ex |= 1u << 17;
-    };
-    auto masks = [&](uint32_t ij, uint32_t kl) -> uint32_t {
-      return inwin[ij & 0xFFFFu] | inwin[ij >> 16] | inwin[kl & 0xFFFFu] | inwin[kl >> 16];
-    };
-    uint32_t aij, akl, aex, bij, bkl, bex;   // slots c0 .. c0 + 63, and the next 64
-    auto mark = [&]() {   // the share bits of chunk a
-      uint32_t nij = __shfl_down(aij, 1, 64), nkl = __shfl_down(akl, 1, 64);
-      const uint32_t fij = __builtin_amdgcn_readlane(bij, 0);
-      const uint32_t fkl = __builtin_amdgcn_readlane(bkl, 0);
-      if (lane == 63) { nij = fij; nkl = fkl; }
-      share(aex, aij, akl, nij, nkl);
-    };
-    auto drop = [&](int x, uint32_t& pre) {   // position x leaves the window
-      const int ph = (int)((phys >> (4 * x)) & 15u);
-      const int ns = (int)((cnt_s >> (8 * x)) & 0xFFu);
-      BatchDev* b = tab + bid[ph];
-      if (lane < ns) {
-        b->i[lane] = bst[(ph * 4 + 0) * 64 + lane];
-        b->j[lane] = bst[(ph * 4 + 1) * 64 + lane];
-        b->k[lane] = bst[(ph * 4 + 2) * 64 + lane];
-        b->l[lane] = bst[(ph * 4 + 3) * 64 + lane];
-      }
+    int32_t* ridx = sc.idx + (int64_t)S * pb;
+    int64_t rpos = 0;
+    int32_t rb = 0;
+    auto emit = [&](const int32_t* row, int cnt, bool) {
+      for (int q = lane; q < cnt; q += 64) ridx[rpos + q] = row[q];
       if (lane == 0) {
-        b->n = ns;
-        b->star = (nstar >> x) & 1u ? 0 : 1;
-        b->npairs = (int32_t)((cnt_p >> (8 * x)) & 0xFFu);
-        b->one_sided = bbits[ph * 5];
-        b->skip[0] = bbits[ph * 5 + 1]; b->skip[1] = bbits[ph * 5 + 2];
-        b->skip[2] = bbits[ph * 5 + 3]; b->skip[3] = bbits[ph * 5 + 4];
+        sc.dir[2 * (F + rb)] = (int32_t)(S * pb + rpos);
+        sc.dir[2 * (F + rb) + 1] = cnt;
       }
-      const uint64_t lowb = (1ull << (8 * x)) - 1ull;
-      cnt_s = (cnt_s & lowb) | ((cnt_s >> 8) & ~lowb);
-      cnt_p = (cnt_p & lowb) | ((cnt_p >> 8) & ~lowb);
-      const uint32_t lown = (1u << (4 * x)) - 1u;
-      phys = (phys & lown) | ((phys >> 4) & ~lown);
-      freep |= 1u << ph;
-      const uint32_t low = (1u << x) - 1u;
-      fit1 = (fit1 & low) | ((fit1 >> 1) & ~low);
-      fit2 = (fit2 & low) | ((fit2 >> 1) & ~low);
-      nstar = (nstar & low) | ((nstar >> 1) & ~low);
-      pre = (pre & low) | ((pre >> 1) & ~low);
-      for (int o = lane; o < n; o += 64) {
-        const uint32_t v = inwin[o];
-        inwin[o] = (v & low) | ((v >> 1) & ~low);
-      }
-      --nopen;
+      ++rb;
+      rpos += cnt;
     };
-    load(0, aij, akl, aex);
-    load(64, bij, bkl, bex);
-    mark();
-    int64_t c0 = 0;
-    uint32_t sij = __builtin_amdgcn_readlane(aij, 0);
-    uint32_t skl = __builtin_amdgcn_readlane(akl, 0);
-    uint32_t sex = __builtin_amdgcn_readlane(aex, 0);
-    uint32_t conf = nslots > 0 ? masks(sij, skl) : 0u;
-    for (int64_t q = 0; q < nslots && !over; ++q) {
-      // the next slot and its masks, read before this one is placed
-      uint32_t nij = 0, nkl = 0, nex = 0, pre = 0;
-      if (q + 1 < nslots) {
-        const int r = (int)(q + 1 - c0);
-        if (r < 64) {
-          nij = __builtin_amdgcn_readlane(aij, r);
-          nkl = __builtin_amdgcn_readlane(akl, r);
-          nex = __builtin_amdgcn_readlane(aex, r);
-        } else {
-          nij = __builtin_amdgcn_readlane(bij, 0);
-          nkl = __builtin_amdgcn_readlane(bkl, 0);
-          nex = __builtin_amdgcn_readlane(bex, 0);
-        }
-        pre = masks(nij, nkl);
-      }
-      const int np = (int)(sex & 0xFFu);
-      const uint32_t cand = (np == 1 ? fit1 : fit2) & ~conf;
-      int x;
-      if (cand) {
-        x = __builtin_ctz(cand);
-      } else {
-        if (nb >= a.max_batches) { over = 1; break; }
-        if (nopen == PK_WIN) drop(0, pre);   // the oldest leaves
-        x = nopen++;
-        const int ph = __builtin_ctz(freep);
-        freep &= ~(1u << ph);
-        phys |= (uint32_t)ph << (4 * x);
-        if (lane == 0) bid[ph] = nb;
-        if (lane < 5) bbits[ph * 5 + lane] = 0ull;
-        ++nb;
-        fit1 |= 1u << x;
-        if (a.ppb >= 2) fit2 |= 1u << x;
-      }
-      const uint32_t bit = 1u << x;
-      const int qs = (int)((cnt_s >> (8 * x)) & 0xFFu);
-      const int ph = (int)((phys >> (4 * x)) & 15u);
-      const uint32_t oi = sij & 0xFFFFu, oj = sij >> 16, ok = skl & 0xFFFFu, ol = skl >> 16;
-      if (lane == 0) {
-        int32_t* st = bst + ph * 256 + qs;
-        st[0] = (int32_t)oi;
-        st[64] = (int32_t)oj;
-        st[128] = ok == NONE_R ? -1 : (int32_t)ok;
-        st[192] = ol == NONE_R ? -1 : (int32_t)ol;
-        atomicOr(&inwin[oi], bit);
-        atomicOr(&inwin[oj], bit);
-        atomicOr(&inwin[ok == NONE_R ? NONE_W : ok], bit);
-        atomicOr(&inwin[ol == NONE_R ? NONE_W : ol], bit);
-      }
-      cnt_s += 1ull << (8 * x);
-      cnt_p += (uint64_t)np << (8 * x);
-      const int fs = qs + 1, fp = (int)((cnt_p >> (8 * x)) & 0xFFu);
-      if (fs >= a.cap || fp + 1 > a.ppb) fit1 &= ~bit;
-      if (fs >= a.cap || fp + 2 > a.ppb) fit2 &= ~bit;
-      if ((sex >> 16) & 1u) nstar |= bit;
-      const uint32_t fl = (sex >> 8) & 0xFFu;
-      if (fl) {   // one-sided or skipped-W bits (virtual orbitals)
-        if (lane < 5 && ((fl >> lane) & 1u))
-          atomicOr(reinterpret_cast<unsigned long long*>(&bbits[ph * 5 + lane]),
-                   1ull << qs);
-      }
-      // the next slot shares an orbital with this one: not at position x
-      if ((sex >> 17) & 1u) pre |= bit;
-      if (fp >= a.ppb || fs >= a.cap) drop(x, pre);   // full
-      sij = nij; skl = nkl; sex = nex; conf = pre;
-      if (q + 1 - c0 == 64) {
-        c0 += 64;
-        aij = bij; akl = bkl; aex = bex;
-        load(c0 + 64, bij, bkl, bex);
-        mark();
-        sex = __builtin_amdgcn_readlane(aex, 0);   // now with its share bit
-      }
-    }
-    if (!over) {
-      uint32_t unused = 0;
-      while (nopen) drop(nopen - 1, unused);
-    }
-    if (lane == 0) { st_nb = nb; st_over = over; }
+    int over = a.force_fallback || F > a.max_batches;
+    if (!over)
+      over = window_ff(a, spi[S], [&](int64_t t) { return sc.rlist[t]; }, sc.slots,
+                       a.max_batches - F, emit, inwin, bidx);
+    if (lane == 0) { st_nb = F + rb; st_over = over; }
   }
   __syncthreads();
-  {
-    int64_t np = 0;
-    for (int64_t q = tid; q < nslots; q += PK_NT) np += sc.slots[q].np;
-    int64_t total = 0;
-    block_scan(np, wtot, &total);
-    if (tid == 0) {
-      if (n_pairs) *n_pairs = total;
-      if (st_over) fallback_schedule(a, sc.kb, sc.db, tab, n_batches);
-      else *n_batches = st_nb;
+  if (tid == 0) {
+    if (n_pairs) *n_pairs = sc.count[1];
+    sc.flags[0] = st_over;
+    sc.flags[1] = st_nb;
+    if (st_over) fallback_schedule(a, sc.kb, sc.db, tab, n_batches);
+    else *n_batches = st_nb;
+  }
+}
+
+// The batch table from the directory: one wave per batch; entries past
+// the last batch are cleared.  Skipped when the fallback wrote the table.
+__global__ __launch_bounds__(64) void k_sched_fill(PackArgs a, PackScratch sc,
+                                                   BatchDev* __restrict__ tab) {
+  if (sc.flags[0]) return;
+  const int lane = threadIdx.x;
+  const int64_t nb = sc.flags[1];
+  for (int64_t g = blockIdx.x; g < a.max_batches; g += gridDim.x) {
+    BatchDev* b = tab + g;
+    if (g >= nb) {
+      if (lane == 0) clear_batch(b);
+      continue;
+    }
+    const int32_t start = sc.dir[2 * g], cnt = sc.dir[2 * g + 1];
+    const bool on = lane < cnt;
+    SlotRec s{-1, -1, -1, -1, 0, 0u};
+    if (on) {
+      s = sc.slots[sc.idx[start + lane]];
+      b->i[lane] = s.i; b->j[lane] = s.j; b->k[lane] = s.k; b->l[lane] = s.l;
+    }
+    const uint64_t os = __ballot(on && (s.flags & 1u));
+    const uint64_t s0 = __ballot(on && ((s.flags >> 1) & 1u));
+    const uint64_t s1 = __ballot(on && ((s.flags >> 2) & 1u));
+    const uint64_t s2 = __ballot(on && ((s.flags >> 3) & 1u));
+    const uint64_t s3 = __ballot(on && ((s.flags >> 4) & 1u));
+    const uint64_t ns = __ballot(on && s.k != s.i);
+    int np = on ? s.np : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) np += __shfl_xor(np, d, 64);
+    if (lane == 0) {
+      b->n = cnt;
+      b->star = ns ? 0 : 1;
+      b->npairs = np;
+      b->one_sided = os;
+      b->skip[0] = s0; b->skip[1] = s1; b->skip[2] = s2; b->skip[3] = s3;
     }
   }
 }
 
 }  // namespace
 
-int64_t sched_scratch_bytes(int n_orb) {
-  const int64_t nv = n_orb + (n_orb & 1), ng = nv / 2;
-  const int64_t words = (n_orb + 63) / 64;
-  auto up = [](int64_t x) { return (x + 255) & ~int64_t(255); };
-  int64_t b = 0;
-  b += up(8 * (int64_t)n_orb * words);                              // kb
-  b += up(8 * words);                                               // db
-  b += up((int64_t)sizeof(SlotRec) * std::max(ng * (nv / 2), nv * nv));  // gstar
-  b += up(8 * ng * nv);                                             // gleft
-  b += up(4 * std::max(2 * ng, nv));                                // gcnt
-  b += up(8 * (2 * nv + 2));                                        // off
-  b += up(8 * ng * nv);                                             // left
-  const int64_t nslot = (int64_t)n_orb * (n_orb + 1) / 2 +
-                        (int64_t)n_orb * n_orb / 4 + n_orb + 8;
-  b += up((int64_t)sizeof(SlotRec) * nslot);                        // slots
-  b += up(64);                                                      // flags
-  return b;
+int sched_sections(int n_orb) {
+  const int64_t s = (int64_t)n_orb * n_orb / 4096;
+  return s < 1 ? 1 : s > 16 ? 16 : (int)s;
 }
+
+int64_t sched_slot_bound(int n_orb) {
+  return (int64_t)n_orb * (n_orb + 1) / 2 + (int64_t)n_orb * n_orb / 4 + n_orb + 8;
+}
+
+namespace {
+
+struct SchedLayout {
+  uint64_t *kb, *db;
+  SlotRec* gstar;
+  int2* gleft;
+  int32_t* gcnt;
+  int64_t* off;
+  uint64_t* lb;
+  int16_t* ytab;
+  uint64_t* rb;
+  SlotRec* slots;
+  int64_t* count;
+  int32_t *idx, *fcnt, *pidx, *scnt, *rlist, *dir, *flags;
+  int64_t per_bound;
+  int64_t bytes;
+};
+
+// The scheduler's scratch regions (base == nullptr: sizes only).
+SchedLayout sched_layout(int n, void* base) {
+  const int64_t nv = n + (n & 1), ng = nv / 2;
+  const int64_t words = (n + 63) / 64;
+  const int64_t nslot = sched_slot_bound(n);
+  const int S = sched_sections(n);
+  // a section is its share of the slots, moved to group boundaries: it
+  // may take up to one group (round) more
+  const int64_t pb = (nslot + S - 1) / S + nv;
+  char* p = static_cast<char*>(base);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    char* q = p ? p + off : nullptr;
+    off += (bytes + 255) & ~int64_t(255);
+    return q;
+  };
+  SchedLayout L;
+  L.kb = reinterpret_cast<uint64_t*>(take(8 * n * words));
+  L.db = reinterpret_cast<uint64_t*>(take(8 * words));
+  L.gstar = reinterpret_cast<SlotRec*>(
+      take((int64_t)sizeof(SlotRec) * std::max(ng * (nv / 2), nv * nv)));
+  L.gleft = reinterpret_cast<int2*>(take(8 * ng * nv));
+  L.gcnt = reinterpret_cast<int32_t*>(take(4 * std::max(2 * ng, nv)));
+  L.off = reinterpret_cast<int64_t*>(take(8 * (2 * nv + 2)));
+  L.lb = reinterpret_cast<uint64_t*>(take(8 * n * ((ng + 63) / 64)));
+  L.ytab = reinterpret_cast<int16_t*>(take(2 * n * ng));
+  L.rb = reinterpret_cast<uint64_t*>(take(8 * n * words));
+  L.slots = reinterpret_cast<SlotRec*>(take((int64_t)sizeof(SlotRec) * nslot));
+  L.count = reinterpret_cast<int64_t*>(take(32));
+  L.idx = reinterpret_cast<int32_t*>(take(4 * 2 * S * pb));
+  L.fcnt = reinterpret_cast<int32_t*>(take(4 * S * pb));
+  L.pidx = reinterpret_cast<int32_t*>(take(4 * S * pb));
+  L.scnt = reinterpret_cast<int32_t*>(take(4 * 4 * S));
+  L.rlist = reinterpret_cast<int32_t*>(take(4 * S * pb));
+  L.dir = reinterpret_cast<int32_t*>(take(4 * 2 * nslot));
+  L.flags = reinterpret_cast<int32_t*>(take(64));
+  L.per_bound = pb;
+  L.bytes = off;
+  return L;
+}
+
+}  // namespace
+
+int64_t sched_scratch_bytes(int n_orb) { return sched_layout(n_orb, nullptr).bytes; }
 
 hipError_t launch_schedule(const SchedDesc& d, hipStream_t st) {
   const int n = d.n_orb, nv = n + (n & 1), ng = nv / 2;
   const int words = (n + 63) / 64;
   if (n < 1 || words > 64 || d.ppb < 1 || d.ppb > PMAX) return hipErrorInvalidValue;
-  char* p = static_cast<char*>(d.scratch);
-  auto up = [](int64_t x) { return (x + 255) & ~int64_t(255); };
-  auto take = [&](int64_t bytes) { char* q = p; p += up(bytes); return q; };
-  uint64_t* kb = reinterpret_cast<uint64_t*>(take(8 * (int64_t)n * words));
-  uint64_t* db = reinterpret_cast<uint64_t*>(take(8 * words));
-  SlotRec* gstar = reinterpret_cast<SlotRec*>(
-      take((int64_t)sizeof(SlotRec) * std::max((int64_t)ng * (nv / 2), (int64_t)nv * nv)));
-  int2* gleft = reinterpret_cast<int2*>(take(8 * (int64_t)ng * nv));
-  int32_t* gcnt = reinterpret_cast<int32_t*>(take(4 * std::max(2 * ng, nv)));
-  int64_t* off = reinterpret_cast<int64_t*>(take(8 * (2 * (int64_t)nv + 2)));
-  int2* left = reinterpret_cast<int2*>(take(8 * (int64_t)ng * nv));
-  const int64_t nslot = (int64_t)n * (n + 1) / 2 + (int64_t)n * n / 4 + n + 8;
-  SlotRec* slots = reinterpret_cast<SlotRec*>(take((int64_t)sizeof(SlotRec) * nslot));
-  int32_t* flags = reinterpret_cast<int32_t*>(take(64));
-  hipError_t e = launch_zero(db, 8 * words, st);
+  const SchedLayout L = sched_layout(n, d.scratch);
+  hipError_t e = launch_zero(L.db, 8 * words, st);
   if (e != hipSuccess) return e;
   if (d.pair_i) {
-    e = launch_zero(kb, 8 * (int64_t)n * words, st);
-    if (e == hipSuccess) e = launch_zero(d.bad ? (void*)d.bad : (void*)flags, 4, st);
+    e = launch_zero(L.kb, 8 * (int64_t)n * words, st);
+    if (e == hipSuccess) e = launch_zero(d.bad ? (void*)d.bad : (void*)L.flags, 4, st);
     if (e != hipSuccess) return e;
     int64_t blocks = (d.n_pairs + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     LACE_LAUNCH(k_sched_bits_list, dim3((unsigned)blocks), dim3(256), 0, st,
-                d.pair_i, d.pair_j, d.n_pairs, n, words, kb, db,
-                d.bad ? d.bad : flags);
+                d.pair_i, d.pair_j, d.n_pairs, n, words, L.kb, L.db,
+                d.bad ? d.bad : L.flags);
   } else {
     int64_t blocks = ((int64_t)n * words + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     LACE_LAUNCH(k_sched_bits_s, dim3((unsigned)blocks), dim3(256), 0, st, d.s,
-                n, d.s_n > 0 ? d.s_n : n, words, d.s_thr, kb, db);
+                n, d.s_n > 0 ? d.s_n : n, words, d.s_thr, L.kb, L.db);
   }
   // real orbitals pack two pairs per slot when a batch takes two pairs
   const bool pack = d.gamma && d.ppb >= 2;
   if (pack) {
-    LACE_LAUNCH(k_sched_groups, dim3(ng), dim3(64), 0, st, kb, n,
-                words, gstar, gleft, gcnt);
+    LACE_LAUNCH(k_sched_groups, dim3(ng), dim3(64), 0, st, L.kb, n,
+                words, L.gstar, L.gleft, L.gcnt);
   } else {
-    LACE_LAUNCH(k_sched_rounds, dim3(nv), dim3(64), 0, st, kb, db,
-                n, d.n_occ, words, gstar, gcnt);
+    LACE_LAUNCH(k_sched_rounds, dim3(nv), dim3(64), 0, st, L.kb, L.db,
+                n, d.n_occ, words, L.gstar, L.gcnt);
   }
   PackArgs a;
   a.n_orb = n; a.n_occ = d.n_occ; a.words = words; a.ppb = d.ppb;
   a.cap = d.gamma ? (d.ppb + 1) / 2 : d.ppb;
   a.gamma = pack ? 1 : 0;
   a.force_fallback = d.force_fallback ? 1 : 0;
+  a.sections = sched_sections(n);
   a.max_batches = d.max_batches;
-  PackScratch sc{gstar, gleft, gcnt, kb, db, slots, off, left};
-  LACE_LAUNCH(k_sched_pack, dim3(1), dim3(PK_NT), 0, st, a, sc, d.table,
+  a.per_bound = L.per_bound;
+  PackScratch sc{L.gstar, L.gleft, L.gcnt, L.kb, L.db, L.slots, L.off,
+                 L.lb, L.ytab, L.rb, L.count, L.idx, L.fcnt, L.pidx, L.scnt,
+                 L.rlist, L.dir, L.flags};
+  LACE_LAUNCH(k_sched_list, dim3(1), dim3(PK_NT), 0, st, a, sc);
+  LACE_LAUNCH(k_sched_sections, dim3(a.sections), dim3(64), 0, st, a, sc);
+  LACE_LAUNCH(k_sched_merge, dim3(1), dim3(PK_NT), 0, st, a, sc, d.table,
               d.n_batches, d.n_kept);
+  int64_t fb = d.max_batches < 1024 ? d.max_batches : 1024;
+  if (fb < 1) fb = 1;
+  LACE_LAUNCH(k_sched_fill, dim3((unsigned)fb), dim3(64), 0, st, a, sc, d.table);
   return hipGetLastError();
 }
 

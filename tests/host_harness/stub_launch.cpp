@@ -192,6 +192,13 @@ hipError_t launch_polar_norm(int, const void* B, int n, double* out, hipStream_t
   return hipSuccess;
 }
 int64_t sched_scratch_bytes(int n_orb) { return 4096 + 64 * (int64_t)n_orb * n_orb; }
+int sched_sections(int n_orb) {
+  const int64_t s = (int64_t)n_orb * n_orb / 4096;
+  return s < 1 ? 1 : s > 16 ? 16 : (int)s;
+}
+int64_t sched_slot_bound(int n_orb) {
+  return (int64_t)n_orb * (n_orb + 1) / 2 + (int64_t)n_orb * n_orb / 4 + n_orb + 8;
+}
 // A schedule of the diagonal pairs, one per batch, written where the device
 // scheduler writes its table; the scratch is touched whole.
 hipError_t launch_schedule(const SchedDesc& d, hipStream_t) {
