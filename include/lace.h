@@ -308,7 +308,8 @@ typedef struct {
 int lace_apply_exchange_batched(lace_plan* plan, lace_job* jobs, int n_jobs,
                                 int flags, lace_stream_t stream);
 
-/* Per-cell tuning of the pair pipeline: pairs per batch (1..64) and the xy
+/* Per-cell tuning of the pair pipeline: pairs per batch (1..64; real-orbital
+ * plans 1..128, two pairs per slot) and the xy
  * schedule: use_plane = 1, fused xy-plane passes (where the plane fits
  * LDS); 2, the xy plane in two halves of N/2 rows after a radix-2 split
  * along y (half the LDS, two workgroups per CU); 0, separate x and y pencil
@@ -319,10 +320,11 @@ int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
                     int* use_plane);
 
 /* Autotuner: times the pair pipeline of this cell on the given orbitals for
- * every candidate (pairs per batch 8, 16, 32, 64; half-plane, plane and
- * pencil schedules where they exist): each candidate schedules all pairs of
- * the n_orb orbitals its own way and is timed on its first batches holding
- * at least 256 pairs.  Keeps the fastest with lace_set_tuning.  Writes up to *n_cand candidates
+ * every candidate (pairs per batch 8, 16, 32, 64, and 128 for real-orbital
+ * plans; half-plane, plane and pencil schedules where they exist): each
+ * candidate schedules all pairs of the n_orb orbitals its own way and is
+ * timed on its first batches holding at least 512 pairs.  Keeps the fastest
+ * with lace_set_tuning.  Writes up to *n_cand candidates
  * (cand_ppb, cand_plane, cand_us_per_pair; host arrays, may be NULL) and
  * sets *n_cand to the number timed.  Synchronizes the stream.  The
  * workspace is the one of lace_workspace_size (W is overwritten). */
@@ -375,8 +377,8 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
  * of the round robin form, then from left-over pairs meeting at an orbital.
  * The slots are packed like the pairs of lace_schedule_pairs (sections of
  * whole cycles, then the unfilled batches once more).  No orbital appears
- * in two slots of one batch; a batch holds at most per_batch pairs and
- * (per_batch + 1) / 2 slots. */
+ * in two slots of one batch; a batch holds at most per_batch pairs
+ * (1..128) and (per_batch + 1) / 2 slots. */
 int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int32_t* slot_of,

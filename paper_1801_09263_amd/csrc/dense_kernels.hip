@@ -30,6 +30,8 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
 // MODE 1: real, op = |.| of float2 inputs (computed in FP64)
 // MODE 2: real, op = |.| of double2 inputs
 // MODE 3, 4: real, op = |.| of float / double inputs (real grids)
+// (the screening product of FP32 grids, modes 1 and 3, runs on the FP32
+// matrix cores in k_gemm_ip_f32 below)
 // Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement, 64 x 64 output,
 // each wave a 32 x 32 block (2 x 2 MFMA tiles).  K is staged through LDS
 // in chunks of KC (32 real, 16 complex) with coalesced row loads; the
@@ -210,6 +212,126 @@ __global__ __launch_bounds__(256) void k_gemm_ip(const void* A, int64_t lda,
       }
 }
 
+// The screening product S = |A|^T |B| of FP32 grids on the FP32 matrix
+// cores: MODE 3 real grids (|x|), MODE 1 complex grids (|z| in FP32).  The
+// same tiling as k_gemm_ip (64 x 64 per workgroup, 2 x 2 waves of 2 x 2
+// v_mfma_f32_16x16x4f32 tiles) with K staged in chunks of 64; each chunk's
+// FP32 sums are added into FP64 accumulators, so FP32 rounding acts on
+// 64-term sums only.  Partials in FP64 as k_gemm_ip's.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int MODE> struct IpLoad32;
+template <> struct IpLoad32<1> {
+  using Raw = float2;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const float2*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return make_float2(0.f, 0.f); }
+  __device__ static inline float conv(Raw v) { return sqrtf(v.x * v.x + v.y * v.y); }
+};
+template <> struct IpLoad32<3> {
+  using Raw = float;
+  __device__ static inline Raw load(const void* p, int64_t off) {
+    return static_cast<const float*>(p)[off];
+  }
+  __device__ static inline Raw zero() { return 0.f; }
+  __device__ static inline float conv(Raw v) { return fabsf(v); }
+};
+
+template <int MODE, bool SYM>
+__global__ __launch_bounds__(256) void k_gemm_ip_f32(const void* A, int64_t lda,
+                                                     int na, const void* B,
+                                                     int64_t ldb, int nb,
+                                                     int64_t K, int64_t kchunk,
+                                                     double* part) {
+  constexpr int KC = 64;
+  constexpr int PT = IP_T * KC / 256;   // elements per thread and matrix
+  __shared__ float sA[IP_T][KC + 1];
+  __shared__ float sB[IP_T][KC + 1];
+  const int tid = threadIdx.x, lane = tid % 64, w = tid / 64;
+  const int wa = w % 2, wb = w / 2;
+  int ta = blockIdx.x, tb = blockIdx.y;
+  if (SYM) {   // blockIdx.x enumerates the tile pairs ta <= tb, column by column
+    ta = blockIdx.x;
+    tb = 0;
+    while (ta > tb) { ta -= tb + 1; ++tb; }
+  }
+  const int a0 = ta * IP_T, b0 = tb * IP_T;
+  const int64_t kb = blockIdx.z * kchunk;
+  int64_t ke = kb + kchunk;
+  if (ke > K) ke = K;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = d4{0, 0, 0, 0};
+
+  using L = IpLoad32<MODE>;
+  typename L::Raw xa[PT], xb[PT];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / KC, kk = idx % KC;
+      const int64_t k = k0 + kk;
+      xa[e] = (a0 + r < na && k < ke) ? L::load(A, (a0 + r) * lda + k) : L::zero();
+      xb[e] = (b0 + r < nb && k < ke) ? L::load(B, (b0 + r) * ldb + k) : L::zero();
+    }
+  };
+  fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += KC) {
+#pragma unroll
+    for (int e = 0; e < PT; ++e) {
+      const int idx = tid + e * 256;
+      const int r = idx / KC, kk = idx % KC;
+      sA[r][kk] = L::conv(xa[e]);
+      sB[r][kk] = L::conv(xb[e]);
+    }
+    __syncthreads();
+    if (k0 + KC < ke) fetch(k0 + KC);
+    f4 c[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) c[p][q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int kk = ks * 4 + lane / 16;
+      float av[2], bv[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        av[p] = sA[wa * 32 + p * 16 + lane % 16][kk];
+        bv[p] = sB[wb * 32 + p * 16 + lane % 16][kk];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          c[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p], bv[q], c[p][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[p][q][e] += (double)c[p][q][e];
+    __syncthreads();
+  }
+  double* out = part + (int64_t)blockIdx.z * na * nb;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // v_mfma_f32_16x16x4f32 holds D[4 (l / 16) + e][l % 16] in lane l
+        const int a = a0 + wa * 32 + p * 16 + 4 * (lane / 16) + e;
+        const int b = b0 + wb * 32 + q * 16 + lane % 16;
+        if (a < na && b < nb) out[(int64_t)a * nb + b] = acc[p][q][e];
+      }
+}
+
 // out[e] = scale * sum_z part[z][e], fixed order over z.  sym_nb > 0: a
 // real sym_nb x sym_nb result of which only the tiles on and above the
 // diagonal were computed; an element below reads its mirror.
@@ -284,6 +406,27 @@ static hipError_t gemm_ip(const void* A, int64_t lda, int na, const void* B,
   return hipGetLastError();
 }
 
+// S of FP32 grids: FP32 products on the matrix cores, FP64 sums.
+template <int MODE>
+static hipError_t gemm_ip_abs_f32(const void* A, int64_t lda, int na,
+                                  int64_t K, double scale, double* out,
+                                  void* part, int64_t part_bytes, hipStream_t st) {
+  const SplitPlan sp = split_plan(na, na, K);
+  if ((int64_t)sp.nsplit * na * na * 8 > part_bytes) return hipErrorInvalidValue;
+  const int ta = (na + IP_T - 1) / IP_T;
+  dim3 grid(ta * (ta + 1) / 2, 1, sp.nsplit);
+  LACE_LAUNCH((k_gemm_ip_f32<MODE, true>), grid, dim3(256), 0, st, A, lda, na,
+              A, lda, na, K, sp.kchunk, static_cast<double*>(part));
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int64_t nel = (int64_t)na * na;
+  int64_t blocks = (nel + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  LACE_LAUNCH(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
+              static_cast<const double*>(part), nel, sp.nsplit, scale, out, na);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_ip_c128(const void* A, int64_t lda, int na,
                                const void* B, int64_t ldb, int nb, int64_t K,
                                double scale, void* out, void* part,
@@ -297,8 +440,7 @@ hipError_t launch_gemm_ip_abs(bool fp64, const void* A, int64_t lda, int na,
                               int64_t part_bytes, hipStream_t st) {
   return fp64 ? gemm_ip<2, true>(A, lda, na, A, lda, na, K, scale, out, part,
                                  part_bytes, st)
-              : gemm_ip<1, true>(A, lda, na, A, lda, na, K, scale, out, part,
-                                 part_bytes, st);
+              : gemm_ip_abs_f32<1>(A, lda, na, K, scale, out, part, part_bytes, st);
 }
 
 hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
@@ -307,8 +449,7 @@ hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
                                    hipStream_t st) {
   return fp64 ? gemm_ip<4, true>(A, lda, na, A, lda, na, K, scale, out, part,
                                  part_bytes, st)
-              : gemm_ip<3, true>(A, lda, na, A, lda, na, K, scale, out, part,
-                                 part_bytes, st);
+              : gemm_ip_abs_f32<3>(A, lda, na, K, scale, out, part, part_bytes, st);
 }
 
 // ------------------------------------------------------------------

@@ -1279,7 +1279,7 @@ hipError_t launch_pair_batch(const CellDev& c, bool fp64, const BatchDev* bt,
                              int cap, const void* psi, void* w, void* tmp,
                              double* epart, hipStream_t st, hipEvent_t* ev,
                              const BatchSync* sy) {
-  if (cap <= 0 || cap > PMAX) return hipErrorInvalidValue;
+  if (cap <= 0 || cap > SMAX) return hipErrorInvalidValue;
   return fp64 ? pair_batch_t<double>(c, bt, cap, psi, w, tmp, epart, st, ev, sy)
               : pair_batch_t<float>(c, bt, cap, psi, w, tmp, epart, st, ev, sy);
 }
@@ -1432,7 +1432,7 @@ hipError_t launch_quad_batch(const CellDev& c, bool fp64, const BatchDev* bt,
                              int cap, const void* psi, void* w, void* tmp,
                              double* epart, hipStream_t st, hipEvent_t* ev,
                              const BatchSync* sy) {
-  if (cap <= 0 || cap > QMAX) return hipErrorInvalidValue;
+  if (cap <= 0 || cap > SMAX) return hipErrorInvalidValue;
   return fp64 ? quad_batch_t<double>(c, bt, cap, psi, w, tmp, epart, st, ev, sy)
               : quad_batch_t<float>(c, bt, cap, psi, w, tmp, epart, st, ev, sy);
 }

@@ -21,32 +21,11 @@ template <auto K> inline hipError_t resolved() {
   return resolve_kernel(reinterpret_cast<const void*>(K), KernelOnce<K>::done);
 }
 
-constexpr int PMAX = 64;  // pairs per batch (kernel-argument table)
-
-struct PairArgs {
-  int n;
-  int i[PMAX];
-  int j[PMAX];
-  // bit q: pair q is one-sided, an occupied orbital i applied to a virtual
-  // orbital j: only W_j is updated and the pair adds nothing to E_x
-  uint64_t one_sided;
-};
-
-// Real (Gamma-point) orbitals: two pair densities of the same kind (both
-// diagonal or both off-diagonal) share one complex transform, rho_ij +
-// i rho_kl.  k = l = -1 when the slot holds a single pair; k = i (a star
-// slot) when the two pairs share orbital i, which is then read once and
-// its W updated once.
-constexpr int QMAX = PMAX / 2 + 1;
-struct QuadArgs {
-  int n;
-  int i[QMAX], j[QMAX], k[QMAX], l[QMAX];
-  // bit q of skip[0..3]: W_i, W_j, W_k, W_l of slot q is not updated (the
-  // occupied orbital of a one-sided pair); bit q of one_sided: the slot
-  // holds one-sided pairs and adds nothing to E_x
-  uint64_t skip[4];
-  uint64_t one_sided;
-};
+// A batch holds at most SMAX slots (one bit per slot in 64-bit masks) and
+// PMAX pairs: one pair per slot for complex orbitals, up to two for real
+// orbitals.
+constexpr int SMAX = 64;
+constexpr int PMAX = 128;
 
 // One batch of the pair pipeline as the kernels read it from device memory.
 // Slot q: complex orbitals hold one pair (i[q], j[q]); real orbitals pack
@@ -61,7 +40,7 @@ struct BatchDev {
   int32_t pad;
   uint64_t one_sided; // bit q: slot q holds one-sided pairs (no energy)
   uint64_t skip[4];   // bit q: W_i, W_j, W_k, W_l of slot q not updated
-  int32_t i[PMAX], j[PMAX], k[PMAX], l[PMAX];
+  int32_t i[SMAX], j[SMAX], k[SMAX], l[SMAX];
 };
 
 // Geometry and device tables of one cell, shared by all launchers.
@@ -76,7 +55,7 @@ struct CellDev {
                         // (n/2+1) + kx (v depends on |G| only; cubic cell)
   const void* tw;       // n twiddles exp(-2 pi i m / n), plan precision
   const int32_t* negidx;  // n_pw: position of -m in the Miller list (Gamma)
-  int ppb;              // pairs per batch (1..PMAX)
+  int ppb;              // pairs per batch (1..PMAX; complex orbitals 1..SMAX)
   int use_plane;        // 1: fused xy-plane passes where the plane fits LDS
 };
 

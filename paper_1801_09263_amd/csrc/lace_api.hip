@@ -196,7 +196,7 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   // two pair buffers and two sets of energy partials: consecutive batches
   // alternate between them, so that one batch's passes A and B can run
   // while the previous batch's pass C still reads its buffer
-  L.tmp = off; off += align_up(gb * PMAX * 2);
+  L.tmp = off; off += align_up(gb * SMAX * 2);
   L.epart = off;
   off += align_up(sizeof(double) * PMAX * 2 * energy_tiles(c.n, fp64));
   L.s = off; off += align_up(sizeof(double) * n_orb * n_orb);
@@ -351,7 +351,7 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
     const double rc = d.rc > 0.0 ? d.rc : 0.5 * d.L;
     cp.dev.n = n; cp.dev.ng = ng; cp.dev.n_pw = d.n_pw;
     cp.dev.L = d.L; cp.dev.rc = rc; cp.dev.omega = d.L * d.L * d.L;
-    cp.dev.ppb = default_pairs_per_batch(n);
+    cp.dev.ppb = std::min(default_pairs_per_batch(n), gamma ? PMAX : SMAX);
     cp.dev.use_plane = plane_fits(n, fp64) ? 1 : 2;
     // sphere -> grid map
     std::vector<int32_t> gidx(d.n_pw);
@@ -579,7 +579,7 @@ static hipError_t enqueue_batch(const lace_plan* p, const CellDev& c,
                                 int64_t b, int ppb, const Layout& L, void* ws,
                                 int lane, hipStream_t st, hipEvent_t* ev,
                                 const BatchSync* sy = nullptr) {
-  void* tmp = at(ws, L.tmp + (size_t)lane * PMAX * c.ng * grid_bytes(p));
+  void* tmp = at(ws, L.tmp + (size_t)lane * SMAX * c.ng * grid_bytes(p));
   double* epart = reinterpret_cast<double*>(at(ws, L.epart)) +
                   (size_t)lane * PMAX * energy_tiles(c.n, p->fp64);
   const BatchDev* bt = reinterpret_cast<const BatchDev*>(at(ws, L.tab)) + b;
@@ -1341,7 +1341,8 @@ int schedule_list(const int32_t* pair_i, const int32_t* pair_j, int64_t n_pairs,
                   int n_orb, int per_batch, bool gamma, int32_t* batch_of,
                   int32_t* slot_of, int64_t* n_batches) {
   if (!pair_i || !pair_j || !batch_of || !n_batches || n_pairs < 0 ||
-      n_orb < 1 || n_orb > 4096 || per_batch < 1 || per_batch > PMAX)
+      n_orb < 1 || n_orb > 4096 || per_batch < 1 ||
+      per_batch > (gamma ? PMAX : SMAX))
     return LACE_EINVAL;
   HostSched h;
   h.n = n_orb; h.n_occ = n_orb; h.ppb = per_batch;
@@ -1426,7 +1427,7 @@ int lace_read_schedule(const lace_plan* p, int cell, int n_orb, const void* ws,
   }
   std::vector<int64_t> where((size_t)n_orb * n_orb, -1);
   for (size_t b = 0; b < tab.size(); ++b)
-    for (int q = 0; q < tab[b].n && q < PMAX; ++q) {
+    for (int q = 0; q < tab[b].n && q < SMAX; ++q) {
       const BatchDev& d = tab[b];
       const int64_t code = (int64_t)b * 64 + q;
       for (int t = 0; t < 2; ++t) {
@@ -1448,7 +1449,7 @@ int lace_read_schedule(const lace_plan* p, int cell, int n_orb, const void* ws,
 
 int lace_set_tuning(lace_plan* p, int cell, int ppb, int use_plane) {
   if (!p || cell < 0 || cell >= (int)p->cells.size()) return LACE_EINVAL;
-  if (ppb < 1 || ppb > PMAX || use_plane < 0 || use_plane > 2)
+  if (ppb < 1 || ppb > (p->gamma ? PMAX : SMAX) || use_plane < 0 || use_plane > 2)
     return LACE_EINVAL;
   CellDev& c = p->cells[cell].dev;
   if (use_plane == 1 && !plane_fits(c.n, p->fp64)) return LACE_EUNSUPPORTED;
@@ -1486,10 +1487,12 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   all.s_n = n_orb;
   struct Cand { int ppb, plane; double us; };
   std::vector<Cand> cands;
-  const int ppbs[4] = {8, 16, 32, 64};
+  // pairs per batch: up to SMAX slots of one pair (complex) or two (real)
+  const int ppbs[5] = {8, 16, 32, 64, 128};
+  const int nppb = p->gamma ? 5 : 4;
   for (int plane = 2; plane >= 0; --plane) {
     if (plane == 1 && !plane_fits(c.n, fp64)) continue;
-    for (int k = 0; k < 4; ++k) cands.push_back({ppbs[k], plane, 0.0});
+    for (int k = 0; k < nppb; ++k) cands.push_back({ppbs[k], plane, 0.0});
   }
   const int save_ppb = c.ppb, save_plane = c.use_plane;
   hipEvent_t t0 = nullptr, t1 = nullptr;

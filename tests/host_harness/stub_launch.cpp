@@ -52,7 +52,7 @@ hipError_t launch_grid_to_pw(const CellDev& c, bool fp64, void* w, int n_orb,
 static hipError_t batch(const CellDev& c, bool fp64, bool real,
                         const BatchDev* bt, int cap, const void* psi, void* w,
                         void* tmp, double* epart, hipEvent_t* ev) {
-  if (cap < 1 || cap > (real ? QMAX : PMAX) || bt->n < 0 || bt->n > cap)
+  if (cap < 1 || cap > SMAX || bt->n < 0 || bt->n > cap)
     return hipErrorInvalidValue;
   if (ev)
     for (int k = 0; k < 4; ++k)

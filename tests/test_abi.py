@@ -131,6 +131,10 @@ def test_schedule_rejects_bad_pairs(lib):
         lace.lace_schedule_pairs([(0, 4)], 4, 4)
     with pytest.raises(lace.LaceError):
         lace.lace_schedule_pairs([(0, 1)], 4, 65)
+    # real orbitals: two pairs per slot, up to 64 slots, so 128 pairs
+    lace.lace_schedule_slots([(0, 1)], 4, 128)
+    with pytest.raises(lace.LaceError):
+        lace.lace_schedule_slots([(0, 1)], 4, 129)
 
 
 def _check_slots(pairs, n_orb, per_batch):
@@ -163,7 +167,7 @@ def _check_slots(pairs, n_orb, per_batch):
     return nb, n_slots, n_star
 
 
-@pytest.mark.parametrize("n_orb,per_batch", [(8, 4), (256, 64), (255, 32),
+@pytest.mark.parametrize("n_orb,per_batch", [(8, 4), (256, 64), (256, 128), (255, 32),
                                              (33, 16), (128, 64), (5, 1)])
 def test_slot_schedule_complete_pair_set(lib, n_orb, per_batch):
     pairs = [(i, j) for j in range(n_orb) for i in range(j + 1)]
@@ -192,7 +196,7 @@ def test_slot_schedule_screened_pair_set(lib, keep):
 
 
 def test_slot_schedule_rejects_bad_pairs(lib):
-    for pairs, n, pb in (([(2, 1)], 4, 4), ([(0, 4)], 4, 4), ([(0, 1)], 4, 65),
+    for pairs, n, pb in (([(2, 1)], 4, 4), ([(0, 4)], 4, 4), ([(0, 1)], 4, 129),
                          ([(0, 1)], 4, 0)):
         with pytest.raises(lace.LaceError):
             lace.lace_schedule_slots(pairs, n, pb)
