@@ -291,8 +291,8 @@ def batched_rows(torch, seed, steps):
         if key not in tuned:
             cands = mc.autotune(k)
             tuned[key] = lace.lace_get_tuning(mc.plan, k) + (
-                min(t for _, _, t in cands),)
-        lace.lace_set_tuning(mc.plan, k, tuned[key][0], tuned[key][1])
+                min(cd[4] for cd in cands),)
+        lace.lace_set_tuning(mc.plan, k, *tuned[key][:4])
     st = torch.cuda.Stream()
     out = {}
     for mode in ("eager", "graph"):
@@ -313,7 +313,8 @@ def batched_rows(torch, seed, steps):
         pair_ffts_per_s_eager=round(kept / out["eager"], 1),
         pair_ffts_per_s_graph=round(kept / out["graph"], 1),
         tuning={f"{n}^3/{no}": dict(pairs_per_batch=t[0], use_plane=t[1],
-                                   us_per_pair=round(t[2], 2))
+                                   z_tile=t[2], radix_order=t[3],
+                                   us_per_pair=round(t[4], 2))
                 for (n, no), t in tuned.items()},
         kept_fraction_by_class={})
     for k, c in enumerate(cells[:4]):
@@ -421,10 +422,12 @@ def main():
     ap.add_argument("--serve-light-rate", type=float, default=5.0,
                     help="arrival rate (jobs/s) of the second, sustainable "
                          "serving stream")
-    ap.add_argument("--tuning", default=None, metavar="PPB,MODE",
+    ap.add_argument("--tuning", default=None, metavar="PPB,MODE[,ZT,RO]",
                     help="fixed pipeline tuning (pairs per batch, xy schedule "
-                         "0 pencil / 1 plane / 2 half plane) instead of "
-                         "autotuning the main workload")
+                         "0 pencil / 1 plane / 2 half plane, optionally the z "
+                         "tile 0 default / 1 half / 2 twice and the radix "
+                         "order 0 / 1) instead of autotuning the main "
+                         "workload")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="small fixed run for hardware-counter passes: a "
                          "1 GiB copy (calibration) and 8 batches of star "
@@ -464,12 +467,13 @@ def main():
     sess.set_orbitals(inp["coeffs"])
     real_dev = sess.check_real()
     if args.tuning:
-        ppb, mode = (int(v) for v in args.tuning.split(","))
-        lace.lace_set_tuning(sess.plan, 0, ppb, mode)
+        lace.lace_set_tuning(sess.plan, 0,
+                             *(int(v) for v in args.tuning.split(",")))
         log(f"orbitals real to {real_dev:.1e}; fixed tuning")
     else:
         log(f"orbitals real to {real_dev:.1e}; autotuning the pair pipeline")
-        cands = lace.lace_autotune(sess.plan, 0, sess.psi, n_orb, sess.ws)
+        cands = lace.lace_autotune(sess.plan, 0, sess.psi, n_orb, sess.ws,
+                                   s_thr=inp["s_thr"])
         log("candidates", cands)
     tuning = lace.lace_get_tuning(sess.plan, 0)
     log("tuning", tuning)
@@ -558,7 +562,7 @@ def main():
         s3 = CellSession(inp, n_orb + n_v, lace.LACE_FP32_GAMMA,
                          n_vec=n_orb + n_v)
         s3.set_orbitals(np.concatenate([inp["coeffs"], virt]))
-        lace.lace_set_tuning(s3.plan, 0, tuning[0], tuning[1])
+        lace.lace_set_tuning(s3.plan, 0, *tuning)
         y3 = torch.empty_like(s3.psi)
         s3.apply_exchange(inp["s_thr"], n_occ=n_orb)
         s3.build_ace("avg")
@@ -644,7 +648,8 @@ def main():
             "e_x": e_x, "e_x_trace": ex_tr, "cholesky_info": info,
             "orbitals": "real (Gamma point), checked to %.1e; two pair "
                         "densities per complex FFT" % real_dev,
-            "tuning": {"pairs_per_batch": tuning[0], "use_plane": tuning[1]},
+            "tuning": {"pairs_per_batch": tuning[0], "use_plane": tuning[1],
+                       "z_tile": tuning[2], "radix_order": tuning[3]},
             "parallelism": "1 GPU",
         },
         "roofline": roofline,

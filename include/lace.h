@@ -308,30 +308,46 @@ typedef struct {
 int lace_apply_exchange_batched(lace_plan* plan, lace_job* jobs, int n_jobs,
                                 int flags, lace_stream_t stream);
 
-/* Per-cell tuning of the pair pipeline: pairs per batch (1..64; real-orbital
- * plans 1..128, two pairs per slot) and the xy
- * schedule: use_plane = 1, fused xy-plane passes (where the plane fits
- * LDS); 2, the xy plane in two halves of N/2 rows after a radix-2 split
- * along y (half the LDS, two workgroups per CU); 0, separate x and y pencil
- * passes.  Host only. */
+/* Per-cell tuning of the pair pipeline (the Poisson solves of Eq. (2) by
+ * FFT), host only:
+ *   pairs_per_batch  1..64; real-orbital plans 1..128 (two pairs per slot)
+ *   use_plane  the xy schedule: 1, fused xy-plane passes (where the plane
+ *              fits LDS); 2, the xy plane in two halves of N/2 rows after a
+ *              radix-2 split along y (half the LDS, two workgroups per CU);
+ *              0, separate x and y pencil passes
+ *   z_tile     the z pass's tile of the flattened xy plane per z row: 0,
+ *              256 bytes (32 FP32 or 16 FP64 complex points); 1, half as
+ *              wide; 2, twice as wide (where the plane divides into such
+ *              tiles, else the default)
+ *   radix_order  0, the radices of each transform length in the listed
+ *              order (e.g. 120 = 8 x 15, 60 = 4 x 15); 1, reversed
+ * EINVAL for values out of range, EUNSUPPORTED for use_plane = 1 where the
+ * plane does not fit LDS. */
 int lace_set_tuning(lace_plan* plan, int cell, int pairs_per_batch,
-                    int use_plane);
+                    int use_plane, int z_tile, int radix_order);
 int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
-                    int* use_plane);
+                    int* use_plane, int* z_tile, int* radix_order);
 
-/* Autotuner: times the pair pipeline of this cell on the given orbitals for
- * every candidate (pairs per batch 8, 16, 32, 64, and 128 for real-orbital
- * plans; half-plane, plane and pencil schedules where they exist): each
- * candidate schedules all pairs of the n_orb orbitals its own way and is
- * timed on its first batches holding at least 512 pairs.  Keeps the fastest
- * with lace_set_tuning.  Writes up to *n_cand candidates
- * (cand_ppb, cand_plane, cand_us_per_pair; host arrays, may be NULL) and
- * sets *n_cand to the number timed.  Synchronizes the stream.  The
- * workspace is the one of lace_workspace_size (W is overwritten). */
+/* Autotuner: times the pair pipeline of this cell on the given orbitals
+ * and the pairs that S keeps at s_thr (Eq. (6); 0 keeps every pair), on
+ * two internal streams as the exchange runs it, each candidate with its
+ * own schedule of those pairs.  Stage 1: every pairs
+ * per batch (8, 16, 32, 64, and 128 for real-orbital plans) with every xy
+ * schedule that exists (half-plane, plane, pencil), timed on its first
+ * batches holding at least 2048 pairs; the three fastest again over their
+ * whole schedules (as the exchange launches them, the batches past the
+ * schedule's end included).  Stage 2, for the fastest of those: the z tiles half and
+ * twice as wide and the reversed radix order, where they differ from the
+ * default, over the whole schedule.  Keeps the fastest whole-schedule time
+ * with lace_set_tuning.  Writes up to *n_cand candidates (cand_ppb,
+ * cand_plane, cand_ztile, cand_radix, cand_us_per_pair: the whole-schedule
+ * time where it was taken, else the first batches'; host arrays, may be
+ * NULL) and sets *n_cand to the number timed.  Synchronizes the stream.
+ * The workspace is the one of lace_workspace_size (W is overwritten). */
 int lace_autotune(lace_plan* plan, int cell, const void* psi_g, int n_orb,
-                  void* ws, size_t ws_bytes, lace_stream_t stream,
-                  int* cand_ppb, int* cand_plane, double* cand_us_per_pair,
-                  int* n_cand);
+                  double s_thr, void* ws, size_t ws_bytes, lace_stream_t stream,
+                  int* cand_ppb, int* cand_plane, int* cand_ztile,
+                  int* cand_radix, double* cand_us_per_pair, int* n_cand);
 
 /* In-place 3D FFT of `count` n^3 grids stored back to back in the plan
  * precision (complex64 or complex128, x fastest).  direction -1: forward

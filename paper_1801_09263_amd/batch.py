@@ -57,7 +57,7 @@ class MultiCell:
     def autotune(self, k, stream=None):
         j = self.jobs[k]
         return lace.lace_autotune(self.plan, k, j["psi_g"], j["n_orb"],
-                                  j["ws"], stream)
+                                  j["ws"], stream, s_thr=j["s_thr"])
 
     def close(self):
         self.plan.close()

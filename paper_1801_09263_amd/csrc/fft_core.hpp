@@ -14,6 +14,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 namespace lace {
 
 template <typename T> struct cplx;
@@ -165,9 +167,12 @@ template <int SIGN, typename T> struct Dft<15, SIGN, T> : Pfa<3, 5, SIGN, T> {};
 // ---------------------------------------------------------------------------
 // Radix plans for the supported lengths (product of the listed radices).
 // ---------------------------------------------------------------------------
-template <int N> struct Plan;
+// Plan<N, 0>: the radices in the listed order; Plan<N, 1>: in reverse
+// order (an equally valid factorization; which runs faster is left to the
+// autotuner).
+template <int N, int RO = 0> struct Plan;
 #define LACE_PLAN(NN, NS, ...)                                   \
-  template <> struct Plan<NN> {                                  \
+  template <> struct Plan<NN, 0> {                               \
     static constexpr int nst = NS;                               \
     static constexpr int r[NS] = {__VA_ARGS__};                  \
   };
@@ -187,10 +192,18 @@ LACE_PLAN(96, 2, 8, 12)
 LACE_PLAN(120, 2, 8, 15)
 #undef LACE_PLAN
 
-template <int N, int S> struct StageP {  // product of radices before stage S
-  static constexpr int value = StageP<N, S - 1>::value * Plan<N>::r[S - 1];
+template <int N, class Seq> struct RevPlan;
+template <int N, int... I> struct RevPlan<N, std::integer_sequence<int, I...>> {
+  static constexpr int nst = sizeof...(I);
+  static constexpr int r[nst] = {Plan<N, 0>::r[nst - 1 - I]...};
 };
-template <int N> struct StageP<N, 0> { static constexpr int value = 1; };
+template <int N>
+struct Plan<N, 1> : RevPlan<N, std::make_integer_sequence<int, Plan<N, 0>::nst>> {};
+
+template <int N, int S, int RO> struct StageP {  // product of radices before stage S
+  static constexpr int value = StageP<N, S - 1, RO>::value * Plan<N, RO>::r[S - 1];
+};
+template <int N, int RO> struct StageP<N, 0, RO> { static constexpr int value = 1; };
 
 // One Stockham stage.  LINES_FAST: consecutive threads walk consecutive
 // lines (use when lines are adjacent in LDS, i.e. ls == 1), else
@@ -241,34 +254,34 @@ __device__ inline void lds_stage(C<T>* s, int ls, int es, const C<T>* tw) {
   __syncthreads();
 }
 
-template <int N, int S> struct NextS {
-  static constexpr int value = (S + 1 < Plan<N>::nst) ? S + 1 : -1;
+template <int N, int S, int RO> struct NextS {
+  static constexpr int value = (S + 1 < Plan<N, RO>::nst) ? S + 1 : -1;
 };
 
 template <typename T, int N, int S, int NL, int NT, int SIGN, bool LF,
-          int TWS>
+          int TWS, int RO>
 struct StagesFrom {
   __device__ static inline void run(C<T>* s, int ls, int es, const C<T>* tw) {
-    lds_stage<T, N, Plan<N>::r[S], StageP<N, S>::value, NL, NT, SIGN, LF,
-              TWS>(s, ls, es, tw);
-    StagesFrom<T, N, NextS<N, S>::value, NL, NT, SIGN, LF, TWS>::run(s, ls,
-                                                                    es, tw);
+    lds_stage<T, N, Plan<N, RO>::r[S], StageP<N, S, RO>::value, NL, NT, SIGN,
+              LF, TWS>(s, ls, es, tw);
+    StagesFrom<T, N, NextS<N, S, RO>::value, NL, NT, SIGN, LF, TWS, RO>::run(
+        s, ls, es, tw);
   }
 };
-template <typename T, int N, int NL, int NT, int SIGN, bool LF, int TWS>
-struct StagesFrom<T, N, -1, NL, NT, SIGN, LF, TWS> {
+template <typename T, int N, int NL, int NT, int SIGN, bool LF, int TWS, int RO>
+struct StagesFrom<T, N, -1, NL, NT, SIGN, LF, TWS, RO> {
   __device__ static inline void run(C<T>*, int, int, const C<T>*) {}
 };
 
 // Stages S .. E-1 of the plan, in plan order.
 template <typename T, int N, int S, int E, int NL, int NT, int SIGN, bool LF,
-          int TWS>
+          int TWS, int RO>
 struct StagesRange {
   __device__ static inline void run(C<T>* s, int ls, int es, const C<T>* tw) {
     if constexpr (S < E) {
-      lds_stage<T, N, Plan<N>::r[S], StageP<N, S>::value, NL, NT, SIGN, LF,
-                TWS>(s, ls, es, tw);
-      StagesRange<T, N, S + 1, E, NL, NT, SIGN, LF, TWS>::run(s, ls, es, tw);
+      lds_stage<T, N, Plan<N, RO>::r[S], StageP<N, S, RO>::value, NL, NT, SIGN,
+                LF, TWS>(s, ls, es, tw);
+      StagesRange<T, N, S + 1, E, NL, NT, SIGN, LF, TWS, RO>::run(s, ls, es, tw);
     }
   }
 };
@@ -276,24 +289,25 @@ struct StagesRange {
 // The plan in reverse order, from stage index S down to 0: radix r[S] after
 // the radices r[S+1..] already applied (P = N / (r[0] ... r[S])).  The
 // reversed plan is an equally valid self-sorting Stockham factorization.
-template <typename T, int N, int S, int NL, int NT, int SIGN, bool LF, int TWS>
+template <typename T, int N, int S, int NL, int NT, int SIGN, bool LF, int TWS,
+          int RO>
 struct StagesReversed {
   __device__ static inline void run(C<T>* s, int ls, int es, const C<T>* tw) {
     if constexpr (S >= 0) {
-      lds_stage<T, N, Plan<N>::r[S], N / StageP<N, S + 1>::value, NL, NT, SIGN,
-                LF, TWS>(s, ls, es, tw);
-      StagesReversed<T, N, S - 1, NL, NT, SIGN, LF, TWS>::run(s, ls, es, tw);
+      lds_stage<T, N, Plan<N, RO>::r[S], N / StageP<N, S + 1, RO>::value, NL, NT,
+                SIGN, LF, TWS>(s, ls, es, tw);
+      StagesReversed<T, N, S - 1, NL, NT, SIGN, LF, TWS, RO>::run(s, ls, es, tw);
     }
   }
 };
 
 // NL length-N transforms in LDS.  Caller must __syncthreads() after filling
 // s; the call ends with a barrier.  The twiddle table holds the roots of a
-// length N * TWS transform.
+// length N * TWS transform.  RO picks the radix order (Plan<N, RO>).
 template <typename T, int N, int NL, int NT, int SIGN, bool LINES_FAST,
-          int TWS = 1>
+          int TWS = 1, int RO = 0>
 __device__ inline void lds_fft(C<T>* s, int ls, int es, const C<T>* tw) {
-  StagesFrom<T, N, 0, NL, NT, SIGN, LINES_FAST, TWS>::run(s, ls, es, tw);
+  StagesFrom<T, N, 0, NL, NT, SIGN, LINES_FAST, TWS, RO>::run(s, ls, es, tw);
 }
 
 }  // namespace lace

@@ -459,7 +459,7 @@ __device__ inline int xcd_logical(int bid, int total) {
 template <int N> struct Pad { static constexpr int LS = N + 1; };
 
 // ------------------------------------------- xy-plane pass (whole plane)
-template <typename T, int N, int NT, int SIGN, class Pro, class Epi>
+template <typename T, int N, int NT, int SIGN, class Pro, class Epi, int RO = 0>
 __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
                                               const C<T>* tw_g, int nslots) {
   constexpr int LS = Pad<N>::LS;
@@ -474,8 +474,8 @@ __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
   with_form(pro, epi, [&](const auto& pf, const auto& ef) {
     stage_in<T, N * N, NT>(s, pf, slot, idx, lds);
     __syncthreads();
-    lds_fft<T, N, N, NT, SIGN, true>(s, LS, 1, tw);  // along x: lines = rows
-    lds_fft<T, N, N, NT, SIGN, true>(s, 1, LS, tw);  // along y: lines = columns
+    lds_fft<T, N, N, NT, SIGN, true, 1, RO>(s, LS, 1, tw);  // along x: lines = rows
+    lds_fft<T, N, N, NT, SIGN, true, 1, RO>(s, 1, LS, tw);  // along y: lines = columns
     stage_out<T, N * N, NT>(s, ef, slot, idx, lds);
   });
 }
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(NT) void k_plane(Pro pro, Epi epi,
 // pass (the z pass) and stored as rows 0 .. H - 1 (a) and H .. N - 1 (b):
 // half h reads only its own contiguous half plane.
 template <typename T, int N, int NT, int MINW, int SIGN, class Pro, class Epi,
-          int SPLIT = 0>
+          int SPLIT = 0, int RO = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
   constexpr int H = N / 2;
@@ -556,8 +556,8 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
     }
   }
   __syncthreads();
-  lds_fft<T, N, H, NT, SIGN, true>(s, LS, 1, tw);          // x: H rows
-  lds_fft<T, H, N, NT, SIGN, true, 2>(s, 1, LS, tw);       // y: N columns
+  lds_fft<T, N, H, NT, SIGN, true, 1, RO>(s, LS, 1, tw);   // x: H rows
+  lds_fft<T, H, N, NT, SIGN, true, 2, RO>(s, 1, LS, tw);   // y: N columns
   auto out = [base, half](int m) {
     if constexpr (SPLIT == 1) return base + half * H * N + m;
     else return base + (2 * (m / N) + half) * N + m % N;
@@ -567,7 +567,8 @@ void k_half(Pro pro, Epi epi, const C<T>* tw_g, int nslots) {
 }
 
 // ---------------------------------------------- x pencils: TY whole rows
-template <typename T, int N, int TY, int NT, int SIGN, class Pro, class Epi>
+template <typename T, int N, int TY, int NT, int SIGN, class Pro, class Epi,
+          int RO = 0>
 __global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
                                                const C<T>* tw_g, int nslots) {
   constexpr int LS = Pad<N>::LS;
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(NT) void k_xlines(Pro pro, Epi epi,
   with_form(pro, epi, [&](const auto& pf, const auto& ef) {
     stage_in<T, TY * N, NT>(s, pf, slot, idx, lds);
     __syncthreads();
-    lds_fft<T, N, TY, NT, SIGN, true>(s, LS, 1, tw);
+    lds_fft<T, N, TY, NT, SIGN, true, 1, RO>(s, LS, 1, tw);
     stage_out<T, TY * N, NT>(s, ef, slot, idx, lds);
   });
 }
@@ -622,7 +623,7 @@ __device__ inline int col_lds(int m) {
 // Grid: one flat dimension of ntiles * nslots workgroups, remapped so that
 // an XCD takes consecutive tiles and all slots of a tile together.
 template <typename T, int N, int AXIS, int TX, int NT, int SIGN, class Pro,
-          class Epi>
+          class Epi, int RO = 0>
 __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
                                              const C<T>* tw_g, int nslots) {
   constexpr int LS = Pad<N>::LS;
@@ -646,7 +647,7 @@ __global__ __launch_bounds__(NT) void k_cols(Pro pro, Epi epi,
   with_form(pro, epi, [&](const auto& pf, const auto& ef) {
     stage_in<T, TX * N, NT>(s, pf, slot, idx, lds);
     __syncthreads();
-    lds_fft<T, N, TX, NT, SIGN, true>(s, LS, 1, tw);
+    lds_fft<T, N, TX, NT, SIGN, true, 1, RO>(s, LS, 1, tw);
     stage_out<T, TX * N, NT>(s, ef, slot, idx, lds);
   });
 }
@@ -685,7 +686,7 @@ __device__ inline double block_sum(double v, double* red) {
 // z transform, so that each half of the inverse xy pass reads only its own
 // half plane (its SPLIT 2 form).
 template <typename T, int N, int TX, int SL, int NT, int MINW, int ORDER = 0,
-          bool DIT = false>
+          bool DIT = false, int RO = 0>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MINW)))
 void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
              const BatchDev* __restrict__ bt, double* epart, int ntiles,
@@ -731,8 +732,8 @@ void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
   // stage (radix RL, no twiddles) reads exactly the RL outputs that a
   // thread holds after the forward's last stage.
   constexpr int NLN = SL * TX;                 // LDS lines
-  constexpr int NST = Plan<N>::nst;
-  constexpr int RL = Plan<N>::r[NST - 1];
+  constexpr int NST = Plan<N, RO>::nst;
+  constexpr int RL = Plan<N, RO>::r[NST - 1];
   constexpr int PL = N / RL;                   // butterflies per line
   constexpr int BF = NLN * PL;
   constexpr int NBF = (BF + NT - 1) / NT;
@@ -788,7 +789,7 @@ void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
     stage_in<T, NE, NT>(s, pro, 0, gidx, lds);
   }
   __syncthreads();
-  StagesRange<T, N, 0, NST - 1, NLN, NT, -1, true, 1>::run(s, LS, 1, tw);
+  StagesRange<T, N, 0, NST - 1, NLN, NT, -1, true, 1, RO>::run(s, LS, 1, tw);
   C<T> x[NBF][RL];
 #pragma unroll
   for (int b = 0; b < NBF; ++b) {
@@ -832,7 +833,7 @@ void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
     }
   }
   __syncthreads();
-  StagesReversed<T, N, NST - 2, NLN, NT, +1, true, 1>::run(s, LS, 1, tw);
+  StagesReversed<T, N, NST - 2, NLN, NT, +1, true, 1, RO>::run(s, LS, 1, tw);
   if constexpr (DIT) {
 #pragma unroll
     for (int q = 0; q < PP; ++q) {
@@ -957,7 +958,8 @@ template <typename T, int N> struct Cfg {
   static constexpr int NT_X = 256;
 };
 
-template <typename T, int N> struct Engine {
+// RO: radix order of every transform the engine launches (Plan<N, RO>).
+template <typename T, int N, int RO = 0> struct Engine {
   using Cf = Cfg<T, N>;
   static constexpr int64_t NG = (int64_t)N * N * N;
 
@@ -965,7 +967,7 @@ template <typename T, int N> struct Engine {
   static hipError_t plane(Pro p, Epi e, int count, const C<T>* tw,
                           hipStream_t st) {
     if constexpr (Cf::plane) {
-      LACE_LAUNCH((k_plane<T, N, Cf::NT_PLANE, SIGN, Pro, Epi>),
+      LACE_LAUNCH((k_plane<T, N, Cf::NT_PLANE, SIGN, Pro, Epi, RO>),
                          dim3(N, count), dim3(Cf::NT_PLANE), 0, st, p, e, tw,
                          count);
       return hipGetLastError();
@@ -981,7 +983,7 @@ template <typename T, int N> struct Engine {
   template <int SIGN, int SPLIT = 0, class Pro, class Epi>
   static hipError_t half(Pro p, Epi e, int count, const C<T>* tw,
                          hipStream_t st) {
-    LACE_LAUNCH((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi, SPLIT>),
+    LACE_LAUNCH((k_half<T, N, NT_HALF, W_HALF, SIGN, Pro, Epi, SPLIT, RO>),
                        dim3(2 * N * count), dim3(NT_HALF), 0, st, p, e, tw,
                        count);
     return hipGetLastError();
@@ -993,21 +995,46 @@ template <typename T, int N> struct Engine {
   // its halves reads only its half plane.
   static constexpr bool XY_DIT = N % 2 == 0 && Cf::TXZ % 2 == 0 &&
                               (Cf::TXZ / 2) % ProGrid<T>::V == 0;
-  template <bool D>
-  static hipError_t zpass(C<T>* tmp, const T* vtab, const BatchDev* bt,
-                          double* epart, int cnt, const C<T>* tw,
-                          hipStream_t st) {
-    const int ntiles = (int)tiles();
-    LACE_LAUNCH((k_zconv<T, N, Cf::TXZ, Cf::SL, Cf::NT_Z, Cf::W_Z, 1, D>),
+  // z tiles: TXZ points of the flattened xy plane per z row by default;
+  // half and twice that are the alternatives the autotuner tries.  Index
+  // z of zt(z): 0 the default, 1 half, 2 twice (0 when not a divisor of
+  // the plane).
+  static constexpr bool zt_ok(int tx) {
+    return tx >= 2 && (N * N) % tx == 0 && Cf::NT_Z % tx == 0 &&
+           (tx / 2) % ProGrid<T>::V == 0;
+  }
+  static constexpr int zt(int z) {
+    const int tx = z == 1 ? Cf::TXZ / 2 : z == 2 ? Cf::TXZ * 2 : Cf::TXZ;
+    return zt_ok(tx) ? tx : Cf::TXZ;
+  }
+  template <bool D, int TX>
+  static hipError_t zpass_tx(C<T>* tmp, const T* vtab, const BatchDev* bt,
+                             double* epart, int cnt, const C<T>* tw,
+                             hipStream_t st) {
+    const int ntiles = N * N / TX;
+    // the wider tile's LDS allows two workgroups per CU: budget registers
+    // for that
+    constexpr int MINW = TX > Cf::TXZ ? 2 : Cf::W_Z;
+    LACE_LAUNCH((k_zconv<T, N, TX, Cf::SL, Cf::NT_Z, MINW, 1, D, RO>),
                        dim3(ntiles * ((cnt + Cf::SL - 1) / Cf::SL)),
                        dim3(Cf::NT_Z), 0, st, tmp, NG, vtab, bt, epart,
                        ntiles, tw);
     return hipGetLastError();
   }
+  template <bool D>
+  static hipError_t zpass(C<T>* tmp, const T* vtab, const BatchDev* bt,
+                          double* epart, int cnt, const C<T>* tw, int ztile,
+                          hipStream_t st) {
+    switch (ztile) {
+      case 1: return zpass_tx<D, zt(1)>(tmp, vtab, bt, epart, cnt, tw, st);
+      case 2: return zpass_tx<D, zt(2)>(tmp, vtab, bt, epart, cnt, tw, st);
+      default: return zpass_tx<D, zt(0)>(tmp, vtab, bt, epart, cnt, tw, st);
+    }
+  }
   template <int SIGN, class Pro, class Epi>
   static hipError_t xlines(Pro p, Epi e, int count, const C<T>* tw,
                            hipStream_t st) {
-    LACE_LAUNCH((k_xlines<T, N, Cf::TY, Cf::NT_X, SIGN, Pro, Epi>),
+    LACE_LAUNCH((k_xlines<T, N, Cf::TY, Cf::NT_X, SIGN, Pro, Epi, RO>),
                        dim3(N * N / Cf::TY, count), dim3(Cf::NT_X), 0, st, p,
                        e, tw, count);
     return hipGetLastError();
@@ -1017,7 +1044,7 @@ template <typename T, int N> struct Engine {
                          hipStream_t st) {
     constexpr int TXC = AXIS == 2 ? Cf::TXC2 : Cf::TX;
     constexpr int ntiles = AXIS == 2 ? N * N / TXC : N * (N / TXC);
-    LACE_LAUNCH((k_cols<T, N, AXIS, TXC, Cf::NT_COLS, SIGN, Pro, Epi>),
+    LACE_LAUNCH((k_cols<T, N, AXIS, TXC, Cf::NT_COLS, SIGN, Pro, Epi, RO>),
                        dim3(ntiles * count), dim3(Cf::NT_COLS), 0, st, p, e,
                        tw, count);
     return hipGetLastError();
@@ -1096,8 +1123,8 @@ template <typename T, int N> struct Engine {
     if (ev && (err = hipEventRecord(ev[1], st)) != hipSuccess) return err;
     // pass B
     const T* vtab = static_cast<const T*>(c.vtab);
-    err = mode == 2 ? zpass<XY_DIT>(tmp, vtab, bt, epart, cap, tw, st)
-                    : zpass<false>(tmp, vtab, bt, epart, cap, tw, st);
+    err = mode == 2 ? zpass<XY_DIT>(tmp, vtab, bt, epart, cap, tw, c.ztile, st)
+                    : zpass<false>(tmp, vtab, bt, epart, cap, tw, c.ztile, st);
     if (err != hipSuccess) return err;
     if (ev && (err = hipEventRecord(ev[2], st)) != hipSuccess) return err;
     if (sy && sy->wait_c && (err = hipStreamWaitEvent(st, sy->wait_c, 0)) != hipSuccess)
@@ -1138,7 +1165,12 @@ template <typename T, int N> struct Engine {
                      bt, cap, tmp, epart, st, ev, sy);
   }
 
-  static int64_t tiles() { return (int64_t)N * N / Cf::TXZ; }
+  // energy partials per slot: enough for the smallest z tile
+  static int64_t tiles() {
+    const int a = zt(0), b = zt(1), c2 = zt(2);
+    const int m = a < b ? (a < c2 ? a : c2) : (b < c2 ? b : c2);
+    return (int64_t)N * N / m;
+  }
 };
 
 // ------------------------------------------------------ runtime dispatch
@@ -1157,6 +1189,38 @@ bool plane_fits(int n, bool fp64) {
   switch (n) {
 #define X(NN) \
   case NN: return fp64 ? Cfg<double, NN>::plane : Cfg<float, NN>::plane;
+    LACE_SIZES(X)
+#undef X
+    default: return false;
+  }
+}
+
+int ztile_points(int n, bool fp64, int z) {
+  switch (n) {
+#define X(NN)                                                         \
+  case NN:                                                            \
+    return fp64 ? (z == 1 ? Engine<double, NN>::zt(1)                 \
+                   : z == 2 ? Engine<double, NN>::zt(2)               \
+                            : Engine<double, NN>::zt(0))              \
+                : (z == 1 ? Engine<float, NN>::zt(1)                  \
+                   : z == 2 ? Engine<float, NN>::zt(2)                \
+                            : Engine<float, NN>::zt(0));
+    LACE_SIZES(X)
+#undef X
+    default: return 0;
+  }
+}
+
+// The radix plan of length n read backwards differs from the plan itself.
+template <int N> static constexpr bool plan_asym() {
+  constexpr int ns = Plan<N, 0>::nst;
+  for (int k = 0; k < ns; ++k)
+    if (Plan<N, 0>::r[k] != Plan<N, 0>::r[ns - 1 - k]) return true;
+  return false;
+}
+bool radix_orders_differ(int n) {
+  switch (n) {
+#define X(NN) case NN: return plan_asym<NN>() || plan_asym<NN / 2>();
     LACE_SIZES(X)
 #undef X
     default: return false;
@@ -1266,9 +1330,14 @@ static hipError_t pair_batch_t(const CellDev& c, const BatchDev* bt, int cap,
   switch (c.n) {
 #define X(NN)                                                               \
   case NN:                                                                  \
-    return Engine<T, NN>::pair_batch(c, bt, cap, static_cast<const C<T>*>(psi), \
-                                     static_cast<C<T>*>(w),                 \
-                                     static_cast<C<T>*>(tmp), epart, st, ev, sy);
+    return c.radix ? Engine<T, NN, 1>::pair_batch(                          \
+                         c, bt, cap, static_cast<const C<T>*>(psi),         \
+                         static_cast<C<T>*>(w), static_cast<C<T>*>(tmp),    \
+                         epart, st, ev, sy)                                 \
+                   : Engine<T, NN, 0>::pair_batch(                          \
+                         c, bt, cap, static_cast<const C<T>*>(psi),         \
+                         static_cast<C<T>*>(w), static_cast<C<T>*>(tmp),    \
+                         epart, st, ev, sy);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;
@@ -1419,9 +1488,14 @@ static hipError_t quad_batch_t(const CellDev& c, const BatchDev* bt, int cap,
   switch (c.n) {
 #define X(NN)                                                                \
   case NN:                                                                   \
-    return Engine<T, NN>::quad_batch(c, bt, cap, static_cast<const T*>(psi), \
-                                     static_cast<T*>(w),                     \
-                                     static_cast<C<T>*>(tmp), epart, st, ev, sy);
+    return c.radix ? Engine<T, NN, 1>::quad_batch(                           \
+                         c, bt, cap, static_cast<const T*>(psi),             \
+                         static_cast<T*>(w), static_cast<C<T>*>(tmp), epart, \
+                         st, ev, sy)                                         \
+                   : Engine<T, NN, 0>::quad_batch(                           \
+                         c, bt, cap, static_cast<const T*>(psi),             \
+                         static_cast<T*>(w), static_cast<C<T>*>(tmp), epart, \
+                         st, ev, sy);
     LACE_SIZES(X)
 #undef X
     default: return hipErrorInvalidValue;

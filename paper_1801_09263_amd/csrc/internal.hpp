@@ -57,6 +57,9 @@ struct CellDev {
   const int32_t* negidx;  // n_pw: position of -m in the Miller list (Gamma)
   int ppb;              // pairs per batch (1..PMAX; complex orbitals 1..SMAX)
   int use_plane;        // 1: fused xy-plane passes where the plane fits LDS
+  int ztile;            // z-pass tile: 0 default, 1 half as wide, 2 twice
+  int radix;            // radix order of the pair passes' transforms: 0, 1
+                        // reversed
 };
 
 bool grid_supported(int n);
@@ -121,6 +124,12 @@ hipError_t launch_gemm_ip_abs_real(bool fp64, const void* A, int64_t lda,
 
 // Number of energy partial slots per pair slot (tiles of the z pass).
 int64_t energy_tiles(int n, bool fp64);
+// z-pass tile width (points of the flattened xy plane per z row) of tile
+// option z (0 default, 1 half, 2 twice) at grid size n.
+int ztile_points(int n, bool fp64, int z);
+// The two radix orders of the pair passes' transforms (lengths n and n/2)
+// differ at grid size n.
+bool radix_orders_differ(int n);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t st);
 // out = factor * sum(part[0..count)), fixed summation order.
 hipError_t launch_reduce_sum(const double* part, int64_t count, double factor,

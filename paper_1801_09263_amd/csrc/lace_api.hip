@@ -352,6 +352,8 @@ int lace_plan_create(const lace_cell_desc* cells, int n_cells,
     cp.dev.n = n; cp.dev.ng = ng; cp.dev.n_pw = d.n_pw;
     cp.dev.L = d.L; cp.dev.rc = rc; cp.dev.omega = d.L * d.L * d.L;
     cp.dev.ppb = std::min(default_pairs_per_batch(n), gamma ? PMAX : SMAX);
+    cp.dev.ztile = 0;
+    cp.dev.radix = 0;
     cp.dev.use_plane = plane_fits(n, fp64) ? 1 : 2;
     // sphere -> grid map
     std::vector<int32_t> gidx(d.n_pw);
@@ -659,6 +661,45 @@ static hipError_t enqueue_schedule(const lace_plan* p, const CellDev& c,
 // previous pass C (they may share W grids), so W is summed in batch order
 // either way.  Profiled calls read the schedule back (they synchronize the
 // stream) and run the batches it holds one launch at a time on `st`.
+// Batches 0 .. nb - 1 of the workspace's table through the pair pipeline.
+// two: on two internal streams (batch b on lane b % 2), a batch's passes A
+// and B overlapping the previous batch's pass C, the C passes in batch
+// order; the caller's stream waits for both lanes at the end.  Else all on
+// the caller's stream.
+static hipError_t enqueue_batches(lace_plan* p, const CellDev& c, int64_t nb,
+                                  int ppb, const Layout& L, void* ws,
+                                  hipStream_t st, bool two) {
+  two = two && nb > 1;
+  hipStream_t lane[2] = {st, st};
+  hipEvent_t cdone[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  if (two) {
+    e = ensure_streams(p, 2);
+    if (e == hipSuccess) {
+      lane[0] = p->streams[0];
+      lane[1] = p->streams[1];
+      cdone[0] = p->events[2];
+      cdone[1] = p->events[3];
+      e = link(p, st, lane[0], 0);
+      if (e == hipSuccess) e = link(p, st, lane[1], 1);
+    }
+  }
+  for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
+    if (two) {
+      BatchSync sy{b > 0 ? cdone[(b - 1) % 2] : nullptr, cdone[b % 2]};
+      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), lane[b % 2], nullptr,
+                        &sy);
+    } else {
+      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), st, nullptr);
+    }
+  }
+  if (e == hipSuccess && two) {
+    e = link(p, lane[0], st, 0);
+    if (e == hipSuccess) e = link(p, lane[1], st, 1);
+  }
+  return e;
+}
+
 static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
                                    const PairSource& src, const Layout& L,
                                    void* ws, void* w_g, double* e_x,
@@ -699,22 +740,9 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (e == hipSuccess && overlap && hipStreamIsCapturing(st, &cap) != hipSuccess)
     cap = hipStreamCaptureStatusNone;
-  const bool two = overlap && !timed && nb > 1 && cap == hipStreamCaptureStatusNone;
-  hipStream_t lane[2] = {st, st};
-  hipEvent_t cdone[2] = {nullptr, nullptr};
-  if (e == hipSuccess && two) {
-    e = ensure_streams(p, 2);
-    if (e == hipSuccess) {
-      lane[0] = p->streams[0];
-      lane[1] = p->streams[1];
-      cdone[0] = p->events[2];
-      cdone[1] = p->events[3];
-      e = link(p, st, lane[0], 0);
-      if (e == hipSuccess) e = link(p, st, lane[1], 1);
-    }
-  }
-  for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
-    if (timed) {
+  const bool two = overlap && !timed && cap == hipStreamCaptureStatusNone;
+  if (e == hipSuccess && timed) {
+    for (int64_t b = 0; e == hipSuccess && b < nb; ++b) {
       const size_t first = pr.used;
       hipEvent_t ev[4];
       for (int k = 0; k < 4; ++k) ev[k] = prof_event(pr);
@@ -725,17 +753,9 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
       batch_bytes(p, c, host_tab[(size_t)b], r.bytes);
       pr.recs.push_back(r);
       e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), st, ev);
-    } else if (two) {
-      BatchSync sy{b > 0 ? cdone[(b - 1) % 2] : nullptr, cdone[b % 2]};
-      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), lane[b % 2], nullptr,
-                        &sy);
-    } else {
-      e = enqueue_batch(p, c, b, ppb, L, ws, (int)(b % 2), st, nullptr);
     }
-  }
-  if (e == hipSuccess && two) {
-    e = link(p, lane[0], st, 0);
-    if (e == hipSuccess) e = link(p, lane[1], st, 1);
+  } else if (e == hipSuccess) {
+    e = enqueue_batches(p, c, nb, ppb, L, ws, st, two);
   }
   if (e == hipSuccess && e_x)
     e = launch_reduce_sum(epart, (int64_t)PMAX * 2 * ntiles,
@@ -1447,60 +1467,82 @@ int lace_read_schedule(const lace_plan* p, int cell, int n_orb, const void* ws,
   return LACE_OK;
 }
 
-int lace_set_tuning(lace_plan* p, int cell, int ppb, int use_plane) {
+int lace_set_tuning(lace_plan* p, int cell, int ppb, int use_plane, int z_tile,
+                    int radix_order) {
   if (!p || cell < 0 || cell >= (int)p->cells.size()) return LACE_EINVAL;
   if (ppb < 1 || ppb > (p->gamma ? PMAX : SMAX) || use_plane < 0 || use_plane > 2)
+    return LACE_EINVAL;
+  if (z_tile < 0 || z_tile > 2 || radix_order < 0 || radix_order > 1)
     return LACE_EINVAL;
   CellDev& c = p->cells[cell].dev;
   if (use_plane == 1 && !plane_fits(c.n, p->fp64)) return LACE_EUNSUPPORTED;
   c.ppb = ppb;
   c.use_plane = use_plane;
+  c.ztile = z_tile;
+  c.radix = radix_order;
   return LACE_OK;
 }
 
-int lace_get_tuning(const lace_plan* p, int cell, int* ppb, int* use_plane) {
+int lace_get_tuning(const lace_plan* p, int cell, int* ppb, int* use_plane,
+                    int* z_tile, int* radix_order) {
   if (!p || cell < 0 || cell >= (int)p->cells.size()) return LACE_EINVAL;
-  if (ppb) *ppb = p->cells[cell].dev.ppb;
-  if (use_plane) *use_plane = p->cells[cell].dev.use_plane;
+  const CellDev& c = p->cells[cell].dev;
+  if (ppb) *ppb = c.ppb;
+  if (use_plane) *use_plane = c.use_plane;
+  if (z_tile) *z_tile = c.ztile;
+  if (radix_order) *radix_order = c.radix;
   return LACE_OK;
 }
 
 int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
-                  void* ws, size_t ws_bytes, lace_stream_t stream,
-                  int* cand_ppb, int* cand_plane, double* cand_us, int* n_cand) {
+                  double s_thr, void* ws, size_t ws_bytes, lace_stream_t stream,
+                  int* cand_ppb, int* cand_plane, int* cand_ztile,
+                  int* cand_radix, double* cand_us, int* n_cand) {
   int rc = check_common(p, cell, n_orb);
   if (rc) return rc;
   if (n_orb > kMaxExchangeOrbitals) return LACE_EINVAL;
-  if (!psi_g || !ws) return LACE_EINVAL;
+  if (!psi_g || !ws || !(s_thr >= 0.0 && s_thr < 1.0)) return LACE_EINVAL;
   const Layout L = layout_for(p, cell, n_orb, 0);
   if (ws_bytes < L.total) return LACE_ENOMEM;
   CellDev& c = p->cells[cell].dev;
   const bool fp64 = p->fp64;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = enqueue_orbitals(p, c, psi_g, n_orb, L, ws, st);
-  if (e != hipSuccess) return LACE_EHIP;
-  // every candidate schedules all pairs its own way and is timed on its
-  // first batches holding at least 4 * PMAX pairs: steady-state batches of
-  // that candidate's own schedule
+  // the pairs the exchange will run: those S keeps at s_thr (Eq. (6))
   PairSource all;
   all.n_occ = n_orb;
   all.s_n = n_orb;
-  struct Cand { int ppb, plane; double us; };
+  if (e == hipSuccess && s_thr > 0.0) {
+    double* s = reinterpret_cast<double*>(at(ws, L.s));
+    e = enqueue_screen(p, c, n_orb, L, ws, s, st);
+    all.s = s;
+    all.s_thr = s_thr;
+  }
+  if (e != hipSuccess) return LACE_EHIP;
+  // every candidate schedules the pairs its own way and is timed on two
+  // lanes as the exchange runs them
+  struct Cand { int ppb, plane, ztile, radix; double us; bool full; };
   std::vector<Cand> cands;
-  // pairs per batch: up to SMAX slots of one pair (complex) or two (real)
+  // stage 1: pairs per batch (up to SMAX slots of one pair, complex, or
+  // two, real) and the xy schedule, each timed on its first batches
   const int ppbs[5] = {8, 16, 32, 64, 128};
   const int nppb = p->gamma ? 5 : 4;
   for (int plane = 2; plane >= 0; --plane) {
     if (plane == 1 && !plane_fits(c.n, fp64)) continue;
-    for (int k = 0; k < nppb; ++k) cands.push_back({ppbs[k], plane, 0.0});
+    for (int k = 0; k < nppb; ++k) cands.push_back({ppbs[k], plane, 0, 0, 0.0, false});
   }
-  const int save_ppb = c.ppb, save_plane = c.use_plane;
+  const CellDev save = c;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
     return LACE_EHIP;
-  for (auto& cd : cands) {
+  // us per pair of a candidate: its first batches holding at least 16 *
+  // PMAX pairs, or (full) its whole schedule; on two lanes as the exchange
+  // runs them; the best of the repetitions after the first
+  auto time_cand = [&](Cand& cd, bool full) {
     c.ppb = cd.ppb;
     c.use_plane = cd.plane;
+    c.ztile = cd.ztile;
+    c.radix = cd.radix;
     if (e == hipSuccess) e = enqueue_schedule(p, c, n_orb, cd.ppb, all, L, ws, nullptr, st);
     Status h{};
     if (e == hipSuccess)
@@ -1513,38 +1555,75 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     int64_t timed_pairs = 0;
     size_t nb = 0;
-    while (nb < tab.size() && timed_pairs < 4 * PMAX) timed_pairs += tab[nb++].npairs;
+    while (nb < tab.size() && (full || timed_pairs < 16 * PMAX))
+      timed_pairs += tab[nb++].npairs;
+    // the whole schedule as the exchange launches it: up to the bound,
+    // the batches past the schedule's end included
+    if (full) nb = (size_t)batch_bound(n_orb, cd.ppb, p->gamma, false);
     double best = 1e30;
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       e = hipEventRecord(t0, st);
-      for (size_t b = 0; e == hipSuccess && b < nb; ++b)
-        e = enqueue_batch(p, c, (int64_t)b, cd.ppb, L, ws, (int)(b % 2), st,
-                          nullptr);
+      if (e == hipSuccess) e = enqueue_batches(p, c, (int64_t)nb, cd.ppb, L, ws, st, true);
       if (e == hipSuccess) e = hipEventRecord(t1, st);
       if (e == hipSuccess) e = hipEventSynchronize(t1);
       float ms = 0.f;
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (rep > 0 && ms < best) best = ms;   // first repetition warms up
     }
-    cd.us = timed_pairs > 0 ? 1e3 * best / double(timed_pairs) : 1e30;
+    const double us = timed_pairs > 0 ? 1e3 * best / double(timed_pairs) : 1e30;
+    // the whole-schedule time is the best over the rounds it is taken in
+    cd.us = full && cd.full ? std::min(cd.us, us) : us;
+    cd.full = full;
+  };
+  for (auto& cd : cands) time_cand(cd, false);
+  // the three fastest of stage 1 again over their whole schedules (the
+  // first batches, stars of whole cycles, pack differently from the rest)
+  std::vector<size_t> order(cands.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::sort(order.begin(), order.end(),
+            [&](size_t x, size_t y) { return cands[x].us < cands[y].us; });
+  // (in two interleaved rounds, so that a drift of the clock over the
+  // tuning does not favour one of them)
+  for (int round = 0; round < 2; ++round)
+    for (size_t k = 0; k < order.size() && k < 3; ++k) time_cand(cands[order[k]], true);
+  auto best_full = [&]() {
+    size_t bi = cands.size();
+    for (size_t k = 0; k < cands.size(); ++k)
+      if (cands[k].full && (bi == cands.size() || cands[k].us < cands[bi].us)) bi = k;
+    return bi;
+  };
+  // stage 2, for the fastest so far: the z tiles half and twice as wide
+  // (where the plane allows them) and the reversed radix order, each over
+  // the whole schedule
+  const size_t stage1 = cands.size();
+  if (e == hipSuccess) {
+    const Cand b = cands[best_full()];
+    const int def = ztile_points(c.n, fp64, 0);
+    for (int z = 1; z <= 2; ++z)
+      if (ztile_points(c.n, fp64, z) != def)
+        cands.push_back({b.ppb, b.plane, z, 0, 0.0, false});
+    if (radix_orders_differ(c.n)) cands.push_back({b.ppb, b.plane, 0, 1, 0.0, false});
   }
+  for (int round = 0; round < 2; ++round)
+    for (size_t k = stage1; k < cands.size(); ++k) time_cand(cands[k], true);
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (e != hipSuccess) {
-    c.ppb = save_ppb;
-    c.use_plane = save_plane;
+    c = save;
     return LACE_EHIP;
   }
-  size_t bi = 0;
-  for (size_t k = 1; k < cands.size(); ++k)
-    if (cands[k].us < cands[bi].us) bi = k;
-  c.ppb = cands[bi].ppb;
-  c.use_plane = cands[bi].plane;
+  const Cand& win = cands[best_full()];
+  c.ppb = win.ppb;
+  c.use_plane = win.plane;
+  c.ztile = win.ztile;
+  c.radix = win.radix;
   if (n_cand) {
     const int cap = *n_cand;
     for (int k = 0; k < (int)cands.size() && k < cap; ++k) {
       if (cand_ppb) cand_ppb[k] = cands[k].ppb;
       if (cand_plane) cand_plane[k] = cands[k].plane;
+      if (cand_ztile) cand_ztile[k] = cands[k].ztile;
+      if (cand_radix) cand_radix[k] = cands[k].radix;
       if (cand_us) cand_us[k] = cands[k].us;
     }
     *n_cand = (int)cands.size();

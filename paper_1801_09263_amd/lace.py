@@ -124,12 +124,11 @@ def load(path: str = LIB_PATH):
                                        p_i32, p_i32, p_i64]
     lib.lace_apply_exchange_batched.argtypes = [vp, ctypes.POINTER(LaceJob),
                                                 i32, i32, vp]
-    lib.lace_set_tuning.argtypes = [vp, i32, i32, i32]
-    lib.lace_get_tuning.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int),
-                                    ctypes.POINTER(ctypes.c_int)]
-    lib.lace_autotune.argtypes = [vp, i32, vp, i32, vp, sz, vp,
-                                  ctypes.POINTER(ctypes.c_int),
-                                  ctypes.POINTER(ctypes.c_int),
+    lib.lace_set_tuning.argtypes = [vp, i32, i32, i32, i32, i32]
+    p_int = ctypes.POINTER(ctypes.c_int)
+    lib.lace_get_tuning.argtypes = [vp, i32, p_int, p_int, p_int, p_int]
+    lib.lace_autotune.argtypes = [vp, i32, vp, i32, dbl, vp, sz, vp,
+                                  p_int, p_int, p_int, p_int,
                                   ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int)]
     lib.lace_status_string.argtypes = [i32]
@@ -610,33 +609,36 @@ def lace_apply_exchange_batched(plan, jobs, graph=False, stream=None):
     return [int(t.item()) for t in counts]
 
 
-def lace_set_tuning(plan, cell, pairs_per_batch, use_plane):
+def lace_set_tuning(plan, cell, pairs_per_batch, use_plane, z_tile=0,
+                    radix_order=0):
     _check(load().lace_set_tuning(plan.handle, cell, int(pairs_per_batch),
-                                  int(use_plane)), "lace_set_tuning")
+                                  int(use_plane), int(z_tile),
+                                  int(radix_order)), "lace_set_tuning")
 
 
 def lace_get_tuning(plan, cell):
-    ppb = ctypes.c_int()
-    pl = ctypes.c_int()
-    _check(load().lace_get_tuning(plan.handle, cell, ctypes.byref(ppb),
-                                  ctypes.byref(pl)), "lace_get_tuning")
-    return ppb.value, pl.value
+    """(pairs_per_batch, use_plane, z_tile, radix_order) of the cell."""
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(load().lace_get_tuning(plan.handle, cell, *[ctypes.byref(x) for x in v]),
+           "lace_get_tuning")
+    return tuple(x.value for x in v)
 
 
-def lace_autotune(plan, cell, psi_g, n_orb, ws, stream=None):
-    """Time every pipeline candidate on this cell, keep the fastest.
-    Returns a list of (pairs_per_batch, use_plane, us_per_pair)."""
+def lace_autotune(plan, cell, psi_g, n_orb, ws, stream=None, s_thr=0.0):
+    """Time the pipeline candidates on this cell for the pairs S keeps at
+    s_thr, keep the fastest.  Returns a list of (pairs_per_batch,
+    use_plane, z_tile, radix_order, us_per_pair)."""
     import torch
     _need(psi_g, n_orb * _n_pw(plan, cell), "psi_g")
-    cap = 16
-    ppb = (ctypes.c_int * cap)()
-    pl = (ctypes.c_int * cap)()
+    cap = 64
+    cols = [(ctypes.c_int * cap)() for _ in range(4)]
     us = (ctypes.c_double * cap)()
     n = ctypes.c_int(cap)
     _check(load().lace_autotune(plan.handle, cell,
                                 _ptr(psi_g, torch.complex128, "psi_g"), n_orb,
-                                _ptr(ws, None, "ws"),
+                                float(s_thr), _ptr(ws, None, "ws"),
                                 ws.numel() * ws.element_size(),
-                                _stream(stream), ppb, pl, us,
+                                _stream(stream), *cols, us,
                                 ctypes.byref(n)), "lace_autotune")
-    return [(ppb[k], pl[k], us[k]) for k in range(min(n.value, cap))]
+    return [(cols[0][k], cols[1][k], cols[2][k], cols[3][k], us[k])
+            for k in range(min(n.value, cap))]

@@ -111,7 +111,8 @@ static void worker(int t, int reps) {
         CHECK(lace_check_real(plan, c, psi, n, ws, wsb, nullptr, &dev_real));
       int ppb[16], pl[16], nc = 16;
       double us[16];
-      CHECK(lace_autotune(plan, c, psi, n, ws, wsb, nullptr, ppb, pl, us, &nc));
+      int zt[16], ro[16];
+      CHECK(lace_autotune(plan, c, psi, n, 0.1, ws, wsb, nullptr, ppb, pl, zt, ro, us, &nc));
       CHECK(lace_profile_enable(plan, 1));
       CHECK(lace_apply_exchange(plan, c, psi, n, 0.05, nullptr, nullptr, 0, w,
                                 e, kept, nullptr, ws, wsb, nullptr));

@@ -192,6 +192,12 @@ hipError_t launch_polar_norm(int, const void* B, int n, double* out, hipStream_t
   return hipSuccess;
 }
 int64_t sched_scratch_bytes(int n_orb) { return 4096 + 64 * (int64_t)n_orb * n_orb; }
+int ztile_points(int n, bool fp64, int z) {
+  const int def = fp64 ? 16 : 32;
+  const int tx = z == 1 ? def / 2 : z == 2 ? def * 2 : def;
+  return (n * n) % tx == 0 ? tx : def;
+}
+bool radix_orders_differ(int n) { return n != 8 && n != 12 && n != 16 && n != 64; }
 int sched_sections(int n_orb) {
   const int64_t s = (int64_t)n_orb * n_orb / 4096;
   return s < 1 ? 1 : s > 16 ? 16 : (int)s;

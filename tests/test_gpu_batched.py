@@ -152,19 +152,25 @@ def test_autotune_picks_a_candidate_and_stays_correct():
     mc.set_orbitals(0, coeffs)
     cands = mc.autotune(0)
     say("  candidates", cands)
-    assert len(cands) == 12     # 4 batch sizes x 3 xy schedules
-    assert all(t > 0 for _, _, t in cands)
-    ppb, plane = lace.lace_get_tuning(mc.plan, 0)
-    best = min(cands, key=lambda c: c[2])
-    assert (ppb, plane) == (best[0], best[1])
+    stage1 = [c for c in cands if c[2] == 0 and c[3] == 0]
+    stage2 = cands[len(stage1):]
+    assert cands[:len(stage1)] == stage1
+    assert len(stage1) == 12     # 4 batch sizes x 3 xy schedules
+    assert all(c[4] > 0 for c in cands)
+    # stage 2 varies the z tile and the radix order of stage 1's best
+    b1 = min(stage1, key=lambda c: c[4])
+    assert stage2 and all((c[0], c[1]) == (b1[0], b1[1]) for c in stage2)
+    assert {(c[2], c[3]) for c in stage2} <= {(1, 0), (2, 0), (0, 1)}
+    best = min(cands, key=lambda c: c[4])
+    assert lace.lace_get_tuning(mc.plan, 0) == best[:4]
     mc.run()
     torch.cuda.synchronize()
     res = O.run_path(coeffs, m, L, n)
     assert rel(mc.jobs[0]["w_g"].cpu().numpy(), res["W_pw"]) <= 1e-5
     # every candidate schedule gives the same W to FP32 rounding
     w0 = mc.jobs[0]["w_g"].clone()
-    for ppb_c, plane_c, _ in cands:
-        lace.lace_set_tuning(mc.plan, 0, ppb_c, plane_c)
+    for ppb_c, plane_c, z_c, r_c, _ in cands:
+        lace.lace_set_tuning(mc.plan, 0, ppb_c, plane_c, z_c, r_c)
         mc.run()
         torch.cuda.synchronize()
         assert rel(mc.jobs[0]["w_g"].cpu().numpy(), w0.cpu().numpy()) <= 2e-6
@@ -174,9 +180,11 @@ def test_autotune_picks_a_candidate_and_stays_correct():
 def test_tuning_rejects_bad_values():
     cell = dict(L=10.0, n=24, miller=synth.miller_sphere(10.0, 15.0))
     plan = lace.lace_plan_create([cell], FP32)
-    for ppb, pl in ((0, 1), (65, 1), (8, 3), (8, -1)):
+    for ppb, pl, zt, ro in ((0, 1, 0, 0), (65, 1, 0, 0), (8, 3, 0, 0),
+                            (8, -1, 0, 0), (8, 2, 3, 0), (8, 2, -1, 0),
+                            (8, 2, 0, 2)):
         with pytest.raises(lace.LaceError):
-            lace.lace_set_tuning(plan, 0, ppb, pl)
+            lace.lace_set_tuning(plan, 0, ppb, pl, zt, ro)
     plan.close()
 
 

@@ -46,7 +46,7 @@ def brute_dft3(a, sign):
 def set_schedule(plan, mode):
     """Select an xy schedule (0 pencils, 1 whole plane, 2 half planes) on
     cell 0; False where the whole plane does not fit LDS."""
-    ppb, _ = lace.lace_get_tuning(plan, 0)
+    ppb = lace.lace_get_tuning(plan, 0)[0]
     try:
         lace.lace_set_tuning(plan, 0, ppb, mode)
     except lace.LaceError:
@@ -483,6 +483,38 @@ def test_pair_pipeline_every_grid_size(n, prec, sched):
     s = CellSession(dict(L=L, n=n, miller=miller), coeffs.shape[0], prec)
     if sched == "half":
         assert set_schedule(s.plan, 2)
+    s.set_orbitals(coeffs)
+    s.apply_exchange(0.0)
+    torch.cuda.synchronize()
+    assert rel(s.w.cpu().numpy(), res["W_pw"]) <= tol["w"]
+    assert abs(s.e_x.item() - res["ex_pairs"]) <= tol["ex"] * abs(
+        res["ex_pairs"])
+    s.close()
+
+
+@pytest.mark.parametrize("variant", [(1, 0), (2, 0), (0, 1), (2, 1)],
+                         ids=["ztile-half", "ztile-twice", "radix-rev",
+                              "ztile-twice-radix-rev"])
+@pytest.mark.parametrize("sched", [0, 1, 2], ids=["pencil", "plane", "half"])
+@pytest.mark.parametrize("prec", [FP32G, FP64], ids=["fp32g", "fp64"])
+@pytest.mark.parametrize("n", [12, 24, 48, 96, 120])
+def test_pair_pipeline_tuning_variants(n, prec, sched, variant):
+    """The autotuner's other instantiations against the oracle: the z pass
+    with tiles half and twice as wide (where the plane divides into them)
+    and every transform with its radices in reverse order (60 = 15 x 4,
+    120 = 15 x 8, ...), under each xy schedule."""
+    zt, ro = variant
+    L, miller, coeffs, res = _every_size_case(n)
+    say(f"tuning variant n={n} prec={prec} sched={sched} z_tile={zt} radix={ro}")
+    tol = TOL[prec]
+    s = CellSession(dict(L=L, n=n, miller=miller), coeffs.shape[0], prec)
+    ppb = lace.lace_get_tuning(s.plan, 0)[0]
+    try:
+        lace.lace_set_tuning(s.plan, 0, ppb, sched, zt, ro)
+    except lace.LaceError:
+        assert sched == 1    # the whole plane does not fit LDS
+        s.close()
+        return
     s.set_orbitals(coeffs)
     s.apply_exchange(0.0)
     torch.cuda.synchronize()
