@@ -52,13 +52,28 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# Algorithmic bytes of each pass come from the library (lace_profile_read):
-# per transform slot with o distinct orbitals, pass A moves o G + U (read the
-# orbitals, write the pair buffer), pass B 2 U, pass C U + 3 o G (read the
-# buffer and the orbitals, read and write their W); U = one complex grid,
-# G = one orbital grid (U, or U / 2 for real orbitals).
+# Two byte counts per pass.
+# Algorithmic (per pair, the minimal fused three-pass schedule taking each
+# pair alone): in units of one orbital grid s N_g (s = 4 B for the real
+# grids of real-orbital FP32 plans, 8 B complex FP32, 16 B complex FP64), an
+# off-diagonal pair moves 3 in pass A (read psi_i, psi_j, write its pair
+# density), 2 in pass B (read and write it), 7 in pass C (read it, re-read
+# psi_i and psi_j, read and write W_i and W_j): 12 per pair; a diagonal pair
+# 2, 2 and 4.
+# Moved (from the library, lace_profile_read): per transform slot with o
+# distinct orbitals, pass A moves o G + U (read the orbitals, write the pair
+# buffer), pass B 2 U, pass C U + 3 o G (read the buffer and the orbitals,
+# read and write their W); U = one complex grid, G = one orbital grid (U, or
+# U / 2 for real orbitals).  A star slot's two pairs share an orbital, so the
+# kernels move fewer bytes than the per-pair count.
 PASS_NAMES = ("pair-product+xy-forward", "z-forward*v*z-backward",
               "xy-backward+accumulate")
+PAIR_GRIDS = ((3, 2), (2, 2), (7, 4))   # (off-diagonal, diagonal) per pass
+
+
+def pass_alg_bytes(k, n_off, n_diag, s, ng):
+    off, dia = PAIR_GRIDS[k]
+    return (off * n_off + dia * n_diag) * s * ng
 
 
 def pass_roofline(prof):
@@ -370,14 +385,13 @@ def synth_rate(rate):
 
 
 def pmc_sample(torch, seed):
-    """Fixed small workload for counter collection: a plain 1 GiB device
-    copy (the calibration of FETCH_SIZE / WRITE_SIZE), then one exchange
-    application over 512 off-diagonal pairs of the localized 120^3
-    workload in the real-orbital mode: four rounds of a round-robin
-    tournament over the 256 orbitals, packed into star slots, 8 full
-    batches of the pair pipeline.  Prints the library's algorithmic bytes
-    per pass for the comparison with the counters."""
-    import numpy as np
+    """Fixed run for hardware-counter passes: a plain 1 GiB device copy
+    (the calibration of FETCH_SIZE / WRITE_SIZE), then one screened
+    exchange application of the localized 120^3 workload in the
+    real-orbital mode (64 pairs per batch, half-plane xy passes) with the
+    pass profiler on, so that only the schedule's batches are launched, one
+    at a time.  Prints the launches, kept pairs and the library's moved
+    bytes per pass for the comparison with the counters."""
     import synth
     from paper_1801_09263_amd import lace
     from paper_1801_09263_amd.session import CellSession
@@ -391,16 +405,74 @@ def pmc_sample(torch, seed):
     sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA)
     sess.set_orbitals(inp["coeffs"])
     lace.lace_set_tuning(sess.plan, 0, 64, 2)
-    m = n_orb - 1                       # n_orb even: rounds of n_orb / 2 pairs
-    pairs = [(i, j) for j in range(n_orb) for i in range(j)
-             if (i if j == m else ((i + j) * (n_orb // 2)) % m) < 4]
     lace.lace_profile_enable(sess.plan, True)
-    sess.apply_exchange(0.0, pairs=np.array(pairs))
+    sess.apply_exchange(inp["s_thr"])
     torch.cuda.synchronize()
     prof = lace.lace_profile_read(sess.plan)
-    print(json.dumps({"pmc_sample": "ok", "pairs": len(pairs),
+    print(json.dumps({"pmc_sample": "ok", "n_kept": sess.n_kept,
+                      "n_orb": n_orb, "n": int(inp["n"]),
                       "launches": prof["launches"],
                       "alg_bytes": prof["alg_bytes"]}), flush=True)
+
+
+PASS_MATCH = ("ProQuad", "k_zconv", "EpiAccQuad")   # pass A, B, C kernels
+
+
+def counter_sums(db_path):
+    """Per kernel name: dispatches and the sum of the counter's value over
+    them (rocprofv3 SQLite output of one --pmc pass)."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select kernel_name, dispatch_id, sum(value) from "
+                      "counters_collection group by dispatch_id").fetchall()
+    db.close()
+    return rows
+
+
+def write_traffic(fetch_db, write_db, sample_log, out_path):
+    """profiles/traffic.json from the FETCH_SIZE and WRITE_SIZE passes of
+    --pmc-sample: each counter is scaled by what it reads for the 1 GiB
+    device copy (the largest copy dispatch of the run), summed over every
+    dispatch of each pass kernel and divided by the launches."""
+    with open(sample_log) as fh:
+        sample = [json.loads(ln) for ln in fh if ln.startswith('{"pmc_sample"')][-1]
+    copy_bytes = float(1 << 30)
+    res = {"kernel_source_hash": kernel_source_hash()}
+    per = {}
+    for tag, path in (("fetch", fetch_db), ("write", write_db)):
+        rows = counter_sums(path)
+        copy_kib = max(v for name, _, v in rows if "copyBuffer" in name)
+        scale = copy_bytes / (copy_kib * 1024.0)
+        res[tag + "_scale"] = scale
+        res["copy_" + tag + "_kib"] = copy_kib
+        for k, key in enumerate(PASS_MATCH):
+            sel = [(name, v) for name, _, v in rows if key in name]
+            d = per.setdefault(str(k), {})
+            d["kernel"] = re.sub(r"\s+", " ", sel[0][0]).split("(")[0]
+            d["launches"] = len(sel)
+            d[tag + "_kib"] = sum(v for _, v in sel) / len(sel)
+            d[tag + "_bytes"] = d[tag + "_kib"] * 1024.0 * scale
+    res["copy_kernel"] = "__amd_rocclr_copyBuffer"
+    res["copy_bytes"] = copy_bytes
+    n_orb, n_kept, n = sample["n_orb"], sample["n_kept"], sample["n"]
+    for k in range(3):
+        d = per[str(k)]
+        launches = sample["launches"][k]
+        assert d["launches"] == launches, (k, d["launches"], launches)
+        d["bytes_per_launch"] = d["fetch_bytes"] + d["write_bytes"]
+        d["moved_bytes_per_launch"] = sample["alg_bytes"][k] / launches
+        d["alg_bytes_per_launch"] = pass_alg_bytes(
+            k, n_kept - n_orb, n_orb, 4, n ** 3) / launches
+        d["ratio"] = d["bytes_per_launch"] / d["moved_bytes_per_launch"]
+        d["ratio_alg"] = d["bytes_per_launch"] / d["alg_bytes_per_launch"]
+    res["passes"] = per
+    res["sample"] = ("one screened exchange of the localized %d^3 workload, "
+                     "%d kept pairs of %d orbitals, 64 pairs per batch, "
+                     "half-plane xy passes, launches one at a time"
+                     % (n, n_kept, n_orb))
+    with open(out_path, "w") as fh:
+        json.dump(res, fh, indent=1)
+    return res
 
 
 def main():
@@ -429,10 +501,20 @@ def main():
                          "order 0 / 1) instead of autotuning the main "
                          "workload")
     ap.add_argument("--pmc-sample", action="store_true",
-                    help="small fixed run for hardware-counter passes: a "
-                         "1 GiB copy (calibration) and 8 batches of star "
-                         "slots of the localized workload")
+                    help="fixed run for hardware-counter passes: a 1 GiB "
+                         "copy (calibration) and one profiled screened "
+                         "exchange of the localized workload")
+    ap.add_argument("--write-traffic", nargs=3,
+                    metavar=("FETCH_DB", "WRITE_DB", "SAMPLE_LOG"),
+                    help="no GPU work: write profiles/traffic.json from the "
+                         "rocprofv3 databases of the FETCH_SIZE and "
+                         "WRITE_SIZE passes of --pmc-sample and its output")
     args = ap.parse_args()
+    if args.write_traffic:
+        res = write_traffic(*args.write_traffic,
+                            os.path.join(ROOT, "profiles", "traffic.json"))
+        print(json.dumps(res["passes"], indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is described, not built", file=sys.stderr)
@@ -501,6 +583,13 @@ def main():
     # roofline of the dominant kernel of the pair pipeline
     rows = pass_roofline(prof)
     dom = max(range(3), key=lambda k: rows[k]["ms_total"])
+    # algorithmic bytes: every diagonal pair is kept (S_ii = 1 > S_thr)
+    n_diag = n_orb
+    n_off = n_kept - n_diag
+    s_bytes, ng = 4, int(inp["n"]) ** 3     # real FP32 grids
+    launches_per_step = rows[dom]["launches"] / args.steps
+    alg_launch = pass_alg_bytes(dom, n_off, n_diag, s_bytes, ng) / launches_per_step
+    achieved = alg_launch / (rows[dom]["avg_launch_us"] * 1e-6) / 1e9
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tpath):
@@ -508,24 +597,33 @@ def main():
             tr = json.load(fh)
         ps = tr.get("passes", {}).get(str(dom))
         if tr.get("kernel_source_hash") == kernel_source_hash() and ps:
-            # counter-measured bytes / algorithmic bytes of this kernel in the
-            # counter sample, applied to this run's mean launch
+            # counter-measured bytes / the library's moved bytes of this
+            # kernel in the counter sample, applied to this run's mean launch
             traffic = round(ps["ratio"] * rows[dom]["bytes_per_launch"], 0)
     pipe_ms = sum(prof["ms"])
     pipe_bytes = sum(prof["alg_bytes"])
     roofline = dict(
         bound="hbm", kernel=rows[dom]["name"],
-        achieved=round(rows[dom]["achieved_GBs"], 1), peak=HBM_PEAK_GBS,
-        unit="GB/s", frac=round(rows[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
+        achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+        unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
         traffic=traffic,
         avg_launch_us=round(rows[dom]["avg_launch_us"], 2),
-        bytes_per_launch=rows[dom]["bytes_per_launch"],
+        bytes_per_launch=round(alg_launch, 0),
+        bytes_model=("per kept pair, in orbital grids of s N_g (s = 4 B real "
+                     "FP32 grids, N_g = %d): pass A 3 (diagonal 2), pass B 2 "
+                     "(2), pass C 7 (4); %d off-diagonal and %d diagonal "
+                     "pairs over %.0f launches per step" %
+                     (ng, n_off, n_diag, launches_per_step)),
+        moved_bytes_per_launch=round(rows[dom]["bytes_per_launch"], 0),
+        moved_GBs=round(rows[dom]["achieved_GBs"], 1),
+        moved_frac=round(rows[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
         passes=[{k: (round(v, 3) if isinstance(v, float) else v)
                  for k, v in r.items()} for r in rows],
         durations=("HIP events around each launch on the library's stream, "
                    "in a profiled repeat of the timed steps that runs the "
-                   "launches one at a time; the timed steps overlap "
-                   "consecutive batches on two streams"),
+                   "launches one at a time (the batches of the schedule only); "
+                   "the timed steps overlap consecutive batches on two "
+                   "streams"),
         exchange_GBs_overlapped=round(pipe_bytes / args.steps / t_exch / 1e9, 1),
         pipeline_GBs=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9, 1),
         pipeline_frac=round(pipe_bytes / (pipe_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
