@@ -375,7 +375,10 @@ int lace_get_info(const void* ws, lace_stream_t stream, int32_t* info_host);
  * round-robin tournament over the orbitals (every round a set of disjoint
  * pairs); the list is cut into sections of whole rounds, each section is
  * placed first-fit into a window of eight open batches, and the pairs of
- * the batches that did not fill are placed first-fit once more. */
+ * the batches that did not fill are placed first-fit once more.  Should
+ * that take more batches than the round robin does (one batch per round,
+ * or several of per_batch pairs, and the diagonal pairs), the round-robin
+ * batches are used instead. */
 int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int64_t* n_batches);
@@ -392,9 +395,12 @@ int lace_schedule_pairs(const int32_t* pair_i, const int32_t* pair_j,
  * Eqs. (2) and (8)).  Stars come from the cycle that two consecutive rounds
  * of the round robin form, then from left-over pairs meeting at an orbital.
  * The slots are packed like the pairs of lace_schedule_pairs (sections of
- * whole cycles, then the unfilled batches once more).  No orbital appears
- * in two slots of one batch; a batch holds at most per_batch pairs
- * (1..128) and (per_batch + 1) / 2 slots. */
+ * whole cycles, then the unfilled batches once more); the round-robin
+ * batches (two pairs of one round per slot, no stars) replace them only
+ * when they would number more than the round robin's count b plus
+ * max(4, b / 64), since star slots move fewer bytes than a few extra
+ * batches cost.  No orbital appears in two slots of one batch; a batch
+ * holds at most per_batch pairs (1..128) and (per_batch + 1) / 2 slots. */
 int lace_schedule_slots(const int32_t* pair_i, const int32_t* pair_j,
                         int64_t n_pairs, int n_orb, int per_batch,
                         int32_t* batch_of, int32_t* slot_of,

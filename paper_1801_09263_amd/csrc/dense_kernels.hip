@@ -332,23 +332,50 @@ __global__ __launch_bounds__(256) void k_gemm_ip_f32(const void* A, int64_t lda,
       }
 }
 
-// out[e] = scale * sum_z part[z][e], fixed order over z.  sym_nb > 0: a
-// real sym_nb x sym_nb result of which only the tiles on and above the
-// diagonal were computed; an element below reads its mirror.
-__global__ void k_splitk_reduce(const double* part, int64_t nel, int nsplit,
-                                double scale, double* out, int sym_nb) {
-  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nel;
-       e += stride) {
-    int64_t src = e;
-    if (sym_nb > 0) {
-      const int64_t a = e / sym_nb, b = e % sym_nb;
-      if (a / IP_T > b / IP_T) src = b * sym_nb + a;
-    }
+// out[e] = scale * sum_z part[z][e].  A workgroup takes 16 elements at a
+// time; lane group g (of 16) sums z = g, g + 16, ... in increasing order,
+// then the 16 group sums are added in group order: one fixed order for any
+// grid, so results repeat bitwise.  sym_nb > 0: a real sym_nb x sym_nb
+// result of which only the tiles on and above the diagonal were computed;
+// an element below reads its mirror.
+constexpr int RED_E = 16, RED_G = 16;
+__global__ __launch_bounds__(RED_E * RED_G) void k_splitk_reduce(
+    const double* part, int64_t nel, int nsplit, double scale, double* out,
+    int sym_nb) {
+  __shared__ double red[RED_G][RED_E + 1];
+  const int el = threadIdx.x % RED_E, g = threadIdx.x / RED_E;
+  for (int64_t e0 = (int64_t)blockIdx.x * RED_E; e0 < nel;
+       e0 += (int64_t)gridDim.x * RED_E) {
+    const int64_t e = e0 + el;
     double t = 0.0;
-    for (int z = 0; z < nsplit; ++z) t += part[(int64_t)z * nel + src];
-    out[e] = scale * t;
+    if (e < nel) {
+      int64_t src = e;
+      if (sym_nb > 0) {
+        const int64_t a = e / sym_nb, b = e % sym_nb;
+        if (a / IP_T > b / IP_T) src = b * sym_nb + a;
+      }
+      for (int z = g; z < nsplit; z += RED_G) t += part[(int64_t)z * nel + src];
+    }
+    red[g][el] = t;
+    __syncthreads();
+    if (g == 0 && e < nel) {
+      double u = 0.0;
+      for (int q = 0; q < RED_G; ++q) u += red[q][el];
+      out[e] = scale * u;
+    }
+    __syncthreads();
   }
+}
+
+static hipError_t launch_splitk_reduce(const double* part, int64_t nel,
+                                       int nsplit, double scale, double* out,
+                                       int sym_nb, hipStream_t st) {
+  int64_t blocks = (nel + RED_E - 1) / RED_E;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  LACE_LAUNCH(k_splitk_reduce, dim3((unsigned)blocks), dim3(RED_E * RED_G), 0,
+              st, part, nel, nsplit, scale, out, sym_nb);
+  return hipGetLastError();
 }
 
 struct SplitPlan {
@@ -398,12 +425,8 @@ static hipError_t gemm_ip(const void* A, int64_t lda, int na, const void* B,
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int64_t nel = (int64_t)na * nb * (cplx ? 2 : 1);
-  int64_t blocks = (nel + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  LACE_LAUNCH(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
-                     static_cast<const double*>(part), nel, sp.nsplit, scale,
-                     out, SYM ? nb : 0);
-  return hipGetLastError();
+  return launch_splitk_reduce(static_cast<const double*>(part), nel, sp.nsplit,
+                              scale, out, SYM ? nb : 0, st);
 }
 
 // S of FP32 grids: FP32 products on the matrix cores, FP64 sums.
@@ -419,12 +442,8 @@ static hipError_t gemm_ip_abs_f32(const void* A, int64_t lda, int na,
               A, lda, na, K, sp.kchunk, static_cast<double*>(part));
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t nel = (int64_t)na * na;
-  int64_t blocks = (nel + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  LACE_LAUNCH(k_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, st,
-              static_cast<const double*>(part), nel, sp.nsplit, scale, out, na);
-  return hipGetLastError();
+  return launch_splitk_reduce(static_cast<const double*>(part), (int64_t)na * na,
+                              sp.nsplit, scale, out, na, st);
 }
 
 hipError_t launch_gemm_ip_c128(const void* A, int64_t lda, int na,

@@ -176,6 +176,19 @@ static int64_t batch_bound(int n_orb, int ppb, bool gamma, bool virt) {
   return (nv - 1) * cdiv(slots_r, sp) + cdiv(cdiv(n_orb, 2), sp);
 }
 
+// Batches the host launches, and the most a schedule may use before the
+// round-robin fallback replaces it.  Slot schedules of real orbitals get a
+// margin above the round-robin bound: their star slots read three orbital
+// grids where the fallback's slots read four, which outweighs a few more
+// batches (a nearly complete pair set of 64 orbitals packs into 66 batches
+// of stars against the fallback's 64 without).  Complex plans gain nothing
+// from more batches than the round robin.
+static int64_t bound_margin(int64_t b) { return std::max<int64_t>(4, b / 64); }
+static int64_t launch_bound(int n_orb, int ppb, bool gamma, bool virt) {
+  const int64_t b = batch_bound(n_orb, ppb, gamma, virt);
+  return gamma && ppb >= 2 ? b + bound_margin(b) : b;
+}
+
 static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   const CellDev& c = p->cells[cell].dev;
   const bool fp64 = p->fp64;
@@ -214,7 +227,9 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.pts = off; off += align_up(sizeof(int32_t) * (size_t)n_orb);
   // batch table, sized for one pair per batch (any tuning) and one-sided
   // pairs
+  // every tuning's launch bound fits (batch_bound falls with ppb)
   L.max_batches = batch_bound(n_orb, 1, p->gamma, true);
+  L.max_batches += bound_margin(L.max_batches);
   L.tab = off; off += align_up(sizeof(BatchDev) * (size_t)L.max_batches);
   L.sched = off; off += align_up((size_t)sched_scratch_bytes(n_orb));
   L.kcnt = off; off += align_up(sizeof(int32_t) * (size_t)n_orb);
@@ -636,7 +651,7 @@ static hipError_t enqueue_schedule(const lace_plan* p, const CellDev& c,
   d.ppb = ppb;
   d.gamma = p->gamma;
   d.force_fallback = p->force_fallback;
-  d.max_batches = batch_bound(n_orb, ppb, p->gamma, src.n_occ < n_orb);
+  d.max_batches = launch_bound(n_orb, ppb, p->gamma, src.n_occ < n_orb);
   d.s = src.s;
   d.s_n = src.s_n;
   d.s_thr = src.s_thr;
@@ -653,7 +668,7 @@ static hipError_t enqueue_schedule(const lace_plan* p, const CellDev& c,
 
 // Schedule, pair pipeline, energy reduction, W back to plane waves.
 // Requires the grid orbitals in the workspace.  Without profiling the host
-// launches the bound of the schedule's batch count (batch_bound) and the
+// launches the bound of the schedule's batch count (launch_bound) and the
 // kernels of batches past the schedule's end return at once, so nothing
 // waits on the host.  Consecutive batches alternate between two internal
 // streams when `overlap` (batch b on lane b % 2): a batch's passes A and B
@@ -714,7 +729,7 @@ static hipError_t enqueue_exchange(lace_plan* p, const CellDev& c, int n_orb,
   if (e == hipSuccess) e = enqueue_schedule(p, c, n_orb, ppb, src, L, ws, n_kept, st);
   Profile& pr = p->prof;
   const bool timed = profile && pr.on;
-  int64_t nb = batch_bound(n_orb, ppb, p->gamma, src.n_occ < n_orb);
+  int64_t nb = launch_bound(n_orb, ppb, p->gamma, src.n_occ < n_orb);
   std::vector<BatchDev> host_tab;
   if (e == hipSuccess && timed) {
     // read the schedule back: the profile records each batch's bytes and
@@ -1370,7 +1385,7 @@ int schedule_list(const int32_t* pair_i, const int32_t* pair_j, int64_t n_pairs,
   h.words = (n_orb + 63) / 64;
   h.gamma = gamma;
   h.force_fallback = false;
-  h.max_batches = batch_bound(n_orb, per_batch, gamma, false);
+  h.max_batches = launch_bound(n_orb, per_batch, gamma, false);
   h.kb.assign((size_t)n_orb * h.words, 0ull);
   h.db.assign((size_t)h.words, 0ull);
   for (int64_t k = 0; k < n_pairs; ++k) {
@@ -1559,7 +1574,7 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
       timed_pairs += tab[nb++].npairs;
     // the whole schedule as the exchange launches it: up to the bound,
     // the batches past the schedule's end included
-    if (full) nb = (size_t)batch_bound(n_orb, cd.ppb, p->gamma, false);
+    if (full) nb = (size_t)launch_bound(n_orb, cd.ppb, p->gamma, false);
     double best = 1e30;
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
       e = hipEventRecord(t0, st);
