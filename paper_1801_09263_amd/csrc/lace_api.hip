@@ -199,16 +199,15 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   // the status block: first, so that lace_get_info finds the info word
   // without the layout
   L.info = off; off += 256;
-  // pair buffer and energy partials sized for the largest batch, so that
-  // one workspace serves every tuning of the cell
   // orbital and W grids; for real orbitals these hold n_orb real grids and
   // double as the scratch of ceil(n_orb / 2) packed complex transforms
   const size_t ob = p->gamma ? gb * ((n_orb + 1) / 2) : gb * n_orb;
   L.psi = off; off += align_up(ob);
   L.w = off; off += align_up(ob);
-  // two pair buffers and two sets of energy partials: consecutive batches
-  // alternate between them, so that one batch's passes A and B can run
-  // while the previous batch's pass C still reads its buffer
+  // two pair buffers and two sets of energy partials, each sized for the
+  // largest batch (so that one workspace serves every tuning of the cell):
+  // consecutive batches alternate between them, so that one batch's passes
+  // A and B can run while the previous batch's pass C still reads its buffer
   L.tmp = off; off += align_up(gb * SMAX * 2);
   L.epart = off;
   off += align_up(sizeof(double) * PMAX * 2 * energy_tiles(c.n, fp64));
@@ -225,9 +224,9 @@ static Layout layout_for(const lace_plan* p, int cell, int n_orb, int n_vec) {
   L.dens = off; off += align_up(sizeof(double) * (size_t)c.ng);
   L.scdm = off; off += align_up((size_t)scdm_scratch_bytes(n_orb));
   L.pts = off; off += align_up(sizeof(int32_t) * (size_t)n_orb);
-  // batch table, sized for one pair per batch (any tuning) and one-sided
-  // pairs
-  // every tuning's launch bound fits (batch_bound falls with ppb)
+  // batch table: the launch bound of one pair per batch, one-sided pairs
+  // included, which every tuning's launch bound stays below (batch_bound
+  // falls as ppb grows)
   L.max_batches = batch_bound(n_orb, 1, p->gamma, true);
   L.max_batches += bound_margin(L.max_batches);
   L.tab = off; off += align_up(sizeof(BatchDev) * (size_t)L.max_batches);
