@@ -354,7 +354,16 @@ __global__ __launch_bounds__(RED_E * RED_G) void k_splitk_reduce(
         const int64_t a = e / sym_nb, b = e % sym_nb;
         if (a / IP_T > b / IP_T) src = b * sym_nb + a;
       }
-      for (int z = g; z < nsplit; z += RED_G) t += part[(int64_t)z * nel + src];
+      constexpr int U = 8;   // loads in flight; the additions stay in order
+      int z = g;
+      for (; z + (U - 1) * RED_G < nsplit; z += U * RED_G) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = part[(int64_t)(z + u * RED_G) * nel + src];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t += v[u];
+      }
+      for (; z < nsplit; z += RED_G) t += part[(int64_t)z * nel + src];
     }
     red[g][el] = t;
     __syncthreads();

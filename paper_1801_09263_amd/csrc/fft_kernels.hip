@@ -917,11 +917,22 @@ __global__ void k_gather(const C<T>* w, int64_t gs, const int32_t* gidx,
   }
 }
 
+// Thread t adds part[t], part[t + 256], ... in that order (16 loads in
+// flight per step, the additions still in order), then the workgroup sum.
 __global__ void k_reduce_sum(const double* part, int64_t count, double factor,
                              double* out) {
   __shared__ double red[256 / 64];
+  constexpr int U = 16;
   double t = 0.0;
-  for (int64_t k = threadIdx.x; k < count; k += 256) t += part[k];
+  int64_t k = threadIdx.x;
+  for (; k + (U - 1) * 256 < count; k += U * 256) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = part[k + u * 256];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t += v[u];
+  }
+  for (; k < count; k += 256) t += part[k];
   const double tot = block_sum<256>(t, red);
   if (threadIdx.x == 0) *out = factor * tot;
 }
