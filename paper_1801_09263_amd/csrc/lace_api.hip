@@ -1168,12 +1168,12 @@ void slot_list(const HostSched& h, std::vector<HSlot>& slots,
         if (rho < rows[v].size() / 2)
           slots.push_back({v, rows[v][2 * rho], v, rows[v][2 * rho + 1], 2, 0u});
   };
-  // left-overs, round 1: at the smaller orbital, in group order
+  // left-overs, first pass: at the smaller orbital, in group order
   std::vector<std::vector<int>> rows(n);
   for (const auto& e : left) rows[e.first].push_back(e.second);
   std::vector<int> pend(n, -1);
   emit_stars(rows, pend);
-  // round 2: the unpaired edges at their larger orbital
+  // second pass: the unpaired edges at their larger orbital
   std::vector<std::vector<int>> rows2(n);
   for (int v = 0; v < n; ++v)
     if (pend[v] >= 0) rows2[pend[v]].push_back(v);   // v ascending

@@ -531,12 +531,12 @@ __global__ __launch_bounds__(PK_NT) void k_sched_list(PackArgs a, PackScratch sc
     }
     __syncthreads();
     nslots = tot[0];
-    // left-overs, round 1: stars at the smaller orbital, in group order
+    // left-overs, first pass: stars at the smaller orbital, in group order
     const int16_t* ytab = sc.ytab;
     nslots += emit_stars(sc.lb, n, gw,
                          [ytab, ng](int v, int g) { return (int)ytab[(int64_t)v * ng + g]; },
                          sc.slots + nslots, vcnt, cur, pend, red);
-    // round 2: the unpaired edges, stars at their larger orbital
+    // second pass: the unpaired edges, stars at their larger orbital
     for (int v = tid; v < n; v += PK_NT) {
       const int y = pend[v];
       if (y >= 0)
