@@ -335,10 +335,11 @@ int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
  * per batch (8, 16, 32, 64, and 128 for real-orbital plans) with every xy
  * schedule that exists (half-plane, plane, pencil), timed on its first
  * batches holding at least 2048 pairs; the three fastest again over their
- * whole schedules (as the exchange launches them, the batches past the
- * schedule's end included).  Stage 2, for the fastest of those: the z tiles half and
- * twice as wide and the reversed radix order, where they differ from the
- * default, over the whole schedule.  Keeps the fastest whole-schedule time
+ * whole schedules as the exchange runs them (the batches past the
+ * schedule's end included); every time includes its pairs' share of the
+ * time the device takes to build the candidate's schedule.  Stage 2, for the fastest of
+ * those: the z tiles half and twice as wide and the reversed radix order,
+ * where they differ from the default, over the whole schedule.  Keeps the fastest whole-schedule time
  * with lace_set_tuning.  Writes up to *n_cand candidates (cand_ppb,
  * cand_plane, cand_ztile, cand_radix, cand_us_per_pair: the whole-schedule
  * time where it was taken, else the first batches'; host arrays, may be

@@ -1550,14 +1550,23 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
     return LACE_EHIP;
   // us per pair of a candidate: its first batches holding at least 16 *
-  // PMAX pairs, or (full) its whole schedule; on two lanes as the exchange
-  // runs them; the best of the repetitions after the first
+  // PMAX pairs, or (full) its whole schedule, on two lanes as the exchange
+  // runs them (the best of the repetitions after the first), plus their
+  // share of the schedule's build time
   auto time_cand = [&](Cand& cd, bool full) {
     c.ppb = cd.ppb;
     c.use_plane = cd.plane;
     c.ztile = cd.ztile;
     c.radix = cd.radix;
+    // the schedule's own build time, charged to the timed pairs in
+    // proportion (batches that never fill leave every slot to the one-wave
+    // refill, which makes the build cost depend on the candidate)
+    if (e == hipSuccess) e = hipEventRecord(t0, st);
     if (e == hipSuccess) e = enqueue_schedule(p, c, n_orb, cd.ppb, all, L, ws, nullptr, st);
+    if (e == hipSuccess) e = hipEventRecord(t1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float sched_ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&sched_ms, t0, t1);
     Status h{};
     if (e == hipSuccess)
       e = hipMemcpyAsync(&h, status_of(ws, L), sizeof(h), hipMemcpyDeviceToHost, st);
@@ -1567,7 +1576,8 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
       e = hipMemcpyAsync(tab.data(), at(ws, L.tab), sizeof(BatchDev) * tab.size(),
                          hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    int64_t timed_pairs = 0;
+    int64_t timed_pairs = 0, all_pairs = 0;
+    for (const BatchDev& b : tab) all_pairs += b.npairs;
     size_t nb = 0;
     while (nb < tab.size() && (full || timed_pairs < 16 * PMAX))
       timed_pairs += tab[nb++].npairs;
@@ -1584,7 +1594,10 @@ int lace_autotune(lace_plan* p, int cell, const void* psi_g, int n_orb,
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
       if (rep > 0 && ms < best) best = ms;   // first repetition warms up
     }
-    const double us = timed_pairs > 0 ? 1e3 * best / double(timed_pairs) : 1e30;
+    const double share = all_pairs > 0 ? double(timed_pairs) / double(all_pairs) : 0.0;
+    const double us = timed_pairs > 0
+                          ? 1e3 * (best + sched_ms * share) / double(timed_pairs)
+                          : 1e30;
     // the whole-schedule time is the best over the rounds it is taken in
     cd.us = full && cd.full ? std::min(cd.us, us) : us;
     cd.full = full;

@@ -157,12 +157,17 @@ def test_autotune_picks_a_candidate_and_stays_correct():
     assert cands[:len(stage1)] == stage1
     assert len(stage1) == 12     # 4 batch sizes x 3 xy schedules
     assert all(c[4] > 0 for c in cands)
-    # stage 2 varies the z tile and the radix order of stage 1's best
-    b1 = min(stage1, key=lambda c: c[4])
-    assert stage2 and all((c[0], c[1]) == (b1[0], b1[1]) for c in stage2)
+    # stage 2 varies the z tile and the radix order of one stage-1
+    # candidate (the fastest over its whole schedule; the other stage-1
+    # times may cover only their first batches, so they are not compared)
+    bases = {(c[0], c[1]) for c in stage2}
+    assert stage2 and len(bases) == 1
+    assert any((c[0], c[1]) in bases for c in stage1)
     assert {(c[2], c[3]) for c in stage2} <= {(1, 0), (2, 0), (0, 1)}
-    best = min(cands, key=lambda c: c[4])
-    assert lace.lace_get_tuning(mc.plan, 0) == best[:4]
+    chosen = lace.lace_get_tuning(mc.plan, 0)
+    assert chosen in [tuple(c[:4]) for c in cands]
+    t_chosen = min(c[4] for c in cands if tuple(c[:4]) == chosen)
+    assert all(t_chosen <= c[4] for c in stage2)
     mc.run()
     torch.cuda.synchronize()
     res = O.run_path(coeffs, m, L, n)
