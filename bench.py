@@ -385,14 +385,14 @@ def synth_rate(rate):
     return synth.SERVE_RATE if rate is None else float(rate)
 
 
-def pmc_sample(torch, seed):
+def pmc_sample(torch, seed, tuning=(64, 2)):
     """Fixed run for hardware-counter passes: a plain 1 GiB device copy
     (the calibration of FETCH_SIZE / WRITE_SIZE), then one screened
     exchange application of the localized 120^3 workload in the
-    real-orbital mode (64 pairs per batch, half-plane xy passes) with the
-    pass profiler on, so that only the schedule's batches are launched, one
-    at a time.  Prints the launches, kept pairs and the library's moved
-    bytes per pass for the comparison with the counters."""
+    real-orbital mode (by default 64 pairs per batch, half-plane xy passes)
+    with the pass profiler on, so that only the schedule's batches are
+    launched, one at a time.  Prints the launches, kept pairs and the
+    library's moved bytes per pass for the comparison with the counters."""
     import synth
     from paper_1801_09263_amd import lace
     from paper_1801_09263_amd.session import CellSession
@@ -405,12 +405,13 @@ def pmc_sample(torch, seed):
     n_orb = inp["coeffs"].shape[0]
     sess = CellSession(inp, n_orb, lace.LACE_FP32_GAMMA)
     sess.set_orbitals(inp["coeffs"])
-    lace.lace_set_tuning(sess.plan, 0, 64, 2)
+    lace.lace_set_tuning(sess.plan, 0, *tuning)
     lace.lace_profile_enable(sess.plan, True)
     sess.apply_exchange(inp["s_thr"])
     torch.cuda.synchronize()
     prof = lace.lace_profile_read(sess.plan)
-    print(json.dumps({"pmc_sample": "ok", "n_kept": sess.n_kept,
+    print(json.dumps({"pmc_sample": "ok", "tuning": list(tuning),
+                      "n_kept": sess.n_kept,
                       "n_orb": n_orb, "n": int(inp["n"]),
                       "launches": prof["launches"],
                       "alg_bytes": prof["alg_bytes"]}), flush=True)
@@ -468,9 +469,10 @@ def write_traffic(fetch_db, write_db, sample_log, out_path):
         d["ratio_alg"] = d["bytes_per_launch"] / d["alg_bytes_per_launch"]
     res["passes"] = per
     res["sample"] = ("one screened exchange of the localized %d^3 workload, "
-                     "%d kept pairs of %d orbitals, 64 pairs per batch, "
-                     "half-plane xy passes, launches one at a time"
-                     % (n, n_kept, n_orb))
+                     "%d kept pairs of %d orbitals, tuning %s (pairs per "
+                     "batch, xy schedule, z tile, radix order), launches one "
+                     "at a time" % (n, n_kept, n_orb,
+                                    sample.get("tuning", [64, 2])))
     with open(out_path, "w") as fh:
         json.dump(res, fh, indent=1)
     return res
@@ -542,7 +544,9 @@ def main():
     lace.load()
 
     if args.pmc_sample:
-        pmc_sample(torch, args.seed)
+        pmc_sample(torch, args.seed,
+                   tuple(int(v) for v in args.tuning.split(","))
+                   if args.tuning else (64, 2))
         return
 
     n_orb = inp["coeffs"].shape[0]
