@@ -183,6 +183,25 @@ def test_slot_schedule_complete_pair_set(lib, n_orb, per_batch):
         assert nb <= 1.1 * len(pairs) / per_batch + 8
 
 
+def test_slot_schedule_nearly_complete_set_keeps_its_stars(lib):
+    """A nearly complete pair set (64 orbitals, 15 pairs missing) packs into
+    66 batches of star slots, two more than the round robin's 64: within
+    the margin max(4, b / 64) above the round-robin count b, so the
+    first-fit schedule is kept rather than replaced by the round robin's
+    slots, which hold no stars."""
+    rng = np.random.default_rng(64)
+    n_orb, per_batch = 64, 128
+    pairs = [(i, j) for j in range(n_orb) for i in range(j + 1)]
+    drop = set(rng.choice([k for k, (i, j) in enumerate(pairs) if i != j], 15,
+                          replace=False).tolist())
+    pairs = [p for k, p in enumerate(pairs) if k not in drop]
+    nb, n_slots, n_star = _check_slots(pairs, n_orb, per_batch)
+    n_off = sum(1 for i, j in pairs if i != j)
+    bound = 63 + 1   # 63 rounds of 32 pairs in one batch each, the diagonal
+    assert bound < nb <= bound + 4
+    assert 2 * n_star >= 0.9 * n_off
+
+
 @pytest.mark.parametrize("keep", [0.7, 0.3])
 def test_slot_schedule_screened_pair_set(lib, keep):
     rng = np.random.default_rng(int(keep * 10) + 1)

@@ -99,7 +99,7 @@ def random_pairs(n, keep, seed):
 
 CASES = [  # (n_orb, keep, pairs per batch)
     (150, 0.4, 64), (150, 1.0, 64), (97, 0.6, 32), (64, 0.2, 16), (33, 0.9, 8),
-    (40, 0.5, 1),
+    (40, 0.5, 1), (64, 0.99, 64),
 ]
 
 
