@@ -331,20 +331,21 @@ int lace_get_tuning(const lace_plan* plan, int cell, int* pairs_per_batch,
 /* Autotuner: times the pair pipeline of this cell on the given orbitals
  * and the pairs that S keeps at s_thr (Eq. (6); 0 keeps every pair), on
  * two internal streams as the exchange runs it, each candidate with its
- * own schedule of those pairs.  Stage 1: every pairs
- * per batch (8, 16, 32, 64, and 128 for real-orbital plans) with every xy
- * schedule that exists (half-plane, plane, pencil), timed on its first
- * batches holding at least 2048 pairs; the three fastest again over their
- * whole schedules as the exchange runs them (the batches past the
- * schedule's end included); every time includes its pairs' share of the
- * time the device takes to build the candidate's schedule.  Stage 2, for the fastest of
- * those: the z tiles half and twice as wide and the reversed radix order,
- * where they differ from the default, over the whole schedule.  Keeps the fastest whole-schedule time
- * with lace_set_tuning.  Writes up to *n_cand candidates (cand_ppb,
- * cand_plane, cand_ztile, cand_radix, cand_us_per_pair: the whole-schedule
- * time where it was taken, else the first batches'; host arrays, may be
- * NULL) and sets *n_cand to the number timed.  Synchronizes the stream.
- * The workspace is the one of lace_workspace_size (W is overwritten). */
+ * own schedule of those pairs.  Stage 1: every pairs per batch (8, 16, 32,
+ * 64, and 128 for real-orbital plans) with every xy schedule that exists
+ * (half-plane, plane, pencil), timed on its first batches holding at
+ * least 2048 pairs; the three fastest again over their whole schedules as
+ * the exchange runs them (the batches past the schedule's end included).
+ * Stage 2, for the fastest of those: the z tiles half and twice as wide
+ * and the reversed radix order, where they differ from the default, over
+ * the whole schedule.  Every time includes its pairs' share of the time
+ * the device takes to build that candidate's schedule.  Keeps the fastest
+ * whole-schedule time with lace_set_tuning.  Writes up to *n_cand
+ * candidates (cand_ppb, cand_plane, cand_ztile, cand_radix,
+ * cand_us_per_pair: the whole-schedule time where it was taken, else the
+ * first batches'; host arrays, may be NULL) and sets *n_cand to the number
+ * timed.  Synchronizes the stream.  The workspace is the one of
+ * lace_workspace_size (W is overwritten). */
 int lace_autotune(lace_plan* plan, int cell, const void* psi_g, int n_orb,
                   double s_thr, void* ws, size_t ws_bytes, lace_stream_t stream,
                   int* cand_ppb, int* cand_plane, int* cand_ztile,
