@@ -62,6 +62,28 @@ __device__ inline void stv(E* p, const Vec<E, V>& r) {
   }
 }
 
+// Nontemporal 16-byte accesses, for the pair buffer of the pipeline: each
+// batch's buffer is written once by pass A, read and rewritten once by the
+// z pass and read once by pass C, and nothing else reads it, so its lines
+// are marked as streaming and leave the caches to the orbitals, the W grids
+// and the kernel table, which later batches read again.
+typedef float f4_nt __attribute__((ext_vector_type(4)));
+template <typename E, int V>
+__device__ inline Vec<E, V> ldv_nt(const E* p) {
+  static_assert(sizeof(E) * V == 16, "16-byte vectors");
+  Vec<E, V> r;
+  const f4_nt t = __builtin_nontemporal_load(reinterpret_cast<const f4_nt*>(p));
+  __builtin_memcpy(&r, &t, 16);
+  return r;
+}
+template <typename E, int V>
+__device__ inline void stv_nt(E* p, const Vec<E, V>& r) {
+  static_assert(sizeof(E) * V == 16, "16-byte vectors");
+  f4_nt t;
+  __builtin_memcpy(&t, &r, 16);
+  __builtin_nontemporal_store(t, reinterpret_cast<f4_nt*>(p));
+}
+
 struct NoPre {};
 
 // Functor traits.  TABLE: the functor reads a batch of the pair pipeline
@@ -112,6 +134,24 @@ template <typename T> struct EpiGrid {
 #pragma unroll
     for (int v = 0; v < V; ++v) y.e[v] = scl<T>(x[v], scale);
     stv<C<T>, V>(buf + slot * gs + g, y);
+  }
+};
+// The pair buffer between the passes of the pipeline, accessed nontemporally.
+template <typename T> struct EpiSlotBuf : EpiGrid<T> {
+  static constexpr int V = EpiGrid<T>::V;
+  __device__ void putv(int g, int slot, const C<T>* x, const NoPre&) const {
+    Vec<C<T>, V> y;
+#pragma unroll
+    for (int v = 0; v < V; ++v) y.e[v] = scl<T>(x[v], this->scale);
+    stv_nt<C<T>, V>(this->buf + slot * this->gs + g, y);
+  }
+};
+template <typename T> struct ProSlotBuf : ProGrid<T> {
+  static constexpr int V = ProGrid<T>::V;
+  __device__ void getv(int g, int slot, C<T>* out) const {
+    const Vec<C<T>, V> x = ldv_nt<C<T>, V>(this->buf + slot * this->gs + g);
+#pragma unroll
+    for (int v = 0; v < V; ++v) out[v] = x.e[v];
   }
 };
 // Two real grids packed as one complex grid: value W_{2p} + i W_{2p+1}
@@ -748,7 +788,7 @@ void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
     const int p = zcol(tile, col), lx = p % N, ly = p / N;
     return (ly <= N - ly ? ly : N - ly) * VH + (lx <= N - lx ? lx : N - lx);
   }();
-  ProGrid<T> pro{g, 0};
+  ProSlotBuf<T> pro{{g, 0}};
   // DIT element pairs (column c < TX/2, column c + TX/2) of each z row
   constexpr int HC = TX / 2;
   constexpr int NVP = NE / 2 / V;
@@ -849,8 +889,8 @@ void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
           ya.e[v] = add<T>(a, b);
           yb.e[v] = mul<T>(sub<T>(a, b), w);
         }
-        stv<C<T>, V>(g + gidx(m), ya);
-        stv<C<T>, V>(g + gidx(m + HC), yb);
+        stv_nt<C<T>, V>(g + gidx(m), ya);
+        stv_nt<C<T>, V>(g + gidx(m + HC), yb);
       }
     }
   } else {
@@ -861,7 +901,7 @@ void k_zconv(C<T>* __restrict__ tmp, int64_t gs, const T* __restrict__ vtab,
         Vec<C<T>, V> y;
 #pragma unroll
         for (int v = 0; v < V; ++v) y.e[v] = s[lds(mv * V + v)];
-        stv<C<T>, V>(g + gidx(mv * V), y);
+        stv_nt<C<T>, V>(g + gidx(mv * V), y);
       }
     }
   }
@@ -1117,17 +1157,18 @@ template <typename T, int N, int RO = 0> struct Engine {
                               const BatchSync* sy) {
     const C<T>* tw = static_cast<const C<T>*>(c.tw);
     ProGrid<T> pt{tmp, NG};
-    EpiGrid<T> et{tmp, NG, T(1)};
+    ProSlotBuf<T> pb{{tmp, NG}};       // the pair buffer, nontemporal
+    EpiSlotBuf<T> eb{{tmp, NG, T(1)}};
     const int mode = (c.use_plane == 1 && !Cf::plane) ? 0 : c.use_plane;
     hipError_t err;
     if (ev && (err = hipEventRecord(ev[0], st)) != hipSuccess) return err;
     // pass A
     if (mode == 2) {
-      err = half<-1, XY_DIT ? 1 : 0>(pa_, et, cap, tw, st);
+      err = half<-1, XY_DIT ? 1 : 0>(pa_, eb, cap, tw, st);
     } else if (mode == 1) {
-      err = plane<-1>(pa_, et, cap, tw, st);
+      err = plane<-1>(pa_, eb, cap, tw, st);
     } else {
-      err = xlines<-1>(pa_, et, cap, tw, st);
+      err = xlines<-1>(pa_, EpiGrid<T>{tmp, NG, T(1)}, cap, tw, st);
       if (err == hipSuccess) err = cols<1, -1>(pt, EpiGridT{tmp, NG, T(1), bt}, cap, tw, st);
     }
     if (err != hipSuccess) return err;
@@ -1142,9 +1183,9 @@ template <typename T, int N, int RO = 0> struct Engine {
       return err;
     // pass C
     if (mode == 2) {
-      err = half<+1, XY_DIT ? 2 : 0>(pt, ec, cap, tw, st);
+      err = half<+1, XY_DIT ? 2 : 0>(pb, ec, cap, tw, st);
     } else if (mode == 1) {
-      err = plane<+1>(pt, ec, cap, tw, st);
+      err = plane<+1>(pb, ec, cap, tw, st);
     } else {
       err = cols<1, +1>(pt, EpiGridT{tmp, NG, T(1), bt}, cap, tw, st);
       if (err == hipSuccess) err = xlines<+1>(pt, ec, cap, tw, st);
